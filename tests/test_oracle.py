@@ -1,0 +1,357 @@
+"""Pins of the CPU oracle (oracle/) against what the paper and the mathematics fix.
+
+None of these tests uses the GPU library.  Each check compares the oracle with
+something other than itself:
+  * integer-exact brute force: entries in [-8, 8] make every product and sum
+    exact in binary64, so the checksum relations of §2.1
+    (e^T C = (e^T A) B,  C e = A (B e)) and the correction of §6.3 must hold
+    bitwise, and numpy's integer matmul gives the exact product;
+  * the worked example in tests/golden/worked_example.json;
+  * closed forms (identity, rank-1, all-ones, alpha = 0, beta = 0 with NaN C);
+  * the published first outputs of SplitMix64 seeded with 0;
+  * bijectivity of the slot permutation (every slot hit exactly once);
+  * rigor of the threshold: rounding alone never trips it on random data.
+A plausible slip in the oracle (a dropped beta term, a transposed operand, a
+wrong sign in the correction, a checksum taken over the wrong index) breaks at
+least one of them.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2104_00897_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "worked_example.json")
+ALPHAS = [0.0, 0.5, 1.0, 1.5, -2.0]
+
+
+def exact_product(A, B, C, alpha, beta, ta, tb):
+    """alpha*op(A)*op(B) + beta*C with integer matmul (exact for these inputs)."""
+    a = (A.T if ta else A).astype(np.int64)
+    b = (B.T if tb else B).astype(np.int64)
+    prod = (a @ b).astype(np.float64)
+    return alpha * prod + (beta * C if beta != 0 else 0.0)
+
+
+# ----------------------------------------------------------------------------- GEMM
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("alpha,beta", [(1.0, 0.0), (1.5, 0.5), (-2.0, 1.0), (0.5, -2.0)])
+def test_gemm_integer_exact(ta, tb, alpha, beta):
+    m, n, k = 37, 29, 53
+    A, B, C = inputs.integer_operands(m, n, k, seed=3, ta=ta, tb=tb)
+    out = oracle.gemm(A, B, C, alpha, beta, ta, tb)
+    np.testing.assert_array_equal(out, exact_product(A, B, C, alpha, beta, ta, tb))
+
+
+def test_gemm_special_cases():
+    rng = np.random.default_rng(1)
+    m, n, k = 9, 7, 9
+    B = np.asfortranarray(rng.uniform(-1, 1, (k, n)))
+    C = np.asfortranarray(rng.uniform(-1, 1, (m, n)))
+    # A = I  =>  C = alpha B + beta C
+    out = oracle.gemm(np.eye(m), B, C, 1.5, 0.5)
+    np.testing.assert_array_equal(out, 1.5 * B + 0.5 * C)
+    # k = 1  =>  rank-1: C_ij = alpha a_i b_j + beta c_ij
+    a = np.asfortranarray(rng.uniform(-1, 1, (m, 1)))
+    b = np.asfortranarray(rng.uniform(-1, 1, (1, n)))
+    out = oracle.gemm(a, b, C, 2.0, -1.0)
+    np.testing.assert_array_equal(out, 2.0 * (a * b) + (-1.0) * C)
+    # all ones  =>  alpha k + beta c
+    out = oracle.gemm(np.ones((m, 11)), np.ones((11, n)), C, 0.5, 2.0)
+    np.testing.assert_array_equal(out, 0.5 * 11 + 2.0 * C)
+    # alpha = 0  =>  beta C (A and B may hold anything)
+    bad = np.full((m, k), np.nan, order="F")
+    out = oracle.gemm(bad, np.full((k, n), np.inf, order="F"), C, 0.0, 3.0)
+    np.testing.assert_array_equal(out, 3.0 * C)
+    # beta = 0  =>  C is not read: NaN/Inf input disappears
+    Cnan = np.full((m, n), np.nan, order="F")
+    out = oracle.gemm(np.eye(m), B, Cnan, 1.0, 0.0)
+    np.testing.assert_array_equal(out, B)
+
+
+def test_gemm_quick_returns_and_errors():
+    lib = oracle._load()
+    C = np.full((3, 3), 7.0, order="F")
+    A = np.ones((3, 3), order="F")
+    # m = 0, n = 0, (alpha = 0 or k = 0) with beta = 1: C untouched
+    for (m, n, k, al) in [(0, 3, 3, 1.0), (3, 0, 3, 1.0), (3, 3, 3, 0.0), (3, 3, 0, 1.0)]:
+        info = lib.ftgo_gemm(0, 0, m, n, k, al, oracle._dptr(A), 3, oracle._dptr(A), 3, 1.0,
+                             oracle._dptr(C), 3)
+        assert info == 0
+        assert np.all(C == 7.0)
+    # BLAS argument numbering
+    d = oracle._dptr(A)
+    assert lib.ftgo_gemm(2, 0, 3, 3, 3, 1.0, d, 3, d, 3, 0.0, d, 3) == 1
+    assert lib.ftgo_gemm(0, 5, 3, 3, 3, 1.0, d, 3, d, 3, 0.0, d, 3) == 2
+    assert lib.ftgo_gemm(0, 0, -1, 3, 3, 1.0, d, 3, d, 3, 0.0, d, 3) == 3
+    assert lib.ftgo_gemm(0, 0, 3, -1, 3, 1.0, d, 3, d, 3, 0.0, d, 3) == 4
+    assert lib.ftgo_gemm(0, 0, 3, 3, -1, 1.0, d, 3, d, 3, 0.0, d, 3) == 5
+    assert lib.ftgo_gemm(0, 0, 3, 3, 3, 1.0, d, 2, d, 3, 0.0, d, 3) == 8
+    assert lib.ftgo_gemm(1, 0, 3, 3, 4, 1.0, d, 3, d, 4, 0.0, d, 3) == 8  # op(A)=A^T: lda >= k
+    assert lib.ftgo_gemm(0, 0, 3, 3, 4, 1.0, d, 3, d, 3, 0.0, d, 3) == 10
+    assert lib.ftgo_gemm(0, 0, 3, 3, 3, 1.0, d, 3, d, 3, 0.0, d, 2) == 13
+
+
+def test_gemm_matches_numpy_float():
+    # independent floating-point reference (LAPACK/BLAS matmul via numpy)
+    A, B, C = inputs.gemm_operands_f64(64, 48, 80, seed=5)
+    out = oracle.gemm(A, B, C, 1.5, 0.5)
+    ref = 1.5 * (A @ B) + 0.5 * C
+    mag = 1.5 * (np.abs(A) @ np.abs(B)) + 0.5 * np.abs(C)
+    assert np.all(np.abs(out - ref) <= 2 * 80 * 2.0 ** -53 * mag * 1.01)
+
+
+def test_gemm_entries_match_full():
+    A, B, C = inputs.gemm_operands_f64(20, 30, 40, seed=2, ta=1, tb=1)
+    full = oracle.gemm(A, B, C, -1.5, 2.0, 1, 1)
+    rows = np.array([0, 19, 5, 7]); cols = np.array([0, 29, 13, 2])
+    ent = oracle.gemm_entries(A, B, C, rows, cols, -1.5, 2.0, 1, 1)
+    np.testing.assert_array_equal(ent, full[rows, cols])
+
+
+# ----------------------------------------------------------------------------- worked example
+def test_worked_example_golden():
+    g = json.load(open(GOLDEN))
+    A = np.array(g["A"], dtype=np.float64, order="F")
+    B = np.array(g["B"], dtype=np.float64, order="F")
+    C = oracle.gemm(A, B)
+    np.testing.assert_array_equal(C, np.array(g["C"]))
+    # the checksum relations of §2.1 on the encoded operands
+    Ac = np.vstack([A, A.sum(axis=0)])
+    Br = np.hstack([B, B.sum(axis=1, keepdims=True)])
+    Cf = oracle.gemm(np.asfortranarray(Ac), np.asfortranarray(Br))
+    np.testing.assert_array_equal(Cf[-1, :-1], g["eT_A_times_B"])
+    np.testing.assert_array_equal(Cf[:-1, -1], g["A_times_B_e"])
+    np.testing.assert_array_equal(A.sum(axis=0), g["eT_A"])
+    np.testing.assert_array_equal(B.sum(axis=1), g["B_e"])
+    # the flip of the example and the resulting checksum differences
+    f = g["fault"]
+    assert oracle.flip64(C[f["row"], f["col"]], f["bit"]) == f["faulty_value"]
+    for fl in g["flips"]:
+        y = oracle.flip64(fl["x"], fl["bit"])
+        if fl["y"] == "inf":
+            assert y == math.inf
+        elif fl["y"] == "nan":
+            assert math.isnan(y)
+        else:
+            assert y == fl["y"]
+        if "delta" in fl:
+            assert y - fl["x"] == fl["delta"]
+
+
+def test_worked_example_abft_locates_and_corrects():
+    g = json.load(open(GOLDEN))
+    A = np.array(g["A"], dtype=np.float64, order="F")
+    B = np.array(g["B"], dtype=np.float64, order="F")
+    f = g["fault"]
+    # flip after the last step (k = 2): the accumulator holds the final 10.0
+    plan = [oracle.Fault(0, 0, 0, f["row"], f["col"], 1, f["bit"], oracle.TARGET_ACC)]
+    C, recs, cnt = oracle.abft(A, B, bm=4, bn=4, plan=plan)
+    np.testing.assert_array_equal(C, np.array(g["C"]))
+    assert cnt["injected"] == 1 and cnt["detected"] == 1 and cnt["corrected_subtract"] == 1
+    assert len(recs) == 1
+    r = recs[0]
+    assert (r.row, r.col, r.kind) == (f["row"], f["col"], oracle.KIND_SUBTRACT)
+    assert r.delta == f["delta_rows"][f["row"]] == f["delta_cols"][f["col"]]
+    # flip after step 0: 3*2 = 6 -> 3, then + 4*1 = 7, so delta = -3
+    plan = [oracle.Fault(0, 0, 0, f["row"], f["col"], 0, f["bit"], oracle.TARGET_ACC)]
+    C, recs, cnt = oracle.abft(A, B, bm=4, bn=4, plan=plan)
+    np.testing.assert_array_equal(C, np.array(g["C"]))
+    assert recs[0].delta == -3.0
+    # sign flip of the final value: delta = -20
+    plan = [oracle.Fault(0, 0, 0, f["row"], f["col"], 1, 63, oracle.TARGET_ACC)]
+    C, recs, cnt = oracle.abft(A, B, bm=4, bn=4, plan=plan)
+    np.testing.assert_array_equal(C, np.array(g["C"]))
+    assert recs[0].delta == -20.0 and recs[0].kind == oracle.KIND_SUBTRACT
+
+
+# ----------------------------------------------------------------------------- ABFT, integer exact
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("alpha,beta", [(1.0, 0.0), (1.5, 0.5), (-2.0, 1.0), (0.5, 1.5)])
+def test_abft_fault_free_integer_exact(ta, tb, alpha, beta):
+    m, n, k = 45, 38, 40
+    A, B, C = inputs.integer_operands(m, n, k, seed=7, ta=ta, tb=tb)
+    out, recs, cnt = oracle.abft(A, B, C, alpha, beta, ta, tb, bm=16, bn=16, kc=16)
+    np.testing.assert_array_equal(out, exact_product(A, B, C, alpha, beta, ta, tb))
+    assert recs == [] and cnt["detected"] == 0
+
+
+@pytest.mark.parametrize("kc", [0, 16])
+def test_abft_integer_faults_corrected_bitwise(kc):
+    m, n, k = 48, 40, 64
+    A, B, C = inputs.integer_operands(m, n, k, seed=11)
+    # mantissa/exponent bits whose flips keep integers exactly representable
+    plan = oracle.fault_plan(seed=5, n_faults=6, m=m, n=n, k=k, bm=16, bn=16, kc=kc, kgran=4,
+                             bit_lo=50, bit_hi=53)
+    assert len(plan) == 6
+    out, recs, cnt = oracle.abft(A, B, C, 1.5, 0.5, bm=16, bn=16, kc=kc, plan=plan)
+    np.testing.assert_array_equal(out, exact_product(A, B, C, 1.5, 0.5, 0, 0))
+    assert cnt["injected"] == 6
+    located = {(r.row, r.col) for r in recs if r.kind in (1, 2)}
+    # a flip can be masked only if it leaves the value unchanged (never for a
+    # single-bit flip), so each fault is found at its planned global position
+    want = {(f.tile_m * 16 + f.row, f.tile_n * 16 + f.col) for f in plan}
+    assert located == want
+    assert cnt["corrected_subtract"] + cnt["corrected_recompute"] == 6
+    assert cnt["uncorrectable"] == 0 and cnt["checksum_only"] == 0
+
+
+# ----------------------------------------------------------------------------- correction paths
+def _rand(m, n, k, seed=0, beta_c=True):
+    return inputs.gemm_operands_f64(m, n, k, seed=seed, with_c=beta_c)
+
+
+def _within(out, ref, A, B, C, alpha, beta, k, tol=None):
+    mag = abs(alpha) * (np.abs(A) @ np.abs(B)) + (abs(beta) * np.abs(C) if beta else 0.0)
+    tol = tol if tol is not None else max(1e-12, 2.2 * k * 2.0 ** -53)
+    return np.all(np.abs(out - ref) <= tol * mag + 1e-300)
+
+
+def test_recompute_path_for_absorbing_exponent_flip():
+    m, n, k = 32, 32, 64
+    A, B, C = _rand(m, n, k, seed=1)
+    ref = oracle.gemm(A, B, C, 1.0, 0.0)
+    # flip the top exponent bit early: the value becomes ~1e307 and absorbs later
+    # updates, so subtracting delta cannot restore it (the recompute fallback must)
+    plan = [oracle.Fault(0, 0, 0, 3, 5, 0, 62, oracle.TARGET_ACC)]
+    out, recs, cnt = oracle.abft(A, B, C, 1.0, 0.0, bm=32, bn=32, plan=plan)
+    assert [(r.row, r.col, r.kind) for r in recs] == [(3, 5, oracle.KIND_RECOMPUTE)]
+    assert _within(out, ref, A, B, C, 1.0, 0.0, k)
+
+
+def test_recompute_path_for_inf_and_nan():
+    m, n, k = 24, 20, 16
+    A = np.asfortranarray(np.full((m, k), 0.25))
+    B = np.asfortranarray(np.full((k, n), 0.25))   # acc after step 0 = 0.0625 = 2^-4
+    ref = oracle.gemm(A, B)
+    for bit in (62,):                               # 2^-4 with bit 62 -> 2^1020 (finite, huge)
+        plan = [oracle.Fault(0, 0, 0, 2, 3, 0, bit, oracle.TARGET_ACC)]
+        out, recs, _ = oracle.abft(A, B, bm=32, bn=32, plan=plan)
+        np.testing.assert_array_equal(out, ref)
+    # acc = 1.0 at step 15 -> +Inf; acc = 1.5 is impossible here, use a NaN-producing case below
+    plan = [oracle.Fault(0, 0, 0, 2, 3, 15, 62, oracle.TARGET_ACC)]
+    out, recs, _ = oracle.abft(A, B, bm=32, bn=32, plan=plan)
+    assert math.isinf(oracle.flip64(1.0, 62))
+    np.testing.assert_array_equal(out, ref)
+    assert recs[0].kind == oracle.KIND_RECOMPUTE and not math.isfinite(recs[0].delta)
+    A2 = np.asfortranarray(np.full((m, 1), 1.5)); B2 = np.asfortranarray(np.ones((1, n)))
+    plan = [oracle.Fault(0, 0, 0, 0, 0, 0, 62, oracle.TARGET_ACC)]   # 1.5 -> NaN
+    out, recs, _ = oracle.abft(A2, B2, bm=32, bn=32, plan=plan)
+    np.testing.assert_array_equal(out, oracle.gemm(A2, B2))
+    assert recs[0].kind == oracle.KIND_RECOMPUTE and math.isnan(recs[0].delta)
+
+
+def test_checksum_only_fault_leaves_data():
+    m, n, k = 40, 40, 48
+    A, B, C = inputs.integer_operands(m, n, k, seed=4)
+    plan = oracle.fault_plan(seed=9, n_faults=3, m=m, n=n, k=k, bm=16, bn=16, kc=16, kgran=4,
+                             bit_lo=50, bit_hi=53, target=oracle.TARGET_CHECKSUM)
+    out, recs, cnt = oracle.abft(A, B, C, 1.0, 1.0, bm=16, bn=16, kc=16, plan=plan)
+    np.testing.assert_array_equal(out, exact_product(A, B, C, 1.0, 1.0, 0, 0))
+    assert cnt["checksum_only"] == 3 and cnt["corrected_subtract"] == 0
+    assert all(r.kind == oracle.KIND_CHECKSUM_ONLY and r.col == -1 for r in recs)
+    # a corrupted checksum is re-based, so no later interval of its tile flags again
+    assert cnt["detected"] == 3
+
+
+def test_two_faults_in_one_slot_uncorrectable():
+    m, n, k = 32, 32, 32
+    A, B, C = inputs.integer_operands(m, n, k, seed=6)
+    plan = oracle.fault_plan(seed=2, n_faults=1, m=m, n=n, k=k, bm=32, bn=32, kgran=4,
+                             bit_lo=50, bit_hi=53, target=oracle.TARGET_TWO_IN_SLOT)
+    assert len(plan) == 2 and plan[0].row != plan[1].row and plan[0].col != plan[1].col
+    exact = exact_product(A, B, C, 1.0, 0.0, 0, 0)
+    out, recs, cnt = oracle.abft(A, B, C, 1.0, 0.0, bm=32, bn=32, plan=plan)
+    assert cnt["uncorrectable"] == 1 and recs[0].kind == oracle.KIND_UNCORRECTABLE
+    assert np.sum(out != exact) == 2          # reported, data left as computed
+    out, recs, cnt = oracle.abft(A, B, C, 1.0, 0.0, bm=32, bn=32, plan=plan,
+                                 uncorrectable_policy=1)
+    assert recs[0].kind == oracle.KIND_TILE_RECOMPUTED and cnt["tiles_recomputed"] == 1
+    np.testing.assert_array_equal(out, exact)
+
+
+def test_interval_mode_corrects_one_fault_per_interval():
+    # three faults in one tile, each in a different interval: all corrected (§2.1)
+    m, n, k = 16, 16, 96
+    A, B, C = inputs.integer_operands(m, n, k, seed=8)
+    plan = [oracle.Fault(0, 0, t, 2 + t, 5 + 2 * t, 32 * t + 7, 51, oracle.TARGET_ACC)
+            for t in range(3)]
+    out, recs, cnt = oracle.abft(A, B, C, 1.0, 0.0, bm=16, bn=16, kc=32, plan=plan)
+    np.testing.assert_array_equal(out, exact_product(A, B, C, 1.0, 0.0, 0, 0))
+    assert [(r.interval, r.row, r.col) for r in recs] == [(t, 2 + t, 5 + 2 * t) for t in range(3)]
+    # the same three faults without interval checks land in one slot: uncorrectable
+    out, recs, cnt = oracle.abft(A, B, C, 1.0, 0.0, bm=16, bn=16, kc=0, plan=[
+        oracle.Fault(0, 0, 0, f.row, f.col, f.pflip, f.bit, f.target) for f in plan])
+    assert cnt["uncorrectable"] == 1
+
+
+def test_correct_policy_always_recompute():
+    A, B, C = inputs.integer_operands(20, 20, 20, seed=1)
+    plan = [oracle.Fault(0, 0, 0, 4, 6, 10, 52, oracle.TARGET_ACC)]
+    out, recs, _ = oracle.abft(A, B, C, 1.0, 0.0, bm=32, bn=32, plan=plan, correct_policy=1)
+    np.testing.assert_array_equal(out, exact_product(A, B, C, 1.0, 0.0, 0, 0))
+    assert recs[0].kind == oracle.KIND_RECOMPUTE
+
+
+# ----------------------------------------------------------------------------- threshold rigor
+@pytest.mark.parametrize("shape,tile,kc,ab", [
+    ((128, 96, 256), (64, 32), 0, (1.5, 0.5)),
+    ((100, 70, 300), (32, 64), 64, (1.0, 0.0)),
+    ((64, 64, 512), (64, 64), 128, (-2.0, 1.0)),
+])
+def test_no_false_positive_fp64(shape, tile, kc, ab):
+    m, n, k = shape
+    for seed in range(3):
+        A, B, C = _rand(m, n, k, seed=seed)
+        out, recs, cnt = oracle.abft(A, B, C, ab[0], ab[1], bm=tile[0], bn=tile[1], kc=kc)
+        assert cnt["detected"] == 0, recs
+        ref = oracle.gemm(A, B, C, ab[0], ab[1])
+        np.testing.assert_array_equal(out, ref)   # same order of every sum as the plain loop
+
+
+def test_threshold_definition_values():
+    # gamma(n) = n u / (1 - n u) with u = 2^-53 (standard model of binary64)
+    for nterms in (1, 100, 4096, 16384):
+        u = 2.0 ** -53
+        assert oracle.gamma(nterms) == pytest.approx(nterms * u / (1 - nterms * u), rel=1e-15)
+    # a fault of magnitude >= 4 tau is always flagged: tau grows linearly with the magnitude
+    assert oracle.tau(1000, 2.0) == pytest.approx(2 * oracle.tau(1000, 1.0))
+
+
+# ----------------------------------------------------------------------------- injector plan
+def test_splitmix64_published_values():
+    # first three outputs of SplitMix64 started from state 0
+    assert oracle.splitmix64(0, 0) == 0xE220A8397B1DCDAF
+    assert oracle.splitmix64(0, 1) == 0x6E789E6AA1B965F4
+    assert oracle.splitmix64(0, 2) == 0x06C45D188009454F
+
+
+@pytest.mark.parametrize("S", list(range(1, 60)) + [64, 97, 128, 1000, 4096])
+def test_slot_permutation_is_bijection(S):
+    a, b = oracle.slot_permutation(12345 + S, S)
+    assert math.gcd(a, S) == 1 or S == 1
+    assert sorted((a * r + b) % S for r in range(S)) == list(range(S))
+
+
+def test_fault_plan_deterministic_distinct_capped():
+    kw = dict(m=300, n=260, k=256, bm=128, bn=128, kc=64, kgran=16)
+    p1 = oracle.fault_plan(seed=42, n_faults=20, **kw)
+    p2 = oracle.fault_plan(seed=42, n_faults=20, **kw)
+    assert p1 == p2
+    slots = {(f.tile_m, f.tile_n, f.interval) for f in p1}
+    assert len(slots) == len(p1) == 20
+    for f in p1:
+        rows = min(128, 300 - 128 * f.tile_m); cols = min(128, 260 - 128 * f.tile_n)
+        assert 0 <= f.row < rows and 0 <= f.col < cols and 40 <= f.bit <= 63
+        lo, hi = 64 * f.interval, 64 * f.interval + 64
+        assert lo <= f.pflip < hi and (f.pflip + 1) % 16 == 0
+    # capped at the number of slots: 3 x 3 tiles x 4 intervals = 36
+    full = oracle.fault_plan(seed=1, n_faults=1000, **kw)
+    assert len(full) == 36
+    assert {(f.tile_m, f.tile_n, f.interval) for f in full} == {
+        (a, b, c) for a in range(3) for b in range(3) for c in range(4)}
+    assert oracle.fault_plan(seed=43, n_faults=20, **kw) != p1
