@@ -1,0 +1,241 @@
+/*
+ * ftgemm.h -- C ABI of the checksum-protected GEMM for AMD MI355X (gfx950).
+ *
+ * Operation (BLAS dgemm semantics, column-major):
+ *     C := alpha * op(A) * op(B) + beta * C,   op(X) = X or X^T,
+ * with op(A) m x k, op(B) k x n, C m x n.  The product is protected by
+ * algorithm-based fault tolerance (ABFT, Zhai et al., "FT-BLAS", ICS'21):
+ *   - checksum encoding A^c = [A; e^T A], B^r = [B, B e]            (§2.1)
+ *   - the relations e^T C = (e^T A) B and C e = A (B e) maintained
+ *     through the rank-k updates of the k loop                       (§2.1)
+ *   - encoding fused into the operand loads and the beta scaling of C,
+ *     reference sums taken from the computed C in registers          (§5.2)
+ *   - a mismatch above the round-off threshold locates the faulty row
+ *     and column; the element is corrected by subtracting the error
+ *     magnitude (§5.1, §6.3), one error per verification interval
+ *     without checkpoint/rollback                                    (§2.1)
+ * Checksums are kept per output tile (the unit each workgroup computes),
+ * so every tile can correct one error per verification interval.
+ *
+ * Conventions for every entry point:
+ *   - Matrix pointers are DEVICE pointers owned by the caller.  C is
+ *     updated in place; C must not alias A or B.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Launches are
+ *     asynchronous on it; no entry point synchronises except
+ *     ftg_report_read with sync = 1.  No entry point allocates memory per
+ *     call: device buffers belong to the handle.
+ *   - Argument errors return FTG_ERR_INVALID_ARG and set
+ *     ftg_last_error_arg() to the BLAS xerbla position of the first bad
+ *     argument of dgemm: 1 transa, 2 transb, 3 m, 4 n, 5 k, 8 lda,
+ *     10 ldb, 13 ldc; 20 for an invalid ftg_config field.
+ *   - Quick return, touching no memory, when m = 0, n = 0, or
+ *     (alpha = 0 or k = 0) and beta = 1.  alpha = 0 (or k = 0) computes
+ *     C := beta*C without reading A or B.  beta = 0 never reads C, so NaN
+ *     or Inf in C on input do not propagate.
+ *   - One handle per stream: calls that share a handle on different
+ *     streams race on its fault report.  No C++ exception crosses the ABI.
+ */
+#ifndef FTGEMM_H
+#define FTGEMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { FTG_OP_N = 0, FTG_OP_T = 1 } ftg_op;
+
+/* operand element types (A and B share one type; C is FTG_F64 or FTG_F32) */
+typedef enum { FTG_F64 = 0, FTG_F32 = 1, FTG_BF16 = 2, FTG_F8_E4M3 = 3 } ftg_dtype;
+
+typedef enum {
+    FTG_OK = 0,
+    FTG_ERR_INVALID_ARG = 1,
+    FTG_ERR_UNSUPPORTED = 2,
+    FTG_ERR_HIP = 3,
+    FTG_ERR_UNCORRECTED = 4 /* only from ftg_report_read */
+} ftg_status;
+
+/* fault-record kinds */
+enum {
+    FTG_KIND_SUBTRACT = 1,        /* located, corrected by subtracting delta   */
+    FTG_KIND_RECOMPUTE = 2,       /* located, corrected by a fresh dot product */
+    FTG_KIND_CHECKSUM_ONLY = 3,   /* one direction only: the checksum was hit  */
+    FTG_KIND_UNCORRECTABLE = 4,   /* more than one error in the slot; reported */
+    FTG_KIND_TILE_RECOMPUTED = 5  /* uncorrectable slot, tile recomputed       */
+};
+
+/* injection targets */
+enum {
+    FTG_TARGET_ACC = 0,         /* a bit of one accumulator element of C           */
+    FTG_TARGET_CHECKSUM = 1,    /* a bit of the maintained row checksum of one row */
+    FTG_TARGET_TWO_IN_SLOT = 2  /* two accumulator faults in one slot (distinct row
+                                   and column): outside the one-error model        */
+};
+
+/* Seeded in-kernel fault injector (emulates the source-level injection of
+ * §6.3 with single-bit flips of values held in registers).
+ *
+ * A "slot" is one (tile, verification interval) pair; slots are numbered
+ * s = (tile_n * tiles_m + tile_m) * n_intervals + interval.  Fault r
+ * (0 <= r < F, F = min(n_faults, #slots)) goes to slot (a*r + b) mod S,
+ * a keyed bijection, so the F slots are distinct.  a and b come from
+ * SplitMix64 (Steele, Lea & Flood 2014) seeded with `seed`: b is output 0
+ * mod S, a the first of outputs 1..64 mapped to 1 + x mod (S-1) that is
+ * coprime to S.  Fault r uses outputs x0..x7 numbered 1024+8r..1024+8r+7:
+ * row = x0 mod rows-in-tile, col = x1 mod cols-in-tile,
+ * step = interval start + x2 mod interval length,
+ * bit = bit_lo + x3 mod (bit_hi - bit_lo + 1); the flip lands right after
+ * the update of the rank-128 block of k holding `step`.  (TWO_IN_SLOT draws
+ * its second fault from x4..x7.)  n_faults = 0 with per_mac_rate > 0 sets
+ * F = ceil(m*n*k*per_mac_rate). */
+typedef struct ftg_inject {
+    uint64_t seed;
+    uint32_t n_faults;
+    uint32_t target;     /* FTG_TARGET_* */
+    double per_mac_rate; /* used when n_faults == 0 */
+    int32_t bit_lo;      /* flipped bit range of the 64-bit (FP64 path) or */
+    int32_t bit_hi;      /* 32-bit (FP32-accumulating paths) value         */
+} ftg_inject;
+
+typedef struct ftg_config {
+    int32_t abft;        /* 1: protected kernel; 0: the same kernel with the ABFT
+                            code compiled out (for overhead measurement)        */
+    int32_t interval_k;  /* verification interval in steps of k; 0 = the whole
+                            k loop (one verification per tile); otherwise a
+                            multiple of 128                                     */
+    double lambda;       /* threshold scale of the FP32-accumulating paths
+                            (0 = default 4); unused for FP64                   */
+    int32_t correct_policy;       /* 0: subtract, re-verify, else recompute;
+                                     1: always recompute the located element    */
+    int32_t uncorrectable_policy; /* 0: report only; 1: recompute the tile      */
+    int32_t tile;        /* tile configuration id (0 = chosen by the tuning
+                            table); see ftg_tile_info                           */
+    int32_t reserved;
+    const ftg_inject* inject; /* NULL = no injection (host memory, read at call) */
+} ftg_config;
+
+/* One detection outcome (per slot; for data faults, the located element). */
+typedef struct ftg_fault_record {
+    int32_t problem;   /* index in a batched call, 0 otherwise */
+    int32_t tile_m, tile_n, interval;
+    int64_t row, col;  /* global element position; -1 where not applicable */
+    int32_t kind;      /* FTG_KIND_* */
+    int32_t reserved;
+    double delta;      /* checksum difference of the located row (or of the
+                          flagged line for checksum-only/uncorrectable)      */
+    double tau;        /* threshold it was compared with                     */
+} ftg_fault_record;
+
+/* One applied injection (written by the kernel as it flips the bit). */
+typedef struct ftg_inject_record {
+    int32_t problem;
+    int32_t tile_m, tile_n, interval;
+    int64_t row, col;  /* global element (row checksum target: col = -1) */
+    int64_t pflip;     /* last k step whose update precedes the flip */
+    int32_t bit, target;
+    double old_val, new_val;
+} ftg_inject_record;
+
+/* Report accumulated on the handle since the last ftg_report_reset.
+ * records/inject_log point to HOST arrays of `capacity` entries owned by
+ * the caller; n_records/n_injected may exceed capacity (entries dropped). */
+typedef struct ftg_fault_report {
+    uint64_t injected, detected, corrected_subtract, corrected_recompute;
+    uint64_t checksum_only, uncorrectable, tiles_recomputed;
+    uint32_t n_records, n_inject_log, capacity, reserved;
+    ftg_fault_record* records;
+    ftg_inject_record* inject_log;
+} ftg_fault_report;
+
+typedef struct ftg_handle_s* ftg_handle;
+
+/* Creates a handle on the current HIP device: allocates the device fault
+ * report with room for `report_capacity` records and injection-log entries,
+ * and the device buffers of the batched entry point.  The report starts
+ * empty. */
+ftg_status ftg_create(ftg_handle* h, size_t report_capacity);
+ftg_status ftg_destroy(ftg_handle h);
+
+/* FP64 protected GEMM (the paper's FT-DGEMM, §5.2), see the file header. */
+ftg_status ftg_dgemm(ftg_handle h, ftg_op transa, ftg_op transb, int64_t m, int64_t n,
+                     int64_t k, double alpha, const double* A, int64_t lda, const double* B,
+                     int64_t ldb, double beta, double* C, int64_t ldc, void* stream,
+                     const ftg_config* cfg);
+
+/* Mixed-precision protected GEMM: A, B of type ab_type (FTG_BF16 or
+ * FTG_F8_E4M3, OCP e4m3fn), FP32 accumulation on MFMA, FP32 maintained
+ * checksums, FP64 reference sums and locate/correct; C of type c_type
+ * (FTG_F32).  For FTG_F8_E4M3, scale_a and scale_b are DEVICE pointers to
+ * one float each (per-tensor scales: the operand value is code * scale) and
+ * the product is alpha * s_A * s_B * (A_q B_q) + beta * C; they are ignored
+ * (may be NULL) for FTG_BF16.  The verification threshold uses the
+ * probabilistic rounding bound lambda * sqrt(n) * 2^-24 in place of
+ * gamma(n).  cfg->inject->bit_lo/hi refer to the FP32 accumulator. */
+ftg_status ftg_gemm_ex(ftg_handle h, ftg_op transa, ftg_op transb, int64_t m, int64_t n,
+                       int64_t k, ftg_dtype ab_type, ftg_dtype c_type, const float* scale_a,
+                       const float* scale_b, float alpha, const void* A, int64_t lda,
+                       const void* B, int64_t ldb, float beta, void* C, int64_t ldc,
+                       void* stream, const ftg_config* cfg);
+
+/* `count` independent FP64 protected GEMMs of arbitrary shapes in ONE
+ * persistent launch: workgroups take (problem, tile) work items from a
+ * device queue.  All arrays are HOST arrays of length count (pointer
+ * arrays hold DEVICE pointers); they are copied into the handle's device
+ * descriptor table with an asynchronous copy on `stream` (so the call can
+ * be captured in a hipGraph when the host arrays are pinned and kept
+ * alive until the graph's replays finish).  Each problem's tile shape comes
+ * from the tuning table for its (m, n, k).  Injection slots are numbered
+ * per problem; cfg->inject->n_faults is the count PER PROBLEM (use
+ * faults_per_problem for a varying count).  count is limited by the
+ * capacity given to ftg_batched_reserve (default 1024).  Fault records
+ * carry the problem index. */
+ftg_status ftg_dgemm_batched_uneven(ftg_handle h, int64_t count, const ftg_op* transa,
+                                    const ftg_op* transb, const int64_t* m, const int64_t* n,
+                                    const int64_t* k, const double* alpha,
+                                    const double* const* A, const int64_t* lda,
+                                    const double* const* B, const int64_t* ldb,
+                                    const double* beta, double* const* C, const int64_t* ldc,
+                                    const uint32_t* faults_per_problem, void* stream,
+                                    const ftg_config* cfg);
+
+/* Grows the batched descriptor table to `capacity` problems (allocates;
+ * not to be called during graph capture). */
+ftg_status ftg_batched_reserve(ftg_handle h, int64_t capacity);
+
+/* Copies the device report into *out (counters always; up to out->capacity
+ * records and injection-log entries into out->records / out->inject_log
+ * when those are non-NULL) with asynchronous copies on `stream`; with
+ * sync = 1 it then waits for the stream.  Returns FTG_ERR_UNCORRECTED when
+ * sync = 1 and some slot stayed uncorrectable (kind 4). */
+ftg_status ftg_report_read(ftg_handle h, void* stream, ftg_fault_report* out, int sync);
+
+/* Clears the device report with a kernel launched on `stream`
+ * (graph-capturable). */
+ftg_status ftg_report_reset(ftg_handle h, void* stream);
+
+/* BLAS info of the last FTG_ERR_INVALID_ARG returned on this handle. */
+int ftg_last_error_arg(ftg_handle h);
+
+/* Tile configurations: id >= 1.  Writes the tile shape (rows, columns,
+ * k-block) of configuration `id` for operand type `ab_type`; returns
+ * FTG_ERR_INVALID_ARG for an unknown id. */
+ftg_status ftg_tile_info(ftg_dtype ab_type, int32_t id, int32_t* bm, int32_t* bn, int32_t* bk);
+
+/* Tuning table: the tile configuration used when cfg->tile == 0.  Entries
+ * map a shape bucket (ceil(log2) of m, n and k, each clamped to [4, 15])
+ * of one operand type to a configuration id.  ftg_tune_set overrides one
+ * bucket; ftg_tune_get reads it (the built-in heuristic when unset). */
+ftg_status ftg_tune_set(ftg_handle h, ftg_dtype ab_type, int64_t m, int64_t n, int64_t k,
+                        int32_t id);
+int32_t ftg_tune_get(ftg_handle h, ftg_dtype ab_type, int64_t m, int64_t n, int64_t k);
+
+/* Human-readable name of a status code (static storage). */
+const char* ftg_status_string(ftg_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FTGEMM_H */

@@ -1,0 +1,843 @@
+// FP64 checksum-protected GEMM kernel for gfx950 (CDNA4).
+//
+//   C := alpha op(A) op(B) + beta C, column-major, one workgroup per BM x BN
+//   output tile, v_mfma_f64_16x16x4_f64 on 64-lane waves.
+//
+// ABFT (Zhai et al., FT-BLAS, ICS'21) fused into the tile computation:
+//   a1  each k-block's A and B panels are staged in LDS; the checksum row
+//       e^T A_I and column B_J e of the encoded operands A^c, B^r (§2.1) are
+//       summed from the staged panels (with |.| sums for the threshold);
+//   a2  MFMA accumulation acc += A_I B_J over the k loop;
+//   a3  maintained checksums er = A_I (B_J e) and ec = (e^T A_I) B_J advanced
+//       with every rank-16 update on the register-resident MFMA operands,
+//       which keeps the outer-product relation of §2.1 true after each step;
+//   a4  at the end, C_in is read once (skipped when beta = 0) and its row and
+//       column sums enter the expected checksums, fused with the beta scaling
+//       (§5.2);
+//   a5  reference sums of the computed C from the accumulators in registers
+//       (§5.2) via cross-lane and cross-wave reductions;
+//   a6  mismatch beyond the round-off threshold (NaN-safe) flags a row/col;
+//   a7  one flagged row and column locate the element, corrected by
+//       subtracting the error magnitude (§6.3), re-verified, else recomputed;
+//       a flag in one direction only is a checksum fault; more is reported
+//       (and the tile recomputed under that policy);
+//   a9  the seeded injector flips a bit of an accumulator (or checksum) after
+//       the planned k-block;
+//   a10 with a verification interval, a5-a7 also run on the accumulators at
+//       the end of every interval (the online scheme of §2.1, one correction
+//       per interval).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ftg_common.hpp"
+#include "ftg_kernels.hpp"
+
+namespace ftg {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+template <int BM, int BN, int WGM, int WGN, bool TA, bool TB>
+struct DCfg {
+    static constexpr int BK = 16;
+    static constexpr int NW = WGM * WGN;
+    static constexpr int NT = NW * 64;
+    static constexpr int WM = BM / WGM, WN = BN / WGN;
+    static constexpr int FM = WM / 16, FN = WN / 16;
+    // LDS layouts: A as [p][i] (TA = 0) or [i][p] (TA = 1); B as [p][j] (TB = 1) or [j][p]
+    static constexpr int SA = TA ? (BK + 2) : (BM + 16);
+    static constexpr int SB = TB ? (BN + 16) : (BK + 2);
+    static constexpr int A_ELEMS = TA ? BM * SA : BK * SA;
+    static constexpr int B_ELEMS = TB ? BK * SB : BN * SB;
+    static constexpr int NA = BM * BK / NT, NB = BN * BK / NT;  // loads per thread
+    static constexpr int PPW = BK / NW, LPP = 64 / PPW;        // encode: p's per wave, lanes per p
+    static constexpr int GSH = FM / WGN, HSH = FN / WGM;        // checksum FMA shares per wave
+    static_assert(BM * BK % NT == 0 && BN * BK % NT == 0, "load split");
+    static_assert(BK % NW == 0 && FM % WGN == 0 && FN % WGM == 0, "checksum split");
+    __device__ static int a_idx(int i, int p) { return TA ? i * SA + p : p * SA + i; }
+    __device__ static int b_idx(int p, int j) { return TB ? p * SB + j : j * SB + p; }
+};
+
+// Per-tile verification bookkeeping in LDS.
+template <int BM, int BN, int WGM, int WGN>
+struct VerifyLds {
+    double rsum[WGN][BM];
+    double csum[WGM][BN];
+    double cir[WGN][BM], cira[WGN][BM];  // C_in row sums (signed, abs)
+    double cic[WGM][BN], cica[WGM][BN];  // C_in column sums
+    double er[BM], mr[BM], ec[BN], mc[BN];
+    double dfi, tfi, dfj, tfj, xold, dotv, cin;
+    int nfr, nfc, fi, fj, xfinite, kind;
+};
+
+// Final-slot repair of one located element of a tile whose output is already
+// stored in C (rare path; one wave; global memory only).  Subtracts the error
+// magnitude (§6.3) and re-verifies the element's row and column against their
+// expected checksums; if that fails, recomputes the element from a fresh dot
+// product and re-verifies; if that fails too, restores the value.
+struct RepairIn {
+    const double* A;
+    const double* B;
+    double* C;
+    int64_t lda, ldb, ldc, m0, n0, K;
+    int R, Q, fi, fj, correct_policy;
+    double alpha, beta, dfi, tfi, tfj, exp_row, exp_col, cin;
+};
+
+template <bool TA, bool TB>
+__device__ __attribute__((noinline)) int repair_final(RepairIn in, int lane)
+{
+    const __amdgpu_buffer_rsrc_t rc = make_rsrc(in.C + in.m0 + in.n0 * in.ldc);
+    const int xo = (int)((in.fi + (int64_t)in.fj * in.ldc) * 8);
+    auto ld = [&](int voff) {  // glc: bypass the CU cache, other waves just stored the tile
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rc, voff, 0, 1));
+    };
+    auto lines_ok = [&]() {
+        double r = 0.0, c = 0.0;
+        for (int j = lane; j < in.Q; j += 64) r += ld((int)((in.fi + (int64_t)j * in.ldc) * 8));
+        for (int i = lane; i < in.R; i += 64) c += ld((int)((i + (int64_t)in.fj * in.ldc) * 8));
+        r = group_sum<64>(r);
+        c = group_sum<64>(c);
+        return !flagged(r - in.exp_row, in.tfi) && !flagged(c - in.exp_col, in.tfj);
+    };
+    auto put = [&](double v) {
+        if (lane == 0) buf_store_f64(v, rc, xo, 0);
+        __threadfence();
+    };
+    const double x = ld(xo);
+    if (in.correct_policy == 0 && isfinite(in.dfi) && isfinite(x)) {
+        put(x - in.dfi);
+        if (lines_ok()) return FTG_KIND_SUBTRACT;
+    }
+    double s = 0.0;
+    const int64_t gi = in.m0 + in.fi, gj = in.n0 + in.fj;
+    for (int64_t p = lane; p < in.K; p += 64) {
+        const double a = TA ? in.A[p + gi * in.lda] : in.A[gi + p * in.lda];
+        const double b = TB ? in.B[gj + p * in.ldb] : in.B[p + gj * in.ldb];
+        s = fma(a, b, s);
+    }
+    s = group_sum<64>(s);
+    double v = in.alpha * s;
+    if (in.beta != 0.0) v += in.beta * in.cin;
+    put(v);
+    if (lines_ok()) return FTG_KIND_RECOMPUTE;
+    put(x);
+    return FTG_KIND_UNCORRECTABLE;
+}
+
+template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool ABFT, bool IVL>
+__global__ __launch_bounds__(WGM* WGN * 64) void dgemm_abft_kernel(DGemmArgs args)
+{
+    using Cf = DCfg<BM, BN, WGM, WGN, TA, TB>;
+    constexpr int BK = Cf::BK, NT = Cf::NT, FM = Cf::FM, FN = Cf::FN;
+    constexpr int WM = Cf::WM, WN = Cf::WN;
+
+    __shared__ double As[2][Cf::A_ELEMS];
+    __shared__ double Bs[2][Cf::B_ELEMS];
+    __shared__ double sums[2][BK][4];  // e^T A_I, |A_I|, B_J e, |B_J| per step p
+    __shared__ VerifyLds<BM, BN, WGM, WGN> V;
+    __shared__ int flt[kMaxIntervals][2][4];  // per interval: up to two faults (row, col, pflip, bit)
+    __shared__ int fltn[kMaxIntervals];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wr = wave / WGN, wc = wave % WGN;
+    const int wm0 = wr * WM, wn0 = wc * WN;
+    const int l16 = lane & 15, lq = lane >> 4;
+
+    int tm, tn;
+    tile_of_block(blockIdx.x, gridDim.x, args.tiles_m, args.tiles_n, 4, &tm, &tn);
+    const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+    const int R = (int)min((int64_t)BM, (int64_t)args.m - m0);
+    const int Q = (int)min((int64_t)BN, (int64_t)args.n - n0);
+    const int64_t K = args.k;  // widened for index math
+    const int nkb = (int)((K + BK - 1) / BK);
+    const int64_t kc = args.kc;  // interval length (multiple of kKGran), >= K means one interval
+    const int n_int = (int)((K + kc - 1) / kc);  // <= kMaxIntervals (checked by the host)
+
+    const double* A = args.A;
+    const double* B = args.B;
+
+    d4v acc[FM][FN];
+    double er[Cf::GSH], mr[Cf::GSH], ec[Cf::HSH], mc[Cf::HSH];
+    double ra[Cf::NA], rb[Cf::NB];
+
+    auto zero_state = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int g = 0; g < FM; ++g)
+#pragma unroll
+            for (int h = 0; h < FN; ++h) acc[g][h] = (d4v){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < Cf::GSH; ++q) er[q] = mr[q] = 0.0;
+#pragma unroll
+        for (int q = 0; q < Cf::HSH; ++q) ec[q] = mc[q] = 0.0;
+    };
+
+    // ---- global -> registers.  Each thread stages a fixed line of the operand
+    // panel and walks along the operand's contiguous dimension, so the q-th load
+    // is the thread's byte offset plus the constant q*8 (an immediate operand of
+    // the buffer instruction: no per-load scalar registers).  Elements outside
+    // the matrix read 0 through an out-of-range offset.
+    //   contiguous along the tile dimension (A with TA=0, B with TB=1):
+    //     16 lanes per k step, element q at tile index lane%16 + 16q;
+    //   contiguous along k (A with TA=1, B with TB=0):
+    //     NT/ROWS threads per tile line, each reading BK*ROWS/NT consecutive steps.
+    static_assert(NT % BM == 0 && NT % BN == 0 && NT == 16 * BK, "staging map");
+    constexpr int APT = TA ? BK * BM / NT : BM / 16;   // elements per thread
+    constexpr int BPT = TB ? BN / 16 : BK * BN / NT;
+    static_assert(APT == Cf::NA && BPT == Cf::NB, "staging count");
+    // A: TA=0 -> (i = tid%16 + 16q, p = tid/16); TA=1 -> (i = tid%BM, p = (tid/BM)*APT + q)
+    const int ai0 = TA ? tid % BM : tid % 16;
+    const int ap0 = TA ? (tid / BM) * APT : tid / 16;
+    // B: TB=1 -> (j = tid%16 + 16q, p = tid/16); TB=0 -> (j = tid%BN, p = (tid/BN)*BPT + q)
+    const int bj0 = TB ? tid % 16 : tid % BN;
+    const int bp0 = TB ? tid / 16 : (tid / BN) * BPT;
+    auto a_ip = [&](int q, int* i, int* p) __attribute__((always_inline)) {
+        if (TA) { *i = ai0; *p = ap0 + q; } else { *i = ai0 + 16 * q; *p = ap0; }
+    };
+    auto b_jp = [&](int q, int* j, int* p) __attribute__((always_inline)) {
+        if (TB) { *j = bj0 + 16 * q; *p = bp0; } else { *j = bj0; *p = bp0 + q; }
+    };
+    const int64_t lda = args.lda, ldb = args.ldb;
+    const int a_voff = (int)((TA ? (ap0 + (int64_t)ai0 * lda) : (ai0 + (int64_t)ap0 * lda)) * 8);
+    const int b_voff = (int)((TB ? (bj0 + (int64_t)bp0 * ldb) : (bp0 + (int64_t)bj0 * ldb)) * 8);
+    constexpr int a_qstep = TA ? 8 : 128, b_qstep = TB ? 128 : 8;  // bytes per q
+    const bool full_mn = (R == BM) && (Q == BN);
+
+    auto load_global = [&](int kb) __attribute__((always_inline)) {
+        const int64_t k0 = (int64_t)kb * BK;
+        const int kv = (int)min((int64_t)BK, K - k0);  // valid steps in this block
+        const __amdgpu_buffer_rsrc_t ra_ = make_rsrc(TA ? A + m0 * lda + k0 : A + m0 + k0 * lda);
+        const __amdgpu_buffer_rsrc_t rb_ = make_rsrc(TB ? B + n0 + k0 * ldb : B + k0 + n0 * ldb);
+        if (full_mn && kv == BK) {
+#pragma unroll
+            for (int q = 0; q < APT; ++q) ra[q] = buf_load_f64(ra_, a_voff + q * a_qstep, 0);
+#pragma unroll
+            for (int q = 0; q < BPT; ++q) rb[q] = buf_load_f64(rb_, b_voff + q * b_qstep, 0);
+        } else {
+#pragma unroll
+            for (int q = 0; q < APT; ++q) {
+                int i, p;
+                a_ip(q, &i, &p);
+                ra[q] = buf_load_f64(ra_, (i < R && p < kv) ? a_voff + q * a_qstep : kOOB, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < BPT; ++q) {
+                int j, p;
+                b_jp(q, &j, &p);
+                rb[q] = buf_load_f64(rb_, (j < Q && p < kv) ? b_voff + q * b_qstep : kOOB, 0);
+            }
+        }
+    };
+    auto store_lds = [&](int st) __attribute__((always_inline)) {
+#pragma unroll
+        for (int q = 0; q < APT; ++q) {
+            int i, p;
+            a_ip(q, &i, &p);
+            As[st][Cf::a_idx(i, p)] = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) {
+            int j, p;
+            b_jp(q, &j, &p);
+            Bs[st][Cf::b_idx(p, j)] = rb[q];
+        }
+    };
+    // ---- a1: checksum row/column of the encoded operands for the staged k-block
+    auto encode = [&](int st) __attribute__((always_inline)) {
+        const int p = wave * Cf::PPW + lane / Cf::LPP;
+        const int sub = lane % Cf::LPP;
+        double sa = 0.0, saa = 0.0, sb = 0.0, sba = 0.0;
+#pragma unroll
+        for (int u = 0; u < BM / Cf::LPP; ++u) {
+            double v = As[st][Cf::a_idx(sub + u * Cf::LPP, p)];
+            sa += v;
+            saa += fabs(v);
+        }
+#pragma unroll
+        for (int u = 0; u < BN / Cf::LPP; ++u) {
+            double v = Bs[st][Cf::b_idx(p, sub + u * Cf::LPP)];
+            sb += v;
+            sba += fabs(v);
+        }
+        sa = group_sum<Cf::LPP>(sa);
+        saa = group_sum<Cf::LPP>(saa);
+        sb = group_sum<Cf::LPP>(sb);
+        sba = group_sum<Cf::LPP>(sba);
+        if (sub == 0) {
+            sums[st][p][0] = sa;
+            sums[st][p][1] = saa;
+            sums[st][p][2] = sb;
+            sums[st][p][3] = sba;
+        }
+    };
+    // ---- a2 + a3: one k-block of MFMA with the checksum updates.  Fragments of
+    // the next rank-4 step are read from LDS while the current step's MFMAs run;
+    // the scheduling fence keeps the compiler from hoisting further reads.
+    auto mfma_block = [&](int st) __attribute__((always_inline)) {
+        constexpr int NS = BK / 4;
+        double a[2][FM], b[2][FN], sm[2][4];
+        auto load_frag = [&](int s_, int buf) __attribute__((always_inline)) {
+            const int p = 4 * s_ + lq;
+#pragma unroll
+            for (int g = 0; g < FM; ++g) a[buf][g] = As[st][Cf::a_idx(wm0 + 16 * g + l16, p)];
+#pragma unroll
+            for (int h = 0; h < FN; ++h) b[buf][h] = Bs[st][Cf::b_idx(p, wn0 + 16 * h + l16)];
+            if (ABFT) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) sm[buf][c] = sums[st][p][c];
+            }
+        };
+        load_frag(0, 0);
+#pragma unroll
+        for (int s_ = 0; s_ < NS; ++s_) {
+            const int cur = s_ & 1;
+            if (s_ + 1 < NS) load_frag(s_ + 1, cur ^ 1);
+#pragma unroll
+            for (int g = 0; g < FM; ++g)
+#pragma unroll
+                for (int h = 0; h < FN; ++h)
+                    acc[g][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[cur][g], b[cur][h], acc[g][h], 0, 0, 0);
+            if (ABFT) {
+                const double as_ = sm[cur][0], asa = sm[cur][1], bs_ = sm[cur][2], bsa = sm[cur][3];
+                // this wave's share of the rows (columns) that the waves of its
+                // wave-row (wave-column) have in common
+#pragma unroll
+                for (int g = 0; g < FM; ++g)
+                    if (g % WGN == wc) {
+                        er[g / WGN] = fma(a[cur][g], bs_, er[g / WGN]);
+                        mr[g / WGN] = fma(fabs(a[cur][g]), bsa, mr[g / WGN]);
+                    }
+#pragma unroll
+                for (int h = 0; h < FN; ++h)
+                    if (h % WGM == wr) {
+                        ec[h / WGM] = fma(as_, b[cur][h], ec[h / WGM]);
+                        mc[h / WGM] = fma(asa, fabs(b[cur][h]), mc[h / WGM]);
+                    }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+
+    // ---- element access by a uniform tile position (rare paths only): a sweep of
+    // selects over the accumulators keeps the code compact and free of
+    // dynamically indexed register arrays.
+    auto elem_index = [&](int row, int col) __attribute__((always_inline)) {
+        const int rr = row % WM, cc = col % WN;
+        return ((rr / 16) * FN + cc / 16) * 4 + (rr % 16) / 4;  // (g, h, r) flattened
+    };
+    auto owner_of = [&](int row, int col) __attribute__((always_inline)) {
+        const int rr = row % WM, cc = col % WN;
+        return (row / WM == wr) && (col / WN == wc) && lane == ((rr % 16) % 4) * 16 + (cc % 16);
+    };
+    auto get_elem = [&](int idx) __attribute__((always_inline)) {
+        double v = 0.0;
+#pragma unroll
+        for (int g = 0; g < FM; ++g)
+#pragma unroll
+            for (int h = 0; h < FN; ++h)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if ((g * FN + h) * 4 + r == idx) v = acc[g][h][r];  // idx is uniform
+        return v;
+    };
+    auto set_elem = [&](int idx, double v, bool own) __attribute__((always_inline)) {
+#pragma unroll
+        for (int g = 0; g < FM; ++g)
+#pragma unroll
+            for (int h = 0; h < FN; ++h)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if ((g * FN + h) * 4 + r == idx) acc[g][h][r] = own ? v : acc[g][h][r];
+    };
+
+    // ---- a9: apply a planned flip to the value it targets (owner lane only)
+    auto apply_fault = [&](const Fault& f, int t) __attribute__((always_inline)) {
+        double oldv = 0.0, newv = 0.0;
+        bool own;
+        const bool ck = args.inj.target == FTG_TARGET_CHECKSUM;
+        if (ck) {
+            const int g = (f.row % WM) / 16;
+            own = (f.row / WM == wr) && (g % WGN == wc) && lane == (f.row % 16);
+#pragma unroll
+            for (int q = 0; q < Cf::GSH; ++q)
+                if (q == g / WGN) {
+                    oldv = er[q];
+                    newv = flip_f64(oldv, f.bit);
+                    er[q] = own ? newv : er[q];
+                }
+        } else {
+            own = owner_of(f.row, f.col);
+            const int idx = __builtin_amdgcn_readfirstlane(elem_index(f.row, f.col));
+            oldv = get_elem(idx);
+            newv = flip_f64(oldv, f.bit);
+            set_elem(idx, newv, own);
+        }
+        if (own)
+            push_inject(args.rep, args.problem, tm, tn, t, m0 + f.row, ck ? -1 : n0 + f.col, f.pflip,
+                        f.bit, ck ? FTG_TARGET_CHECKSUM : FTG_TARGET_ACC, oldv, newv);
+    };
+
+    // ---- a4 + a5 + a6: reductions and flags; results in V.nfr / V.nfc (and the
+    // first flagged row/column with its delta and tau).  On a final check acc
+    // holds C_out and the C_in sums are in V.
+    auto reduce_and_flag = [&](bool final, int64_t pend) __attribute__((always_inline)) {
+#pragma unroll
+        for (int g = 0; g < FM; ++g) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double s = 0.0;
+#pragma unroll
+                for (int h = 0; h < FN; ++h) s += acc[g][h][r];
+                s = group_sum<16>(s);
+                if (l16 == 0) V.rsum[wc][wm0 + 16 * g + 4 * r + lq] = s;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int h = 0; h < FN; ++h) {
+            double s = 0.0;
+#pragma unroll
+            for (int g = 0; g < FM; ++g)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) s += acc[g][h][r];
+            s = quarter_sum(s);
+            if (lq == 0) V.csum[wr][wn0 + 16 * h + l16] = s;
+        }
+        // maintained checksums: complete after summing the four p lanes
+#pragma unroll
+        for (int q = 0; q < Cf::GSH; ++q) {
+            const double e = quarter_sum(er[q]), mm = quarter_sum(mr[q]);
+            if (lq == 0) {
+                const int row = wm0 + 16 * (q * WGN + wc) + l16;
+                V.er[row] = e;
+                V.mr[row] = mm;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < Cf::HSH; ++q) {
+            const double e = quarter_sum(ec[q]), mm = quarter_sum(mc[q]);
+            if (lq == 0) {
+                const int col = wn0 + 16 * (q * WGM + wr) + l16;
+                V.ec[col] = e;
+                V.mc[col] = mm;
+            }
+        }
+        if (tid == 0) { V.nfr = 0; V.nfc = 0; }
+        __syncthreads();
+        const bool cin = final && args.beta != 0.0;
+        for (int line = tid; line < BM + BN; line += NT) {
+            const bool isrow = line < BM;
+            const int x = isrow ? line : line - BM;
+            if (x >= (isrow ? R : Q)) continue;
+            double ref = 0.0, ci = 0.0, cia = 0.0;
+            if (isrow) {
+#pragma unroll
+                for (int w = 0; w < WGN; ++w) {
+                    ref += V.rsum[w][x];
+                    if (cin) { ci += V.cir[w][x]; cia += V.cira[w][x]; }
+                }
+            } else {
+#pragma unroll
+                for (int w = 0; w < WGM; ++w) {
+                    ref += V.csum[w][x];
+                    if (cin) { ci += V.cic[w][x]; cia += V.cica[w][x]; }
+                }
+            }
+            double ex = isrow ? V.er[x] : V.ec[x];
+            double mag = isrow ? V.mr[x] : V.mc[x];
+            if (final) {
+                ex = args.alpha * ex;
+                mag = fabs(args.alpha) * mag;
+                if (cin) { ex += args.beta * ci; mag += fabs(args.beta) * cia; }
+            }
+            const double d = ref - ex;
+            const double tau = tau_of(0, 0.0, pend + (isrow ? Q : R) + 8, mag);
+            if (flagged(d, tau)) {
+                if (isrow) {
+                    if (atomicAdd(&V.nfr, 1) == 0) { V.fi = x; V.dfi = d; V.tfi = tau; }
+                } else {
+                    if (atomicAdd(&V.nfc, 1) == 0) { V.fj = x; V.dfj = d; V.tfj = tau; }
+                }
+            }
+        }
+        __syncthreads();
+    };
+
+    // fresh dot product of tile row fi and column fj over steps [0, pend), by wave 0
+    auto fresh_dot = [&](int fi, int fj, int64_t pend) __attribute__((always_inline)) {
+        if (wave == 0) {
+            const int64_t gi = m0 + fi, gj = n0 + fj;
+            double s = 0.0;
+            for (int64_t p = lane; p < pend; p += 64) {
+                const double a = TA ? A[p + gi * lda] : A[gi + p * lda];
+                const double b = TB ? B[gj + p * ldb] : B[p + gj * ldb];
+                s = fma(a, b, s);
+            }
+            s = group_sum<64>(s);
+            if (lane == 0) V.dotv = s;
+        }
+        __syncthreads();
+        return V.dotv;
+    };
+
+    // ---- a7: verification of one slot (a small state machine around one
+    // reduce-and-flag pass): check -> subtract (§6.3) -> recompute -> give up.
+    // Returns true when the tile must be recomputed (uncorrectable, policy 1).
+    const int64_t ldc = args.ldc;
+    // a tile is recomputed at most once: with non-finite inputs the checks can
+    // never pass, and the second attempt is reported instead of repeated
+    int redo_budget = 1;
+    auto verify = [&](bool final, int64_t pend, int t) __attribute__((always_inline)) -> bool {
+        int stage = 0;  // 0 first check, 1 after subtract, 2 after recompute
+        int fi = 0, fj = 0, idx = 0;
+        bool own = false;
+        double dfi = 0.0, tfi = 0.0, xold = 0.0;
+        for (;;) {
+            reduce_and_flag(final, pend);
+            const int nr = __builtin_amdgcn_readfirstlane(V.nfr);
+            const int nc = __builtin_amdgcn_readfirstlane(V.nfc);
+            int kind = 0;  // outcome to record; 0 = try the recompute next
+            if (stage == 0) {
+                if (nr == 0 && nc == 0) return false;
+                if (tid == 0) atomicAdd(&args.rep->cnt[kDetected], 1ull);
+                if (nr == 1 && nc == 1) {
+                    fi = __builtin_amdgcn_readfirstlane(V.fi);
+                    fj = __builtin_amdgcn_readfirstlane(V.fj);
+                    dfi = V.dfi;
+                    tfi = V.tfi;
+                    own = owner_of(fi, fj);
+                    idx = __builtin_amdgcn_readfirstlane(elem_index(fi, fj));
+                    const double x = get_elem(idx);
+                    __syncthreads();
+                    if (own) { V.xold = x; V.xfinite = isfinite(x) ? 1 : 0; }
+                    __syncthreads();
+                    xold = V.xold;
+                    stage = 1;
+                    if (args.correct_policy == 0 && isfinite(dfi) &&
+                        __builtin_amdgcn_readfirstlane(V.xfinite)) {
+                        set_elem(idx, xold - dfi, own);  // subtract the error (§6.3)
+                        continue;
+                    }
+                } else if (nr + nc == 1) {
+                    // one direction only: the maintained checksum is the faulty value;
+                    // re-base it on the data for the following intervals
+                    const int fr = __builtin_amdgcn_readfirstlane(V.fi);
+                    const int fc = __builtin_amdgcn_readfirstlane(V.fj);
+                    if (!final) {
+                        if (nr) {
+                            const int g = (fr % WM) / 16;
+#pragma unroll
+                            for (int q = 0; q < Cf::GSH; ++q)
+                                if (q == g / WGN && fr / WM == wr && g % WGN == wc && lane == fr % 16)
+                                    er[q] += V.dfi;
+                        } else {
+                            const int h = (fc % WN) / 16;
+#pragma unroll
+                            for (int q = 0; q < Cf::HSH; ++q)
+                                if (q == h / WGM && fc / WN == wc && h % WGM == wr && lane == fc % 16)
+                                    ec[q] += V.dfj;
+                        }
+                    }
+                    if (tid == 0) {
+                        atomicAdd(&args.rep->cnt[kChecksumOnly], 1ull);
+                        push_record(args.rep, args.problem, tm, tn, t, nr ? m0 + fr : -1,
+                                    nr ? -1 : n0 + fc, FTG_KIND_CHECKSUM_ONLY, nr ? V.dfi : V.dfj,
+                                    nr ? V.tfi : V.tfj);
+                    }
+                    __syncthreads();
+                    return false;
+                } else {
+                    kind = FTG_KIND_UNCORRECTABLE;
+                }
+            } else if (nr == 0 && nc == 0) {
+                kind = stage == 1 ? FTG_KIND_SUBTRACT : FTG_KIND_RECOMPUTE;
+            } else {
+                set_elem(idx, xold, own);  // undo the attempt
+                if (stage == 2) kind = FTG_KIND_UNCORRECTABLE;
+            }
+            if (kind == 0) {
+                // recompute the located element from a fresh dot product
+                const double dot = fresh_dot(fi, fj, pend);
+                double v = dot;
+                if (final) {
+                    v = args.alpha * dot;
+                    if (args.beta != 0.0) v += args.beta * args.C[(m0 + fi) + (n0 + fj) * ldc];
+                }
+                set_elem(idx, v, own);
+                stage = 2;
+                continue;
+            }
+            bool redo = false;
+            if (kind == FTG_KIND_UNCORRECTABLE && args.uncorrectable_policy == 1 && redo_budget > 0) {
+                redo = true;
+                kind = FTG_KIND_TILE_RECOMPUTED;
+            }
+            if (tid == 0) {
+                if (kind == FTG_KIND_SUBTRACT) atomicAdd(&args.rep->cnt[kCorrSub], 1ull);
+                if (kind == FTG_KIND_RECOMPUTE) atomicAdd(&args.rep->cnt[kCorrRecomp], 1ull);
+                if (kind >= FTG_KIND_UNCORRECTABLE) atomicAdd(&args.rep->cnt[kUncorrectable], 1ull);
+                if (kind == FTG_KIND_TILE_RECOMPUTED) atomicAdd(&args.rep->cnt[kTilesRecomputed], 1ull);
+                const bool loc = kind == FTG_KIND_SUBTRACT || kind == FTG_KIND_RECOMPUTE;
+                const double d = (stage > 0) ? dfi : (nr ? V.dfi : V.dfj);
+                const double tt = (stage > 0) ? tfi : (nr ? V.tfi : V.tfj);
+                push_record(args.rep, args.problem, tm, tn, t, loc ? m0 + fi : -1, loc ? n0 + fj : -1,
+                            kind, d, tt);
+            }
+            __syncthreads();
+            return redo;
+        }
+    };
+
+    // ---- a4: C_out = alpha acc + beta C_in in registers, C_in sums to LDS.
+    // Lane (lq, l16) holds rows wm0 + 16g + 4r + lq, columns wn0 + 16h + l16.
+    // element (g, h, r): row bytes (16g + 4r)*8 < 4096 ride in the instruction's
+    // immediate offset; the column step 16*h*ldc*8 is one uniform offset per h.
+    const int c_voff = (int)((wm0 + lq + (int64_t)(wn0 + l16) * ldc) * 8);
+    const int c_hstep = (int)(16 * ldc * 8);
+    auto c_vo = [&](int g, int r, bool ok) __attribute__((always_inline)) {
+        return ok ? c_voff + (16 * g + 4 * r) * 8 : kOOB;
+    };
+    auto c_ok = [&](int g, int h, int r) __attribute__((always_inline)) {
+        return full_mn || ((wm0 + 16 * g + 4 * r + lq < R) && (wn0 + 16 * h + l16 < Q));
+    };
+    auto finalize_output = [&]() __attribute__((always_inline)) {
+        const bool cin = args.beta != 0.0;
+        const __amdgpu_buffer_rsrc_t rc = make_rsrc(args.C + m0 + n0 * ldc);
+        double cs[FN], csa[FN];
+#pragma unroll
+        for (int h = 0; h < FN; ++h) cs[h] = csa[h] = 0.0;
+#pragma unroll
+        for (int g = 0; g < FM; ++g)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double s = 0.0, sa = 0.0;
+#pragma unroll
+                for (int h = 0; h < FN; ++h) {
+                    double c = 0.0;
+                    if (cin) c = buf_load_f64(rc, c_vo(g, r, c_ok(g, h, r)), h * c_hstep);
+                    acc[g][h][r] = cin ? args.alpha * acc[g][h][r] + args.beta * c
+                                       : args.alpha * acc[g][h][r];
+                    s += c;
+                    sa += fabs(c);
+                    cs[h] += c;
+                    csa[h] += fabs(c);
+                }
+                if (ABFT && cin) {
+                    s = group_sum<16>(s);
+                    sa = group_sum<16>(sa);
+                    if (l16 == 0) {
+                        V.cir[wc][wm0 + 16 * g + 4 * r + lq] = s;
+                        V.cira[wc][wm0 + 16 * g + 4 * r + lq] = sa;
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        if (ABFT && cin) {
+#pragma unroll
+            for (int h = 0; h < FN; ++h) {
+                const double s = quarter_sum(cs[h]), sa = quarter_sum(csa[h]);
+                if (lq == 0) { V.cic[wr][wn0 + 16 * h + l16] = s; V.cica[wr][wn0 + 16 * h + l16] = sa; }
+            }
+        }
+    };
+
+    // ------------------------------------------------------------------ main loop
+    // a9: the tile's injection plan, one thread per interval, kept in LDS so the
+    // k loop only reads a few uniform values at interval starts.
+    const bool inj = ABFT && args.inj.on;
+    int inj_from = 0;  // intervals below this one replay fault-free after a recompute
+    if (inj) {
+        const uint64_t tile_id = (uint64_t)tn * args.tiles_m + tm;
+        for (int tt = tid; tt < n_int; tt += NT) {
+            const int64_t plo = (int64_t)tt * kc, phi = min(K, plo + kc);
+            Fault f2[2];
+            const int nf = slot_faults(args.inj, tile_id * n_int + tt, R, Q, plo, phi, f2);
+            fltn[tt] = nf;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                flt[tt][q][0] = f2[q].row;
+                flt[tt][q][1] = f2[q].col;
+                flt[tt][q][2] = (int)f2[q].pflip;
+                flt[tt][q][3] = f2[q].bit;
+            }
+        }
+        __syncthreads();
+    }
+    // fault q of interval tt that lands after k-block kb (read from LDS when needed)
+    auto fault_kb = [&](int tt, int q) __attribute__((always_inline)) {
+        if (!inj || tt < inj_from || q >= fltn[tt]) return -1;
+        return flt[tt][q][2] / BK;
+    };
+    auto load_fault = [&](int tt, int q) __attribute__((always_inline)) {
+        Fault f;
+        f.row = __builtin_amdgcn_readfirstlane(flt[tt][q][0]);
+        f.col = __builtin_amdgcn_readfirstlane(flt[tt][q][1]);
+        f.pflip = __builtin_amdgcn_readfirstlane(flt[tt][q][2]);
+        f.bit = __builtin_amdgcn_readfirstlane(flt[tt][q][3]);
+        return f;
+    };
+
+    // One pass of the k loop, repeated only when a slot turned out
+    // uncorrectable and the policy asks for the tile to be recomputed.  The k
+    // loop runs in segments that end where something has to happen to the
+    // accumulators (a planned flip, an interval check), so the hot loop body
+    // holds nothing but staging, encode and MFMA work.
+    const int kb_per_int = (int)(kc / BK);
+    int t = 0;
+    for (;;) {
+        zero_state();
+        t = 0;
+        load_global(0);
+        store_lds(0);
+        __syncthreads();
+        if (ABFT) { encode(0); __syncthreads(); }
+        bool restart = false;
+        int kb = 0;
+        while (kb < nkb) {
+            // end of this segment: the interval end or the next planned flip
+            int seg = IVL ? min(nkb, (t + 1) * kb_per_int) : nkb;
+            if (inj) {
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int fkb = __builtin_amdgcn_readfirstlane(fault_kb(t, q));
+                    if (fkb >= kb && fkb + 1 < seg) seg = fkb + 1;
+                }
+            }
+            for (; kb < seg; ++kb) {
+                const int st = kb & 1;
+                if (kb + 1 < nkb) load_global(kb + 1);
+                mfma_block(st);
+                if (kb + 1 < nkb) {
+                    store_lds(st ^ 1);
+                    __syncthreads();
+                    if (ABFT) { encode(st ^ 1); __syncthreads(); }
+                }
+            }
+            if (!ABFT) continue;
+            // accumulators now hold the sum over steps [0, kb * BK)
+            if (inj) {
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    if (__builtin_amdgcn_readfirstlane(fault_kb(t, q)) == kb - 1)
+                        apply_fault(load_fault(t, q), t);
+            }
+            if (IVL && kb < nkb && kb % kb_per_int == 0) {
+                // a10: online verification of the accumulators at the interval end
+                if (verify(false, (int64_t)kb * BK, t)) {
+                    --redo_budget;
+                    inj_from = t + 1;  // replay intervals 0..t fault-free
+                    restart = true;
+                    break;
+                }
+                ++t;
+            }
+        }
+        if (restart) { __syncthreads(); continue; }
+        finalize_output();
+        if (!ABFT) break;
+        // a5-a7 on the output: flags in registers; a located element is repaired
+        // after the store, from global memory
+        __syncthreads();
+        reduce_and_flag(true, K);
+        const int nr = __builtin_amdgcn_readfirstlane(V.nfr);
+        const int nc = __builtin_amdgcn_readfirstlane(V.nfc);
+        if (nr == 0 && nc == 0) break;
+        if (nr == 1 && nc == 1) {
+            if (tid == 0) {
+                atomicAdd(&args.rep->cnt[kDetected], 1ull);
+                V.cin = args.beta != 0.0 ? args.C[(m0 + V.fi) + (n0 + V.fj) * ldc] : 0.0;
+            }
+            __syncthreads();
+            break;  // store, then repair
+        }
+        if (tid == 0) {
+            atomicAdd(&args.rep->cnt[kDetected], 1ull);
+            if (nr + nc == 1) {
+                atomicAdd(&args.rep->cnt[kChecksumOnly], 1ull);
+                push_record(args.rep, args.problem, tm, tn, t, nr ? m0 + V.fi : -1, nr ? -1 : n0 + V.fj,
+                            FTG_KIND_CHECKSUM_ONLY, nr ? V.dfi : V.dfj, nr ? V.tfi : V.tfj);
+            } else {
+                const bool redo = args.uncorrectable_policy == 1 && redo_budget > 0;
+                atomicAdd(&args.rep->cnt[kUncorrectable], 1ull);
+                if (redo) atomicAdd(&args.rep->cnt[kTilesRecomputed], 1ull);
+                push_record(args.rep, args.problem, tm, tn, t, -1, -1,
+                            redo ? FTG_KIND_TILE_RECOMPUTED : FTG_KIND_UNCORRECTABLE,
+                            nr ? V.dfi : V.dfj, nr ? V.tfi : V.tfj);
+            }
+        }
+        __syncthreads();
+        if (nr + nc == 1 || args.uncorrectable_policy != 1 || redo_budget <= 0) break;
+        --redo_budget;
+        inj_from = n_int;  // final slot uncorrectable: recompute without injection
+    }
+
+    // ---- a8: store the tile
+    {
+        const __amdgpu_buffer_rsrc_t rc = make_rsrc(args.C + m0 + n0 * ldc);
+#pragma unroll
+        for (int g = 0; g < FM; ++g)
+#pragma unroll
+            for (int h = 0; h < FN; ++h)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    buf_store_f64(acc[g][h][r], rc, c_vo(g, r, c_ok(g, h, r)), h * c_hstep);
+    }
+    if (!ABFT) return;
+    if (__builtin_amdgcn_readfirstlane(V.nfr) != 1 || __builtin_amdgcn_readfirstlane(V.nfc) != 1) return;
+    __threadfence();
+    __syncthreads();
+    if (wave == 0) {
+        RepairIn in;
+        in.A = A; in.B = B; in.C = args.C;
+        in.lda = lda; in.ldb = ldb; in.ldc = ldc; in.m0 = m0; in.n0 = n0; in.K = K;
+        in.R = R; in.Q = Q; in.fi = V.fi; in.fj = V.fj; in.correct_policy = args.correct_policy;
+        in.alpha = args.alpha; in.beta = args.beta; in.dfi = V.dfi; in.tfi = V.tfi; in.tfj = V.tfj;
+        double cr = 0.0, cc = 0.0;
+#pragma unroll
+        for (int w = 0; w < WGN; ++w) cr += V.cir[w][V.fi];
+#pragma unroll
+        for (int w = 0; w < WGM; ++w) cc += V.cic[w][V.fj];
+        const bool cin = args.beta != 0.0;
+        in.exp_row = args.alpha * V.er[V.fi] + (cin ? args.beta * cr : 0.0);
+        in.exp_col = args.alpha * V.ec[V.fj] + (cin ? args.beta * cc : 0.0);
+        in.cin = V.cin;
+        const int kind = repair_final<TA, TB>(in, lane);
+        if (lane == 0) {
+            if (kind == FTG_KIND_SUBTRACT) atomicAdd(&args.rep->cnt[kCorrSub], 1ull);
+            else if (kind == FTG_KIND_RECOMPUTE) atomicAdd(&args.rep->cnt[kCorrRecomp], 1ull);
+            else atomicAdd(&args.rep->cnt[kUncorrectable], 1ull);
+            const bool loc = kind != FTG_KIND_UNCORRECTABLE;
+            push_record(args.rep, args.problem, tm, tn, t, loc ? m0 + V.fi : -1, loc ? n0 + V.fj : -1,
+                        kind, V.dfi, V.tfi);
+        }
+    }
+
+}
+
+// ------------------------------------------------------------------ launcher
+template <int BM, int BN, int WGM, int WGN, bool IVL_OK>
+hipError_t launch_tile(const DGemmArgs& a, bool abft, hipStream_t s)
+{
+    const dim3 grid(a.tiles_m * a.tiles_n), block(WGM * WGN * 64);
+    const bool ivl = abft && a.kc < a.k;
+    if (ivl && !IVL_OK) return hipErrorInvalidValue;
+#define FTG_L(TA_, TB_, AB_, IV_) \
+    hipLaunchKernelGGL((dgemm_abft_kernel<BM, BN, WGM, WGN, TA_, TB_, AB_, IV_>), grid, block, 0, s, a)
+#define FTG_T(AB_, IV_)                                       \
+    do {                                                      \
+        if (!a.ta && !a.tb) FTG_L(false, false, AB_, IV_);    \
+        else if (a.ta && !a.tb) FTG_L(true, false, AB_, IV_); \
+        else if (!a.ta && a.tb) FTG_L(false, true, AB_, IV_); \
+        else FTG_L(true, true, AB_, IV_);                     \
+    } while (0)
+    if (!abft) FTG_T(false, false);
+    else if (!ivl) FTG_T(true, false);
+    else if constexpr (IVL_OK) FTG_T(true, true);
+#undef FTG_T
+#undef FTG_L
+    return hipGetLastError();
+}
+
+}  // namespace ftg

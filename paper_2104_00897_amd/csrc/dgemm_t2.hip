@@ -1,0 +1,6 @@
+// FP64 protected GEMM, tile configuration 2: 128 x 128 output tile, 2 x 2 waves.
+#include "dgemm_kernel.hpp"
+
+namespace ftg {
+template hipError_t launch_tile<128, 128, 2, 2, true>(const DGemmArgs&, bool, hipStream_t);
+}  // namespace ftg

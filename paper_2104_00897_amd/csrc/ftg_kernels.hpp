@@ -1,0 +1,55 @@
+// Launch interfaces of the protected GEMM kernels (host side of the kernels,
+// used by the C ABI in ftgemm_runtime.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ftg_common.hpp"
+
+namespace ftg {
+
+struct DGemmArgs {
+    const double* A;
+    const double* B;
+    double* C;
+    int lda, ldb, ldc;     // < 2^20 (buffer offsets are 32-bit)
+    int m, n, k;           // < 2^31
+    int kc;                // verification interval (>= k: one interval)
+    int tiles_m, tiles_n;
+    int ta, tb;
+    int correct_policy, uncorrectable_policy;
+    int problem;
+    double alpha, beta;
+    InjectParams inj;
+    DevReport* rep;
+};
+
+// FP64 tile configurations: 1 = 256x128, 2 = 128x128, 3 = 64x64 (k-block 16).
+// Verification intervals shorter than k need tile 2 or 3.
+template <int BM, int BN, int WGM, int WGN, bool IVL_OK>
+hipError_t launch_tile(const DGemmArgs& a, bool abft, hipStream_t s);
+
+inline hipError_t launch_dgemm(const DGemmArgs& a, int tile_id, bool abft, hipStream_t s)
+{
+    switch (tile_id) {
+    case 1: return launch_tile<256, 128, 2, 2, false>(a, abft, s);
+    case 2: return launch_tile<128, 128, 2, 2, true>(a, abft, s);
+    case 3: return launch_tile<64, 64, 2, 2, true>(a, abft, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+inline bool dgemm_tile_intervals(int id) { return id == 2 || id == 3; }
+hipError_t launch_dscale(double* C, int64_t m, int64_t n, int64_t ldc, double beta, hipStream_t s);
+
+inline void dgemm_tile_shape(int id, int* bm, int* bn, int* bk)
+{
+    *bk = 16;
+    switch (id) {
+    case 1: *bm = 256; *bn = 128; break;
+    case 2: *bm = 128; *bn = 128; break;
+    case 3: *bm = 64; *bn = 64; break;
+    default: *bm = *bn = *bk = 0;
+    }
+}
+
+}  // namespace ftg

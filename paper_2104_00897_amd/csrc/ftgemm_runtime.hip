@@ -1,0 +1,361 @@
+// Host runtime of the protected GEMM: the C ABI declared in include/ftgemm.h.
+//
+// A handle owns the device fault report (counters, record ring, injection
+// log), the batched descriptor table and the tuning table.  Entry points
+// check arguments with BLAS numbering, derive the injector parameters and
+// launch the kernels asynchronously on the caller's stream; nothing is
+// allocated per call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "../../include/ftgemm.h"
+#include "ftg_kernels.hpp"
+#include "ftg_lowp.hpp"
+#include "ftg_batched.hpp"
+
+namespace {
+
+using ftg::DevReport;
+
+constexpr int kTuneBuckets = 12;  // ceil(log2) of a dimension clamped to [4, 15]
+constexpr int kDtypes = 4;
+
+}  // namespace
+
+struct ftg_handle_s {
+    int device = 0;
+    DevReport* rep = nullptr;              // device
+    ftg_fault_record* d_records = nullptr;  // device
+    ftg_inject_record* d_inject = nullptr;  // device
+    size_t capacity = 0;
+    int last_info = 0;
+    // batched descriptor table
+    ftg::BatchDesc* d_batch = nullptr;
+    ftg::BatchDesc* h_batch = nullptr;      // pinned staging
+    int* d_queue = nullptr;                  // work counter(s)
+    int64_t batch_cap = 0;
+    int64_t* d_tile_prefix = nullptr;
+    int64_t* h_tile_prefix = nullptr;
+    // tuning table: configuration id per (dtype, bucket m, n, k); 0 = heuristic
+    int8_t tune[kDtypes][kTuneBuckets][kTuneBuckets][kTuneBuckets];
+};
+
+namespace {
+
+int bucket(int64_t x)
+{
+    int b = 0;
+    while ((int64_t(1) << b) < x && b < 62) ++b;
+    return std::min(15, std::max(4, b)) - 4;
+}
+
+int heuristic_tile_f64(int64_t m, int64_t n, int64_t k, bool need_intervals)
+{
+    // one workgroup per tile and 256 CUs: prefer the largest tile that still
+    // gives every CU work, fall back to smaller tiles for small problems
+    auto tiles = [&](int bm, int bn) { return ((m + bm - 1) / bm) * ((n + bn - 1) / bn); };
+    if (!need_intervals && tiles(256, 128) >= 256) return 1;
+    if (tiles(128, 128) >= 128) return 2;
+    (void)k;
+    return 3;
+}
+
+ftg_status set_err(ftg_handle h, int info)
+{
+    if (h) h->last_info = info;
+    return FTG_ERR_INVALID_ARG;
+}
+
+uint64_t gcd_u64(uint64_t a, uint64_t b)
+{
+    while (b) {
+        uint64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// modular inverse of a mod S (gcd(a, S) = 1), extended Euclid
+uint64_t inv_mod(uint64_t a, uint64_t S)
+{
+    if (S <= 1) return 0;
+    int64_t t = 0, nt = 1;
+    int64_t r = (int64_t)S, nr = (int64_t)(a % S);
+    while (nr != 0) {
+        int64_t q = r / nr;
+        int64_t tmp = t - q * nt;
+        t = nt;
+        nt = tmp;
+        tmp = r - q * nr;
+        r = nr;
+        nr = tmp;
+    }
+    if (t < 0) t += (int64_t)S;
+    return (uint64_t)t;
+}
+
+}  // namespace
+
+namespace ftg {
+
+// Injector parameters for one problem with the given slot count.
+// Returns false when the slot count does not fit the 32-bit slot arithmetic.
+bool make_inject(const ftg_inject* in, int64_t m, int64_t n, int64_t k, int64_t slots,
+                 int default_lo, int default_hi, InjectParams* ip, uint32_t faults_override,
+                 bool use_override)
+{
+    std::memset(ip, 0, sizeof(*ip));
+    if (!in) return true;
+    uint64_t F = in->n_faults;
+    if (use_override) F = faults_override;
+    else if (F == 0 && in->per_mac_rate > 0.0)
+        F = (uint64_t)std::ceil((double)m * (double)n * (double)k * in->per_mac_rate);
+    if (F == 0 || slots <= 0) return true;
+    if (slots >= (int64_t(1) << 32)) return false;
+    const uint64_t S = (uint64_t)slots;
+    uint64_t a = 1, b = 0;
+    if (S > 1) {
+        b = splitmix64(in->seed, 0) % S;
+        for (uint64_t t = 1; t <= 64; ++t) {
+            const uint64_t cand = 1 + splitmix64(in->seed, t) % (S - 1);
+            if (gcd_u64(cand, S) == 1) {
+                a = cand;
+                break;
+            }
+        }
+    }
+    ip->on = 1;
+    ip->target = (int)in->target;
+    ip->bit_lo = in->bit_lo;
+    ip->bit_hi = in->bit_hi;
+    if (ip->bit_lo == 0 && ip->bit_hi == 0) {
+        ip->bit_lo = default_lo;
+        ip->bit_hi = default_hi;
+    }
+    ip->seed = in->seed;
+    ip->S = (uint32_t)S;
+    ip->F = (uint32_t)std::min<uint64_t>(F, S);
+    ip->a_inv = (uint32_t)inv_mod(a, S);
+    ip->b = (uint32_t)b;
+    return true;
+}
+
+}  // namespace ftg
+
+extern "C" {
+
+const char* ftg_status_string(ftg_status s)
+{
+    switch (s) {
+    case FTG_OK: return "ok";
+    case FTG_ERR_INVALID_ARG: return "invalid argument";
+    case FTG_ERR_UNSUPPORTED: return "unsupported";
+    case FTG_ERR_HIP: return "HIP error";
+    case FTG_ERR_UNCORRECTED: return "uncorrected fault";
+    }
+    return "unknown status";
+}
+
+ftg_status ftg_create(ftg_handle* out, size_t report_capacity)
+{
+    if (!out) return FTG_ERR_INVALID_ARG;
+    *out = nullptr;
+    ftg_handle h = new (std::nothrow) ftg_handle_s();
+    if (!h) return FTG_ERR_HIP;
+    std::memset(h->tune, 0, sizeof(h->tune));
+    if (hipGetDevice(&h->device) != hipSuccess) { delete h; return FTG_ERR_HIP; }
+    h->capacity = report_capacity;
+    bool ok = hipMalloc(&h->rep, sizeof(DevReport)) == hipSuccess;
+    ok = ok && hipMalloc(&h->d_records, sizeof(ftg_fault_record) * std::max<size_t>(1, report_capacity)) == hipSuccess;
+    ok = ok && hipMalloc(&h->d_inject, sizeof(ftg_inject_record) * std::max<size_t>(1, report_capacity)) == hipSuccess;
+    if (ok) {
+        DevReport r;
+        std::memset(&r, 0, sizeof(r));
+        r.capacity = (unsigned)report_capacity;
+        r.records = h->d_records;
+        r.inject_log = h->d_inject;
+        ok = hipMemcpy(h->rep, &r, sizeof(r), hipMemcpyHostToDevice) == hipSuccess;
+    }
+    if (ok) ok = ftg_batched_reserve(h, 1024) == FTG_OK;
+    if (!ok) { ftg_destroy(h); return FTG_ERR_HIP; }
+    *out = h;
+    return FTG_OK;
+}
+
+ftg_status ftg_destroy(ftg_handle h)
+{
+    if (!h) return FTG_OK;
+    hipDeviceSynchronize();
+    if (h->rep) hipFree(h->rep);
+    if (h->d_records) hipFree(h->d_records);
+    if (h->d_inject) hipFree(h->d_inject);
+    if (h->d_batch) hipFree(h->d_batch);
+    if (h->d_queue) hipFree(h->d_queue);
+    if (h->d_tile_prefix) hipFree(h->d_tile_prefix);
+    if (h->h_batch) hipHostFree(h->h_batch);
+    if (h->h_tile_prefix) hipHostFree(h->h_tile_prefix);
+    delete h;
+    return FTG_OK;
+}
+
+int ftg_last_error_arg(ftg_handle h) { return h ? h->last_info : 0; }
+
+ftg_status ftg_tile_info(ftg_dtype ab_type, int32_t id, int32_t* bm, int32_t* bn, int32_t* bk)
+{
+    int a = 0, b = 0, c = 0;
+    if (ab_type == FTG_F64) ftg::dgemm_tile_shape(id, &a, &b, &c);
+    else if (ab_type == FTG_BF16 || ab_type == FTG_F8_E4M3) ftg::lowp_tile_shape(ab_type, id, &a, &b, &c);
+    if (a == 0) return FTG_ERR_INVALID_ARG;
+    if (bm) *bm = a;
+    if (bn) *bn = b;
+    if (bk) *bk = c;
+    return FTG_OK;
+}
+
+ftg_status ftg_tune_set(ftg_handle h, ftg_dtype t, int64_t m, int64_t n, int64_t k, int32_t id)
+{
+    if (!h || (int)t < 0 || (int)t >= kDtypes) return FTG_ERR_INVALID_ARG;
+    int32_t a, b, c;
+    if (id != 0 && ftg_tile_info(t, id, &a, &b, &c) != FTG_OK) return FTG_ERR_INVALID_ARG;
+    h->tune[t][bucket(m)][bucket(n)][bucket(k)] = (int8_t)id;
+    return FTG_OK;
+}
+
+int32_t ftg_tune_get(ftg_handle h, ftg_dtype t, int64_t m, int64_t n, int64_t k)
+{
+    if (!h || (int)t < 0 || (int)t >= kDtypes) return 0;
+    const int v = h->tune[t][bucket(m)][bucket(n)][bucket(k)];
+    if (v) return v;
+    if (t == FTG_F64) return heuristic_tile_f64(m, n, k, false);
+    return ftg::lowp_heuristic_tile(t, m, n, k);
+}
+
+// Shared argument checks (BLAS xerbla numbering of dgemm).
+static ftg_status check_gemm(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n, int64_t k,
+                             int64_t lda, int64_t ldb, int64_t ldc, const ftg_config* cfg)
+{
+    if (ta != FTG_OP_N && ta != FTG_OP_T) return set_err(h, 1);
+    if (tb != FTG_OP_N && tb != FTG_OP_T) return set_err(h, 2);
+    if (m < 0) return set_err(h, 3);
+    if (n < 0) return set_err(h, 4);
+    if (k < 0) return set_err(h, 5);
+    if (lda < std::max<int64_t>(1, ta == FTG_OP_N ? m : k)) return set_err(h, 8);
+    if (ldb < std::max<int64_t>(1, tb == FTG_OP_N ? k : n)) return set_err(h, 10);
+    if (ldc < std::max<int64_t>(1, m)) return set_err(h, 13);
+    if (cfg) {
+        if (cfg->interval_k < 0 || cfg->interval_k % ftg::kKGran != 0) return set_err(h, 20);
+        if (cfg->correct_policy < 0 || cfg->correct_policy > 1) return set_err(h, 20);
+        if (cfg->uncorrectable_policy < 0 || cfg->uncorrectable_policy > 1) return set_err(h, 20);
+        if (cfg->inject) {
+            const ftg_inject* in = cfg->inject;
+            if (in->target > FTG_TARGET_TWO_IN_SLOT) return set_err(h, 20);
+            if (in->bit_lo < 0 || in->bit_hi < in->bit_lo) return set_err(h, 20);
+            if (in->per_mac_rate < 0.0) return set_err(h, 20);
+        }
+    }
+    return FTG_OK;
+}
+
+ftg_status ftg_dgemm(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n, int64_t k,
+                     double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+                     double beta, double* C, int64_t ldc, void* stream, const ftg_config* cfg)
+{
+    if (!h) return FTG_ERR_INVALID_ARG;
+    ftg_status st = check_gemm(h, ta, tb, m, n, k, lda, ldb, ldc, cfg);
+    if (st != FTG_OK) return st;
+    if (cfg && cfg->inject && cfg->inject->bit_hi > 63) return set_err(h, 20);
+    hipStream_t s = (hipStream_t)stream;
+    if (m == 0 || n == 0 || ((alpha == 0.0 || k == 0) && beta == 1.0)) return FTG_OK;
+    if (alpha == 0.0 || k == 0)
+        return ftg::launch_dscale(C, m, n, ldc, beta, s) == hipSuccess ? FTG_OK : FTG_ERR_HIP;
+    // 32-bit buffer offsets: every in-tile byte offset stays below 2^31
+    if (m >= (int64_t(1) << 31) || n >= (int64_t(1) << 31) || k >= (int64_t(1) << 31) ||
+        lda >= (1 << 20) || ldb >= (1 << 20) || ldc >= (1 << 20))
+        return FTG_ERR_UNSUPPORTED;
+
+    const bool abft = !cfg || cfg->abft;
+    const int64_t kc = (cfg && cfg->interval_k > 0 && cfg->interval_k < k) ? cfg->interval_k : k;
+    const bool intervals = kc < k;
+    int tile = cfg && cfg->tile ? cfg->tile : 0;
+    if (!tile) {
+        tile = h->tune[FTG_F64][bucket(m)][bucket(n)][bucket(k)];
+        if (!tile || (intervals && !ftg::dgemm_tile_intervals(tile)))
+            tile = heuristic_tile_f64(m, n, k, intervals);
+    }
+    int bm, bn, bk;
+    ftg::dgemm_tile_shape(tile, &bm, &bn, &bk);
+    if (bm == 0) return set_err(h, 20);
+    if (abft && intervals && !ftg::dgemm_tile_intervals(tile)) return FTG_ERR_UNSUPPORTED;
+
+    ftg::DGemmArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.A = A; a.B = B; a.C = C;
+    a.lda = (int)lda; a.ldb = (int)ldb; a.ldc = (int)ldc;
+    a.m = (int)m; a.n = (int)n; a.k = (int)k;
+    a.kc = (int)kc;
+    a.tiles_m = (int)((m + bm - 1) / bm);
+    a.tiles_n = (int)((n + bn - 1) / bn);
+    a.ta = ta == FTG_OP_T; a.tb = tb == FTG_OP_T;
+    a.alpha = alpha; a.beta = beta;
+    a.correct_policy = cfg ? cfg->correct_policy : 0;
+    a.uncorrectable_policy = cfg ? cfg->uncorrectable_policy : 0;
+    a.problem = 0;
+    a.rep = h->rep;
+    const int64_t n_int = (k + kc - 1) / kc;
+    if (abft && cfg && cfg->inject) {
+        if (n_int > ftg::kMaxIntervals) return FTG_ERR_UNSUPPORTED;
+        const int64_t slots = (int64_t)a.tiles_m * a.tiles_n * n_int;
+        if (!ftg::make_inject(cfg->inject, m, n, k, slots, 40, 63, &a.inj, 0, false))
+            return FTG_ERR_UNSUPPORTED;
+    }
+    const hipError_t e = ftg::launch_dgemm(a, tile, abft, s);
+    return e == hipSuccess ? FTG_OK : FTG_ERR_HIP;
+}
+
+ftg_status ftg_report_read(ftg_handle h, void* stream, ftg_fault_report* out, int sync)
+{
+    if (!h || !out) return FTG_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    DevReport r;
+    if (hipMemcpyAsync(&r, h->rep, sizeof(r), hipMemcpyDeviceToHost, s) != hipSuccess) return FTG_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return FTG_ERR_HIP;
+    out->injected = r.cnt[ftg::kInjected];
+    out->detected = r.cnt[ftg::kDetected];
+    out->corrected_subtract = r.cnt[ftg::kCorrSub];
+    out->corrected_recompute = r.cnt[ftg::kCorrRecomp];
+    out->checksum_only = r.cnt[ftg::kChecksumOnly];
+    out->uncorrectable = r.cnt[ftg::kUncorrectable];
+    out->tiles_recomputed = r.cnt[ftg::kTilesRecomputed];
+    out->n_records = r.n_records;
+    out->n_inject_log = r.n_inject;
+    const size_t nr = std::min<size_t>({(size_t)r.n_records, (size_t)out->capacity, h->capacity});
+    const size_t ni = std::min<size_t>({(size_t)r.n_inject, (size_t)out->capacity, h->capacity});
+    if (out->records && nr)
+        if (hipMemcpyAsync(out->records, h->d_records, nr * sizeof(ftg_fault_record),
+                           hipMemcpyDeviceToHost, s) != hipSuccess)
+            return FTG_ERR_HIP;
+    if (out->inject_log && ni)
+        if (hipMemcpyAsync(out->inject_log, h->d_inject, ni * sizeof(ftg_inject_record),
+                           hipMemcpyDeviceToHost, s) != hipSuccess)
+            return FTG_ERR_HIP;
+    if (sync) {
+        if (hipStreamSynchronize(s) != hipSuccess) return FTG_ERR_HIP;
+        // uncorrectable slots left as they were (not recomputed)
+        if (out->uncorrectable > out->tiles_recomputed) return FTG_ERR_UNCORRECTED;
+    }
+    return FTG_OK;
+}
+
+ftg_status ftg_report_reset(ftg_handle h, void* stream)
+{
+    if (!h) return FTG_ERR_INVALID_ARG;
+    return ftg::launch_report_reset(h->rep, (hipStream_t)stream) == hipSuccess ? FTG_OK : FTG_ERR_HIP;
+}
+
+}  // extern "C"

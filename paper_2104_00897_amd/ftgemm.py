@@ -1,0 +1,251 @@
+"""ctypes binding of the protected-GEMM C ABI (include/ftgemm.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libftgemm.so.  torch provides device memory and the current
+stream.  Matrices are column-major; a column-major (rows x cols) matrix is
+held in a torch tensor of shape (cols, rows) (see ``to_device``/``to_host``).
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libftgemm.so")
+
+OP_N, OP_T = 0, 1
+F64, F32, BF16, F8_E4M3 = 0, 1, 2, 3
+OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_UNCORRECTED = 0, 1, 2, 3, 4
+KIND_SUBTRACT, KIND_RECOMPUTE, KIND_CHECKSUM_ONLY, KIND_UNCORRECTABLE, KIND_TILE_RECOMPUTED = 1, 2, 3, 4, 5
+TARGET_ACC, TARGET_CHECKSUM, TARGET_TWO_IN_SLOT = 0, 1, 2
+KGRAN = 128  # injection / interval granularity in k
+
+
+class FtgError(RuntimeError):
+    def __init__(self, status: int, what: str, info: int = 0):
+        self.status = status
+        self.info = info
+        super().__init__(f"{what}: status {status}" + (f" (argument {info})" if info else ""))
+
+
+class Inject(ct.Structure):
+    _fields_ = [("seed", ct.c_uint64), ("n_faults", ct.c_uint32), ("target", ct.c_uint32),
+                ("per_mac_rate", ct.c_double), ("bit_lo", ct.c_int32), ("bit_hi", ct.c_int32)]
+
+
+class Config(ct.Structure):
+    _fields_ = [("abft", ct.c_int32), ("interval_k", ct.c_int32), ("lam", ct.c_double),
+                ("correct_policy", ct.c_int32), ("uncorrectable_policy", ct.c_int32),
+                ("tile", ct.c_int32), ("reserved", ct.c_int32), ("inject", ct.POINTER(Inject))]
+
+
+class FaultRecord(ct.Structure):
+    _fields_ = [("problem", ct.c_int32), ("tile_m", ct.c_int32), ("tile_n", ct.c_int32),
+                ("interval", ct.c_int32), ("row", ct.c_int64), ("col", ct.c_int64),
+                ("kind", ct.c_int32), ("reserved", ct.c_int32), ("delta", ct.c_double),
+                ("tau", ct.c_double)]
+
+
+class InjectRecord(ct.Structure):
+    _fields_ = [("problem", ct.c_int32), ("tile_m", ct.c_int32), ("tile_n", ct.c_int32),
+                ("interval", ct.c_int32), ("row", ct.c_int64), ("col", ct.c_int64),
+                ("pflip", ct.c_int64), ("bit", ct.c_int32), ("target", ct.c_int32),
+                ("old_val", ct.c_double), ("new_val", ct.c_double)]
+
+
+class FaultReport(ct.Structure):
+    _fields_ = [("injected", ct.c_uint64), ("detected", ct.c_uint64),
+                ("corrected_subtract", ct.c_uint64), ("corrected_recompute", ct.c_uint64),
+                ("checksum_only", ct.c_uint64), ("uncorrectable", ct.c_uint64),
+                ("tiles_recomputed", ct.c_uint64), ("n_records", ct.c_uint32),
+                ("n_inject_log", ct.c_uint32), ("capacity", ct.c_uint32), ("reserved", ct.c_uint32),
+                ("records", ct.POINTER(FaultRecord)), ("inject_log", ct.POINTER(InjectRecord))]
+
+
+EXPORTS = [
+    "ftg_create", "ftg_destroy", "ftg_dgemm", "ftg_gemm_ex", "ftg_dgemm_batched_uneven",
+    "ftg_batched_reserve", "ftg_report_read", "ftg_report_reset", "ftg_last_error_arg",
+    "ftg_tile_info", "ftg_tune_set", "ftg_tune_get", "ftg_status_string",
+]
+
+_lib = None
+
+
+def load() -> ct.CDLL:
+    """Loads libftgemm.so (built by __graft_entry__.build / build.py); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FtgError(ERR_HIP, f"HIP library missing: {LIB_PATH} (run the build first)")
+    lib = ct.CDLL(LIB_PATH)
+    i64, vp, i32 = ct.c_int64, ct.c_void_p, ct.c_int32
+    h = ct.c_void_p
+    lib.ftg_create.argtypes = [ct.POINTER(h), ct.c_size_t]
+    lib.ftg_destroy.argtypes = [h]
+    lib.ftg_dgemm.argtypes = [h, i32, i32, i64, i64, i64, ct.c_double, vp, i64, vp, i64,
+                              ct.c_double, vp, i64, vp, ct.POINTER(Config)]
+    lib.ftg_gemm_ex.argtypes = [h, i32, i32, i64, i64, i64, i32, i32, vp, vp, ct.c_float, vp, i64,
+                                vp, i64, ct.c_float, vp, i64, vp, ct.POINTER(Config)]
+    lib.ftg_dgemm_batched_uneven.argtypes = [h, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                             vp, vp, vp, vp, ct.POINTER(Config)]
+    lib.ftg_batched_reserve.argtypes = [h, i64]
+    lib.ftg_report_read.argtypes = [h, vp, ct.POINTER(FaultReport), ct.c_int]
+    lib.ftg_report_reset.argtypes = [h, vp]
+    lib.ftg_last_error_arg.argtypes = [h]
+    lib.ftg_tile_info.argtypes = [i32, i32, ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(i32)]
+    lib.ftg_tune_set.argtypes = [h, i32, i64, i64, i64, i32]
+    lib.ftg_tune_get.argtypes = [h, i32, i64, i64, i64]
+    lib.ftg_status_string.argtypes = [i32]
+    lib.ftg_status_string.restype = ct.c_char_p
+    for name in EXPORTS:
+        if name != "ftg_status_string":
+            getattr(lib, name).restype = ct.c_int
+    _lib = lib
+    return lib
+
+
+def tile_info(dtype: int, tile_id: int):
+    a, b, c = ct.c_int32(), ct.c_int32(), ct.c_int32()
+    st = load().ftg_tile_info(dtype, tile_id, ct.byref(a), ct.byref(b), ct.byref(c))
+    return None if st != OK else (a.value, b.value, c.value)
+
+
+@dataclass
+class Report:
+    injected: int = 0
+    detected: int = 0
+    corrected_subtract: int = 0
+    corrected_recompute: int = 0
+    checksum_only: int = 0
+    uncorrectable: int = 0
+    tiles_recomputed: int = 0
+    status: int = OK
+    records: list = field(default_factory=list)
+    inject_log: list = field(default_factory=list)
+
+
+def make_config(abft=True, interval_k=0, lam=0.0, correct_policy=0, uncorrectable_policy=0,
+                tile=0, seed=None, n_faults=0, per_mac_rate=0.0, bit_lo=0, bit_hi=0,
+                target=TARGET_ACC):
+    cfg = Config(int(abft), interval_k, lam, correct_policy, uncorrectable_policy, tile, 0, None)
+    inj = None
+    if seed is not None and (n_faults > 0 or per_mac_rate > 0.0):
+        inj = Inject(seed & (2**64 - 1), n_faults, target, per_mac_rate, bit_lo, bit_hi)
+        cfg.inject = ct.pointer(inj)
+    cfg._keep = inj  # keep the injector alive with the config
+    return cfg
+
+
+class Handle:
+    """Owns an ftg handle (device report, batched table, tuning table)."""
+
+    def __init__(self, capacity: int = 4096):
+        self.lib = load()
+        self.h = ct.c_void_p()
+        self.capacity = capacity
+        st = self.lib.ftg_create(ct.byref(self.h), capacity)
+        if st != OK:
+            raise FtgError(st, "ftg_create")
+
+    def close(self):
+        if self.h:
+            self.lib.ftg_destroy(self.h)
+            self.h = ct.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, what):
+        if st != OK:
+            raise FtgError(st, what, self.lib.ftg_last_error_arg(self.h))
+
+    def dgemm(self, ta, tb, m, n, k, alpha, A_ptr, lda, B_ptr, ldb, beta, C_ptr, ldc,
+              stream=None, cfg=None):
+        st = self.lib.ftg_dgemm(self.h, ta, tb, m, n, k, alpha, A_ptr, lda, B_ptr, ldb, beta,
+                                C_ptr, ldc, stream, ct.byref(cfg) if cfg is not None else None)
+        self._check(st, "ftg_dgemm")
+
+    def gemm_ex(self, ta, tb, m, n, k, ab_type, c_type, scale_a, scale_b, alpha, A_ptr, lda,
+                B_ptr, ldb, beta, C_ptr, ldc, stream=None, cfg=None):
+        st = self.lib.ftg_gemm_ex(self.h, ta, tb, m, n, k, ab_type, c_type, scale_a, scale_b,
+                                  alpha, A_ptr, lda, B_ptr, ldb, beta, C_ptr, ldc, stream,
+                                  ct.byref(cfg) if cfg is not None else None)
+        self._check(st, "ftg_gemm_ex")
+
+    def reset(self, stream=None):
+        self._check(self.lib.ftg_report_reset(self.h, stream), "ftg_report_reset")
+
+    def read(self, stream=None) -> Report:
+        recs = (FaultRecord * self.capacity)()
+        logs = (InjectRecord * self.capacity)()
+        out = FaultReport()
+        out.capacity = self.capacity
+        out.records = ct.cast(recs, ct.POINTER(FaultRecord))
+        out.inject_log = ct.cast(logs, ct.POINTER(InjectRecord))
+        st = self.lib.ftg_report_read(self.h, stream, ct.byref(out), 1)
+        if st not in (OK, ERR_UNCORRECTED):
+            raise FtgError(st, "ftg_report_read")
+        rep = Report(out.injected, out.detected, out.corrected_subtract, out.corrected_recompute,
+                     out.checksum_only, out.uncorrectable, out.tiles_recomputed, st)
+        fields = [f for f, _ in FaultRecord._fields_ if f != "reserved"]
+        rep.records = [{f: getattr(r, f) for f in fields}
+                       for r in recs[:min(out.n_records, self.capacity)]]
+        lf = [f for f, _ in InjectRecord._fields_]
+        rep.inject_log = [{f: getattr(r, f) for f in lf}
+                          for r in logs[:min(out.n_inject_log, self.capacity)]]
+        return rep
+
+    def tune_set(self, dtype, m, n, k, tile_id):
+        self._check(self.lib.ftg_tune_set(self.h, dtype, m, n, k, tile_id), "ftg_tune_set")
+
+    def tune_get(self, dtype, m, n, k) -> int:
+        return self.lib.ftg_tune_get(self.h, dtype, m, n, k)
+
+
+# ---------------------------------------------------------------- torch helpers
+def _torch():
+    import torch
+    return torch
+
+
+def current_stream_ptr():
+    torch = _torch()
+    return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def to_device(a: np.ndarray, dtype=None, device="cuda"):
+    """Column-major numpy (rows x cols) -> contiguous torch tensor (cols x rows) on the GPU."""
+    torch = _torch()
+    t = torch.from_numpy(np.ascontiguousarray(np.asarray(a).T))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to(device)
+
+
+def to_host(t) -> np.ndarray:
+    """Inverse of to_device: returns a Fortran-ordered (rows x cols) numpy array."""
+    return np.asfortranarray(t.detach().cpu().numpy().T)
+
+
+def ptr(t) -> ct.c_void_p:
+    return ct.c_void_p(t.data_ptr())
+
+
+def gemm_f64(handle: Handle, A, B, C, alpha=1.0, beta=0.0, ta=OP_N, tb=OP_N, cfg=None, m=None,
+             n=None, k=None):
+    """C := alpha op(A) op(B) + beta C on column-major float64 device tensors (see to_device)."""
+    rows_a, cols_a = A.shape[1], A.shape[0]
+    rows_b, cols_b = B.shape[1], B.shape[0]
+    m = m if m is not None else (cols_a if ta else rows_a)
+    k = k if k is not None else (rows_a if ta else cols_a)
+    n = n if n is not None else (rows_b if tb else cols_b)
+    handle.dgemm(ta, tb, m, n, k, alpha, ptr(A), max(1, rows_a), ptr(B), max(1, rows_b), beta,
+                 ptr(C), max(1, C.shape[1]), current_stream_ptr(), cfg)
+    return C
