@@ -30,6 +30,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 #include "ftg_common.hpp"
 #include "ftg_kernels.hpp"
 
@@ -180,29 +182,30 @@ __global__ __launch_bounds__(WGM* WGN * 64) void dgemm_abft_kernel(DGemmArgs arg
     // the buffer instruction: no per-load scalar registers).  Elements outside
     // the matrix read 0 through an out-of-range offset.
     //   contiguous along the tile dimension (A with TA=0, B with TB=1):
-    //     16 lanes per k step, element q at tile index lane%16 + 16q;
+    //     LPT = NT/BK lanes per k step, element q at tile index lane%LPT + LPT*q;
     //   contiguous along k (A with TA=1, B with TB=0):
     //     NT/ROWS threads per tile line, each reading BK*ROWS/NT consecutive steps.
-    static_assert(NT % BM == 0 && NT % BN == 0 && NT == 16 * BK, "staging map");
-    constexpr int APT = TA ? BK * BM / NT : BM / 16;   // elements per thread
-    constexpr int BPT = TB ? BN / 16 : BK * BN / NT;
+    constexpr int LPT = NT / BK;
+    static_assert(NT % BM == 0 && NT % BN == 0 && NT % BK == 0, "staging map");
+    constexpr int APT = TA ? BK * BM / NT : BM / LPT;   // elements per thread
+    constexpr int BPT = TB ? BN / LPT : BK * BN / NT;
     static_assert(APT == Cf::NA && BPT == Cf::NB, "staging count");
-    // A: TA=0 -> (i = tid%16 + 16q, p = tid/16); TA=1 -> (i = tid%BM, p = (tid/BM)*APT + q)
-    const int ai0 = TA ? tid % BM : tid % 16;
-    const int ap0 = TA ? (tid / BM) * APT : tid / 16;
-    // B: TB=1 -> (j = tid%16 + 16q, p = tid/16); TB=0 -> (j = tid%BN, p = (tid/BN)*BPT + q)
-    const int bj0 = TB ? tid % 16 : tid % BN;
-    const int bp0 = TB ? tid / 16 : (tid / BN) * BPT;
+    // A: TA=0 -> (i = tid%LPT + LPT q, p = tid/LPT); TA=1 -> (i = tid%BM, p = (tid/BM)*APT + q)
+    const int ai0 = TA ? tid % BM : tid % LPT;
+    const int ap0 = TA ? (tid / BM) * APT : tid / LPT;
+    // B: TB=1 -> (j = tid%LPT + LPT q, p = tid/LPT); TB=0 -> (j = tid%BN, p = (tid/BN)*BPT + q)
+    const int bj0 = TB ? tid % LPT : tid % BN;
+    const int bp0 = TB ? tid / LPT : (tid / BN) * BPT;
     auto a_ip = [&](int q, int* i, int* p) __attribute__((always_inline)) {
-        if (TA) { *i = ai0; *p = ap0 + q; } else { *i = ai0 + 16 * q; *p = ap0; }
+        if (TA) { *i = ai0; *p = ap0 + q; } else { *i = ai0 + LPT * q; *p = ap0; }
     };
     auto b_jp = [&](int q, int* j, int* p) __attribute__((always_inline)) {
-        if (TB) { *j = bj0 + 16 * q; *p = bp0; } else { *j = bj0; *p = bp0 + q; }
+        if (TB) { *j = bj0 + LPT * q; *p = bp0; } else { *j = bj0; *p = bp0 + q; }
     };
     const int64_t lda = args.lda, ldb = args.ldb;
     const int a_voff = (int)((TA ? (ap0 + (int64_t)ai0 * lda) : (ai0 + (int64_t)ap0 * lda)) * 8);
     const int b_voff = (int)((TB ? (bj0 + (int64_t)bp0 * ldb) : (bp0 + (int64_t)bj0 * ldb)) * 8);
-    constexpr int a_qstep = TA ? 8 : 128, b_qstep = TB ? 128 : 8;  // bytes per q
+    constexpr int a_qstep = TA ? 8 : 8 * LPT, b_qstep = TB ? 8 * LPT : 8;  // bytes per q
     const bool full_mn = (R == BM) && (Q == BN);
 
     auto load_global = [&](int kb) __attribute__((always_inline)) {
@@ -275,7 +278,9 @@ __global__ __launch_bounds__(WGM* WGN * 64) void dgemm_abft_kernel(DGemmArgs arg
     // ---- a2 + a3: one k-block of MFMA with the checksum updates.  Fragments of
     // the next rank-4 step are read from LDS while the current step's MFMAs run;
     // the scheduling fence keeps the compiler from hoisting further reads.
-    auto mfma_block = [&](int st) __attribute__((always_inline)) {
+    // WRc, WCc: this wave's position, as compile-time constants so that its
+    // share of the checksum updates is fixed at compile time (no selects).
+    auto mfma_block = [&]<int WRc, int WCc>(int st) __attribute__((always_inline)) {
         constexpr int NS = BK / 4;
         double a[2][FM], b[2][FN], sm[2][4];
         auto load_frag = [&](int s_, int buf) __attribute__((always_inline)) {
@@ -305,13 +310,13 @@ __global__ __launch_bounds__(WGM* WGN * 64) void dgemm_abft_kernel(DGemmArgs arg
                 // wave-row (wave-column) have in common
 #pragma unroll
                 for (int g = 0; g < FM; ++g)
-                    if (g % WGN == wc) {
+                    if (g % WGN == WCc) {
                         er[g / WGN] = fma(a[cur][g], bs_, er[g / WGN]);
                         mr[g / WGN] = fma(fabs(a[cur][g]), bsa, mr[g / WGN]);
                     }
 #pragma unroll
                 for (int h = 0; h < FN; ++h)
-                    if (h % WGM == wr) {
+                    if (h % WGM == WRc) {
                         ec[h / WGM] = fma(as_, b[cur][h], ec[h / WGM]);
                         mc[h / WGM] = fma(asa, fabs(b[cur][h]), mc[h / WGM]);
                     }
@@ -705,16 +710,22 @@ __global__ __launch_bounds__(WGM* WGN * 64) void dgemm_abft_kernel(DGemmArgs arg
                     if (fkb >= kb && fkb + 1 < seg) seg = fkb + 1;
                 }
             }
-            for (; kb < seg; ++kb) {
-                const int st = kb & 1;
-                if (kb + 1 < nkb) load_global(kb + 1);
-                mfma_block(st);
-                if (kb + 1 < nkb) {
-                    store_lds(st ^ 1);
-                    __syncthreads();
-                    if (ABFT) { encode(st ^ 1); __syncthreads(); }
+            // the hot loop, instantiated per wave position (uniform dispatch)
+            auto hot = [&]<int W>() __attribute__((always_inline)) {
+                for (; kb < seg; ++kb) {
+                    const int st = kb & 1;
+                    if (kb + 1 < nkb) load_global(kb + 1);
+                    mfma_block.template operator()<W / WGN, W % WGN>(st);
+                    if (kb + 1 < nkb) {
+                        store_lds(st ^ 1);
+                        __syncthreads();
+                        if (ABFT) { encode(st ^ 1); __syncthreads(); }
+                    }
                 }
-            }
+            };
+            [&]<int... W>(std::integer_sequence<int, W...>) __attribute__((always_inline)) {
+                ((wave == W ? (hot.template operator()<W>(), 0) : 0), ...);
+            }(std::make_integer_sequence<int, WGM * WGN>{});
             if (!ABFT) continue;
             // accumulators now hold the sum over steps [0, kb * BK)
             if (inj) {
