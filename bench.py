@@ -37,6 +37,7 @@ def parse():
     p.add_argument("--n", type=int, default=8192)
     p.add_argument("--tile", type=int, default=0)
     p.add_argument("--sweep", action="store_true", help="also time the FP64 size sweep and rank-k shapes")
+    p.add_argument("--tiles", action="store_true", help="time every FP64 tile configuration at --n")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     return p.parse_args()
 
@@ -155,6 +156,10 @@ def main():
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64_MFMA, 4),
                      "traffic": None},
     }
+    if args.tiles:
+        for t in (1, 2, 3, 4):
+            r, _ = measure(torch, ftgemm, h, n, n, n, 1.5, 0.5, 0, 0, max(3, args.steps // 2), 1, t)
+            print(json.dumps({"tile_sweep": r}), file=sys.stderr, flush=True)
     if args.sweep:
         sweep = []
         for nn in (1024, 2048, 4096, 8192, 16384):

@@ -72,63 +72,9 @@ struct VerifyLds {
     int nfr, nfc, fi, fj, xfinite, kind;
 };
 
-// Final-slot repair of one located element of a tile whose output is already
-// stored in C (rare path; one wave; global memory only).  Subtracts the error
-// magnitude (§6.3) and re-verifies the element's row and column against their
-// expected checksums; if that fails, recomputes the element from a fresh dot
-// product and re-verifies; if that fails too, restores the value.
-struct RepairIn {
-    const double* A;
-    const double* B;
-    double* C;
-    int64_t lda, ldb, ldc, m0, n0, K;
-    int R, Q, fi, fj, correct_policy;
-    double alpha, beta, dfi, tfi, tfj, exp_row, exp_col, cin;
-};
-
-template <bool TA, bool TB>
-__device__ __attribute__((noinline)) int repair_final(RepairIn in, int lane)
-{
-    const __amdgpu_buffer_rsrc_t rc = make_rsrc(in.C + in.m0 + in.n0 * in.ldc);
-    const int xo = (int)((in.fi + (int64_t)in.fj * in.ldc) * 8);
-    auto ld = [&](int voff) {  // glc: bypass the CU cache, other waves just stored the tile
-        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rc, voff, 0, 1));
-    };
-    auto lines_ok = [&]() {
-        double r = 0.0, c = 0.0;
-        for (int j = lane; j < in.Q; j += 64) r += ld((int)((in.fi + (int64_t)j * in.ldc) * 8));
-        for (int i = lane; i < in.R; i += 64) c += ld((int)((i + (int64_t)in.fj * in.ldc) * 8));
-        r = group_sum<64>(r);
-        c = group_sum<64>(c);
-        return !flagged(r - in.exp_row, in.tfi) && !flagged(c - in.exp_col, in.tfj);
-    };
-    auto put = [&](double v) {
-        if (lane == 0) buf_store_f64(v, rc, xo, 0);
-        __threadfence();
-    };
-    const double x = ld(xo);
-    if (in.correct_policy == 0 && isfinite(in.dfi) && isfinite(x)) {
-        put(x - in.dfi);
-        if (lines_ok()) return FTG_KIND_SUBTRACT;
-    }
-    double s = 0.0;
-    const int64_t gi = in.m0 + in.fi, gj = in.n0 + in.fj;
-    for (int64_t p = lane; p < in.K; p += 64) {
-        const double a = TA ? in.A[p + gi * in.lda] : in.A[gi + p * in.lda];
-        const double b = TB ? in.B[gj + p * in.ldb] : in.B[p + gj * in.ldb];
-        s = fma(a, b, s);
-    }
-    s = group_sum<64>(s);
-    double v = in.alpha * s;
-    if (in.beta != 0.0) v += in.beta * in.cin;
-    put(v);
-    if (lines_ok()) return FTG_KIND_RECOMPUTE;
-    put(x);
-    return FTG_KIND_UNCORRECTABLE;
-}
-
-template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool ABFT, bool IVL>
-__global__ __launch_bounds__(WGM* WGN * 64) void dgemm_abft_kernel(DGemmArgs args)
+// MINB: workgroups per CU the register allocation must allow (occupancy target).
+template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool ABFT, bool IVL, int MINB>
+__global__ __launch_bounds__(WGM* WGN * 64, MINB) void dgemm_abft_kernel(DGemmArgs args)
 {
     using Cf = DCfg<BM, BN, WGM, WGN, TA, TB>;
     constexpr int BK = Cf::BK, NT = Cf::NT, FM = Cf::FM, FN = Cf::FN;
@@ -248,39 +194,63 @@ __global__ __launch_bounds__(WGM* WGN * 64) void dgemm_abft_kernel(DGemmArgs arg
         }
     };
     // ---- a1: checksum row/column of the encoded operands for the staged k-block
-    auto encode = [&](int st) __attribute__((always_inline)) {
+    // Each wave owns PPW steps p of the block; LPP lanes per step sum the A
+    // column and B row of that step, then reduce across the LPP lanes.  The
+    // work is split in four slices so that the protected k loop can spread it
+    // over the four rank-4 MFMA steps of the previous block (its LDS and
+    // shuffle latency then hides under MFMA execution).
+    struct EncAcc { double sa, saa, sb, sba; };
+    auto encode_slice = [&](int st, int slice, EncAcc& e) __attribute__((always_inline)) {
         const int p = wave * Cf::PPW + lane / Cf::LPP;
         const int sub = lane % Cf::LPP;
-        double sa = 0.0, saa = 0.0, sb = 0.0, sba = 0.0;
+        constexpr int UA = BM / Cf::LPP, UB = BN / Cf::LPP;
+        if (slice == 0) {
+            e.sa = e.saa = e.sb = e.sba = 0.0;
 #pragma unroll
-        for (int u = 0; u < BM / Cf::LPP; ++u) {
-            double v = As[st][Cf::a_idx(sub + u * Cf::LPP, p)];
-            sa += v;
-            saa += fabs(v);
-        }
+            for (int u = 0; u < UA / 2; ++u) {
+                const double v = As[st][Cf::a_idx(sub + u * Cf::LPP, p)];
+                e.sa += v;
+                e.saa += fabs(v);
+            }
+        } else if (slice == 1) {
 #pragma unroll
-        for (int u = 0; u < BN / Cf::LPP; ++u) {
-            double v = Bs[st][Cf::b_idx(p, sub + u * Cf::LPP)];
-            sb += v;
-            sba += fabs(v);
+            for (int u = UA / 2; u < UA; ++u) {
+                const double v = As[st][Cf::a_idx(sub + u * Cf::LPP, p)];
+                e.sa += v;
+                e.saa += fabs(v);
+            }
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
+                const double v = Bs[st][Cf::b_idx(p, sub + u * Cf::LPP)];
+                e.sb += v;
+                e.sba += fabs(v);
+            }
+        } else if (slice == 2) {
+            e.sa = group_sum<Cf::LPP>(e.sa);
+            e.saa = group_sum<Cf::LPP>(e.saa);
+        } else {
+            e.sb = group_sum<Cf::LPP>(e.sb);
+            e.sba = group_sum<Cf::LPP>(e.sba);
+            if (sub == 0) {
+                sums[st][p][0] = e.sa;
+                sums[st][p][1] = e.saa;
+                sums[st][p][2] = e.sb;
+                sums[st][p][3] = e.sba;
+            }
         }
-        sa = group_sum<Cf::LPP>(sa);
-        saa = group_sum<Cf::LPP>(saa);
-        sb = group_sum<Cf::LPP>(sb);
-        sba = group_sum<Cf::LPP>(sba);
-        if (sub == 0) {
-            sums[st][p][0] = sa;
-            sums[st][p][1] = saa;
-            sums[st][p][2] = sb;
-            sums[st][p][3] = sba;
-        }
+    };
+    auto encode = [&](int st) __attribute__((always_inline)) {
+        EncAcc e;
+#pragma unroll
+        for (int sl = 0; sl < 4; ++sl) encode_slice(st, sl, e);
     };
     // ---- a2 + a3: one k-block of MFMA with the checksum updates.  Fragments of
     // the next rank-4 step are read from LDS while the current step's MFMAs run;
     // the scheduling fence keeps the compiler from hoisting further reads.
     // WRc, WCc: this wave's position, as compile-time constants so that its
     // share of the checksum updates is fixed at compile time (no selects).
-    auto mfma_block = [&]<int WRc, int WCc>(int st) __attribute__((always_inline)) {
+    auto mfma_block = [&]<int WRc, int WCc, bool ENC>(int st) __attribute__((always_inline)) {
+        EncAcc enc;
         constexpr int NS = BK / 4;
         double a[2][FM], b[2][FN], sm[2][4];
         auto load_frag = [&](int s_, int buf) __attribute__((always_inline)) {
@@ -321,6 +291,7 @@ __global__ __launch_bounds__(WGM* WGN * 64) void dgemm_abft_kernel(DGemmArgs arg
                         mc[h / WGM] = fma(asa, fabs(b[cur][h]), mc[h / WGM]);
                     }
             }
+            if (ENC) encode_slice(st ^ 1, s_, enc);
             __builtin_amdgcn_sched_barrier(0);
         }
     };
@@ -697,7 +668,11 @@ __global__ __launch_bounds__(WGM* WGN * 64) void dgemm_abft_kernel(DGemmArgs arg
         load_global(0);
         store_lds(0);
         __syncthreads();
-        if (ABFT) { encode(0); __syncthreads(); }
+        if (ABFT) {
+            encode(0);
+            if (nkb > 1) load_global(1);
+            __syncthreads();
+        }
         bool restart = false;
         int kb = 0;
         while (kb < nkb) {
@@ -714,12 +689,22 @@ __global__ __launch_bounds__(WGM* WGN * 64) void dgemm_abft_kernel(DGemmArgs arg
             auto hot = [&]<int W>() __attribute__((always_inline)) {
                 for (; kb < seg; ++kb) {
                     const int st = kb & 1;
-                    if (kb + 1 < nkb) load_global(kb + 1);
-                    mfma_block.template operator()<W / WGN, W % WGN>(st);
-                    if (kb + 1 < nkb) {
+                    if (!ABFT) {
+                        if (kb + 1 < nkb) load_global(kb + 1);
+                        mfma_block.template operator()<W / WGN, W % WGN, false>(st);
+                        if (kb + 1 < nkb) {
+                            store_lds(st ^ 1);
+                            __syncthreads();
+                        }
+                    } else if (kb + 1 < nkb) {
+                        // block kb+1: staged now, encoded while block kb's MFMAs run
                         store_lds(st ^ 1);
                         __syncthreads();
-                        if (ABFT) { encode(st ^ 1); __syncthreads(); }
+                        if (kb + 2 < nkb) load_global(kb + 2);
+                        mfma_block.template operator()<W / WGN, W % WGN, true>(st);
+                        __syncthreads();
+                    } else {
+                        mfma_block.template operator()<W / WGN, W % WGN, false>(st);
                     }
                 }
             };
@@ -755,33 +740,46 @@ __global__ __launch_bounds__(WGM* WGN * 64) void dgemm_abft_kernel(DGemmArgs arg
         const int nr = __builtin_amdgcn_readfirstlane(V.nfr);
         const int nc = __builtin_amdgcn_readfirstlane(V.nfc);
         if (nr == 0 && nc == 0) break;
-        if (nr == 1 && nc == 1) {
+        const bool many = nr > 1 || nc > 1;
+        if (many && args.uncorrectable_policy == 1 && redo_budget > 0) {
+            // more than one error in the final slot: recompute the tile, no injection
             if (tid == 0) {
                 atomicAdd(&args.rep->cnt[kDetected], 1ull);
-                V.cin = args.beta != 0.0 ? args.C[(m0 + V.fi) + (n0 + V.fj) * ldc] : 0.0;
-            }
-            __syncthreads();
-            break;  // store, then repair
-        }
-        if (tid == 0) {
-            atomicAdd(&args.rep->cnt[kDetected], 1ull);
-            if (nr + nc == 1) {
-                atomicAdd(&args.rep->cnt[kChecksumOnly], 1ull);
-                push_record(args.rep, args.problem, tm, tn, t, nr ? m0 + V.fi : -1, nr ? -1 : n0 + V.fj,
-                            FTG_KIND_CHECKSUM_ONLY, nr ? V.dfi : V.dfj, nr ? V.tfi : V.tfj);
-            } else {
-                const bool redo = args.uncorrectable_policy == 1 && redo_budget > 0;
                 atomicAdd(&args.rep->cnt[kUncorrectable], 1ull);
-                if (redo) atomicAdd(&args.rep->cnt[kTilesRecomputed], 1ull);
-                push_record(args.rep, args.problem, tm, tn, t, -1, -1,
-                            redo ? FTG_KIND_TILE_RECOMPUTED : FTG_KIND_UNCORRECTABLE,
+                atomicAdd(&args.rep->cnt[kTilesRecomputed], 1ull);
+                push_record(args.rep, args.problem, tm, tn, t, -1, -1, FTG_KIND_TILE_RECOMPUTED,
                             nr ? V.dfi : V.dfj, nr ? V.tfi : V.tfj);
             }
+            __syncthreads();
+            --redo_budget;
+            inj_from = n_int;
+            continue;
         }
-        __syncthreads();
-        if (nr + nc == 1 || args.uncorrectable_policy != 1 || redo_budget <= 0) break;
-        --redo_budget;
-        inj_from = n_int;  // final slot uncorrectable: recompute without injection
+        // hand the slot to the repair kernel (it runs after this kernel on the
+        // same stream and works on the stored tile in global memory)
+        if (tid == 0) {
+            RepairReq q;
+            q.problem = args.problem; q.tm = tm; q.tn = tn; q.interval = t;
+            q.nr = nr; q.nc = nc; q.fi = V.fi; q.fj = V.fj; q.R = R; q.Q = Q;
+            q.pad0 = q.pad1 = 0; q.m0 = m0; q.n0 = n0;
+            q.dfi = V.dfi; q.tfi = V.tfi; q.dfj = V.dfj; q.tfj = V.tfj;
+            const bool cin = args.beta != 0.0;
+            double cr = 0.0, cc = 0.0;
+            q.exp_row = q.exp_col = 0.0;
+            if (nr) {
+#pragma unroll
+                for (int w = 0; w < WGN; ++w) cr += V.cir[w][V.fi];
+                q.exp_row = args.alpha * V.er[V.fi] + (cin ? args.beta * cr : 0.0);
+            }
+            if (nc) {
+#pragma unroll
+                for (int w = 0; w < WGM; ++w) cc += V.cic[w][V.fj];
+                q.exp_col = args.alpha * V.ec[V.fj] + (cin ? args.beta * cc : 0.0);
+            }
+            q.cin = (cin && nr == 1 && nc == 1) ? args.C[(m0 + V.fi) + (n0 + V.fj) * ldc] : 0.0;
+            push_repair(args.rep, q);
+        }
+        break;
     }
 
     // ---- a8: store the tile
@@ -795,47 +793,17 @@ __global__ __launch_bounds__(WGM* WGN * 64) void dgemm_abft_kernel(DGemmArgs arg
                 for (int r = 0; r < 4; ++r)
                     buf_store_f64(acc[g][h][r], rc, c_vo(g, r, c_ok(g, h, r)), h * c_hstep);
     }
-    if (!ABFT) return;
-    if (__builtin_amdgcn_readfirstlane(V.nfr) != 1 || __builtin_amdgcn_readfirstlane(V.nfc) != 1) return;
-    __threadfence();
-    __syncthreads();
-    if (wave == 0) {
-        RepairIn in;
-        in.A = A; in.B = B; in.C = args.C;
-        in.lda = lda; in.ldb = ldb; in.ldc = ldc; in.m0 = m0; in.n0 = n0; in.K = K;
-        in.R = R; in.Q = Q; in.fi = V.fi; in.fj = V.fj; in.correct_policy = args.correct_policy;
-        in.alpha = args.alpha; in.beta = args.beta; in.dfi = V.dfi; in.tfi = V.tfi; in.tfj = V.tfj;
-        double cr = 0.0, cc = 0.0;
-#pragma unroll
-        for (int w = 0; w < WGN; ++w) cr += V.cir[w][V.fi];
-#pragma unroll
-        for (int w = 0; w < WGM; ++w) cc += V.cic[w][V.fj];
-        const bool cin = args.beta != 0.0;
-        in.exp_row = args.alpha * V.er[V.fi] + (cin ? args.beta * cr : 0.0);
-        in.exp_col = args.alpha * V.ec[V.fj] + (cin ? args.beta * cc : 0.0);
-        in.cin = V.cin;
-        const int kind = repair_final<TA, TB>(in, lane);
-        if (lane == 0) {
-            if (kind == FTG_KIND_SUBTRACT) atomicAdd(&args.rep->cnt[kCorrSub], 1ull);
-            else if (kind == FTG_KIND_RECOMPUTE) atomicAdd(&args.rep->cnt[kCorrRecomp], 1ull);
-            else atomicAdd(&args.rep->cnt[kUncorrectable], 1ull);
-            const bool loc = kind != FTG_KIND_UNCORRECTABLE;
-            push_record(args.rep, args.problem, tm, tn, t, loc ? m0 + V.fi : -1, loc ? n0 + V.fj : -1,
-                        kind, V.dfi, V.tfi);
-        }
-    }
-
 }
 
 // ------------------------------------------------------------------ launcher
-template <int BM, int BN, int WGM, int WGN, bool IVL_OK>
+template <int BM, int BN, int WGM, int WGN, bool IVL_OK, int MINB>
 hipError_t launch_tile(const DGemmArgs& a, bool abft, hipStream_t s)
 {
     const dim3 grid(a.tiles_m * a.tiles_n), block(WGM * WGN * 64);
     const bool ivl = abft && a.kc < a.k;
     if (ivl && !IVL_OK) return hipErrorInvalidValue;
 #define FTG_L(TA_, TB_, AB_, IV_) \
-    hipLaunchKernelGGL((dgemm_abft_kernel<BM, BN, WGM, WGN, TA_, TB_, AB_, IV_>), grid, block, 0, s, a)
+    hipLaunchKernelGGL((dgemm_abft_kernel<BM, BN, WGM, WGN, TA_, TB_, AB_, IV_, MINB>), grid, block, 0, s, a)
 #define FTG_T(AB_, IV_)                                       \
     do {                                                      \
         if (!a.ta && !a.tb) FTG_L(false, false, AB_, IV_);    \

@@ -2,5 +2,5 @@
 #include "dgemm_kernel.hpp"
 
 namespace ftg {
-template hipError_t launch_tile<256, 128, 2, 2, false>(const DGemmArgs&, bool, hipStream_t);
+template hipError_t launch_tile<256, 128, 2, 2, false, 1>(const DGemmArgs&, bool, hipStream_t);
 }  // namespace ftg

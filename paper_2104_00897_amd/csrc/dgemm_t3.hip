@@ -2,5 +2,5 @@
 #include "dgemm_kernel.hpp"
 
 namespace ftg {
-template hipError_t launch_tile<64, 64, 2, 2, true>(const DGemmArgs&, bool, hipStream_t);
+template hipError_t launch_tile<64, 64, 2, 2, true, 2>(const DGemmArgs&, bool, hipStream_t);
 }  // namespace ftg

@@ -1,0 +1,6 @@
+// FP64 protected GEMM, tile configuration 4: 256 x 128 output tile, 4 x 2 waves.
+#include "dgemm_kernel.hpp"
+
+namespace ftg {
+template hipError_t launch_tile<256, 128, 4, 2, false, 1>(const DGemmArgs&, bool, hipStream_t);
+}  // namespace ftg

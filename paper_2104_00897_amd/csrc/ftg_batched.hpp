@@ -22,6 +22,21 @@ struct BatchDesc {
     InjectParams inj;
 };
 
+// What the repair kernel needs to know about one problem.
+struct RepairProblem {
+    const void* A;
+    const void* B;
+    void* C;
+    int64_t lda, ldb, ldc, k;
+    int ta, tb, correct_policy, ab_type, c_type, pad;
+    double alpha, beta;
+    double scale;  // product scale of the operands (s_A s_B for FP8, else 1)
+};
+
+constexpr int kRepairBlocks = 8;
+
 hipError_t launch_report_reset(DevReport* rep, hipStream_t s);
+hipError_t launch_repair(DevReport* rep, const RepairProblem& single, const RepairProblem* table,
+                         hipStream_t s);
 
 }  // namespace ftg

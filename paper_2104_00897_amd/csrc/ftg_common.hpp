@@ -15,14 +15,40 @@ constexpr int kKGran = 128;
 // Most verification intervals per tile with injection on (LDS fault table).
 constexpr int kMaxIntervals = 128;
 
+// A flagged final-slot check handed from a GEMM kernel to the repair kernel.
+// Row/column indices are tile-local; expected checksums already include the
+// alpha/beta scaling; cin is C_in at the located element (0 when beta = 0).
+struct RepairReq {
+    int problem, tm, tn, interval;
+    int nr, nc, fi, fj;  // flagged row/column counts, first flagged row/column
+    int R, Q, pad0, pad1;
+    int64_t m0, n0;
+    double dfi, tfi, dfj, tfj, exp_row, exp_col, cin;
+};
+
 // Fault report kept on the device by the handle.  Counters are updated with
-// device atomics; records are appended at atomically reserved indices.
+// device atomics; records are appended at atomically reserved indices.  The
+// repair queue collects flagged tiles until the repair kernel drains it.
 struct DevReport {
     unsigned long long cnt[8];  // see Cnt
     unsigned int n_records, n_inject, capacity, pad;
     ftg_fault_record* records;
     ftg_inject_record* inject_log;
+    unsigned int rq_count, rq_done, rq_capacity, rq_lost;
+    RepairReq* rq;
 };
+
+// Appends a repair request (one thread); returns false when the queue is full.
+__device__ inline bool push_repair(DevReport* rep, const RepairReq& r)
+{
+    const unsigned int idx = atomicAdd(&rep->rq_count, 1u);
+    if (idx < rep->rq_capacity) {
+        rep->rq[idx] = r;
+        return true;
+    }
+    atomicAdd(&rep->rq_lost, 1u);
+    return false;
+}
 
 enum Cnt {
     kInjected = 0,

@@ -24,17 +24,19 @@ struct DGemmArgs {
     DevReport* rep;
 };
 
-// FP64 tile configurations: 1 = 256x128, 2 = 128x128, 3 = 64x64 (k-block 16).
+// FP64 tile configurations (k-block 16): 1 = 256x128 on 4 waves, 2 = 128x128,
+// 3 = 64x64, 4 = 256x128 on 8 waves.
 // Verification intervals shorter than k need tile 2 or 3.
-template <int BM, int BN, int WGM, int WGN, bool IVL_OK>
+template <int BM, int BN, int WGM, int WGN, bool IVL_OK, int MINB>
 hipError_t launch_tile(const DGemmArgs& a, bool abft, hipStream_t s);
 
 inline hipError_t launch_dgemm(const DGemmArgs& a, int tile_id, bool abft, hipStream_t s)
 {
     switch (tile_id) {
-    case 1: return launch_tile<256, 128, 2, 2, false>(a, abft, s);
-    case 2: return launch_tile<128, 128, 2, 2, true>(a, abft, s);
-    case 3: return launch_tile<64, 64, 2, 2, true>(a, abft, s);
+    case 1: return launch_tile<256, 128, 2, 2, false, 1>(a, abft, s);
+    case 2: return launch_tile<128, 128, 2, 2, true, 2>(a, abft, s);
+    case 3: return launch_tile<64, 64, 2, 2, true, 2>(a, abft, s);
+    case 4: return launch_tile<256, 128, 4, 2, false, 1>(a, abft, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -48,6 +50,7 @@ inline void dgemm_tile_shape(int id, int* bm, int* bn, int* bk)
     case 1: *bm = 256; *bn = 128; break;
     case 2: *bm = 128; *bn = 128; break;
     case 3: *bm = 64; *bn = 64; break;
+    case 4: *bm = 256; *bn = 128; break;
     default: *bm = *bn = *bk = 0;
     }
 }

@@ -32,6 +32,7 @@ struct ftg_handle_s {
     DevReport* rep = nullptr;              // device
     ftg_fault_record* d_records = nullptr;  // device
     ftg_inject_record* d_inject = nullptr;  // device
+    ftg::RepairReq* d_repair = nullptr;     // device repair queue
     size_t capacity = 0;
     int last_info = 0;
     // batched descriptor table
@@ -174,12 +175,15 @@ ftg_status ftg_create(ftg_handle* out, size_t report_capacity)
     bool ok = hipMalloc(&h->rep, sizeof(DevReport)) == hipSuccess;
     ok = ok && hipMalloc(&h->d_records, sizeof(ftg_fault_record) * std::max<size_t>(1, report_capacity)) == hipSuccess;
     ok = ok && hipMalloc(&h->d_inject, sizeof(ftg_inject_record) * std::max<size_t>(1, report_capacity)) == hipSuccess;
+    ok = ok && hipMalloc(&h->d_repair, sizeof(ftg::RepairReq) * std::max<size_t>(1, report_capacity)) == hipSuccess;
     if (ok) {
         DevReport r;
         std::memset(&r, 0, sizeof(r));
         r.capacity = (unsigned)report_capacity;
         r.records = h->d_records;
         r.inject_log = h->d_inject;
+        r.rq_capacity = (unsigned)report_capacity;
+        r.rq = h->d_repair;
         ok = hipMemcpy(h->rep, &r, sizeof(r), hipMemcpyHostToDevice) == hipSuccess;
     }
     if (ok) ok = ftg_batched_reserve(h, 1024) == FTG_OK;
@@ -195,6 +199,7 @@ ftg_status ftg_destroy(ftg_handle h)
     if (h->rep) hipFree(h->rep);
     if (h->d_records) hipFree(h->d_records);
     if (h->d_inject) hipFree(h->d_inject);
+    if (h->d_repair) hipFree(h->d_repair);
     if (h->d_batch) hipFree(h->d_batch);
     if (h->d_queue) hipFree(h->d_queue);
     if (h->d_tile_prefix) hipFree(h->d_tile_prefix);
@@ -314,7 +319,17 @@ ftg_status ftg_dgemm(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n, i
         if (!ftg::make_inject(cfg->inject, m, n, k, slots, 40, 63, &a.inj, 0, false))
             return FTG_ERR_UNSUPPORTED;
     }
-    const hipError_t e = ftg::launch_dgemm(a, tile, abft, s);
+    hipError_t e = ftg::launch_dgemm(a, tile, abft, s);
+    if (e == hipSuccess && abft) {
+        ftg::RepairProblem rp;
+        std::memset(&rp, 0, sizeof(rp));
+        rp.A = A; rp.B = B; rp.C = C;
+        rp.lda = lda; rp.ldb = ldb; rp.ldc = ldc; rp.k = k;
+        rp.ta = a.ta; rp.tb = a.tb; rp.correct_policy = a.correct_policy;
+        rp.ab_type = FTG_F64; rp.c_type = FTG_F64;
+        rp.alpha = alpha; rp.beta = beta; rp.scale = 1.0;
+        e = ftg::launch_repair(h->rep, rp, nullptr, s);
+    }
     return e == hipSuccess ? FTG_OK : FTG_ERR_HIP;
 }
 

@@ -1,23 +1,142 @@
-// Device fault report maintenance.
+// Device fault report maintenance and the repair kernel.
+//
+// A protected GEMM kernel only computes flags for a tile's final check; a
+// flagged tile is stored as computed and queued.  The repair kernel, launched
+// after it on the same stream, classifies each queued slot and corrects a
+// located element in global memory: subtract the error magnitude (FT-BLAS
+// §6.3) and re-verify the element's row and column against their expected
+// checksums; failing that, recompute the element from a fresh dot product and
+// re-verify; failing that too, restore it and report the slot uncorrectable.
 #include <hip/hip_runtime.h>
 
 #include "ftg_batched.hpp"
 
 namespace ftg {
 
-// Clears counters and append indices (a kernel, not a memset, so that the
-// reset can sit inside a captured graph).
 __global__ void report_reset_kernel(DevReport* rep)
 {
     const int t = threadIdx.x;
     if (t < 8) rep->cnt[t] = 0ull;
     if (t == 8) rep->n_records = 0u;
     if (t == 9) rep->n_inject = 0u;
+    if (t == 10) rep->rq_lost = 0u;
 }
 
 hipError_t launch_report_reset(DevReport* rep, hipStream_t s)
 {
     hipLaunchKernelGGL(report_reset_kernel, dim3(1), dim3(64), 0, s, rep);
+    return hipGetLastError();
+}
+
+// operand element of op(A)(i, p) / op(B)(p, j) as binary64 (exact for bf16/fp8)
+__device__ inline double opnd(const RepairProblem& P, bool isA, int64_t r, int64_t c)
+{
+    const void* base = isA ? P.A : P.B;
+    const int t = isA ? P.ta : P.tb;
+    const int64_t ld = isA ? P.lda : P.ldb;
+    const int64_t idx = t ? (c + r * ld) : (r + c * ld);  // op = T swaps the roles
+    if (P.ab_type == FTG_F64) return ((const double*)base)[idx];
+    if (P.ab_type == FTG_BF16) {
+        const unsigned short b = ((const unsigned short*)base)[idx];
+        return (double)__uint_as_float((unsigned int)b << 16);
+    }
+    // FP8 e4m3fn code
+    const unsigned char q = ((const unsigned char*)base)[idx];
+    const int s = q >> 7, e = (q >> 3) & 0xF, f = q & 7;
+    double v = (e == 0) ? ldexp((double)f / 8.0, -6) : ldexp(1.0 + (double)f / 8.0, e - 7);
+    if (e == 0xF && f == 7) v = __longlong_as_double(0x7FF8000000000000ll);
+    return s ? -v : v;
+}
+
+__device__ inline double c_get(const RepairProblem& P, int64_t i, int64_t j)
+{
+    // volatile: other workgroups of the producing kernel wrote C; bypass stale caches
+    if (P.c_type == FTG_F64) return ((volatile const double*)P.C)[i + j * P.ldc];
+    return (double)((volatile const float*)P.C)[i + j * P.ldc];
+}
+
+__device__ inline void c_set(const RepairProblem& P, int64_t i, int64_t j, double v)
+{
+    if (P.c_type == FTG_F64) ((volatile double*)P.C)[i + j * P.ldc] = v;
+    else ((volatile float*)P.C)[i + j * P.ldc] = (float)v;
+    __threadfence();
+}
+
+__global__ __launch_bounds__(256) void repair_kernel(DevReport* rep, RepairProblem single,
+                                                     const RepairProblem* table)
+{
+    const int lane = threadIdx.x & 63;
+    const int gwave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    const unsigned int n = min(rep->rq_count, rep->rq_capacity);
+    for (unsigned int r = gwave; r < n; r += nwaves) {
+        const RepairReq q = rep->rq[r];
+        const RepairProblem P = table ? table[q.problem] : single;
+        int kind;
+        int64_t row = -1, col = -1;
+        double d = q.nr ? q.dfi : q.dfj, tau = q.nr ? q.tfi : q.tfj;
+        if (q.nr == 1 && q.nc == 1) {
+            const int64_t gi = q.m0 + q.fi, gj = q.n0 + q.fj;
+            auto lines_ok = [&]() {
+                double rs = 0.0, cs = 0.0;
+                for (int j = lane; j < q.Q; j += 64) rs += c_get(P, gi, q.n0 + j);
+                for (int i = lane; i < q.R; i += 64) cs += c_get(P, q.m0 + i, gj);
+                rs = group_sum<64>(rs);
+                cs = group_sum<64>(cs);
+                return !flagged(rs - q.exp_row, q.tfi) && !flagged(cs - q.exp_col, q.tfj);
+            };
+            const double x = c_get(P, gi, gj);
+            kind = 0;
+            if (P.correct_policy == 0 && isfinite(q.dfi) && isfinite(x)) {
+                if (lane == 0) c_set(P, gi, gj, x - q.dfi);
+                __threadfence();
+                if (lines_ok()) kind = FTG_KIND_SUBTRACT;
+            }
+            if (!kind) {
+                double s = 0.0;
+                for (int64_t p = lane; p < P.k; p += 64) s = fma(opnd(P, true, gi, p), opnd(P, false, p, gj), s);
+                s = group_sum<64>(s);
+                double v = P.alpha * s * P.scale;
+                if (P.beta != 0.0) v += P.beta * q.cin;
+                if (lane == 0) c_set(P, gi, gj, v);
+                __threadfence();
+                kind = lines_ok() ? FTG_KIND_RECOMPUTE : FTG_KIND_UNCORRECTABLE;
+                if (kind == FTG_KIND_UNCORRECTABLE && lane == 0) c_set(P, gi, gj, x);
+            }
+            if (kind != FTG_KIND_UNCORRECTABLE) { row = gi; col = gj; }
+            d = q.dfi;
+            tau = q.tfi;
+        } else if (q.nr + q.nc == 1) {
+            kind = FTG_KIND_CHECKSUM_ONLY;
+            if (q.nr) row = q.m0 + q.fi; else col = q.n0 + q.fj;
+        } else {
+            kind = FTG_KIND_UNCORRECTABLE;
+        }
+        if (lane == 0) {
+            atomicAdd(&rep->cnt[kDetected], 1ull);
+            if (kind == FTG_KIND_SUBTRACT) atomicAdd(&rep->cnt[kCorrSub], 1ull);
+            else if (kind == FTG_KIND_RECOMPUTE) atomicAdd(&rep->cnt[kCorrRecomp], 1ull);
+            else if (kind == FTG_KIND_CHECKSUM_ONLY) atomicAdd(&rep->cnt[kChecksumOnly], 1ull);
+            else atomicAdd(&rep->cnt[kUncorrectable], 1ull);
+            push_record(rep, q.problem, q.tm, q.tn, q.interval, row, col, kind, d, tau);
+        }
+    }
+    // the last workgroup to finish empties the queue for the next call
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&rep->rq_done, 1u) == gridDim.x - 1) {
+            rep->rq_count = 0u;
+            rep->rq_done = 0u;
+            __threadfence();
+        }
+    }
+}
+
+hipError_t launch_repair(DevReport* rep, const RepairProblem& single, const RepairProblem* table,
+                         hipStream_t s)
+{
+    hipLaunchKernelGGL(repair_kernel, dim3(kRepairBlocks), dim3(256), 0, s, rep, single, table);
     return hipGetLastError();
 }
 

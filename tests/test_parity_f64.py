@@ -16,7 +16,7 @@ from tests.gpu_util import assert_close_f64, magnitude
 
 pytestmark = pytest.mark.gpu
 
-TILES = {1: (256, 128), 2: (128, 128), 3: (64, 64)}
+TILES = {1: (256, 128), 2: (128, 128), 3: (64, 64), 4: (256, 128)}
 
 
 @pytest.fixture(scope="module")
@@ -47,7 +47,7 @@ def run(env, A, B, C, alpha, beta, ta, tb, cfg=None, m=None, n=None, k=None):
 
 
 # ----------------------------------------------------------------------------- fault-free
-@pytest.mark.parametrize("tile", [1, 2, 3])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4])
 @pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
 def test_fault_free_ragged(env, tile, ta, tb):
     ftgemm = env[0]
@@ -61,7 +61,7 @@ def test_fault_free_ragged(env, tile, ta, tb):
         assert rep.detected == 0 and rep.records == [], rep.records[:3]
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4])
 def test_unprotected_same_result(env, tile):
     ftgemm = env[0]
     m, n, k = 260, 130, 300
@@ -71,7 +71,7 @@ def test_unprotected_same_result(env, tile):
     assert_close_f64(out, ref, magnitude(A, B, C, 1.5, 0.5, 0, 0), k)
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4])
 def test_integer_exact_bitwise(env, tile):
     ftgemm = env[0]
     m, n, k = 200, 140, 160
@@ -163,7 +163,7 @@ def test_cfg1_256_four_faults(env):
         assert ocnt["corrected_subtract"] + ocnt["corrected_recompute"] == 4
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4])
 @pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0)])
 def test_faults_every_tile_exponent_bits(env, tile, ta, tb):
     """Exponent/sign flips are always far above the threshold: 100% corrected."""
