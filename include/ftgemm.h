@@ -180,18 +180,30 @@ ftg_status ftg_gemm_ex(ftg_handle h, ftg_op transa, ftg_op transb, int64_t m, in
                        const void* B, int64_t ldb, float beta, void* C, int64_t ldc,
                        void* stream, const ftg_config* cfg);
 
-/* `count` independent FP64 protected GEMMs of arbitrary shapes in ONE
- * persistent launch: workgroups take (problem, tile) work items from a
- * device queue.  All arrays are HOST arrays of length count (pointer
- * arrays hold DEVICE pointers); they are copied into the handle's device
- * descriptor table with an asynchronous copy on `stream` (so the call can
- * be captured in a hipGraph when the host arrays are pinned and kept
- * alive until the graph's replays finish).  Each problem's tile shape comes
- * from the tuning table for its (m, n, k).  Injection slots are numbered
- * per problem; cfg->inject->n_faults is the count PER PROBLEM (use
- * faults_per_problem for a varying count).  count is limited by the
- * capacity given to ftg_batched_reserve (default 1024).  Fault records
- * carry the problem index. */
+/* `count` independent FP64 protected GEMMs of arbitrary shapes (the
+ * paper's DGEMM of §5.2 applied to each), run as persistent launches:
+ * workgroups take (problem, tile) work items from a device counter, largest
+ * k first.  Problems are grouped by tile configuration and transposes, one
+ * launch per group present.  A problem's tile configuration is cfg->tile
+ * (2 or 3; 1 and 4 give FTG_ERR_UNSUPPORTED), else an explicit tuning-table
+ * entry of 2 or 3 for its (m, n, k), else 3 (64 x 64).
+ * All arrays are HOST arrays of length count (the pointer arrays hold
+ * DEVICE pointers); they are read during the call and may be reused at
+ * once.  The call packs them into a pinned staging area of the handle and
+ * copies that to the device with one asynchronous copy on `stream`; it
+ * waits on the host only for the copy made two batched calls earlier.
+ * Under stream capture the copy reads a staging area kept for captures, so
+ * a captured graph replays the call as it was captured (one captured
+ * batched call per handle).
+ * BLAS argument checks and quick returns apply per problem; the first
+ * invalid problem sets ftg_last_error_arg to the dgemm argument position;
+ * count < 0 gives position 2; a NULL array gives 20.
+ * Injection slots are numbered per problem as in ftg_inject; problem p
+ * draws with seed SplitMix64(seed, 2^32 + p) (output of the generator for
+ * that counter) and F_p = faults_per_problem[p] faults when that array is
+ * given, else cfg->inject->n_faults (or the per-MAC rate) per problem.
+ * count is limited by ftg_batched_reserve (1024 after ftg_create).  Fault
+ * records and injection-log entries carry the problem index. */
 ftg_status ftg_dgemm_batched_uneven(ftg_handle h, int64_t count, const ftg_op* transa,
                                     const ftg_op* transb, const int64_t* m, const int64_t* n,
                                     const int64_t* k, const double* alpha,
@@ -201,14 +213,15 @@ ftg_status ftg_dgemm_batched_uneven(ftg_handle h, int64_t count, const ftg_op* t
                                     const uint32_t* faults_per_problem, void* stream,
                                     const ftg_config* cfg);
 
-/* Grows the batched descriptor table to `capacity` problems (allocates;
- * not to be called during graph capture). */
+/* Grows the batched descriptor table to `capacity` problems (at most
+ * 2^24).  Allocates and waits for the device: not during stream capture. */
 ftg_status ftg_batched_reserve(ftg_handle h, int64_t capacity);
 
-/* Copies the device report into *out (counters always; up to out->capacity
- * records and injection-log entries into out->records / out->inject_log
- * when those are non-NULL) with asynchronous copies on `stream`; with
- * sync = 1 it then waits for the stream.  Returns FTG_ERR_UNCORRECTED when
+/* Copies the device report into *out: the counters (after waiting for
+ * `stream`, so every call queued on it before is included), then up to
+ * out->capacity records and injection-log entries into out->records /
+ * out->inject_log when those are non-NULL, with asynchronous copies on
+ * `stream`; with sync = 1 it waits for those copies too.  Returns FTG_ERR_UNCORRECTED when
  * sync = 1 and some slot stayed uncorrectable (kind 4). */
 ftg_status ftg_report_read(ftg_handle h, void* stream, ftg_fault_report* out, int sync);
 

@@ -30,6 +30,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <utility>
 
 #include "ftg_common.hpp"
@@ -72,9 +73,11 @@ struct VerifyLds {
     int nfr, nfc, fi, fj, xfinite, kind;
 };
 
-// MINB: workgroups per CU the register allocation must allow (occupancy target).
-template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool ABFT, bool IVL, int MINB>
-__global__ __launch_bounds__(WGM* WGN * 64, MINB) void dgemm_abft_kernel(DGemmArgs args)
+// The work of one workgroup on output tile (tm, tn) of one problem.  Shared by
+// the one-launch-per-problem kernel and the persistent batched kernel.
+template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool ABFT, bool IVL>
+__device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs& args, const int tm,
+                                                                 const int tn)
 {
     using Cf = DCfg<BM, BN, WGM, WGN, TA, TB>;
     constexpr int BK = Cf::BK, NT = Cf::NT, FM = Cf::FM, FN = Cf::FN;
@@ -94,8 +97,6 @@ __global__ __launch_bounds__(WGM* WGN * 64, MINB) void dgemm_abft_kernel(DGemmAr
     const int wm0 = wr * WM, wn0 = wc * WN;
     const int l16 = lane & 15, lq = lane >> 4;
 
-    int tm, tn;
-    tile_of_block(blockIdx.x, gridDim.x, args.tiles_m, args.tiles_n, 4, &tm, &tn);
     const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
     const int R = (int)min((int64_t)BM, (int64_t)args.m - m0);
     const int Q = (int)min((int64_t)BN, (int64_t)args.n - n0);
@@ -779,6 +780,9 @@ __global__ __launch_bounds__(WGM* WGN * 64, MINB) void dgemm_abft_kernel(DGemmAr
             q.cin = (cin && nr == 1 && nc == 1) ? args.C[(m0 + V.fi) + (n0 + V.fj) * ldc] : 0.0;
             push_repair(args.rep, q);
         }
+        // C_in at the located element is read above before any wave stores
+        // its part of the tile over it
+        __syncthreads();
         break;
     }
 
@@ -795,7 +799,59 @@ __global__ __launch_bounds__(WGM* WGN * 64, MINB) void dgemm_abft_kernel(DGemmAr
     }
 }
 
-// ------------------------------------------------------------------ launcher
+// One problem, one workgroup per output tile.
+// MINB: workgroups per CU the register allocation must allow (occupancy target).
+template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool ABFT, bool IVL, int MINB>
+__global__ __launch_bounds__(WGM* WGN * 64, MINB) void dgemm_abft_kernel(DGemmArgs args)
+{
+    int tm, tn;
+    tile_of_block(blockIdx.x, gridDim.x, args.tiles_m, args.tiles_n, 4, &tm, &tn);
+    dgemm_tile<BM, BN, WGM, WGN, TA, TB, ABFT, IVL>(args, tm, tn);
+}
+
+// Many problems in one persistent launch.  Work item w is tile
+// w - first[p] (column-major over the problem's tile grid) of the problem p
+// with first[p] <= w < first[p + 1]; the host orders the problems so that
+// the most expensive tiles (largest k) are taken first.  Every workgroup
+// starts with item blockIdx.x and then takes the next free item from a
+// device counter until none is left; the last workgroup to finish resets the
+// counter for the next launch.
+template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool ABFT, bool IVL, int MINB>
+__global__ __launch_bounds__(WGM* WGN * 64, MINB) void dgemm_batched_kernel(BatchLaunch L)
+{
+    __shared__ int s_item;
+    int item = blockIdx.x;
+    for (;;) {
+        if (item >= L.total) break;
+        // problem of this item: binary search of the first-tile table
+        int lo = 0, hi = L.count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (L.first[mid] <= item) lo = mid; else hi = mid - 1;
+        }
+        const int p = __builtin_amdgcn_readfirstlane(lo);
+        const DGemmArgs a = L.desc[p];
+        const int local = item - L.first[p];
+        const int tm = __builtin_amdgcn_readfirstlane(local % a.tiles_m);
+        const int tn = __builtin_amdgcn_readfirstlane(local / a.tiles_m);
+        dgemm_tile<BM, BN, WGM, WGN, TA, TB, ABFT, IVL>(a, tm, tn);
+        // all LDS use of this tile ends before the next item is published
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = (int)gridDim.x + (int)atomicAdd(&L.queue[0], 1u);
+        __syncthreads();
+        item = __builtin_amdgcn_readfirstlane(s_item);
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&L.queue[1], 1u) == gridDim.x - 1) {
+            atomicExch(&L.queue[0], 0u);
+            atomicExch(&L.queue[1], 0u);
+            __threadfence();
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launchers
 template <int BM, int BN, int WGM, int WGN, bool IVL_OK, int MINB>
 hipError_t launch_tile(const DGemmArgs& a, bool abft, hipStream_t s)
 {
@@ -810,6 +866,51 @@ hipError_t launch_tile(const DGemmArgs& a, bool abft, hipStream_t s)
         else if (a.ta && !a.tb) FTG_L(true, false, AB_, IV_); \
         else if (!a.ta && a.tb) FTG_L(false, true, AB_, IV_); \
         else FTG_L(true, true, AB_, IV_);                     \
+    } while (0)
+    if (!abft) FTG_T(false, false);
+    else if (!ivl) FTG_T(true, false);
+    else if constexpr (IVL_OK) FTG_T(true, true);
+#undef FTG_T
+#undef FTG_L
+    return hipGetLastError();
+}
+
+// Persistent grid: as many workgroups as are resident on the device at once
+// (from the kernel's register and LDS use), never more than there are work
+// items.  Queried once per kernel instantiation.
+template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool AB, bool IV, int MINB>
+int batched_grid(int total)
+{
+    static int resident = 0;
+    if (resident == 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, dgemm_batched_kernel<BM, BN, WGM, WGN, TA, TB, AB, IV, MINB>, WGM * WGN * 64, 0) !=
+                hipSuccess)
+            return std::min(total, 256);
+        resident = std::max(1, cus) * std::max(1, per_cu);
+    }
+    return std::min(total, resident);
+}
+
+template <int BM, int BN, int WGM, int WGN, bool IVL_OK, int MINB>
+hipError_t launch_batched(const BatchLaunch& L, int ta, int tb, bool abft, bool ivl, hipStream_t s)
+{
+    if (L.total <= 0) return hipSuccess;
+    if (ivl && !IVL_OK) return hipErrorInvalidValue;
+    const dim3 block(WGM * WGN * 64);
+#define FTG_L(TA_, TB_, AB_, IV_)                                                                         \
+    hipLaunchKernelGGL((dgemm_batched_kernel<BM, BN, WGM, WGN, TA_, TB_, AB_, IV_, MINB>),                  \
+                       dim3(batched_grid<BM, BN, WGM, WGN, TA_, TB_, AB_, IV_, MINB>(L.total)), block, 0, s, \
+                       L)
+#define FTG_T(AB_, IV_)                                  \
+    do {                                                 \
+        if (!ta && !tb) FTG_L(false, false, AB_, IV_);   \
+        else if (ta && !tb) FTG_L(true, false, AB_, IV_); \
+        else if (!ta && tb) FTG_L(false, true, AB_, IV_); \
+        else FTG_L(true, true, AB_, IV_);                \
     } while (0)
     if (!abft) FTG_T(false, false);
     else if (!ivl) FTG_T(true, false);

@@ -1,4 +1,4 @@
-// Batched (many uneven problems, one persistent launch) protected FP64 GEMM.
+// Repair-kernel interface shared by the single, batched and low-precision entry points.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -6,21 +6,6 @@
 #include "ftg_common.hpp"
 
 namespace ftg {
-
-// One problem of a batched call (device-resident descriptor table).
-struct BatchDesc {
-    const double* A;
-    const double* B;
-    double* C;
-    int lda, ldb, ldc;
-    int m, n, k;
-    int ta, tb;
-    int tile;          // tile configuration id
-    int tiles_m, tiles_n;
-    int kc;
-    double alpha, beta;
-    InjectParams inj;
-};
 
 // What the repair kernel needs to know about one problem.
 struct RepairProblem {

@@ -24,6 +24,16 @@ struct DGemmArgs {
     DevReport* rep;
 };
 
+// One persistent launch over the problems of a batched call that share a tile
+// configuration and transposes (device tables written by the host).
+struct BatchLaunch {
+    const DGemmArgs* __restrict__ desc;  // problem descriptors, in work order
+    const int* __restrict__ first;       // first work item of each problem (count + 1 entries)
+    int count;                           // problems
+    int total;                           // work items (tiles) = first[count]
+    unsigned int* queue;                 // [0] next item - grid, [1] finished workgroups; zero at launch
+};
+
 // FP64 tile configurations (k-block 16): 1 = 256x128 on 4 waves, 2 = 128x128,
 // 3 = 64x64, 4 = 256x128 on 8 waves.
 // Verification intervals shorter than k need tile 2 or 3.
@@ -37,6 +47,19 @@ inline hipError_t launch_dgemm(const DGemmArgs& a, int tile_id, bool abft, hipSt
     case 2: return launch_tile<128, 128, 2, 2, true, 2>(a, abft, s);
     case 3: return launch_tile<64, 64, 2, 2, true, 2>(a, abft, s);
     case 4: return launch_tile<256, 128, 4, 2, false, 1>(a, abft, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+template <int BM, int BN, int WGM, int WGN, bool IVL_OK, int MINB>
+hipError_t launch_batched(const BatchLaunch& L, int ta, int tb, bool abft, bool ivl, hipStream_t s);
+
+// Batched launches exist for the configurations with verification intervals.
+inline hipError_t launch_dgemm_batched(const BatchLaunch& L, int tile_id, int ta, int tb, bool abft,
+                                       bool ivl, hipStream_t s)
+{
+    switch (tile_id) {
+    case 2: return launch_batched<128, 128, 2, 2, true, 2>(L, ta, tb, abft, ivl, s);
+    case 3: return launch_batched<64, 64, 2, 2, true, 2>(L, ta, tb, abft, ivl, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -35,13 +35,16 @@ struct ftg_handle_s {
     ftg::RepairReq* d_repair = nullptr;     // device repair queue
     size_t capacity = 0;
     int last_info = 0;
-    // batched descriptor table
-    ftg::BatchDesc* d_batch = nullptr;
-    ftg::BatchDesc* h_batch = nullptr;      // pinned staging
-    int* d_queue = nullptr;                  // work counter(s)
+    // batched calls: a device table (descriptors, first-tile tables, repair
+    // table) filled by one copy per call from a pinned staging area; staging
+    // slots 0 and 1 alternate between eager calls, slot 2 serves stream capture
+    unsigned char* d_blob = nullptr;
+    unsigned char* h_blob[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t blob_ev[2] = {nullptr, nullptr};
+    bool blob_pending[2] = {false, false};
+    int next_slot = 0;
+    unsigned int* d_queue = nullptr;  // work counter of the persistent launch
     int64_t batch_cap = 0;
-    int64_t* d_tile_prefix = nullptr;
-    int64_t* h_tile_prefix = nullptr;
     // tuning table: configuration id per (dtype, bucket m, n, k); 0 = heuristic
     int8_t tune[kDtypes][kTuneBuckets][kTuneBuckets][kTuneBuckets];
 };
@@ -57,12 +60,15 @@ int bucket(int64_t x)
 
 int heuristic_tile_f64(int64_t m, int64_t n, int64_t k, bool need_intervals)
 {
-    // one workgroup per tile and 256 CUs: prefer the largest tile that still
-    // gives every CU work, fall back to smaller tiles for small problems
+    // One workgroup per tile and 256 CUs.  The 128 x 128 tile is the fastest
+    // protected configuration measured at large sizes (the 256 x 128 tiles
+    // need more registers than a SIMD holds once the checksum state is added),
+    // so it is the default; small problems drop to 64 x 64 to fill the chip.
+    // Explicit choices (config tile or the tuning table) may still pick 1 or 4.
     auto tiles = [&](int bm, int bn) { return ((m + bm - 1) / bm) * ((n + bn - 1) / bn); };
-    if (!need_intervals && tiles(256, 128) >= 256) return 1;
-    if (tiles(128, 128) >= 128) return 2;
     (void)k;
+    (void)need_intervals;
+    if (tiles(128, 128) >= 128) return 2;
     return 3;
 }
 
@@ -200,11 +206,12 @@ ftg_status ftg_destroy(ftg_handle h)
     if (h->d_records) hipFree(h->d_records);
     if (h->d_inject) hipFree(h->d_inject);
     if (h->d_repair) hipFree(h->d_repair);
-    if (h->d_batch) hipFree(h->d_batch);
+    if (h->d_blob) hipFree(h->d_blob);
     if (h->d_queue) hipFree(h->d_queue);
-    if (h->d_tile_prefix) hipFree(h->d_tile_prefix);
-    if (h->h_batch) hipHostFree(h->h_batch);
-    if (h->h_tile_prefix) hipHostFree(h->h_tile_prefix);
+    for (int i = 0; i < 3; ++i)
+        if (h->h_blob[i]) hipHostFree(h->h_blob[i]);
+    for (int i = 0; i < 2; ++i)
+        if (h->blob_ev[i]) hipEventDestroy(h->blob_ev[i]);
     delete h;
     return FTG_OK;
 }
@@ -331,6 +338,200 @@ ftg_status ftg_dgemm(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n, i
         e = ftg::launch_repair(h->rep, rp, nullptr, s);
     }
     return e == hipSuccess ? FTG_OK : FTG_ERR_HIP;
+}
+
+// ---------------------------------------------------------------- batched
+namespace {
+
+constexpr int kMaxGroups = 8;  // (tile 2 or 3) x 4 transpose pairs
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Bytes of the batched table for `count` problems: descriptors, first-tile
+// tables of up to kMaxGroups groups, repair table.
+void blob_layout(int64_t count, size_t* off_first, size_t* off_rep, size_t* total)
+{
+    *off_first = align256((size_t)count * sizeof(ftg::DGemmArgs));
+    *off_rep = align256(*off_first + (size_t)(count + kMaxGroups) * sizeof(int));
+    *total = *off_rep + (size_t)count * sizeof(ftg::RepairProblem);
+}
+
+}  // namespace
+
+ftg_status ftg_batched_reserve(ftg_handle h, int64_t capacity)
+{
+    if (!h || capacity < 0 || capacity > (int64_t(1) << 24)) return FTG_ERR_INVALID_ARG;
+    if (capacity <= h->batch_cap && h->d_blob) return FTG_OK;
+    if (hipDeviceSynchronize() != hipSuccess) return FTG_ERR_HIP;
+    size_t of, orp, bytes;
+    blob_layout(std::max<int64_t>(1, capacity), &of, &orp, &bytes);
+    if (h->d_blob) { hipFree(h->d_blob); h->d_blob = nullptr; }
+    for (int i = 0; i < 3; ++i)
+        if (h->h_blob[i]) { hipHostFree(h->h_blob[i]); h->h_blob[i] = nullptr; }
+    h->batch_cap = 0;
+    bool ok = hipMalloc(&h->d_blob, bytes) == hipSuccess;
+    for (int i = 0; i < 3 && ok; ++i) ok = hipHostMalloc(&h->h_blob[i], bytes, hipHostMallocDefault) == hipSuccess;
+    if (ok && !h->d_queue) {
+        ok = hipMalloc(&h->d_queue, 2 * sizeof(unsigned int)) == hipSuccess;
+        ok = ok && hipMemset(h->d_queue, 0, 2 * sizeof(unsigned int)) == hipSuccess;
+    }
+    for (int i = 0; i < 2 && ok; ++i)
+        if (!h->blob_ev[i]) ok = hipEventCreateWithFlags(&h->blob_ev[i], hipEventDisableTiming) == hipSuccess;
+    if (ok) ok = hipDeviceSynchronize() == hipSuccess;
+    if (!ok) return FTG_ERR_HIP;
+    h->blob_pending[0] = h->blob_pending[1] = false;
+    h->batch_cap = std::max<int64_t>(1, capacity);
+    return FTG_OK;
+}
+
+ftg_status ftg_dgemm_batched_uneven(ftg_handle h, int64_t count, const ftg_op* transa,
+                                    const ftg_op* transb, const int64_t* m, const int64_t* n,
+                                    const int64_t* k, const double* alpha,
+                                    const double* const* A, const int64_t* lda,
+                                    const double* const* B, const int64_t* ldb,
+                                    const double* beta, double* const* C, const int64_t* ldc,
+                                    const uint32_t* faults_per_problem, void* stream,
+                                    const ftg_config* cfg)
+{
+    if (!h) return FTG_ERR_INVALID_ARG;
+    if (count < 0) return set_err(h, 2);
+    if (count == 0) return FTG_OK;
+    if (!transa || !transb || !m || !n || !k || !alpha || !A || !lda || !B || !ldb || !beta || !C || !ldc)
+        return set_err(h, 20);
+    if (count > h->batch_cap) return FTG_ERR_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    const bool abft = !cfg || cfg->abft;
+    if (cfg && cfg->tile && cfg->tile != 2 && cfg->tile != 3) return FTG_ERR_UNSUPPORTED;
+
+    // per problem: checks, tile configuration, group
+    struct Item { int64_t p; int group; int64_t k; };
+    Item* items = new (std::nothrow) Item[(size_t)count];
+    if (!items) return FTG_ERR_HIP;
+    struct Guard { Item* p; ~Guard() { delete[] p; } } guard{items};
+    int64_t n_items = 0;
+    for (int64_t p = 0; p < count; ++p) {
+        ftg_status st = check_gemm(h, transa[p], transb[p], m[p], n[p], k[p], lda[p], ldb[p], ldc[p], cfg);
+        if (st != FTG_OK) return st;
+        if (cfg && cfg->inject && cfg->inject->bit_hi > 63) return set_err(h, 20);
+        if (m[p] >= (int64_t(1) << 31) || n[p] >= (int64_t(1) << 31) || k[p] >= (int64_t(1) << 31) ||
+            lda[p] >= (1 << 20) || ldb[p] >= (1 << 20) || ldc[p] >= (1 << 20))
+            return FTG_ERR_UNSUPPORTED;
+        if (m[p] == 0 || n[p] == 0 || ((alpha[p] == 0.0 || k[p] == 0) && beta[p] == 1.0)) continue;
+        int tile = cfg && cfg->tile ? cfg->tile : h->tune[FTG_F64][bucket(m[p])][bucket(n[p])][bucket(k[p])];
+        if (tile != 2 && tile != 3) tile = 3;
+        const int g = (tile - 2) * 4 + (transa[p] == FTG_OP_T) * 2 + (transb[p] == FTG_OP_T);
+        items[n_items++] = Item{p, g, alpha[p] == 0.0 ? 0 : k[p]};
+    }
+    if (n_items == 0) return FTG_OK;
+    // group by configuration, most expensive tiles (largest k) first
+    std::sort(items, items + n_items, [](const Item& x, const Item& y) {
+        return x.group != y.group ? x.group < y.group : (x.k != y.k ? x.k > y.k : x.p < y.p);
+    });
+
+    // staging slot: wait until the copy that last read it has run
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) return FTG_ERR_HIP;
+    const bool capturing = cs != hipStreamCaptureStatusNone;
+    const int slot = capturing ? 2 : h->next_slot;
+    if (!capturing) {
+        if (h->blob_pending[slot] && hipEventSynchronize(h->blob_ev[slot]) != hipSuccess) return FTG_ERR_HIP;
+        h->next_slot ^= 1;
+    }
+    size_t off_first, off_rep, bytes;
+    blob_layout(count, &off_first, &off_rep, &bytes);
+    unsigned char* hb = h->h_blob[slot];
+    auto* hdesc = (ftg::DGemmArgs*)hb;
+    auto* hfirst = (int*)(hb + off_first);
+    auto* hrep = (ftg::RepairProblem*)(hb + off_rep);
+    std::memset(hrep, 0, (size_t)count * sizeof(ftg::RepairProblem));
+
+    struct Group { int64_t d0, d1; int f0; int tile, ta, tb; bool ivl; };
+    Group groups[kMaxGroups];
+    int ng = 0;
+    int nfirst = 0;
+    int64_t total = 0;
+    for (int64_t it = 0; it < n_items; ++it) {
+        const int64_t p = items[it].p;
+        if (ng == 0 || groups[ng - 1].tile * 4 + groups[ng - 1].ta * 2 + groups[ng - 1].tb - 8 != items[it].group) {
+            if (ng > 0) hfirst[nfirst++] = (int)total;  // closing entry of the previous group
+            Group& G = groups[ng++];
+            G.d0 = it; G.d1 = it; G.f0 = nfirst;
+            G.tile = items[it].group / 4 + 2; G.ta = (items[it].group >> 1) & 1; G.tb = items[it].group & 1;
+            G.ivl = false;
+            total = 0;
+        }
+        Group& G = groups[ng - 1];
+        int bm, bn, bk;
+        ftg::dgemm_tile_shape(G.tile, &bm, &bn, &bk);
+        const int64_t kk = items[it].k;
+        // one interval: a multiple of 128 no shorter than k, so that problems of
+        // both kinds can share a launch with interval checks compiled in
+        const int64_t kc = (cfg && cfg->interval_k > 0 && cfg->interval_k < kk)
+                               ? cfg->interval_k
+                               : (std::max<int64_t>(kk, 1) + ftg::kKGran - 1) / ftg::kKGran * ftg::kKGran;
+        ftg::DGemmArgs& a = hdesc[it];
+        std::memset(&a, 0, sizeof(a));
+        a.A = A[p]; a.B = B[p]; a.C = C[p];
+        a.lda = (int)lda[p]; a.ldb = (int)ldb[p]; a.ldc = (int)ldc[p];
+        a.m = (int)m[p]; a.n = (int)n[p]; a.k = (int)kk;
+        a.kc = (int)kc;
+        a.tiles_m = (int)((m[p] + bm - 1) / bm);
+        a.tiles_n = (int)((n[p] + bn - 1) / bn);
+        a.ta = G.ta; a.tb = G.tb;
+        a.alpha = alpha[p]; a.beta = beta[p];
+        a.correct_policy = cfg ? cfg->correct_policy : 0;
+        a.uncorrectable_policy = cfg ? cfg->uncorrectable_policy : 0;
+        a.problem = (int)p;
+        a.rep = h->rep;
+        if (kc < kk) G.ivl = true;
+        const int64_t n_int = (kk + kc - 1) / kc;
+        if (abft && cfg && cfg->inject && kk > 0) {
+            if (n_int > ftg::kMaxIntervals) return FTG_ERR_UNSUPPORTED;
+            ftg_inject in = *cfg->inject;
+            in.seed = ftg::splitmix64(cfg->inject->seed, (uint64_t(1) << 32) + (uint64_t)p);
+            const int64_t slots = (int64_t)a.tiles_m * a.tiles_n * n_int;
+            if (!ftg::make_inject(&in, m[p], n[p], kk, slots, 40, 63, &a.inj,
+                                  faults_per_problem ? faults_per_problem[p] : 0u, faults_per_problem != nullptr))
+                return FTG_ERR_UNSUPPORTED;
+        }
+        hfirst[nfirst++] = (int)total;
+        total += (int64_t)a.tiles_m * a.tiles_n;
+        if (total >= (int64_t(1) << 31)) return FTG_ERR_UNSUPPORTED;
+        G.d1 = it + 1;
+        ftg::RepairProblem& rp = hrep[p];
+        rp.A = a.A; rp.B = a.B; rp.C = a.C;
+        rp.lda = lda[p]; rp.ldb = ldb[p]; rp.ldc = ldc[p]; rp.k = kk;
+        rp.ta = a.ta; rp.tb = a.tb; rp.correct_policy = a.correct_policy;
+        rp.ab_type = FTG_F64; rp.c_type = FTG_F64;
+        rp.alpha = alpha[p]; rp.beta = beta[p]; rp.scale = 1.0;
+    }
+    hfirst[nfirst++] = (int)total;
+
+    if (hipMemcpyAsync(h->d_blob, hb, bytes, hipMemcpyHostToDevice, s) != hipSuccess) return FTG_ERR_HIP;
+    if (!capturing) {
+        if (hipEventRecord(h->blob_ev[slot], s) != hipSuccess) return FTG_ERR_HIP;
+        h->blob_pending[slot] = true;
+    }
+    const auto* ddesc = (const ftg::DGemmArgs*)h->d_blob;
+    const auto* dfirst = (const int*)(h->d_blob + off_first);
+    for (int g = 0; g < ng; ++g) {
+        const Group& G = groups[g];
+        ftg::BatchLaunch L;
+        L.desc = ddesc + G.d0;
+        L.first = dfirst + G.f0;
+        L.count = (int)(G.d1 - G.d0);
+        L.total = hfirst[G.f0 + L.count];
+        L.queue = h->d_queue;
+        hipError_t e = ftg::launch_dgemm_batched(L, G.tile, G.ta, G.tb, abft, abft && G.ivl, s);
+        if (e != hipSuccess) return FTG_ERR_HIP;
+    }
+    if (abft) {
+        ftg::RepairProblem none;
+        std::memset(&none, 0, sizeof(none));
+        if (ftg::launch_repair(h->rep, none, (const ftg::RepairProblem*)(h->d_blob + off_rep), s) != hipSuccess)
+            return FTG_ERR_HIP;
+    }
+    return FTG_OK;
 }
 
 ftg_status ftg_report_read(ftg_handle h, void* stream, ftg_fault_report* out, int sync)

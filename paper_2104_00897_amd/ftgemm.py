@@ -202,11 +202,49 @@ class Handle:
                           for r in logs[:min(out.n_inject_log, self.capacity)]]
         return rep
 
+    def dgemm_batched(self, plan: "BatchPlan", stream=None, cfg=None, faults_per_problem=None):
+        f = None
+        if faults_per_problem is not None:
+            f = (ct.c_uint32 * plan.count)(*[int(x) for x in faults_per_problem])
+        st = self.lib.ftg_dgemm_batched_uneven(
+            self.h, plan.count, plan.ta, plan.tb, plan.m, plan.n, plan.k, plan.alpha, plan.A,
+            plan.lda, plan.B, plan.ldb, plan.beta, plan.C, plan.ldc, f, stream,
+            ct.byref(cfg) if cfg is not None else None)
+        self._check(st, "ftg_dgemm_batched_uneven")
+
+    def batched_reserve(self, capacity: int):
+        self._check(self.lib.ftg_batched_reserve(self.h, capacity), "ftg_batched_reserve")
+
     def tune_set(self, dtype, m, n, k, tile_id):
         self._check(self.lib.ftg_tune_set(self.h, dtype, m, n, k, tile_id), "ftg_tune_set")
 
     def tune_get(self, dtype, m, n, k) -> int:
         return self.lib.ftg_tune_get(self.h, dtype, m, n, k)
+
+
+class BatchPlan:
+    """Host argument arrays of one batched call (built once, reusable across
+    calls and graph captures).  problems: sequence of dicts with keys
+    ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc (A/B/C device
+    addresses as ints)."""
+
+    def __init__(self, problems):
+        cnt = len(problems)
+        self.count = cnt
+        col = lambda key: [p[key] for p in problems]
+        self.ta = (ct.c_int32 * cnt)(*col("ta"))
+        self.tb = (ct.c_int32 * cnt)(*col("tb"))
+        self.m = (ct.c_int64 * cnt)(*col("m"))
+        self.n = (ct.c_int64 * cnt)(*col("n"))
+        self.k = (ct.c_int64 * cnt)(*col("k"))
+        self.lda = (ct.c_int64 * cnt)(*col("lda"))
+        self.ldb = (ct.c_int64 * cnt)(*col("ldb"))
+        self.ldc = (ct.c_int64 * cnt)(*col("ldc"))
+        self.alpha = (ct.c_double * cnt)(*col("alpha"))
+        self.beta = (ct.c_double * cnt)(*col("beta"))
+        self.A = (ct.c_void_p * cnt)(*col("A"))
+        self.B = (ct.c_void_p * cnt)(*col("B"))
+        self.C = (ct.c_void_p * cnt)(*col("C"))
 
 
 # ---------------------------------------------------------------- torch helpers
@@ -249,3 +287,13 @@ def gemm_f64(handle: Handle, A, B, C, alpha=1.0, beta=0.0, ta=OP_N, tb=OP_N, cfg
     handle.dgemm(ta, tb, m, n, k, alpha, ptr(A), max(1, rows_a), ptr(B), max(1, rows_b), beta,
                  ptr(C), max(1, C.shape[1]), current_stream_ptr(), cfg)
     return C
+
+
+def batch_problem(A, B, C, alpha=1.0, beta=0.0, ta=OP_N, tb=OP_N):
+    """One entry of a BatchPlan from column-major device tensors (see to_device)."""
+    rows_a, cols_a = A.shape[1], A.shape[0]
+    rows_b, cols_b = B.shape[1], B.shape[0]
+    return dict(ta=ta, tb=tb, m=cols_a if ta else rows_a, n=rows_b if tb else cols_b,
+                k=rows_a if ta else cols_a, alpha=alpha, beta=beta, A=A.data_ptr(),
+                lda=max(1, rows_a), B=B.data_ptr(), ldb=max(1, rows_b), C=C.data_ptr(),
+                ldc=max(1, C.shape[1]))

@@ -266,3 +266,35 @@ def test_deterministic_rerun(env):
     np.testing.assert_array_equal(out1, out2)
     key = lambda r: (r["row"], r["col"], r["kind"])
     assert sorted(map(key, rep1.records)) == sorted(map(key, rep2.records))
+
+
+@pytest.mark.parametrize("tile", [2, 3])
+def test_recompute_in_other_waves_with_beta(env, tile):
+    """Flips that the subtraction cannot undo (absorption) force the recompute
+    path, which needs C_in at the element; placed in elements owned by waves
+    other than the first, with beta != 0 (regression: C_in must be read before
+    the owning wave stores the tile)."""
+    ftgemm = env[0]
+    m, n, k = 381, 276, 273
+    A, B, C = inputs.gemm_operands_f64(m, n, k, seed=12)
+    bm, bn = TILES[tile]
+    chosen = []
+    for seed in range(400):
+        plan = plan_for(seed, 3, m, n, k, tile, bit_lo=60, bit_hi=62)
+        if not all((f.row % bm) >= bm // 2 or (f.col % bn) >= bn // 2 for f in plan):
+            continue
+        _, orecs, ocnt = oracle.abft(A, B, C, 1.5, 0.5, bm=bm, bn=bn, plan=plan)
+        if ocnt["corrected_recompute"] >= 1:
+            chosen.append((seed, plan, orecs))
+        if len(chosen) == 3:
+            break
+    assert len(chosen) == 3
+    ref = oracle.gemm(A, B, C, 1.5, 0.5)
+    M = magnitude(A, B, C, 1.5, 0.5, 0, 0)
+    for seed, plan, orecs in chosen:
+        cfg = ftgemm.make_config(tile=tile, seed=seed, n_faults=3, bit_lo=60, bit_hi=62)
+        out, rep = run(env, A, B, C, 1.5, 0.5, 0, 0, cfg)
+        check_log_matches_plan(rep, plan, tile)
+        got = sorted((r["row"], r["col"], r["kind"]) for r in rep.records)
+        assert got == sorted((r.row, r.col, r.kind) for r in orecs)
+        assert_close_f64(out, ref, M, k)
