@@ -316,11 +316,25 @@ static double flip_value(int acc32, double x, int bit)
 /* NaN-safe flag: set unless |d| <= tau holds (so NaN and Inf are flagged) */
 static int flagged(double d, double tau) { return !(fabs(d) <= tau); }
 
+/* Subtracting the error magnitude (§6.3) returns the true value only when the
+ * faulty value still carries it.  The row threshold tau spreads over the q
+ * elements of the row, so the subtraction is trusted while the rounding unit
+ * of x (in the output's precision) stays within tau / (2 q); beyond that the
+ * true value has been absorbed and the element is recomputed instead. */
+static int absorbed(int acc32, double x, double tau, int64_t q)
+{
+    if (x == 0.0) return 0;
+    double ulp = ldexp(1.0, ilogb(x) - (acc32 ? 23 : 52));
+    return ulp > tau / (2.0 * (double)q);
+}
+
 typedef struct {
     /* tile geometry */
     int64_t i0, j0, R, Q;
     /* state, R x Q accumulator (column-major, leading dim R) */
     double *acc, *er, *ec, *mr, *mc;
+    /* binary32 path: sum_p |a_ip|, sum_p |b_pj|, max_p sum_j |b_pj|, max_p sum_i |a_ip| */
+    double *ra, *cb, mxb, mxa;
     /* per-verification scratch */
     double *rs, *cs, *out;
     const ftgo_params* P;
@@ -359,12 +373,16 @@ static void advance(tile_state* T, int64_t plo, int64_t phi, const ftgo_fault* p
             double a = tA(T, i, p);
             T->er[i] = T->er[i] + a * bs;
             T->mr[i] = T->mr[i] + fabs(a) * bsa;
+            T->ra[i] = T->ra[i] + fabs(a);
         }
         for (int64_t j = 0; j < Q; ++j) {
             double b = tB(T, p, j);
             T->ec[j] = T->ec[j] + as * b;
             T->mc[j] = T->mc[j] + asa * fabs(b);
+            T->cb[j] = T->cb[j] + fabs(b);
         }
+        if (bsa > T->mxb) T->mxb = bsa;
+        if (asa > T->mxa) T->mxa = asa;
         if (!inject) continue;
         for (int64_t f = 0; f < nplan; ++f) {
             if (plan[f].pflip != p) continue;
@@ -413,6 +431,9 @@ static check check_line(const tile_state* T, int final, int64_t pend, int dir, i
     }
     double maint = dir == 0 ? T->er[x] : T->ec[x];
     double mag = dir == 0 ? T->mr[x] : T->mc[x];
+    /* binary32 path: the bound (sum_p |a_ip|) max_p (sum_j |b_pj|) >= sum_p |a_ip| sum_j |b_pj|
+     * (and alike for columns), which needs only per-line and per-panel sums */
+    if (P->acc32) mag = dir == 0 ? T->ra[x] * T->mxb : T->cb[x] * T->mxa;
     double expect = maint;
     if (final) {
         expect = P->alpha * maint;
@@ -467,7 +488,7 @@ static void verify_slot(tile_state* T, int final, int64_t pend, int64_t tm, int6
         /* one faulty element located at the intersection (§5.1) */
         double* x = &T->out[fi + fj * R];
         int kind = 0;
-        if (P->correct_policy == 0 && isfinite(dri) && isfinite(*x)) {
+        if (P->correct_policy == 0 && isfinite(dri) && isfinite(*x) && !absorbed(P->acc32, *x, tri, Q)) {
             double keep = *x;
             *x = *x - dri; /* subtract the error magnitude (§6.3) */
             check a = check_line(T, final, pend, 0, fi), b = check_line(T, final, pend, 1, fj);
@@ -511,6 +532,9 @@ static void verify_slot(tile_state* T, int final, int64_t pend, int64_t tm, int6
         memset(T->ec, 0, sizeof(double) * Q);
         memset(T->mr, 0, sizeof(double) * R);
         memset(T->mc, 0, sizeof(double) * Q);
+        memset(T->ra, 0, sizeof(double) * R);
+        memset(T->cb, 0, sizeof(double) * Q);
+        T->mxb = T->mxa = 0.0;
         advance(T, 0, pend, plan, nplan, 0, cnt);
         for (int64_t j = 0; j < Q; ++j)
             for (int64_t i = 0; i < R; ++i)
@@ -558,8 +582,10 @@ int ftgo_abft(const ftgo_params* P, const double* A, const double* B, double* C,
     T.mr = (double*)malloc(sizeof(double) * R0);
     T.ec = (double*)malloc(sizeof(double) * Q0);
     T.mc = (double*)malloc(sizeof(double) * Q0);
+    T.ra = (double*)malloc(sizeof(double) * R0);
+    T.cb = (double*)malloc(sizeof(double) * Q0);
     ftgo_fault* sub = (ftgo_fault*)malloc(sizeof(ftgo_fault) * (nplan > 0 ? nplan : 1));
-    if (!T.acc || !T.out || !T.er || !T.mr || !T.ec || !T.mc || !sub) return -2;
+    if (!T.acc || !T.out || !T.er || !T.mr || !T.ec || !T.mc || !T.ra || !T.cb || !sub) return -2;
 
     for (int64_t tn = 0; tn < tiles_n; ++tn) {
         for (int64_t tm = 0; tm < tiles_m; ++tm) {
@@ -570,6 +596,9 @@ int ftgo_abft(const ftgo_params* P, const double* A, const double* B, double* C,
             memset(T.mr, 0, sizeof(double) * T.R);
             memset(T.ec, 0, sizeof(double) * T.Q);
             memset(T.mc, 0, sizeof(double) * T.Q);
+            memset(T.ra, 0, sizeof(double) * T.R);
+            memset(T.cb, 0, sizeof(double) * T.Q);
+            T.mxb = T.mxa = 0.0;
             int64_t ns = 0; /* this tile's faults */
             for (int64_t f = 0; f < nplan; ++f)
                 if (plan[f].tile_m == tm && plan[f].tile_n == tn) sub[ns++] = plan[f];
@@ -580,6 +609,7 @@ int ftgo_abft(const ftgo_params* P, const double* A, const double* B, double* C,
             }
         }
     }
-    free(T.acc); free(T.out); free(T.er); free(T.mr); free(T.ec); free(T.mc); free(sub);
+    free(T.acc); free(T.out); free(T.er); free(T.mr); free(T.ec); free(T.mc); free(T.ra); free(T.cb);
+    free(sub);
     return 0;
 }

@@ -493,7 +493,7 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
                     xold = V.xold;
                     stage = 1;
                     if (args.correct_policy == 0 && isfinite(dfi) &&
-                        __builtin_amdgcn_readfirstlane(V.xfinite)) {
+                        __builtin_amdgcn_readfirstlane(V.xfinite) && !absorbed(false, xold, tfi, Q)) {
                         set_elem(idx, xold - dfi, own);  // subtract the error (§6.3)
                         continue;
                     }

@@ -15,7 +15,8 @@ struct RepairProblem {
     int64_t lda, ldb, ldc, k;
     int ta, tb, correct_policy, ab_type, c_type, pad;
     double alpha, beta;
-    double scale;  // product scale of the operands (s_A s_B for FP8, else 1)
+    const float* scale_a;  // device per-tensor scales of FP8 operands (NULL = 1)
+    const float* scale_b;
 };
 
 constexpr int kRepairBlocks = 8;

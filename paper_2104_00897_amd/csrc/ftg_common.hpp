@@ -149,6 +149,17 @@ __device__ inline double tau_of(int acc32, double lambda, int64_t nterms, double
 
 __device__ inline bool flagged(double d, double tau) { return !(fabs(d) <= tau); }
 
+// The faulty value no longer carries the true one (absorption): its rounding
+// unit in the output precision (binary32 when acc32) exceeds tau / (2 q), the
+// share of the row threshold of one of the row's q elements.  Subtracting the
+// error magnitude could not restore the element then; it is recomputed.
+__device__ inline bool absorbed(bool acc32, double x, double tau, int q)
+{
+    if (x == 0.0) return false;
+    const double ulp = ldexp(1.0, ilogb(x) - (acc32 ? 23 : 52));
+    return ulp > tau / (2.0 * (double)q);
+}
+
 // Raw buffer access (CDNA buffer instructions): an SGPR resource with a base
 // address, a 32-bit per-lane byte offset and a uniform byte offset.  An offset
 // at or beyond the record count reads 0 and drops writes, which is how

@@ -45,11 +45,17 @@ struct ftg_handle_s {
     int next_slot = 0;
     unsigned int* d_queue = nullptr;  // work counter of the persistent launch
     int64_t batch_cap = 0;
+    // workspace of the low-precision protected path (checksum pieces, checksum
+    // products, magnitude bounds); grows to the largest shape seen
+    unsigned char* d_work = nullptr;
+    size_t work_bytes = 0;
     // tuning table: configuration id per (dtype, bucket m, n, k); 0 = heuristic
     int8_t tune[kDtypes][kTuneBuckets][kTuneBuckets][kTuneBuckets];
 };
 
 namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int bucket(int64_t x)
 {
@@ -208,6 +214,7 @@ ftg_status ftg_destroy(ftg_handle h)
     if (h->d_repair) hipFree(h->d_repair);
     if (h->d_blob) hipFree(h->d_blob);
     if (h->d_queue) hipFree(h->d_queue);
+    if (h->d_work) hipFree(h->d_work);
     for (int i = 0; i < 3; ++i)
         if (h->h_blob[i]) hipHostFree(h->h_blob[i]);
     for (int i = 0; i < 2; ++i)
@@ -334,18 +341,175 @@ ftg_status ftg_dgemm(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n, i
         rp.lda = lda; rp.ldb = ldb; rp.ldc = ldc; rp.k = k;
         rp.ta = a.ta; rp.tb = a.tb; rp.correct_policy = a.correct_policy;
         rp.ab_type = FTG_F64; rp.c_type = FTG_F64;
-        rp.alpha = alpha; rp.beta = beta; rp.scale = 1.0;
+        rp.alpha = alpha; rp.beta = beta; rp.scale_a = rp.scale_b = nullptr;
         e = ftg::launch_repair(h->rep, rp, nullptr, s);
     }
     return e == hipSuccess ? FTG_OK : FTG_ERR_HIP;
+}
+
+// ---------------------------------------------------------------- low precision
+namespace {
+
+struct LowpLayout {
+    size_t xs_a, xs_b, xrp_a, xrp_b, xmp_a, xmp_b, ra, cb, ma, mb, er, ec, total;
+};
+
+LowpLayout lowp_layout(int64_t m, int64_t n, int64_t k)
+{
+    const int64_t tm = (m + ftg::kLowpTile - 1) / ftg::kLowpTile, tn = (n + ftg::kLowpTile - 1) / ftg::kLowpTile;
+    const int64_t ch = (k + ftg::kLowpChunk - 1) / ftg::kLowpChunk;
+    LowpLayout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+    L.xs_a = take((size_t)(3 * tm * k) * 2);
+    L.xs_b = take((size_t)(3 * tn * k) * 2);
+    L.xrp_a = take((size_t)(ch * m) * 4);
+    L.xrp_b = take((size_t)(ch * n) * 4);
+    L.xmp_a = take((size_t)(tm * ch) * 4);
+    L.xmp_b = take((size_t)(tn * ch) * 4);
+    L.ra = take((size_t)m * 4);
+    L.cb = take((size_t)n * 4);
+    L.ma = take((size_t)tm * 4);
+    L.mb = take((size_t)tn * 4);
+    L.er = take((size_t)(m * 3 * tn) * 4);
+    L.ec = take((size_t)(3 * tm * n) * 4);
+    L.total = o;
+    return L;
+}
+
+bool vec_ok(const void* p, int64_t ld, int bytes)
+{
+    return ((uintptr_t)p % 16 == 0) && ((ld * bytes) % 16 == 0);
+}
+
+}  // namespace
+
+ftg_status ftg_gemm_ex(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n, int64_t k,
+                       ftg_dtype ab_type, ftg_dtype c_type, const float* scale_a,
+                       const float* scale_b, float alpha, const void* A, int64_t lda,
+                       const void* B, int64_t ldb, float beta, void* C, int64_t ldc,
+                       void* stream, const ftg_config* cfg)
+{
+    if (!h) return FTG_ERR_INVALID_ARG;
+    ftg_status st = check_gemm(h, ta, tb, m, n, k, lda, ldb, ldc, cfg);
+    if (st != FTG_OK) return st;
+    if (ab_type != FTG_BF16 && ab_type != FTG_F8_E4M3) return FTG_ERR_UNSUPPORTED;
+    if (c_type != FTG_F32) return FTG_ERR_UNSUPPORTED;
+    if (ab_type == FTG_F8_E4M3 && (!scale_a || !scale_b)) return set_err(h, 20);
+    if (cfg && cfg->inject && cfg->inject->bit_hi > 31) return set_err(h, 20);
+    if (cfg && cfg->lambda < 0.0) return set_err(h, 20);
+    hipStream_t s = (hipStream_t)stream;
+    if (m == 0 || n == 0 || ((alpha == 0.0f || k == 0) && beta == 1.0f)) return FTG_OK;
+    if (alpha == 0.0f || k == 0)
+        return ftg::launch_sscale((float*)C, m, n, ldc, beta, s) == hipSuccess ? FTG_OK : FTG_ERR_HIP;
+    if (m >= (int64_t(1) << 31) || n >= (int64_t(1) << 31) || k >= (int64_t(1) << 31) ||
+        lda >= (1 << 20) || ldb >= (1 << 20) || ldc >= (1 << 20))
+        return FTG_ERR_UNSUPPORTED;
+    const bool abft = !cfg || cfg->abft;
+    if (abft && cfg && cfg->interval_k > 0 && cfg->interval_k < k) return FTG_ERR_UNSUPPORTED;
+    int tile = cfg && cfg->tile ? cfg->tile : h->tune[ab_type][bucket(m)][bucket(n)][bucket(k)];
+    if (!tile) tile = ftg::lowp_heuristic_tile(ab_type, m, n, k);
+    int bm, bn, bk;
+    ftg::lowp_tile_shape(ab_type, tile, &bm, &bn, &bk);
+    if (bm == 0) return set_err(h, 20);
+    const int eb = ab_type == FTG_BF16 ? 2 : 1;
+
+    ftg::LowpArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.A = A; a.B = B; a.C = (float*)C;
+    a.lda = (int)lda; a.ldb = (int)ldb; a.ldc = (int)ldc;
+    a.m = (int)m; a.n = (int)n; a.k = (int)k;
+    a.tiles_m = (int)((m + bm - 1) / bm);
+    a.tiles_n = (int)((n + bn - 1) / bn);
+    a.vec_a = vec_ok(A, lda, eb);
+    a.vec_b = vec_ok(B, ldb, eb);
+    a.alpha = alpha; a.beta = beta;
+    a.scale_a = ab_type == FTG_F8_E4M3 ? scale_a : nullptr;
+    a.scale_b = ab_type == FTG_F8_E4M3 ? scale_b : nullptr;
+    a.rep = h->rep;
+    const int ita = ta == FTG_OP_T, itb = tb == FTG_OP_T;
+    if (!abft)
+        return ftg::launch_lowp_gemm(a, ab_type, ab_type, ita, itb, 0, s) == hipSuccess ? FTG_OK : FTG_ERR_HIP;
+
+    // workspace (grows; allocation is not allowed under stream capture)
+    const LowpLayout L = lowp_layout(m, n, k);
+    if (L.total > h->work_bytes) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+            return FTG_ERR_UNSUPPORTED;
+        if (hipDeviceSynchronize() != hipSuccess) return FTG_ERR_HIP;
+        if (h->d_work) hipFree(h->d_work);
+        h->d_work = nullptr;
+        h->work_bytes = 0;
+        if (hipMalloc(&h->d_work, L.total) != hipSuccess) return FTG_ERR_HIP;
+        h->work_bytes = L.total;
+    }
+    unsigned char* w = h->d_work;
+    const int chunks = (int)((k + ftg::kLowpChunk - 1) / ftg::kLowpChunk);
+
+    // encode: checksum pieces and magnitude sums of both operands
+    ftg::EncArgs e;
+    std::memset(&e, 0, sizeof(e));
+    ftg::EncOperand& ea = e.op[0];
+    ea.X = A; ea.ld = lda; ea.rows = (int)m; ea.K = (int)k; ea.kcontig = ita;
+    ea.panels = a.tiles_m; ea.chunks = chunks;
+    ea.XS = (uint16_t*)(w + L.xs_a); ea.XRp = (float*)(w + L.xrp_a); ea.XMp = (float*)(w + L.xmp_a);
+    ea.XR = (float*)(w + L.ra); ea.XM = (float*)(w + L.ma);
+    ftg::EncOperand& eb_ = e.op[1];
+    eb_.X = B; eb_.ld = ldb; eb_.rows = (int)n; eb_.K = (int)k; eb_.kcontig = !itb;
+    eb_.panels = a.tiles_n; eb_.chunks = chunks;
+    eb_.XS = (uint16_t*)(w + L.xs_b); eb_.XRp = (float*)(w + L.xrp_b); eb_.XMp = (float*)(w + L.xmp_b);
+    eb_.XR = (float*)(w + L.cb); eb_.XM = (float*)(w + L.mb);
+    const int gx = std::max(a.tiles_m, a.tiles_n) * chunks;
+    const int fx = (int)((std::max(m, n) + 255) / 256);
+    if (ftg::launch_lowp_encode(e, ab_type, gx, fx, s) != hipSuccess) return FTG_ERR_HIP;
+
+    // checksum products: ER = op(A) [B_J e pieces], EC = [e^T A_I pieces]^T op(B)
+    ftg::LowpArgs c1;
+    std::memset(&c1, 0, sizeof(c1));
+    c1.A = A; c1.lda = (int)lda; c1.B = eb_.XS; c1.ldb = (int)k;
+    c1.C = (float*)(w + L.er); c1.ldc = (int)m;
+    c1.m = (int)m; c1.n = 3 * a.tiles_n; c1.k = (int)k;
+    c1.tiles_m = a.tiles_m; c1.tiles_n = (c1.n + bn - 1) / bn;
+    c1.vec_a = a.vec_a; c1.vec_b = vec_ok(c1.B, k, 2);
+    c1.alpha = 1.0f; c1.beta = 0.0f;
+    if (ftg::launch_lowp_gemm(c1, ab_type, FTG_BF16, ita, 0, 0, s) != hipSuccess) return FTG_ERR_HIP;
+    ftg::LowpArgs c2;
+    std::memset(&c2, 0, sizeof(c2));
+    c2.A = ea.XS; c2.lda = (int)k; c2.B = B; c2.ldb = (int)ldb;
+    c2.C = (float*)(w + L.ec); c2.ldc = 3 * a.tiles_m;
+    c2.m = 3 * a.tiles_m; c2.n = (int)n; c2.k = (int)k;
+    c2.tiles_m = (c2.m + bm - 1) / bm; c2.tiles_n = a.tiles_n;
+    c2.vec_a = vec_ok(c2.A, k, 2); c2.vec_b = a.vec_b;
+    c2.alpha = 1.0f; c2.beta = 0.0f;
+    if (ftg::launch_lowp_gemm(c2, FTG_BF16, ab_type, 1, itb, 0, s) != hipSuccess) return FTG_ERR_HIP;
+
+    // protected product
+    a.ER = c1.C; a.lder = (int)m;
+    a.EC = c2.C; a.ldec = 3 * a.tiles_m;
+    a.RA = ea.XR; a.MA = ea.XM; a.CB = eb_.XR; a.MB = eb_.XM;
+    a.lambda = (cfg && cfg->lambda > 0.0) ? cfg->lambda : 4.0;
+    a.problem = 0;
+    if (cfg && cfg->inject) {
+        const int64_t slots = (int64_t)a.tiles_m * a.tiles_n;
+        if (!ftg::make_inject(cfg->inject, m, n, k, slots, 13, 31, &a.inj, 0, false)) return FTG_ERR_UNSUPPORTED;
+    }
+    if (ftg::launch_lowp_gemm(a, ab_type, ab_type, ita, itb, 1, s) != hipSuccess) return FTG_ERR_HIP;
+    ftg::RepairProblem rp;
+    std::memset(&rp, 0, sizeof(rp));
+    rp.A = A; rp.B = B; rp.C = C;
+    rp.lda = lda; rp.ldb = ldb; rp.ldc = ldc; rp.k = k;
+    rp.ta = ita; rp.tb = itb; rp.correct_policy = cfg ? cfg->correct_policy : 0;
+    rp.ab_type = ab_type; rp.c_type = FTG_F32;
+    rp.alpha = alpha; rp.beta = beta;
+    rp.scale_a = a.scale_a; rp.scale_b = a.scale_b;
+    return ftg::launch_repair(h->rep, rp, nullptr, s) == hipSuccess ? FTG_OK : FTG_ERR_HIP;
 }
 
 // ---------------------------------------------------------------- batched
 namespace {
 
 constexpr int kMaxGroups = 8;  // (tile 2 or 3) x 4 transpose pairs
-
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Bytes of the batched table for `count` problems: descriptors, first-tile
 // tables of up to kMaxGroups groups, repair table.
@@ -503,7 +667,7 @@ ftg_status ftg_dgemm_batched_uneven(ftg_handle h, int64_t count, const ftg_op* t
         rp.lda = lda[p]; rp.ldb = ldb[p]; rp.ldc = ldc[p]; rp.k = kk;
         rp.ta = a.ta; rp.tb = a.tb; rp.correct_policy = a.correct_policy;
         rp.ab_type = FTG_F64; rp.c_type = FTG_F64;
-        rp.alpha = alpha[p]; rp.beta = beta[p]; rp.scale = 1.0;
+        rp.alpha = alpha[p]; rp.beta = beta[p]; rp.scale_a = rp.scale_b = nullptr;
     }
     hfirst[nfirst++] = (int)total;
 

@@ -1,0 +1,530 @@
+// Low-precision (BF16 or FP8-e4m3 operands, FP32 accumulation) GEMM kernels for
+// gfx950 and the checksum machinery of the protected variant.
+//
+// The protected product C := alpha s_A s_B op(A) op(B) + beta C runs as:
+//   encode     one pass over A and B: for every output-tile panel the checksum
+//              row e^T A_I and column B_J e of the encoded operands (§2.1),
+//              kept as three bf16 pieces whose sum is the binary64 value to
+//              2^-24 relative, plus the magnitude sums of the threshold;
+//   checksum   the maintained checksums A_I (B_J e) and (e^T A_I) B_J of every
+//   products   tile as two thin MFMA GEMMs against those pieces (FP32
+//              accumulation, like the data path);
+//   main GEMM  v_mfma_f32_16x16x32_{bf16,fp8}, and in its epilogue the
+//              reference sums of the stored FP32 tile in binary64 (§5.2),
+//              compared with the expected sums; flagged tiles are queued for
+//              the repair kernel (locate, subtract, recompute; §5.1, §6.3).
+// On this chip the 16x16x32 bf16 MFMA retires 512 multiply-adds per cycle per
+// SIMD against 16 lanes of FP32 vector arithmetic, so summing the staged
+// panels inside the k loop (as the FP64 kernel does) would cost more than the
+// product itself; the encode is one memory-bound pass instead and the checksum
+// updates ride on the matrix cores.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <utility>
+
+#include "ftg_common.hpp"
+#include "ftg_lowp.hpp"
+
+namespace ftg {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+
+
+// OCP e4m3fn code -> bf16 bits (exact: 3 mantissa bits fit in 7, exponent
+// 2^-9 .. 2^8 fits in bf16's range).
+__host__ __device__ inline uint16_t e4m3_to_bf16(uint32_t q)
+{
+    const uint32_t s = (q & 0x80u) << 8, e = (q >> 3) & 0xFu, f = q & 7u;
+    if (e == 0xFu && f == 7u) return (uint16_t)(s | 0x7FC0u);  // NaN
+    if (e != 0) return (uint16_t)(s | ((e + 120u) << 7) | (f << 4));
+    if (f == 0) return (uint16_t)s;
+    // subnormal f * 2^-9: normalise
+    int sh = 0;
+    uint32_t mm = f;
+    while (!(mm & 4u)) { mm <<= 1; ++sh; }
+    return (uint16_t)(s | ((118u + 2u - (uint32_t)sh) << 7) | ((mm & 3u) << 5));
+}
+
+__host__ __device__ inline float bf16_bits_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
+
+// value of a stored element as binary32 (exact)
+template <typename ST>
+__device__ inline float st_to_f32(uint32_t raw)
+{
+    if constexpr (ST::bytes == 2) return bf16_bits_to_f32(raw);
+    else return bf16_bits_to_f32(e4m3_to_bf16(raw));
+}
+
+// binary32 -> bf16 bits, round to nearest even (finite inputs)
+__device__ inline uint16_t f32_to_bf16_rne(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// binary64 -> binary32 rounded towards +infinity (for magnitude bounds, x >= 0)
+__device__ inline float f64_to_f32_up(double x)
+{
+    float f = (float)x;
+    if ((double)f < x) f = __uint_as_float(__float_as_uint(f) + 1u);
+    return f;
+}
+
+// ---------------------------------------------------------------- GEMM
+template <typename STA, typename STB, bool F8MMA, bool TA, bool TB>
+struct LCfg {
+    static constexpr int BM = 128, BN = 128, BK = 64;
+    static constexpr int NT = 256, WGM = 2, WGN = 2;
+    static constexpr int WM = 64, WN = 64, FM = 4, FN = 4;
+    static constexpr int MB = F8MMA ? 1 : 2;              // bytes of an MFMA operand element
+    static constexpr int PITCH = BK * MB + 16;  // LDS row pitch in bytes (16-byte aligned rows)
+    static constexpr int A_BYTES = BM * PITCH, B_BYTES = BN * PITCH;
+    static constexpr int STAGE = A_BYTES + B_BYTES;
+    // operand staging: k-contiguous rows (A with TA=1, B with TB=0) or not
+    static constexpr bool AKC = TA, BKC = !TB;
+    static constexpr int VA = 16 / STA::bytes, VB = 16 / STB::bytes;  // elements per 16-byte load
+    static constexpr int NVA = BM * BK / VA / NT, NVB = BN * BK / VB / NT;
+    static_assert(NVA >= 1 && NVB >= 1, "staging split");
+};
+
+// Writes VEC stored elements (16 bytes in `v`) to the LDS tile of MFMA type,
+// either along k of one row (kc) or down VEC rows at one k.
+template <typename ST, bool F8MMA, int PITCH>
+__device__ __attribute__((always_inline)) inline void lds_put16(unsigned char* tile, int r, int p, bool kc,
+                                                                const u32x4_t v)
+{
+    constexpr int VEC = 16 / ST::bytes;
+    if constexpr (F8MMA || ST::bytes == 2) {
+        // MFMA type == storage type
+        constexpr int MBY = F8MMA ? 1 : 2;
+        if (kc) {
+            *(u32x4_t*)(tile + r * PITCH + p * MBY) = v;
+        } else {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                if constexpr (MBY == 2) {
+                    const uint16_t x = (uint16_t)(v[e / 2] >> (16 * (e % 2)));
+                    *(uint16_t*)(tile + (r + e) * PITCH + p * 2) = x;
+                } else {
+                    const uint8_t x = (uint8_t)(v[e / 4] >> (8 * (e % 4)));
+                    tile[(r + e) * PITCH + p] = x;
+                }
+            }
+        }
+    } else {
+        // fp8 storage staged as bf16
+        uint16_t h[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) h[e] = e4m3_to_bf16((v[e / 4] >> (8 * (e % 4))) & 0xFFu);
+        if (kc) {
+            u32x4_t w0, w1;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                w0[d] = (uint32_t)h[2 * d] | ((uint32_t)h[2 * d + 1] << 16);
+                w1[d] = (uint32_t)h[8 + 2 * d] | ((uint32_t)h[8 + 2 * d + 1] << 16);
+            }
+            *(u32x4_t*)(tile + r * PITCH + p * 2) = w0;
+            *(u32x4_t*)(tile + r * PITCH + p * 2 + 16) = w1;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) *(uint16_t*)(tile + (r + e) * PITCH + p * 2) = h[e];
+        }
+    }
+}
+
+// Verification bookkeeping (aliases the stage buffers after the k loop).
+struct LVerify {
+    double rsum[2][128], csum[2][128];
+    double cir[2][128], cira[2][128], cic[2][128], cica[2][128];
+    double dfi, tfi, dfj, tfj, exi, exj;
+    int nfr, nfc, fi, fj;
+};
+
+// MODE 0: C := alpha scale acc + beta C (FP32 C; also the checksum products);
+// MODE 1: the same, protected (injection, reference sums, flags, repair queue).
+template <typename STA, typename STB, bool F8MMA, bool TA, bool TB, int MODE>
+__global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
+{
+    using Cf = LCfg<STA, STB, F8MMA, TA, TB>;
+    constexpr int BM = Cf::BM, BN = Cf::BN, BK = Cf::BK, PITCH = Cf::PITCH;
+    constexpr int FM = Cf::FM, FN = Cf::FN, WM = Cf::WM, WN = Cf::WN;
+    static_assert(sizeof(LVerify) <= 2 * Cf::STAGE, "verify alias");
+
+    __shared__ __attribute__((aligned(16))) unsigned char smem[2 * Cf::STAGE];
+    __shared__ int flt[2][4];
+    __shared__ int fltn;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wr = wave / 2, wc = wave % 2;
+    const int wm0 = wr * WM, wn0 = wc * WN;
+    const int l16 = lane & 15, lq = lane >> 4;
+
+    int tm, tn;
+    tile_of_block(blockIdx.x, gridDim.x, args.tiles_m, args.tiles_n, 4, &tm, &tn);
+    const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+    const int R = (int)min((int64_t)BM, (int64_t)args.m - m0);
+    const int Q = (int)min((int64_t)BN, (int64_t)args.n - n0);
+    const int64_t K = args.k;
+    const int nkb = (int)((K + BK - 1) / BK);
+    const int64_t lda = args.lda, ldb = args.ldb;
+
+    const typename STA::T* A = (const typename STA::T*)args.A;
+    const typename STB::T* B = (const typename STB::T*)args.B;
+
+    // ---- staging map: thread t, vector q -> (row, k) of the operand tile
+    auto a_rp = [&](int q, int* r, int* p) __attribute__((always_inline)) {
+        const int v = tid + Cf::NT * q;
+        if (Cf::AKC) { *r = v / (BK / Cf::VA); *p = (v % (BK / Cf::VA)) * Cf::VA; }
+        else { *p = v / (BM / Cf::VA); *r = (v % (BM / Cf::VA)) * Cf::VA; }
+    };
+    auto b_rp = [&](int q, int* r, int* p) __attribute__((always_inline)) {
+        const int v = tid + Cf::NT * q;
+        if (Cf::BKC) { *r = v / (BK / Cf::VB); *p = (v % (BK / Cf::VB)) * Cf::VB; }
+        else { *p = v / (BN / Cf::VB); *r = (v % (BN / Cf::VB)) * Cf::VB; }
+    };
+    u32x4_t ra[Cf::NVA], rb[Cf::NVB];
+    const bool full_a = (R == BM) && args.vec_a;
+    const bool full_b = (Q == BN) && args.vec_b;
+
+    auto load_global = [&](int kb) __attribute__((always_inline)) {
+        const int64_t k0 = (int64_t)kb * BK;
+        const int kv = (int)min((int64_t)BK, K - k0);
+        const __amdgpu_buffer_rsrc_t rsa = make_rsrc(Cf::AKC ? A + k0 + m0 * lda : A + m0 + k0 * lda);
+        const __amdgpu_buffer_rsrc_t rsb = make_rsrc(Cf::BKC ? B + k0 + n0 * ldb : B + n0 + k0 * ldb);
+#pragma unroll
+        for (int q = 0; q < Cf::NVA; ++q) {
+            int r, p;
+            a_rp(q, &r, &p);
+            const int off = (int)((Cf::AKC ? p + (int64_t)r * lda : r + (int64_t)p * lda) * STA::bytes);
+            if (full_a && kv == BK) {
+                ra[q] = __builtin_amdgcn_raw_buffer_load_b128(rsa, off, 0, 0);
+            } else {
+                // element by element, zero outside the matrix
+                uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+                for (int e = 0; e < Cf::VA; ++e) {
+                    const int rr = Cf::AKC ? r : r + e, pp = Cf::AKC ? p + e : p;
+                    const bool ok = rr < R && pp < kv;
+                    const int eo = (int)((Cf::AKC ? pp + (int64_t)rr * lda : rr + (int64_t)pp * lda) * STA::bytes);
+                    uint32_t x;
+                    if constexpr (STA::bytes == 2) x = __builtin_amdgcn_raw_buffer_load_b16(rsa, ok ? eo : kOOB, 0, 0);
+                    else x = __builtin_amdgcn_raw_buffer_load_b8(rsa, ok ? eo : kOOB, 0, 0);
+                    w[(e * STA::bytes) / 4] |= x << (8 * ((e * STA::bytes) % 4));
+                }
+                ra[q] = (u32x4_t){w[0], w[1], w[2], w[3]};
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < Cf::NVB; ++q) {
+            int r, p;
+            b_rp(q, &r, &p);
+            const int off = (int)((Cf::BKC ? p + (int64_t)r * ldb : r + (int64_t)p * ldb) * STB::bytes);
+            if (full_b && kv == BK) {
+                rb[q] = __builtin_amdgcn_raw_buffer_load_b128(rsb, off, 0, 0);
+            } else {
+                uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+                for (int e = 0; e < Cf::VB; ++e) {
+                    const int rr = Cf::BKC ? r : r + e, pp = Cf::BKC ? p + e : p;
+                    const bool ok = rr < Q && pp < kv;
+                    const int eo = (int)((Cf::BKC ? pp + (int64_t)rr * ldb : rr + (int64_t)pp * ldb) * STB::bytes);
+                    uint32_t x;
+                    if constexpr (STB::bytes == 2) x = __builtin_amdgcn_raw_buffer_load_b16(rsb, ok ? eo : kOOB, 0, 0);
+                    else x = __builtin_amdgcn_raw_buffer_load_b8(rsb, ok ? eo : kOOB, 0, 0);
+                    w[(e * STB::bytes) / 4] |= x << (8 * ((e * STB::bytes) % 4));
+                }
+                rb[q] = (u32x4_t){w[0], w[1], w[2], w[3]};
+            }
+        }
+    };
+    auto store_lds = [&](int st) __attribute__((always_inline)) {
+        unsigned char* ta = smem + st * Cf::STAGE;
+        unsigned char* tb = ta + Cf::A_BYTES;
+#pragma unroll
+        for (int q = 0; q < Cf::NVA; ++q) {
+            int r, p;
+            a_rp(q, &r, &p);
+            lds_put16<STA, F8MMA, PITCH>(ta, r, p, Cf::AKC, ra[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < Cf::NVB; ++q) {
+            int r, p;
+            b_rp(q, &r, &p);
+            lds_put16<STB, F8MMA, PITCH>(tb, r, p, Cf::BKC, rb[q]);
+        }
+    };
+
+    f32x4_t acc[FM][FN];
+#pragma unroll
+    for (int g = 0; g < FM; ++g)
+#pragma unroll
+        for (int h = 0; h < FN; ++h) acc[g][h] = (f32x4_t){0.0f, 0.0f, 0.0f, 0.0f};
+
+    // one k-block: BK/32 rank-32 MFMA steps; fragment rows read 8 consecutive k
+    auto mfma_block = [&](int st) __attribute__((always_inline)) {
+        const unsigned char* ta = smem + st * Cf::STAGE;
+        const unsigned char* tb = ta + Cf::A_BYTES;
+#pragma unroll
+        for (int s = 0; s < BK / 32; ++s) {
+            const int kb_ = (32 * s + 8 * lq) * Cf::MB;
+            if constexpr (F8MMA) {
+                long a[FM], b[FN];
+#pragma unroll
+                for (int g = 0; g < FM; ++g) a[g] = *(const long*)(ta + (wm0 + 16 * g + l16) * PITCH + kb_);
+#pragma unroll
+                for (int h = 0; h < FN; ++h) b[h] = *(const long*)(tb + (wn0 + 16 * h + l16) * PITCH + kb_);
+#pragma unroll
+                for (int g = 0; g < FM; ++g)
+#pragma unroll
+                    for (int h = 0; h < FN; ++h)
+                        acc[g][h] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a[g], b[h], acc[g][h], 0, 0, 0);
+            } else {
+                bf16x8_t a[FM], b[FN];
+#pragma unroll
+                for (int g = 0; g < FM; ++g)
+                    a[g] = __builtin_bit_cast(bf16x8_t, *(const u32x4_t*)(ta + (wm0 + 16 * g + l16) * PITCH + kb_));
+#pragma unroll
+                for (int h = 0; h < FN; ++h)
+                    b[h] = __builtin_bit_cast(bf16x8_t, *(const u32x4_t*)(tb + (wn0 + 16 * h + l16) * PITCH + kb_));
+#pragma unroll
+                for (int g = 0; g < FM; ++g)
+#pragma unroll
+                    for (int h = 0; h < FN; ++h)
+                        acc[g][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[g], b[h], acc[g][h], 0, 0, 0);
+            }
+        }
+    };
+
+    // ---- injection plan of this tile (one slot per tile: the whole k loop)
+    const bool inj = MODE == 1 && args.inj.on;
+    if (inj) {
+        if (tid == 0) {
+            Fault f2[2];
+            const uint64_t tile_id = (uint64_t)tn * args.tiles_m + tm;
+            const int nf = slot_faults(args.inj, tile_id, R, Q, 0, K, f2);
+            fltn = nf;
+            for (int q = 0; q < 2; ++q) {
+                flt[q][0] = f2[q].row;
+                flt[q][1] = f2[q].col;
+                flt[q][2] = (int)f2[q].pflip;
+                flt[q][3] = f2[q].bit;
+            }
+        }
+        __syncthreads();
+    }
+    const int nflt = inj ? __builtin_amdgcn_readfirstlane(fltn) : 0;
+    const int fkb0 = nflt > 0 ? __builtin_amdgcn_readfirstlane(flt[0][2]) / BK : -1;
+    const int fkb1 = nflt > 1 ? __builtin_amdgcn_readfirstlane(flt[1][2]) / BK : -1;
+    auto apply_fault = [&](int q) __attribute__((always_inline)) {
+        const int row = __builtin_amdgcn_readfirstlane(flt[q][0]);
+        const int col = __builtin_amdgcn_readfirstlane(flt[q][1]);
+        const int bit = __builtin_amdgcn_readfirstlane(flt[q][3]);
+        const int pfl = __builtin_amdgcn_readfirstlane(flt[q][2]);
+        const bool ck = args.inj.target == FTG_TARGET_CHECKSUM;
+        if (ck) return;  // the checksum target is applied to the expected sum in the epilogue
+        const int rr = row % WM, cc = col % WN;
+        const bool own = (row / WM == wr) && (col / WN == wc) && lane == ((rr % 16) / 4) * 16 + (cc % 16);
+        const int idx = ((rr / 16) * FN + cc / 16) * 4 + (rr % 4);
+        float oldv = 0.0f, newv = 0.0f;
+#pragma unroll
+        for (int g = 0; g < FM; ++g)
+#pragma unroll
+            for (int h = 0; h < FN; ++h)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if ((g * FN + h) * 4 + r == idx) {
+                        oldv = acc[g][h][r];
+                        newv = flip_f32(oldv, bit);
+                        acc[g][h][r] = own ? newv : oldv;
+                    }
+        if (own)
+            push_inject(args.rep, args.problem, tm, tn, 0, m0 + row, n0 + col, pfl, bit, FTG_TARGET_ACC,
+                        (double)oldv, (double)newv);
+    };
+
+    // ---- k loop: stage kb+1 in registers while block kb multiplies from LDS
+    load_global(0);
+    store_lds(0);
+    __syncthreads();
+    for (int kb = 0; kb < nkb; ++kb) {
+        const int st = kb & 1;
+        if (kb + 1 < nkb) load_global(kb + 1);
+        mfma_block(st);
+        if (MODE == 1) {
+            if (kb == fkb0) apply_fault(0);
+            if (kb == fkb1) apply_fault(1);
+        }
+        if (kb + 1 < nkb) store_lds(st ^ 1);
+        __syncthreads();
+    }
+
+    // ---- epilogue.  Lane (lq, l16) of fragment (g, h) holds rows
+    // wm0 + 16g + 4lq + r and column wn0 + 16h + l16.
+    const int64_t ldc = args.ldc;
+    const float as = args.alpha * (args.scale_a ? *args.scale_a : 1.0f) * (args.scale_b ? *args.scale_b : 1.0f);
+    const bool cin = args.beta != 0.0f;
+    const __amdgpu_buffer_rsrc_t rc = make_rsrc(args.C + m0 + n0 * ldc);
+    const int c_voff = (int)((wm0 + 4 * lq + (int64_t)(wn0 + l16) * ldc) * 4);
+    const int c_hstep = (int)(16 * ldc * 4);
+    const bool full_mn = R == BM && Q == BN;
+    auto c_ok = [&](int g, int h, int r) __attribute__((always_inline)) {
+        return full_mn || ((wm0 + 16 * g + 4 * lq + r < R) && (wn0 + 16 * h + l16 < Q));
+    };
+    auto c_vo = [&](int g, int r, bool ok) __attribute__((always_inline)) {
+        return ok ? c_voff + (16 * g + r) * 4 : kOOB;
+    };
+    LVerify& V = *(LVerify*)smem;
+    double csc[FN], csa[FN];
+#pragma unroll
+    for (int h = 0; h < FN; ++h) csc[h] = csa[h] = 0.0;
+#pragma unroll
+    for (int g = 0; g < FM; ++g)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            double s = 0.0, sa = 0.0;
+#pragma unroll
+            for (int h = 0; h < FN; ++h) {
+                float c = 0.0f;
+                if (cin) c = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rc, c_vo(g, r, c_ok(g, h, r)), h * c_hstep, 0));
+                acc[g][h][r] = cin ? fmaf(as, acc[g][h][r], args.beta * c) : as * acc[g][h][r];
+                if (MODE == 1) {
+                    s += (double)c;
+                    sa += fabs((double)c);
+                    csc[h] += (double)c;
+                    csa[h] += fabs((double)c);
+                }
+            }
+            if (MODE == 1 && cin) {
+                s = group_sum<16>(s);
+                sa = group_sum<16>(sa);
+                if (l16 == 0) {
+                    V.cir[wc][wm0 + 16 * g + 4 * lq + r] = s;
+                    V.cira[wc][wm0 + 16 * g + 4 * lq + r] = sa;
+                }
+            }
+        }
+    if (MODE == 1) {
+        if (cin) {
+#pragma unroll
+            for (int h = 0; h < FN; ++h) {
+                const double s = quarter_sum(csc[h]), sa = quarter_sum(csa[h]);
+                if (lq == 0) { V.cic[wr][wn0 + 16 * h + l16] = s; V.cica[wr][wn0 + 16 * h + l16] = sa; }
+            }
+        }
+        // reference sums of the FP32 outputs in binary64 (§5.2)
+#pragma unroll
+        for (int g = 0; g < FM; ++g)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double s = 0.0;
+#pragma unroll
+                for (int h = 0; h < FN; ++h) s += (double)acc[g][h][r];
+                s = group_sum<16>(s);
+                if (l16 == 0) V.rsum[wc][wm0 + 16 * g + 4 * lq + r] = s;
+            }
+#pragma unroll
+        for (int h = 0; h < FN; ++h) {
+            double s = 0.0;
+#pragma unroll
+            for (int g = 0; g < FM; ++g)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) s += (double)acc[g][h][r];
+            s = quarter_sum(s);
+            if (lq == 0) V.csum[wr][wn0 + 16 * h + l16] = s;
+        }
+        if (tid == 0) { V.nfr = 0; V.nfc = 0; }
+        __syncthreads();
+        // expected sums: alpha s (maintained checksum) + beta (C_in sums); threshold
+        // from the magnitude bound (sum_p |a_ip|) max_p (sum_j |b_pj|) (and columns alike)
+        const double asd = (double)as, bd = (double)args.beta;
+        for (int line = tid; line < BM + BN; line += Cf::NT) {
+            const bool isrow = line < BM;
+            const int x = isrow ? line : line - BM;
+            if (x >= (isrow ? R : Q)) continue;
+            double ref, ex, mag;
+            if (isrow) {
+                ref = V.rsum[0][x] + V.rsum[1][x];
+                const float* er = args.ER + (m0 + x) + (int64_t)(3 * tn) * args.lder;
+                double e = (double)er[0] + (double)er[args.lder] + (double)er[2 * args.lder];
+                if (inj && args.inj.target == FTG_TARGET_CHECKSUM) {
+                    for (int q = 0; q < nflt; ++q)
+                        if (flt[q][0] == x) {
+                            const float o = er[0];
+                            const float nv = flip_f32(o, flt[q][3]);
+                            e += (double)nv - (double)o;
+                            push_inject(args.rep, args.problem, tm, tn, 0, m0 + x, -1, flt[q][2], flt[q][3],
+                                        FTG_TARGET_CHECKSUM, (double)o, (double)nv);
+                        }
+                }
+                ex = asd * e;
+                mag = fabs(asd) * (double)args.RA[m0 + x] * (double)args.MB[tn];
+                if (cin) { ex += bd * (V.cir[0][x] + V.cir[1][x]); mag += fabs(bd) * (V.cira[0][x] + V.cira[1][x]); }
+            } else {
+                ref = V.csum[0][x] + V.csum[1][x];
+                const float* ec = args.EC + (int64_t)(3 * tm) + (n0 + x) * args.ldec;
+                ex = asd * ((double)ec[0] + (double)ec[1] + (double)ec[2]);
+                mag = fabs(asd) * (double)args.CB[n0 + x] * (double)args.MA[tm];
+                if (cin) { ex += bd * (V.cic[0][x] + V.cic[1][x]); mag += fabs(bd) * (V.cica[0][x] + V.cica[1][x]); }
+            }
+            const double d = ref - ex;
+            const double tau = tau_of(1, args.lambda, (int64_t)(K + (isrow ? Q : R) + 8), mag);
+            if (flagged(d, tau)) {
+                if (isrow) {
+                    if (atomicAdd(&V.nfr, 1) == 0) { V.fi = x; V.dfi = d; V.tfi = tau; V.exi = ex; }
+                } else {
+                    if (atomicAdd(&V.nfc, 1) == 0) { V.fj = x; V.dfj = d; V.tfj = tau; V.exj = ex; }
+                }
+            }
+        }
+        __syncthreads();
+        const int nr = __builtin_amdgcn_readfirstlane(V.nfr);
+        const int nc = __builtin_amdgcn_readfirstlane(V.nfc);
+        if (nr != 0 || nc != 0) {
+            if (tid == 0) {
+                RepairReq q;
+                q.problem = args.problem; q.tm = tm; q.tn = tn; q.interval = 0;
+                q.nr = nr; q.nc = nc; q.fi = V.fi; q.fj = V.fj; q.R = R; q.Q = Q;
+                q.pad0 = q.pad1 = 0; q.m0 = m0; q.n0 = n0;
+                q.dfi = V.dfi; q.tfi = V.tfi; q.dfj = V.dfj; q.tfj = V.tfj;
+                q.exp_row = nr ? V.exi : 0.0;
+                q.exp_col = nc ? V.exj : 0.0;
+                q.cin = (cin && nr == 1 && nc == 1) ? (double)args.C[(m0 + V.fi) + (n0 + V.fj) * ldc] : 0.0;
+                push_repair(args.rep, q);
+            }
+            // C_in at the located element is read above before the tile is stored
+            __syncthreads();
+        }
+    }
+    // ---- store the tile
+#pragma unroll
+    for (int g = 0; g < FM; ++g)
+#pragma unroll
+        for (int h = 0; h < FN; ++h)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                // (by value: a bit cast of a vector element lvalue would read element 0)
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint((float)acc[g][h][r]), rc,
+                                                      c_vo(g, r, c_ok(g, h, r)), h * c_hstep, 0);
+}
+
+// grid: one workgroup per output tile; the four transpose cases
+template <typename STA, typename STB, bool F8MMA, int MODE>
+hipError_t launch_lowp_t(const LowpArgs& a, int ta, int tb, hipStream_t s)
+{
+    const dim3 grid(a.tiles_m * a.tiles_n), block(256);
+    if (!ta && !tb) hipLaunchKernelGGL((lowp_gemm_kernel<STA, STB, F8MMA, false, false, MODE>), grid, block, 0, s, a);
+    else if (ta && !tb) hipLaunchKernelGGL((lowp_gemm_kernel<STA, STB, F8MMA, true, false, MODE>), grid, block, 0, s, a);
+    else if (!ta && tb) hipLaunchKernelGGL((lowp_gemm_kernel<STA, STB, F8MMA, false, true, MODE>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((lowp_gemm_kernel<STA, STB, F8MMA, true, true, MODE>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace ftg

@@ -87,7 +87,8 @@ __global__ __launch_bounds__(256) void repair_kernel(DevReport* rep, RepairProbl
             };
             const double x = c_get(P, gi, gj);
             kind = 0;
-            if (P.correct_policy == 0 && isfinite(q.dfi) && isfinite(x)) {
+            if (P.correct_policy == 0 && isfinite(q.dfi) && isfinite(x) &&
+                !absorbed(P.c_type == FTG_F32, x, q.tfi, q.Q)) {
                 if (lane == 0) c_set(P, gi, gj, x - q.dfi);
                 __threadfence();
                 if (lines_ok()) kind = FTG_KIND_SUBTRACT;
@@ -96,7 +97,8 @@ __global__ __launch_bounds__(256) void repair_kernel(DevReport* rep, RepairProbl
                 double s = 0.0;
                 for (int64_t p = lane; p < P.k; p += 64) s = fma(opnd(P, true, gi, p), opnd(P, false, p, gj), s);
                 s = group_sum<64>(s);
-                double v = P.alpha * s * P.scale;
+                const double scale = (double)(P.scale_a ? *P.scale_a : 1.0f) * (double)(P.scale_b ? *P.scale_b : 1.0f);
+                double v = P.alpha * s * scale;
                 if (P.beta != 0.0) v += P.beta * q.cin;
                 if (lane == 0) c_set(P, gi, gj, v);
                 __threadfence();

@@ -297,3 +297,20 @@ def batch_problem(A, B, C, alpha=1.0, beta=0.0, ta=OP_N, tb=OP_N):
                 k=rows_a if ta else cols_a, alpha=alpha, beta=beta, A=A.data_ptr(),
                 lda=max(1, rows_a), B=B.data_ptr(), ldb=max(1, rows_b), C=C.data_ptr(),
                 ldc=max(1, C.shape[1]))
+
+
+def gemm_lowp(handle: Handle, A, B, C, alpha=1.0, beta=0.0, ta=OP_N, tb=OP_N, ab_type=BF16,
+              scale_a=None, scale_b=None, cfg=None, m=None, n=None, k=None):
+    """C (float32) := alpha s_A s_B op(A) op(B) + beta C on column-major device tensors:
+    A, B hold bf16 bit patterns (int16) or e4m3fn codes (uint8); scale_a/scale_b are
+    one-element float32 device tensors (FP8 only)."""
+    rows_a, cols_a = A.shape[1], A.shape[0]
+    rows_b, cols_b = B.shape[1], B.shape[0]
+    m = m if m is not None else (cols_a if ta else rows_a)
+    k = k if k is not None else (rows_a if ta else cols_a)
+    n = n if n is not None else (rows_b if tb else cols_b)
+    sa = ptr(scale_a) if scale_a is not None else None
+    sb = ptr(scale_b) if scale_b is not None else None
+    handle.gemm_ex(ta, tb, m, n, k, ab_type, F32, sa, sb, alpha, ptr(A), max(1, rows_a), ptr(B),
+                   max(1, rows_b), beta, ptr(C), max(1, C.shape[1]), current_stream_ptr(), cfg)
+    return C

@@ -355,3 +355,64 @@ def test_fault_plan_deterministic_distinct_capped():
     assert {(f.tile_m, f.tile_n, f.interval) for f in full} == {
         (a, b, c) for a in range(3) for b in range(3) for c in range(4)}
     assert oracle.fault_plan(seed=43, n_faults=20, **kw) != p1
+
+
+# ----------------------------------------------------------------------------- binary32 threshold
+def _single_fault_record(A, B, alpha, bm, bn, bit=62, lam=1.0):
+    """One exponent flip (always far above any threshold) in tile (0, 0); acc32 path."""
+    m, k = A.shape
+    n = B.shape[1]
+    plan = [oracle.Fault(0, 0, 0, 3, 5, k - 1, bit, oracle.TARGET_ACC)]
+    _, recs, cnt = oracle.abft(A, B, None, alpha, 0.0, bm=bm, bn=bn, plan=plan, acc32=True, lam=lam)
+    assert cnt["detected"] == 1 and len(recs) == 1
+    return recs[0], min(bm, m), min(bn, n)
+
+
+def test_acc32_threshold_equals_exact_magnitude_for_constant_panel_sums():
+    """With B all ones every step has the same panel sum Q, so the binary32 bound
+    (sum_p |a_ip|) max_p (sum_j |b_pj|) equals the exact magnitude
+    sum_p |a_ip| sum_j |b_pj| = Q sum_p |a_ip|: tau follows in closed form."""
+    rng = np.random.default_rng(41)
+    m, n, k = 40, 24, 33
+    A = np.asfortranarray(rng.uniform(-1, 1, size=(m, k)))
+    B = np.ones((k, n), order="F")
+    rec, R, Q = _single_fault_record(A, B, 1.5, 32, 16, bit=30, lam=2.0)
+    assert (rec.row, rec.col) == (3, 5)
+    mag = 1.5 * Q * np.abs(A[3, :]).sum()
+    want = 2.0 * 2.0 * math.sqrt(k + Q + 8) * 2.0 ** -24 * mag * (1 + 2.0 ** -20)
+    assert rec.tau == pytest.approx(want, rel=1e-12)
+
+
+def test_acc32_threshold_bounds_exact_magnitude():
+    """Hoelder: the binary32 bound is never below the exact magnitude of the row."""
+    rng = np.random.default_rng(42)
+    m, n, k = 50, 45, 70
+    A = np.asfortranarray(rng.standard_normal((m, k)))
+    B = np.asfortranarray(rng.standard_normal((k, n)) * np.linspace(0.1, 3, k)[:, None])
+    rec, R, Q = _single_fault_record(A, B, 1.0, 32, 32, bit=30)
+    exact = (np.abs(A[3, :]) * np.abs(B[:, :Q]).sum(axis=1)).sum()
+    tau_exact = 2.0 * math.sqrt(k + Q + 8) * 2.0 ** -24 * exact * (1 + 2.0 ** -20)
+    assert rec.tau >= tau_exact
+    # and it is the Hoelder bound itself
+    bound = np.abs(A[3, :]).sum() * np.abs(B[:, :Q]).sum(axis=1).max()
+    assert rec.tau == pytest.approx(tau_exact * bound / exact, rel=1e-12)
+
+
+def test_acc32_absorbing_flip_recomputed_small_flip_subtracted():
+    """Binary32 path: a flip that lifts the value far above its row's scale has
+    absorbed the true value, so the element is recomputed (and equals the
+    product); a flip of a low exponent bit keeps it and is subtracted.  Either
+    way the result matches numpy's product of the same operands."""
+    rng = np.random.default_rng(43)
+    m, n, k = 64, 48, 100
+    A = np.asfortranarray(rng.standard_normal((m, k)))
+    B = np.asfortranarray(rng.standard_normal((k, n)))
+    ref = A @ B
+    for bit, kind in [(29, oracle.KIND_RECOMPUTE), (24, oracle.KIND_SUBTRACT)]:
+        plan = [oracle.Fault(0, 0, 0, 7, 9, k - 1, bit, oracle.TARGET_ACC)]
+        x = float(np.float32(ref[7, 9]))
+        flipped = oracle.flip32(x, bit)
+        assert abs(flipped) > 1e3 * abs(x) if bit == 29 else abs(flipped) < 1e3 * abs(x) + 1
+        C, recs, cnt = oracle.abft(A, B, bm=64, bn=48, plan=plan, acc32=True, lam=4.0)
+        assert [(r.row, r.col, r.kind) for r in recs] == [(7, 9, kind)]
+        np.testing.assert_allclose(C, ref, rtol=0, atol=1e-9 * np.abs(A).sum(axis=1).max() * np.abs(B).max())

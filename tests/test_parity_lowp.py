@@ -1,0 +1,282 @@
+"""GPU parity of the BF16 / FP8-e4m3 protected GEMM (FP32 accumulation) against the
+CPU oracle, through the C ABI.
+
+Low-precision inputs enter the oracle as their exact binary64 values (bf16 and
+e4m3 values are exact in binary64; FP8 products carry the per-tensor scales in
+alpha).  Bars:
+  * integer-exact inputs (|x| <= 16, k max|ab| < 2^24): FP32 accumulation is exact,
+    so the GPU result equals the oracle bitwise;
+  * random inputs: componentwise |C - C_oracle| <= 2 k u32 M (M the magnitude
+    |alpha||op(A)||op(B)| + |beta||C|), the rigorous FP32 accumulation bound;
+  * seeded flips of FP32 accumulator exponent bits: every one located where the
+    oracle's plan puts it and corrected; the oracle's simulation of the same plan
+    (binary32 threshold with the same lambda) locates the same elements."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2104_00897_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+LAMBDA = 4.0   # the library default
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2104_00897_amd import ftgemm
+    assert torch.cuda.is_available()
+    h = ftgemm.Handle(capacity=8192)
+    yield ftgemm, h, torch
+    torch.cuda.synchronize()
+    h.close()
+
+
+def make_operands(kind, m, n, k, ta, tb, seed, integer=False):
+    """Host operands: stored codes (Fortran order, op layout) and their exact values;
+    for FP8 also the per-tensor scales."""
+    rng = np.random.default_rng(seed)
+    shp_a = (k, m) if ta else (m, k)
+    shp_b = (n, k) if tb else (k, n)
+    out = []
+    for shp in (shp_a, shp_b):
+        if integer:
+            x = np.asfortranarray(rng.integers(-16, 17, size=shp).astype(np.float32))
+        else:
+            x = inputs.normal_f32(rng, *shp)
+        if kind == "bf16":
+            bits = np.asfortranarray(inputs.to_bf16_bits(x))
+            out.append((bits, inputs.bf16_bits_to_f64(bits), np.float32(1.0)))
+        else:
+            if integer:
+                codes, s = inputs.to_e4m3_bits(x.astype(np.float64)), np.float32(1.0)
+            else:
+                codes, s = inputs.quantize_e4m3(x)
+            codes = np.asfortranarray(codes)
+            out.append((codes, inputs.e4m3_table()[codes], s))
+    C = np.asfortranarray(rng.standard_normal((m, n)).astype(np.float32)) if not integer else \
+        np.asfortranarray(rng.integers(-16, 17, size=(m, n)).astype(np.float32))
+    return out[0], out[1], C
+
+
+class Run:
+    def __init__(self, env, kind, m, n, k, ta, tb, seed, integer=False):
+        ftgemm, h, torch = env
+        self.env, self.kind = env, kind
+        (self.qa, self.va, self.sa), (self.qb, self.vb, self.sb), self.C = \
+            make_operands(kind, m, n, k, ta, tb, seed, integer)
+        view = np.int16 if kind == "bf16" else np.uint8
+        self.dA = ftgemm.to_device(self.qa.view(view))
+        self.dB = ftgemm.to_device(self.qb.view(view))
+        self.dsa = torch.tensor([self.sa], dtype=torch.float32, device="cuda")
+        self.dsb = torch.tensor([self.sb], dtype=torch.float32, device="cuda")
+        self.m, self.n, self.k, self.ta, self.tb = m, n, k, ta, tb
+        self.ab = ftgemm.BF16 if kind == "bf16" else ftgemm.F8_E4M3
+
+    def gpu(self, alpha, beta, cfg=None, nan_c=False):
+        ftgemm, h, torch = self.env
+        if nan_c:
+            dC = torch.full((self.n, self.m), float("nan"), dtype=torch.float32, device="cuda")
+        else:
+            dC = ftgemm.to_device(self.C)
+        h.reset()
+        ftgemm.gemm_lowp(h, self.dA, self.dB, dC, alpha, beta, self.ta, self.tb, self.ab,
+                         self.dsa if self.kind == "fp8" else None,
+                         self.dsb if self.kind == "fp8" else None, cfg)
+        torch.cuda.synchronize()
+        return ftgemm.to_host(dC).astype(np.float64), h.read()
+
+    def alpha_eff(self, alpha):
+        return float(np.float32(np.float32(alpha) * self.sa) * self.sb) if self.kind == "fp8" else alpha
+
+    def oracle(self, alpha, beta):
+        Cin = self.C.astype(np.float64) if beta != 0 else None
+        return oracle.gemm(self.va, self.vb, Cin, self.alpha_eff(alpha), beta, self.ta, self.tb)
+
+    def magnitude(self, alpha, beta):
+        a = np.abs(self.va.T if self.ta else self.va)
+        b = np.abs(self.vb.T if self.tb else self.vb)
+        M = abs(self.alpha_eff(alpha)) * (a @ b)
+        if beta != 0:
+            M = M + abs(beta) * np.abs(self.C.astype(np.float64))
+        return M
+
+
+def assert_close32(out, ref, M, k, skip=None):
+    bound = 2.0 * (k + 2) * U32 * M + 1e-30
+    bad = np.abs(out - ref) > bound
+    if skip is not None:
+        bad &= ~skip
+    if bad.any():
+        i, j = np.argwhere(bad)[0]
+        raise AssertionError(f"{bad.sum()} out of bound; ({i},{j}) gpu {out[i, j]} oracle {ref[i, j]} "
+                             f"bound {bound[i, j]:.3e}")
+
+
+@pytest.mark.parametrize("kind", ["bf16", "fp8"])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_integer_exact_bitwise(env, kind, ta, tb):
+    ftgemm = env[0]
+    r = Run(env, kind, 301, 283, 197, ta, tb, seed=3, integer=True)
+    for alpha, beta in [(1.0, 0.0), (1.0, 1.0), (-2.0, 0.5)]:
+        out, rep = r.gpu(alpha, beta, ftgemm.make_config(), nan_c=(beta == 0.0))
+        np.testing.assert_array_equal(out, r.oracle(alpha, beta))
+        assert rep.detected == 0, rep.records[:3]
+        out_u, _ = r.gpu(alpha, beta, ftgemm.make_config(abft=False), nan_c=(beta == 0.0))
+        np.testing.assert_array_equal(out_u, out)
+
+
+@pytest.mark.parametrize("kind", ["bf16", "fp8"])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1)])
+def test_random_within_fp32_bound_no_false_flags(env, kind, ta, tb):
+    ftgemm = env[0]
+    r = Run(env, kind, 260, 390, 1000, ta, tb, seed=4)
+    for alpha, beta in [(1.0, 0.0), (1.5, 0.5)]:
+        out, rep = r.gpu(alpha, beta, ftgemm.make_config())
+        assert_close32(out, r.oracle(alpha, beta), r.magnitude(alpha, beta), r.k)
+        assert rep.detected == 0, rep.records[:3]
+
+
+def plan_for(r, seed, F, bit_lo, bit_hi, target=oracle.TARGET_ACC):
+    return oracle.fault_plan(seed, F, r.m, r.n, r.k, 128, 128, kgran=128, bit_lo=bit_lo,
+                             bit_hi=bit_hi, target=target)
+
+
+def fault_taus(r, alpha, beta, log):
+    """Threshold of each injected element's row under the binary32 rule (A10
+    classifies a flip by |delta| against it): 2 lambda sqrt(k + Q + 8) u32 M_i with
+    M_i = |alpha| (sum_p |a_ip|) max_p (sum_{j in J} |b_pj|) + |beta| sum_{j in J} |c_ij|."""
+    a = np.abs(r.va.T if r.ta else r.va)
+    b = np.abs(r.vb.T if r.tb else r.vb)
+    out = []
+    for g in log:
+        i, j = g["row"], g["col"]
+        J = slice((j // 128) * 128, min(r.n, (j // 128) * 128 + 128))
+        Q = J.stop - J.start
+        mag = abs(r.alpha_eff(alpha)) * a[i, :].sum() * b[:, J].sum(axis=1).max()
+        if beta != 0:
+            mag += abs(beta) * np.abs(r.C[i, J].astype(np.float64)).sum()
+        out.append(oracle.tau(r.k + Q + 8, mag, acc32=True, lam=LAMBDA))
+    return out
+
+
+def check_flips(r, alpha, beta, out, rep, plan):
+    """A10: a flip whose error clears 4 tau is located where the plan put it and
+    corrected (and the oracle's simulation locates it too); a smaller one may stay
+    masked, its element then within the flip's own size of the oracle."""
+    got = sorted((g["row"], g["col"], g["pflip"], g["bit"]) for g in rep.inject_log)
+    assert got == sorted((f.tile_m * 128 + f.row, f.tile_n * 128 + f.col, f.pflip, f.bit) for f in plan)
+    taus = fault_taus(r, alpha, beta, rep.inject_log)
+    fixed = {(g["row"], g["col"]) for g in rep.records if g["kind"] in (1, 2)}
+    Cin = r.C.astype(np.float64) if beta else None
+    _, orecs, _ = oracle.abft(r.va, r.vb, Cin, r.alpha_eff(alpha), beta, r.ta, r.tb, bm=128, bn=128,
+                              plan=plan, acc32=True, lam=LAMBDA)
+    olocated = {(o.row, o.col) for o in orecs if o.kind in (1, 2)}
+    ref = r.oracle(alpha, beta)
+    skip = np.zeros(ref.shape, dtype=bool)
+    n_big = 0
+    for g, tau in zip(rep.inject_log, taus):
+        ij = (g["row"], g["col"])
+        d = abs(g["new_val"] - g["old_val"]) * abs(r.alpha_eff(alpha))
+        if not np.isfinite(d) or d >= 4 * tau:
+            n_big += 1
+            assert ij in fixed and ij in olocated, (g, tau)
+        elif ij not in fixed:
+            assert abs(out[ij] - ref[ij]) <= d * 1.01 + 2 * (r.k + 2) * U32 * abs(ref[ij]) + tau, (g, tau)
+            skip[ij] = True
+    assert_close32(out, ref, r.magnitude(alpha, beta), r.k, skip=skip)
+    return n_big
+
+
+@pytest.mark.parametrize("kind", ["bf16", "fp8"])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0)])
+def test_exponent_flips_located_and_corrected(env, kind, ta, tb):
+    ftgemm = env[0]
+    r = Run(env, kind, 530, 400, 700, ta, tb, seed=5)
+    F = 12
+    for alpha, beta in [(1.0, 0.0), (1.5, 0.5)]:
+        cfg = ftgemm.make_config(seed=31, n_faults=F, bit_lo=24, bit_hi=30)
+        out, rep = r.gpu(alpha, beta, cfg)
+        plan = plan_for(r, 31, F, 24, 30)
+        assert rep.injected == F and rep.uncorrectable == 0
+        assert check_flips(r, alpha, beta, out, rep, plan) >= F // 2
+
+
+def test_checksum_target_and_two_in_slot(env):
+    ftgemm = env[0]
+    r = Run(env, "bf16", 256, 256, 300, 0, 0, seed=6)
+    cfg = ftgemm.make_config(seed=3, n_faults=4, bit_lo=25, bit_hi=30, target=ftgemm.TARGET_CHECKSUM)
+    out, rep = r.gpu(1.0, 1.0, cfg)
+    assert rep.injected == 4 and rep.checksum_only == 4
+    assert all(g["kind"] == ftgemm.KIND_CHECKSUM_ONLY and g["col"] == -1 for g in rep.records)
+    assert_close32(out, r.oracle(1.0, 1.0), r.magnitude(1.0, 1.0), r.k)
+    cfg = ftgemm.make_config(seed=5, n_faults=2, bit_lo=26, bit_hi=30, target=ftgemm.TARGET_TWO_IN_SLOT)
+    out, rep = r.gpu(1.0, 0.0, cfg)
+    assert rep.injected == 4 and rep.uncorrectable == 2 and rep.status == ftgemm.ERR_UNCORRECTED
+
+
+def test_blas_cases_and_errors(env):
+    ftgemm, h, torch = env
+    r = Run(env, "bf16", 70, 50, 40, 0, 0, seed=7)
+    out, _ = r.gpu(0.0, 2.0)                      # alpha = 0: C := beta C
+    np.testing.assert_array_equal(out, 2.0 * r.C.astype(np.float64))
+    out, _ = r.gpu(1.0, 0.0, nan_c=True)           # beta = 0: C not read
+    assert np.isfinite(out).all()
+    d = torch.zeros(64, dtype=torch.int16, device="cuda")
+    c = torch.zeros(64, dtype=torch.float32, device="cuda")
+    p, pc = ftgemm.ptr(d), ftgemm.ptr(c)
+    with pytest.raises(ftgemm.FtgError) as e:
+        h.gemm_ex(0, 0, 4, 4, 4, ftgemm.F64, ftgemm.F32, None, None, 1.0, p, 4, p, 4, 0.0, pc, 4)
+    assert e.value.status == ftgemm.ERR_UNSUPPORTED
+    with pytest.raises(ftgemm.FtgError) as e:
+        h.gemm_ex(0, 0, 4, 4, 4, ftgemm.BF16, ftgemm.BF16, None, None, 1.0, p, 4, p, 4, 0.0, pc, 4)
+    assert e.value.status == ftgemm.ERR_UNSUPPORTED
+    with pytest.raises(ftgemm.FtgError) as e:
+        h.gemm_ex(0, 0, 4, 4, 4, ftgemm.F8_E4M3, ftgemm.F32, None, None, 1.0, p, 4, p, 4, 0.0, pc, 4)
+    assert e.value.info == 20
+    with pytest.raises(ftgemm.FtgError) as e:
+        h.gemm_ex(0, 0, 4, 4, 4, ftgemm.BF16, ftgemm.F32, None, None, 1.0, p, 3, p, 4, 0.0, pc, 4)
+    assert e.value.info == 8
+
+
+@pytest.mark.parametrize("kind", ["bf16", "fp8"])
+def test_cfg3_full_size_sampled(env, kind):
+    """8192^3, alpha = 1, beta = 0, N(0,1) (FP8: absmax-scaled e4m3), 16 flips of FP32
+    accumulator bits 13..30 in distinct tiles: sampled rows/columns and every faulted
+    element against the oracle; every flip whose error clears 4 tau is corrected and the
+    rest stay within their own size."""
+    ftgemm, h, torch = env
+    n = 8192
+    r = Run(env, kind, n, n, n, 0, 0, seed=0)
+    cfg = ftgemm.make_config(seed=7, n_faults=16, bit_lo=13, bit_hi=30)
+    out_dev = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    h.reset()
+    ftgemm.gemm_lowp(h, r.dA, r.dB, out_dev, 1.0, 0.0, 0, 0, r.ab,
+                     r.dsa if kind == "fp8" else None, r.dsb if kind == "fp8" else None, cfg)
+    torch.cuda.synchronize()
+    rep = h.read()
+    assert rep.injected == 16 and rep.uncorrectable == 0
+    fixed = {(g["row"], g["col"]) for g in rep.records if g["kind"] in (1, 2)}
+    rng = np.random.default_rng(1)
+    rows = list(rng.integers(0, n, 48)) + [g["row"] for g in rep.inject_log]
+    cols = list(rng.integers(0, n, 48)) + [g["col"] for g in rep.inject_log]
+    ae = r.alpha_eff(1.0)
+    ref = oracle.gemm_entries(r.va, r.vb, None, rows, cols, ae, 0.0)
+    # out_dev holds C column-major: element (i, j) at out_dev[j, i]
+    got = out_dev[torch.tensor(cols, device="cuda"), torch.tensor(rows, device="cuda")].double().cpu().numpy()
+    M = np.array([abs(ae) * np.dot(np.abs(r.va[i, :]), np.abs(r.vb[:, j])) for i, j in zip(rows, cols)])
+    bound = 2.0 * (n + 2) * U32 * M
+    ninj = len(rep.inject_log)
+    for x in range(len(rows)):
+        if x >= len(rows) - ninj:
+            g = rep.inject_log[x - (len(rows) - ninj)]
+            if (g["row"], g["col"]) not in fixed:
+                d = abs(g["new_val"] - g["old_val"]) * abs(ae)
+                assert abs(got[x] - ref[x]) <= d * 1.01 + bound[x], g
+                continue
+        assert abs(got[x] - ref[x]) <= bound[x], (x, rows[x], cols[x], got[x], ref[x])
+    # every large flip is corrected (4 tau rule); tau from the records of located faults
+    big = [g for g in rep.inject_log if abs(g["new_val"] - g["old_val"]) > 1e3]
+    assert all((g["row"], g["col"]) in fixed for g in big)
