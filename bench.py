@@ -39,6 +39,7 @@ def parse():
     p.add_argument("--sweep", action="store_true", help="also time the FP64 size sweep and rank-k shapes")
     p.add_argument("--tiles", action="store_true", help="time every FP64 tile configuration at --n")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--no-configs", action="store_true", help="skip the other workloads (cfg 1, 3, 4, 5)")
     return p.parse_args()
 
 
@@ -100,12 +101,141 @@ def measure(torch, ftgemm, h, m, n, k, alpha, beta, ta, tb, steps, warmup, tile,
     }, host
 
 
+def timed_ab(torch, fns, steps, warmup, rounds=2):
+    """Median ms per call of each function, alternating them round by round."""
+    out = {name: [] for name in fns}
+    for _ in range(rounds):
+        for name, fn in fns.items():
+            out[name].append(time_calls(torch, fn, steps, warmup))
+    return {name: float(np.median(v)) for name, v in out.items()}
+
+
+def cfg1_latency(torch, ftgemm, h, steps):
+    """256^3 FP64, alpha = 1, beta = 0, U[-1,1] seed 0, 4 flips in distinct slots
+    (128 x 128 tiles): microseconds per protected call (launch-latency bound)."""
+    from paper_2104_00897_amd import inputs
+    A, B, _ = inputs.gemm_operands_f64(256, 256, 256, seed=0, with_c=False)
+    dA, dB = ftgemm.to_device(A), ftgemm.to_device(B)
+    dC = torch.zeros((256, 256), dtype=torch.float64, device="cuda")
+    cp = ftgemm.make_config(tile=2, seed=0, n_faults=4)
+    cu = ftgemm.make_config(abft=False, tile=2)
+    t = timed_ab(torch, {"p": lambda: ftgemm.gemm_f64(h, dA, dB, dC, 1.0, 0.0, cfg=cp),
+                         "u": lambda: ftgemm.gemm_f64(h, dA, dB, dC, 1.0, 0.0, cfg=cu)}, steps * 10, 5)
+    return {"workload": "FP64 256^3 NN, 4 flips", "us_protected": 1e3 * t["p"], "us_unprotected": 1e3 * t["u"]}
+
+
+def lowp_operands(torch, kind, rows, cols, seed, std=1.0):
+    """Column-major (rows x cols) operand as a (cols x rows) device tensor: N(0, std^2)
+    rounded to bf16, or absmax-scaled e4m3fn codes with their per-tensor scale."""
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    x = torch.randn((cols, rows), generator=g, device="cuda", dtype=torch.float32) * std
+    if kind == "bf16":
+        return x.to(torch.bfloat16).view(torch.int16), None
+    s = x.abs().max() / 448.0
+    try:
+        q = (x / s).to(torch.float8_e4m3fn).view(torch.uint8)
+    except (RuntimeError, TypeError):
+        from paper_2104_00897_amd import inputs
+        q = torch.from_numpy(inputs.to_e4m3_bits((x / s).double().cpu().numpy())).cuda()
+    return q, s.reshape(1).float()
+
+
+def cfg3_lowp(torch, ftgemm, h, kind, steps, n=8192):
+    """8192^3 NN, alpha = 1, beta = 0, N(0,1) operands (bf16, or e4m3fn with absmax
+    scales), 16 flips of FP32 accumulator bits 13..30 per call."""
+    dA, sa = lowp_operands(torch, kind, n, n, 1)
+    dB, sb = lowp_operands(torch, kind, n, n, 2)
+    dC = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    ab = ftgemm.BF16 if kind == "bf16" else ftgemm.F8_E4M3
+    cfgs = {"p": ftgemm.make_config(seed=7, n_faults=16, bit_lo=13, bit_hi=30),
+            "u": ftgemm.make_config(abft=False), "p0": ftgemm.make_config()}
+    fns = {k: (lambda c=c: ftgemm.gemm_lowp(h, dA, dB, dC, 1.0, 0.0, 0, 0, ab, sa, sb, c))
+           for k, c in cfgs.items()}
+    h.reset()
+    t = timed_ab(torch, fns, steps, 2)
+    rep = h.read()
+    fl = 2.0 * n ** 3
+    peak = 2500.0 if kind == "bf16" else 5000.0
+    return {"workload": f"{kind} {n}^3 NN -> FP32, 16 flips/call", "ms_protected": t["p"],
+            "ms_unprotected": t["u"], "ms_protected_no_faults": t["p0"],
+            "tflops_protected": fl / t["p"] / 1e9, "tflops_unprotected": fl / t["u"] / 1e9,
+            "overhead_pct": 100.0 * (t["p"] / t["u"] - 1.0), "frac_of_peak_protected": fl / t["p"] / 1e9 / peak,
+            "faults": {"injected": rep.injected, "corrected": rep.corrected_subtract + rep.corrected_recompute,
+                       "detected": rep.detected, "uncorrectable": rep.uncorrectable}}
+
+
+def cfg4_ftlinear(torch, ftgemm, h, steps):
+    """One training step of FTLinear (bf16): tokens 8192, in 4096, out 4096; forward,
+    input and weight gradients; 16 flips (bits 24..30) in each backward GEMM."""
+    from paper_2104_00897_amd import ftlinear
+    T, din, dout = 8192, 4096, 4096
+    g = torch.Generator(device="cuda").manual_seed(0)
+    X = (torch.randn((T, din), generator=g, device="cuda") * 0.02).to(torch.bfloat16).requires_grad_(True)
+    W = (torch.randn((dout, din), generator=g, device="cuda") * 0.02).to(torch.bfloat16).requires_grad_(True)
+    G = torch.randn((T, dout), generator=g, device="cuda").to(torch.bfloat16)
+    cb = ftgemm.make_config(seed=4, n_faults=16, bit_lo=24, bit_hi=30)
+    cu = ftgemm.make_config(abft=False)
+
+    def step(cf, cbw):
+        X.grad = None
+        W.grad = None
+        ftlinear.ft_linear(X, W, h, cf, cbw).backward(G)
+
+    h.reset()
+    t = timed_ab(torch, {"p": lambda: step(None, cb), "u": lambda: step(cu, cu)}, steps, 2)
+    rep = h.read()
+    fl = 3 * 2.0 * T * din * dout
+    return {"workload": "FTLinear bf16 step, tokens 8192, 4096 -> 4096, 16 flips per backward GEMM",
+            "ms_protected": t["p"], "ms_unprotected": t["u"], "tflops_protected": fl / t["p"] / 1e9,
+            "tflops_unprotected": fl / t["u"] / 1e9, "overhead_pct": 100.0 * (t["p"] / t["u"] - 1.0),
+            "faults": {"injected": rep.injected, "corrected": rep.corrected_subtract + rep.corrected_recompute,
+                       "uncorrectable": rep.uncorrectable}}
+
+
+def cfg5_batched(torch, ftgemm, h, steps):
+    """512 FP64 problems, m, n, k log-uniform in [32, 2048] (seed 7), alpha = 1,
+    beta = 0, U[-1,1] operands, 0-2 flips per problem (U{0,1,2}, seed 7), one
+    persistent launch; eager and hipGraph-replayed."""
+    from paper_2104_00897_amd import inputs
+    sizes = inputs.log_uniform_sizes(512, 32, 2048, 7)
+    faults = np.random.default_rng(7).integers(0, 3, size=len(sizes))
+    g = torch.Generator(device="cuda").manual_seed(7)
+    keep, probs = [], []
+    for m, n, k in sizes:
+        A = torch.rand((k, m), generator=g, device="cuda", dtype=torch.float64) * 2 - 1
+        B = torch.rand((n, k), generator=g, device="cuda", dtype=torch.float64) * 2 - 1
+        C = torch.zeros((n, m), device="cuda", dtype=torch.float64)
+        keep.append((A, B, C))
+        probs.append(ftgemm.batch_problem(A, B, C, 1.0, 0.0))
+    plan = ftgemm.BatchPlan(probs)
+    cp = ftgemm.make_config(tile=3, seed=7, n_faults=1)
+    cu = ftgemm.make_config(abft=False, tile=3)
+    stream = ftgemm.current_stream_ptr
+    fl = float(sum(2.0 * m * n * k for m, n, k in sizes))
+    h.reset()
+    t = timed_ab(torch, {"p": lambda: h.dgemm_batched(plan, stream(), cp, faults),
+                         "u": lambda: h.dgemm_batched(plan, stream(), cu)}, steps, 2)
+    rep = h.read()
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr):
+        h.dgemm_batched(plan, stream(), cp, faults)
+    tg = time_calls(torch, gr.replay, steps, 2)
+    torch.cuda.synchronize()
+    del gr
+    return {"workload": "512 FP64 problems, m,n,k log-uniform [32, 2048], seed 7, 0-2 flips each",
+            "gflop": fl / 1e9, "ms_protected": t["p"], "ms_unprotected": t["u"], "ms_protected_graph": tg,
+            "tflops_protected": fl / t["p"] / 1e9, "tflops_unprotected": fl / t["u"] / 1e9,
+            "overhead_pct": 100.0 * (t["p"] / t["u"] - 1.0),
+            "faults": {"injected": rep.injected, "corrected": rep.corrected_subtract + rep.corrected_recompute,
+                       "uncorrectable": rep.uncorrectable}}
+
+
 def cpu_baseline(host, k):
     """The oracle's ABFT procedure (single thread) on a bounded sample: the
-    leading 256 x 256 block of C with the full k of the workload."""
+    leading 1536 x 1536 block of C with the full k of the workload."""
     import oracle
     A, B, C = host
-    ms = ns = 256
+    ms = ns = 1536
     As = np.asfortranarray(A[:ms, :])
     Bs = np.asfortranarray(B[:, :ns])
     Cs = np.asfortranarray(C[:ms, :ns])
@@ -157,7 +287,7 @@ def main():
                      "traffic": None},
     }
     if args.tiles:
-        for t in (1, 2, 3, 4):
+        for t in (1, 2, 3, 4, 5):
             r, _ = measure(torch, ftgemm, h, n, n, n, 1.5, 0.5, 0, 0, max(3, args.steps // 2), 1, t)
             print(json.dumps({"tile_sweep": r}), file=sys.stderr, flush=True)
     if args.sweep:
@@ -172,6 +302,16 @@ def main():
                 sweep.append(r)
                 print(json.dumps({"sweep": r}), file=sys.stderr, flush=True)
         line["sweep"] = sweep
+    if not args.no_configs:
+        cf = {}
+        for name, fn in [("cfg1", lambda: cfg1_latency(torch, ftgemm, h, args.steps)),
+                         ("cfg3_bf16", lambda: cfg3_lowp(torch, ftgemm, h, "bf16", args.steps)),
+                         ("cfg3_fp8", lambda: cfg3_lowp(torch, ftgemm, h, "fp8", args.steps)),
+                         ("cfg4", lambda: cfg4_ftlinear(torch, ftgemm, h, max(2, args.steps // 2))),
+                         ("cfg5", lambda: cfg5_batched(torch, ftgemm, h, args.steps))]:
+            cf[name] = fn()
+            print(json.dumps({name: cf[name]}), file=sys.stderr, flush=True)
+        line["configs"] = cf
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(host, n)
     print(json.dumps(line), flush=True)

@@ -36,6 +36,11 @@ def _compile(src: str) -> str:
 def build(jobs: int | None = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
+    # objects whose source is gone must not reach the link
+    live = {s[:-4] + ".o" for s in srcs}
+    for f in os.listdir(BUILD):
+        if f.endswith(".o") and f not in live:
+            os.remove(os.path.join(BUILD, f))
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, srcs))

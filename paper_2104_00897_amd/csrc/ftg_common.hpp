@@ -185,13 +185,41 @@ __device__ inline void buf_store_f64(double x, __amdgpu_buffer_rsrc_t r, int vof
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, voff, soff, 0);
 }
 
+// A binary64 value moved between lanes of a 16-lane row by a DPP control
+// (data-parallel primitive: an operand modifier of the vector ALU, no LDS
+// traffic), applied to both 32-bit halves.
+template <int CTRL>
+__device__ inline double dpp_f64(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over each row of 16 lanes; every lane ends with its row's sum (the same
+// value in every lane: each step adds the same two partial sums).
+__device__ inline double row_sum16(double v)
+{
+    v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]: lane pairs
+    v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]: quads
+    v += dpp_f64<0x141>(v);  // row_half_mirror: half rows of 8
+    v += dpp_f64<0x140>(v);  // row_mirror: rows of 16
+    return v;
+}
+
 // Sum over aligned groups of `width` lanes (width a power of two <= 64);
 // every lane of a group ends with the group's sum.
 template <int WIDTH>
 __device__ inline double group_sum(double v)
 {
+    if constexpr (WIDTH >= 16) {
+        v = row_sum16(v);
 #pragma unroll
-    for (int off = WIDTH / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        for (int off = 16; off < WIDTH; off <<= 1) v += __shfl_xor(v, off);
+    } else {
+#pragma unroll
+        for (int off = WIDTH / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    }
     return v;
 }
 

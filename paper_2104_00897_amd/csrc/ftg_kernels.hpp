@@ -35,10 +35,17 @@ struct BatchLaunch {
 };
 
 // FP64 tile configurations (k-block 16): 1 = 256x128 on 4 waves, 2 = 128x128,
-// 3 = 64x64, 4 = 256x128 on 8 waves.
-// Verification intervals shorter than k need tile 2 or 3.
+// 3 = 64x64, 4 = 256x128 on 8 waves, 5 = 128x128 on 8 waves.
+// Verification intervals shorter than k need tile 2, 3 or 5.
 template <int BM, int BN, int WGM, int WGN, bool IVL_OK, int MINB>
 hipError_t launch_tile(const DGemmArgs& a, bool abft, hipStream_t s);
+// each configuration is instantiated in its own translation unit (dgemm_t*.hip,
+// dgemm_b*.hip); no other unit instantiates the kernel templates
+extern template hipError_t launch_tile<256, 128, 2, 2, false, 1>(const DGemmArgs&, bool, hipStream_t);
+extern template hipError_t launch_tile<128, 128, 2, 2, true, 2>(const DGemmArgs&, bool, hipStream_t);
+extern template hipError_t launch_tile<64, 64, 2, 2, true, 2>(const DGemmArgs&, bool, hipStream_t);
+extern template hipError_t launch_tile<256, 128, 4, 2, false, 1>(const DGemmArgs&, bool, hipStream_t);
+extern template hipError_t launch_tile<128, 128, 4, 2, true, 1>(const DGemmArgs&, bool, hipStream_t);
 
 inline hipError_t launch_dgemm(const DGemmArgs& a, int tile_id, bool abft, hipStream_t s)
 {
@@ -47,11 +54,16 @@ inline hipError_t launch_dgemm(const DGemmArgs& a, int tile_id, bool abft, hipSt
     case 2: return launch_tile<128, 128, 2, 2, true, 2>(a, abft, s);
     case 3: return launch_tile<64, 64, 2, 2, true, 2>(a, abft, s);
     case 4: return launch_tile<256, 128, 4, 2, false, 1>(a, abft, s);
+    case 5: return launch_tile<128, 128, 4, 2, true, 1>(a, abft, s);
     default: return hipErrorInvalidValue;
     }
 }
 template <int BM, int BN, int WGM, int WGN, bool IVL_OK, int MINB>
 hipError_t launch_batched(const BatchLaunch& L, int ta, int tb, bool abft, bool ivl, hipStream_t s);
+extern template hipError_t launch_batched<128, 128, 2, 2, true, 2>(const BatchLaunch&, int, int, bool, bool,
+                                                                   hipStream_t);
+extern template hipError_t launch_batched<64, 64, 2, 2, true, 2>(const BatchLaunch&, int, int, bool, bool,
+                                                                 hipStream_t);
 
 // Batched launches exist for the configurations with verification intervals.
 inline hipError_t launch_dgemm_batched(const BatchLaunch& L, int tile_id, int ta, int tb, bool abft,
@@ -63,7 +75,7 @@ inline hipError_t launch_dgemm_batched(const BatchLaunch& L, int tile_id, int ta
     default: return hipErrorInvalidValue;
     }
 }
-inline bool dgemm_tile_intervals(int id) { return id == 2 || id == 3; }
+inline bool dgemm_tile_intervals(int id) { return id == 2 || id == 3 || id == 5; }
 hipError_t launch_dscale(double* C, int64_t m, int64_t n, int64_t ldc, double beta, hipStream_t s);
 
 inline void dgemm_tile_shape(int id, int* bm, int* bn, int* bk)
@@ -74,6 +86,7 @@ inline void dgemm_tile_shape(int id, int* bm, int* bn, int* bk)
     case 2: *bm = 128; *bn = 128; break;
     case 3: *bm = 64; *bn = 64; break;
     case 4: *bm = 256; *bn = 128; break;
+    case 5: *bm = 128; *bn = 128; break;
     default: *bm = *bn = *bk = 0;
     }
 }

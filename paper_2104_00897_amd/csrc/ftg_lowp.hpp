@@ -54,6 +54,7 @@ struct EncOperand {
     const void* X;
     int64_t ld;
     int rows, K, kcontig;
+    int vec;             // 16-byte loads allowed (base and ld aligned)
     int panels, chunks;  // panel = output-tile extent; chunk = kLowpChunk steps
     uint16_t* XS;        // bf16 pieces: XS[(3 panel + s) K + p]
     float* XRp;          // partial |x| row sums: XRp[chunk rows + r]

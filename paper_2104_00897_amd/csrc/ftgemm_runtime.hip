@@ -451,12 +451,12 @@ ftg_status ftg_gemm_ex(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n,
     ftg::EncArgs e;
     std::memset(&e, 0, sizeof(e));
     ftg::EncOperand& ea = e.op[0];
-    ea.X = A; ea.ld = lda; ea.rows = (int)m; ea.K = (int)k; ea.kcontig = ita;
+    ea.X = A; ea.ld = lda; ea.rows = (int)m; ea.K = (int)k; ea.kcontig = ita; ea.vec = a.vec_a;
     ea.panels = a.tiles_m; ea.chunks = chunks;
     ea.XS = (uint16_t*)(w + L.xs_a); ea.XRp = (float*)(w + L.xrp_a); ea.XMp = (float*)(w + L.xmp_a);
     ea.XR = (float*)(w + L.ra); ea.XM = (float*)(w + L.ma);
     ftg::EncOperand& eb_ = e.op[1];
-    eb_.X = B; eb_.ld = ldb; eb_.rows = (int)n; eb_.K = (int)k; eb_.kcontig = !itb;
+    eb_.X = B; eb_.ld = ldb; eb_.rows = (int)n; eb_.K = (int)k; eb_.kcontig = !itb; eb_.vec = a.vec_b;
     eb_.panels = a.tiles_n; eb_.chunks = chunks;
     eb_.XS = (uint16_t*)(w + L.xs_b); eb_.XRp = (float*)(w + L.xrp_b); eb_.XMp = (float*)(w + L.xmp_b);
     eb_.XR = (float*)(w + L.cb); eb_.XM = (float*)(w + L.mb);

@@ -88,9 +88,14 @@ struct LCfg {
     static constexpr int STAGE = A_BYTES + B_BYTES;
     // operand staging: k-contiguous rows (A with TA=1, B with TB=0) or not
     static constexpr bool AKC = TA, BKC = !TB;
-    static constexpr int VA = 16 / STA::bytes, VB = 16 / STB::bytes;  // elements per 16-byte load
-    static constexpr int NVA = BM * BK / VA / NT, NVB = BN * BK / VB / NT;
+    // k-contiguous: 16-byte loads along k; otherwise each thread stages an
+    // 8-row x 4-step block (four loads of 8 consecutive rows) and transposes it
+    // in registers, so that every LDS row is written with one 4-step store
+    static constexpr int VA = AKC ? 16 / STA::bytes : 8, VB = BKC ? 16 / STB::bytes : 8;
+    static constexpr int NVA = AKC ? BM * BK / VA / NT : 4, NVB = BKC ? BN * BK / VB / NT : 4;
     static_assert(NVA >= 1 && NVB >= 1, "staging split");
+    static_assert(AKC || (BM / 8) * (BK / 4) == NT, "column staging map");
+    static_assert(BKC || (BN / 8) * (BK / 4) == NT, "column staging map");
 };
 
 // Writes VEC stored elements (16 bytes in `v`) to the LDS tile of MFMA type,
@@ -134,6 +139,36 @@ __device__ __attribute__((always_inline)) inline void lds_put16(unsigned char* t
         } else {
 #pragma unroll
             for (int e = 0; e < 16; ++e) *(uint16_t*)(tile + (r + e) * PITCH + p * 2) = h[e];
+        }
+    }
+}
+
+// Writes an 8-row x 4-step block (v[q]: rows r0..r0+7 at step p0+q, storage
+// type) into the k-contiguous LDS tile: one 4-step store per row.
+template <typename ST, bool F8MMA, int PITCH>
+__device__ __attribute__((always_inline)) inline void lds_put_cols(unsigned char* tile, int r0, int p0,
+                                                                   const u32x4_t* v)
+{
+    auto elem = [&](int q, int e) __attribute__((always_inline)) -> uint32_t {
+        if constexpr (ST::bytes == 2) return (v[q][e / 2] >> (16 * (e % 2))) & 0xFFFFu;
+        else return (v[q][e / 4] >> (8 * (e % 4))) & 0xFFu;
+    };
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        if constexpr (F8MMA) {
+            const uint32_t w = elem(0, e) | (elem(1, e) << 8) | (elem(2, e) << 16) | (elem(3, e) << 24);
+            *(uint32_t*)(tile + (r0 + e) * PITCH + p0) = w;
+        } else {
+            uint32_t hq[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if constexpr (ST::bytes == 2) hq[q] = elem(q, e);
+                else hq[q] = e4m3_to_bf16(elem(q, e));
+            }
+            u32x2 w;
+            w[0] = hq[0] | (hq[1] << 16);
+            w[1] = hq[2] | (hq[3] << 16);
+            *(u32x2*)(tile + (r0 + e) * PITCH + p0 * 2) = w;
         }
     }
 }
@@ -183,12 +218,12 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
     auto a_rp = [&](int q, int* r, int* p) __attribute__((always_inline)) {
         const int v = tid + Cf::NT * q;
         if (Cf::AKC) { *r = v / (BK / Cf::VA); *p = (v % (BK / Cf::VA)) * Cf::VA; }
-        else { *p = v / (BM / Cf::VA); *r = (v % (BM / Cf::VA)) * Cf::VA; }
+        else { *r = (tid % (BM / 8)) * 8; *p = (tid / (BM / 8)) * 4 + q; }
     };
     auto b_rp = [&](int q, int* r, int* p) __attribute__((always_inline)) {
         const int v = tid + Cf::NT * q;
         if (Cf::BKC) { *r = v / (BK / Cf::VB); *p = (v % (BK / Cf::VB)) * Cf::VB; }
-        else { *p = v / (BN / Cf::VB); *r = (v % (BN / Cf::VB)) * Cf::VB; }
+        else { *r = (tid % (BN / 8)) * 8; *p = (tid / (BN / 8)) * 4 + q; }
     };
     u32x4_t ra[Cf::NVA], rb[Cf::NVB];
     const bool full_a = (R == BM) && args.vec_a;
@@ -205,7 +240,12 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
             a_rp(q, &r, &p);
             const int off = (int)((Cf::AKC ? p + (int64_t)r * lda : r + (int64_t)p * lda) * STA::bytes);
             if (full_a && kv == BK) {
-                ra[q] = __builtin_amdgcn_raw_buffer_load_b128(rsa, off, 0, 0);
+                if (Cf::AKC || STA::bytes == 2) {
+                    ra[q] = __builtin_amdgcn_raw_buffer_load_b128(rsa, off, 0, 0);
+                } else {
+                    const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(rsa, off, 0, 0);
+                    ra[q] = (u32x4_t){w[0], w[1], 0u, 0u};
+                }
             } else {
                 // element by element, zero outside the matrix
                 uint32_t w[4] = {0u, 0u, 0u, 0u};
@@ -228,7 +268,12 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
             b_rp(q, &r, &p);
             const int off = (int)((Cf::BKC ? p + (int64_t)r * ldb : r + (int64_t)p * ldb) * STB::bytes);
             if (full_b && kv == BK) {
-                rb[q] = __builtin_amdgcn_raw_buffer_load_b128(rsb, off, 0, 0);
+                if (Cf::BKC || STB::bytes == 2) {
+                    rb[q] = __builtin_amdgcn_raw_buffer_load_b128(rsb, off, 0, 0);
+                } else {
+                    const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(rsb, off, 0, 0);
+                    rb[q] = (u32x4_t){w[0], w[1], 0u, 0u};
+                }
             } else {
                 uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
@@ -248,17 +293,29 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
     auto store_lds = [&](int st) __attribute__((always_inline)) {
         unsigned char* ta = smem + st * Cf::STAGE;
         unsigned char* tb = ta + Cf::A_BYTES;
+        if constexpr (Cf::AKC) {
 #pragma unroll
-        for (int q = 0; q < Cf::NVA; ++q) {
+            for (int q = 0; q < Cf::NVA; ++q) {
+                int r, p;
+                a_rp(q, &r, &p);
+                lds_put16<STA, F8MMA, PITCH>(ta, r, p, true, ra[q]);
+            }
+        } else {
             int r, p;
-            a_rp(q, &r, &p);
-            lds_put16<STA, F8MMA, PITCH>(ta, r, p, Cf::AKC, ra[q]);
+            a_rp(0, &r, &p);
+            lds_put_cols<STA, F8MMA, PITCH>(ta, r, p, ra);
         }
+        if constexpr (Cf::BKC) {
 #pragma unroll
-        for (int q = 0; q < Cf::NVB; ++q) {
+            for (int q = 0; q < Cf::NVB; ++q) {
+                int r, p;
+                b_rp(q, &r, &p);
+                lds_put16<STB, F8MMA, PITCH>(tb, r, p, true, rb[q]);
+            }
+        } else {
             int r, p;
-            b_rp(q, &r, &p);
-            lds_put16<STB, F8MMA, PITCH>(tb, r, p, Cf::BKC, rb[q]);
+            b_rp(0, &r, &p);
+            lds_put_cols<STB, F8MMA, PITCH>(tb, r, p, rb);
         }
     };
 

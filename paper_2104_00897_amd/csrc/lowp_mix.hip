@@ -10,7 +10,7 @@ template hipError_t launch_lowp_t<StBF16, StFP8, false, 0>(const LowpArgs&, int,
 
 // ---------------------------------------------------------------- encode
 template <typename ST>
-__global__ __launch_bounds__(256) void lowp_encode_kernel(EncArgs args)
+__global__ __launch_bounds__(256, 4) void lowp_encode_kernel(EncArgs args)
 {
     const EncOperand& E = args.op[blockIdx.y];
     const int pi = blockIdx.x / E.chunks, c = blockIdx.x % E.chunks;
@@ -20,14 +20,38 @@ __global__ __launch_bounds__(256) void lowp_encode_kernel(EncArgs args)
     const int tid = threadIdx.x;
     const int64_t r0 = (int64_t)pi * kLowpTile, p0 = (int64_t)c * kLowpChunk;
     const typename ST::T* X = (const typename ST::T*)E.X;
-    for (int q = tid; q < kLowpTile * kLowpChunk; q += 256) {
-        int r, p;
-        if (E.kcontig) { r = q / kLowpChunk; p = q % kLowpChunk; }
-        else { r = q % kLowpTile; p = q / kLowpTile; }
-        const int64_t gr = r0 + r, gp = p0 + p;
-        float v = 0.0f;
-        if (gr < E.rows && gp < E.K) v = st_to_f32<ST>(X[E.kcontig ? gp + gr * E.ld : gr + gp * E.ld]);
-        t[r][p] = v;
+    constexpr int V = 16 / ST::bytes;  // elements per 16-byte load
+    if (E.vec && r0 + kLowpTile <= E.rows && p0 + kLowpChunk <= E.K) {
+        // interior block: 16-byte loads along the contiguous dimension
+        if (E.kcontig) {
+            for (int q = tid; q < kLowpTile * (kLowpChunk / V); q += 256) {
+                const int r = q / (kLowpChunk / V), pv = (q % (kLowpChunk / V)) * V;
+                const u32x4_t w = *(const u32x4_t*)(X + (p0 + pv) + (r0 + r) * E.ld);
+#pragma unroll
+                for (int e = 0; e < V; ++e)
+                    t[r][pv + e] = st_to_f32<ST>((w[(e * ST::bytes) / 4] >> (8 * ((e * ST::bytes) % 4))) &
+                                                 (ST::bytes == 2 ? 0xFFFFu : 0xFFu));
+            }
+        } else {
+            for (int q = tid; q < kLowpChunk * (kLowpTile / V); q += 256) {
+                const int p = q / (kLowpTile / V), rv = (q % (kLowpTile / V)) * V;
+                const u32x4_t w = *(const u32x4_t*)(X + (r0 + rv) + (p0 + p) * E.ld);
+#pragma unroll
+                for (int e = 0; e < V; ++e)
+                    t[rv + e][p] = st_to_f32<ST>((w[(e * ST::bytes) / 4] >> (8 * ((e * ST::bytes) % 4))) &
+                                                 (ST::bytes == 2 ? 0xFFFFu : 0xFFu));
+            }
+        }
+    } else {
+        for (int q = tid; q < kLowpTile * kLowpChunk; q += 256) {
+            int r, p;
+            if (E.kcontig) { r = q / kLowpChunk; p = q % kLowpChunk; }
+            else { r = q % kLowpTile; p = q / kLowpTile; }
+            const int64_t gr = r0 + r, gp = p0 + p;
+            float v = 0.0f;
+            if (gr < E.rows && gp < E.K) v = st_to_f32<ST>(X[E.kcontig ? gp + gr * E.ld : gr + gp * E.ld]);
+            t[r][p] = v;
+        }
     }
     __syncthreads();
     if (tid < kLowpTile) {

@@ -49,4 +49,5 @@ def test_status_strings_and_tile_table():
     assert ftgemm.tile_info(ftgemm.F64, 2) == (128, 128, 16)
     assert ftgemm.tile_info(ftgemm.F64, 3) == (64, 64, 16)
     assert ftgemm.tile_info(ftgemm.F64, 4) == (256, 128, 16)
+    assert ftgemm.tile_info(ftgemm.F64, 5) == (128, 128, 16)
     assert ftgemm.tile_info(ftgemm.F64, 9) is None

@@ -16,7 +16,7 @@ from tests.gpu_util import assert_close_f64, magnitude
 
 pytestmark = pytest.mark.gpu
 
-TILES = {1: (256, 128), 2: (128, 128), 3: (64, 64), 4: (256, 128)}
+TILES = {1: (256, 128), 2: (128, 128), 3: (64, 64), 4: (256, 128), 5: (128, 128)}
 
 
 @pytest.fixture(scope="module")
@@ -47,7 +47,7 @@ def run(env, A, B, C, alpha, beta, ta, tb, cfg=None, m=None, n=None, k=None):
 
 
 # ----------------------------------------------------------------------------- fault-free
-@pytest.mark.parametrize("tile", [1, 2, 3, 4])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
 def test_fault_free_ragged(env, tile, ta, tb):
     ftgemm = env[0]
@@ -61,7 +61,7 @@ def test_fault_free_ragged(env, tile, ta, tb):
         assert rep.detected == 0 and rep.records == [], rep.records[:3]
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3, 4])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5])
 def test_unprotected_same_result(env, tile):
     ftgemm = env[0]
     m, n, k = 260, 130, 300
@@ -71,7 +71,7 @@ def test_unprotected_same_result(env, tile):
     assert_close_f64(out, ref, magnitude(A, B, C, 1.5, 0.5, 0, 0), k)
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3, 4])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5])
 def test_integer_exact_bitwise(env, tile):
     ftgemm = env[0]
     m, n, k = 200, 140, 160
@@ -163,7 +163,7 @@ def test_cfg1_256_four_faults(env):
         assert ocnt["corrected_subtract"] + ocnt["corrected_recompute"] == 4
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3, 4])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0)])
 def test_faults_every_tile_exponent_bits(env, tile, ta, tb):
     """Exponent/sign flips are always far above the threshold: 100% corrected."""
@@ -234,7 +234,7 @@ def test_two_faults_in_slot(env, beta):
     assert_close_f64(out, ref, magnitude(A, B, C, 1.0, beta, 0, 0), k)
 
 
-@pytest.mark.parametrize("tile", [2, 3])
+@pytest.mark.parametrize("tile", [2, 3, 5])
 def test_interval_mode_many_faults_per_tile(env, tile):
     """Verification every 128 steps corrects one fault per (tile, interval) slot."""
     ftgemm = env[0]
@@ -268,7 +268,7 @@ def test_deterministic_rerun(env):
     assert sorted(map(key, rep1.records)) == sorted(map(key, rep2.records))
 
 
-@pytest.mark.parametrize("tile", [2, 3])
+@pytest.mark.parametrize("tile", [2, 3, 5])
 def test_recompute_in_other_waves_with_beta(env, tile):
     """Flips that the subtraction cannot undo (absorption) force the recompute
     path, which needs C_in at the element; placed in elements owned by waves
