@@ -113,7 +113,13 @@ typedef struct ftg_config {
     int32_t uncorrectable_policy; /* 0: report only; 1: recompute the tile      */
     int32_t tile;        /* tile configuration id (0 = chosen by the tuning
                             table); see ftg_tile_info                           */
-    int32_t reserved;
+    int32_t encode_in_loop; /* FP64 single calls: 0 = the checksum row/column
+                            of the encoded operands come from one encode pass
+                            over A and B before the product (default); 1 =
+                            summed from the staged panels inside the k loop
+                            (§5.2's fused encoding).  Batched calls always
+                            encode in the loop; low precision always uses its
+                            encode pass                                         */
     const ftg_inject* inject; /* NULL = no injection (host memory, read at call) */
 } ftg_config;
 

@@ -75,7 +75,10 @@ struct VerifyLds {
 
 // The work of one workgroup on output tile (tm, tn) of one problem.  Shared by
 // the one-launch-per-problem kernel and the persistent batched kernel.
-template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool ABFT, bool IVL>
+// PRE: the checksum row/column of the encoded operands come from the encode
+// pass (args.asp / args.bsp) and are staged with the operands; otherwise they
+// are summed from the staged panels inside the k loop.
+template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool ABFT, bool IVL, bool PRE>
 __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs& args, const int tm,
                                                                  const int tn)
 {
@@ -155,9 +158,18 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
     constexpr int a_qstep = TA ? 8 : 8 * LPT, b_qstep = TB ? 8 * LPT : 8;  // bytes per q
     const bool full_mn = (R == BM) && (Q == BN);
 
+    double rsum = 0.0;  // encode-pass value staged by threads tid < 4 BK
     auto load_global = [&](int kb) __attribute__((always_inline)) {
         const int64_t k0 = (int64_t)kb * BK;
-        const int kv = (int)min((int64_t)BK, K - k0);  // valid steps in this block
+        const int kv = (int)min((int64_t)BK, K - k0);
+        if constexpr (ABFT && PRE) {
+            if (tid < 4 * BK) {
+                const int p = tid >> 2, c = tid & 3;
+                const double* src = c < 2 ? args.asp + ((int64_t)tm * K + k0 + p) * 2 + c
+                                          : args.bsp + ((int64_t)tn * K + k0 + p) * 2 + (c - 2);
+                rsum = p < kv ? *src : 0.0;
+            }
+        }  // valid steps in this block
         const __amdgpu_buffer_rsrc_t ra_ = make_rsrc(TA ? A + m0 * lda + k0 : A + m0 + k0 * lda);
         const __amdgpu_buffer_rsrc_t rb_ = make_rsrc(TB ? B + n0 + k0 * ldb : B + k0 + n0 * ldb);
         if (full_mn && kv == BK) {
@@ -181,6 +193,9 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
         }
     };
     auto store_lds = [&](int st) __attribute__((always_inline)) {
+        if constexpr (ABFT && PRE) {
+            if (tid < 4 * BK) sums[st][tid >> 2][tid & 3] = rsum;
+        }
 #pragma unroll
         for (int q = 0; q < APT; ++q) {
             int i, p;
@@ -669,7 +684,7 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
         load_global(0);
         store_lds(0);
         __syncthreads();
-        if (ABFT) {
+        if (ABFT && !PRE) {
             encode(0);
             if (nkb > 1) load_global(1);
             __syncthreads();
@@ -690,7 +705,9 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
             auto hot = [&]<int W>() __attribute__((always_inline)) {
                 for (; kb < seg; ++kb) {
                     const int st = kb & 1;
-                    if (!ABFT) {
+                    if (!ABFT || PRE) {
+                        // (with the encode pass, the checksum updates need no
+                        // extra barrier: the sums travel with the operands)
                         if (kb + 1 < nkb) load_global(kb + 1);
                         mfma_block.template operator()<W / WGN, W % WGN, false>(st);
                         if (kb + 1 < nkb) {
@@ -801,12 +818,12 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
 
 // One problem, one workgroup per output tile.
 // MINB: workgroups per CU the register allocation must allow (occupancy target).
-template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool ABFT, bool IVL, int MINB>
+template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool ABFT, bool IVL, int MINB, bool PRE>
 __global__ __launch_bounds__(WGM* WGN * 64, MINB) void dgemm_abft_kernel(DGemmArgs args)
 {
     int tm, tn;
     tile_of_block(blockIdx.x, gridDim.x, args.tiles_m, args.tiles_n, 4, &tm, &tn);
-    dgemm_tile<BM, BN, WGM, WGN, TA, TB, ABFT, IVL>(args, tm, tn);
+    dgemm_tile<BM, BN, WGM, WGN, TA, TB, ABFT, IVL, PRE>(args, tm, tn);
 }
 
 // Many problems in one persistent launch.  Work item w is tile
@@ -834,7 +851,7 @@ __global__ __launch_bounds__(WGM* WGN * 64, MINB) void dgemm_batched_kernel(Batc
         const int local = item - L.first[p];
         const int tm = __builtin_amdgcn_readfirstlane(local % a.tiles_m);
         const int tn = __builtin_amdgcn_readfirstlane(local / a.tiles_m);
-        dgemm_tile<BM, BN, WGM, WGN, TA, TB, ABFT, IVL>(a, tm, tn);
+        dgemm_tile<BM, BN, WGM, WGN, TA, TB, ABFT, IVL, false>(a, tm, tn);
         // all LDS use of this tile ends before the next item is published
         __syncthreads();
         if (threadIdx.x == 0) s_item = (int)gridDim.x + (int)atomicAdd(&L.queue[0], 1u);
@@ -858,18 +875,24 @@ hipError_t launch_tile(const DGemmArgs& a, bool abft, hipStream_t s)
     const dim3 grid(a.tiles_m * a.tiles_n), block(WGM * WGN * 64);
     const bool ivl = abft && a.kc < a.k;
     if (ivl && !IVL_OK) return hipErrorInvalidValue;
-#define FTG_L(TA_, TB_, AB_, IV_) \
-    hipLaunchKernelGGL((dgemm_abft_kernel<BM, BN, WGM, WGN, TA_, TB_, AB_, IV_, MINB>), grid, block, 0, s, a)
-#define FTG_T(AB_, IV_)                                       \
-    do {                                                      \
-        if (!a.ta && !a.tb) FTG_L(false, false, AB_, IV_);    \
-        else if (a.ta && !a.tb) FTG_L(true, false, AB_, IV_); \
-        else if (!a.ta && a.tb) FTG_L(false, true, AB_, IV_); \
-        else FTG_L(true, true, AB_, IV_);                     \
+    const bool pre = abft && a.asp != nullptr;
+#define FTG_L(TA_, TB_, AB_, IV_, PR_) \
+    hipLaunchKernelGGL((dgemm_abft_kernel<BM, BN, WGM, WGN, TA_, TB_, AB_, IV_, MINB, PR_>), grid, block, 0, s, a)
+#define FTG_T(AB_, IV_, PR_)                                       \
+    do {                                                           \
+        if (!a.ta && !a.tb) FTG_L(false, false, AB_, IV_, PR_);    \
+        else if (a.ta && !a.tb) FTG_L(true, false, AB_, IV_, PR_); \
+        else if (!a.ta && a.tb) FTG_L(false, true, AB_, IV_, PR_); \
+        else FTG_L(true, true, AB_, IV_, PR_);                     \
     } while (0)
-    if (!abft) FTG_T(false, false);
-    else if (!ivl) FTG_T(true, false);
-    else if constexpr (IVL_OK) FTG_T(true, true);
+    if (!abft) FTG_T(false, false, false);
+    else if (!ivl) {
+        if (pre) FTG_T(true, false, true);
+        else FTG_T(true, false, false);
+    } else if constexpr (IVL_OK) {
+        if (pre) FTG_T(true, true, true);
+        else FTG_T(true, true, false);
+    }
 #undef FTG_T
 #undef FTG_L
     return hipGetLastError();

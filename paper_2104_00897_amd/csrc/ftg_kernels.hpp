@@ -22,7 +22,27 @@ struct DGemmArgs {
     double alpha, beta;
     InjectParams inj;
     DevReport* rep;
+    // checksum row/column of the encoded operands from the encode pass:
+    // asp[(tile_m K + p) 2 + {0, 1}] = sum_{i in I} (a_ip, |a_ip|), bsp likewise
+    // for the tile's columns; NULL = encode inside the k loop
+    const double* asp;
+    const double* bsp;
 };
+
+// Encode pass of one FP64 operand: rows r (i of op(A) or j of op(B)) grouped in
+// panels of `panel` rows (the output-tile extent), steps p; element (r, p) at
+// X[p + r ld] when kcontig, else X[r + p ld].
+struct DEncOperand {
+    const double* X;
+    int64_t ld;
+    int rows, K, kcontig, panel, panels, chunks;
+    double* out;  // out[(panel K + p) 2 + {0, 1}]
+};
+struct DEncArgs {
+    DEncOperand op[2];
+};
+constexpr int kDEncChunk = 16;  // steps per encode workgroup
+hipError_t launch_dencode(const DEncArgs& e, int grid_x, hipStream_t s);
 
 // One persistent launch over the problems of a batched call that share a tile
 // configuration and transposes (device tables written by the host).

@@ -66,14 +66,16 @@ int bucket(int64_t x)
 
 int heuristic_tile_f64(int64_t m, int64_t n, int64_t k, bool need_intervals)
 {
-    // One workgroup per tile and 256 CUs.  The 128 x 128 tile is the fastest
-    // protected configuration measured at large sizes (the 256 x 128 tiles
-    // need more registers than a SIMD holds once the checksum state is added),
-    // so it is the default; small problems drop to 64 x 64 to fill the chip.
-    // Explicit choices (config tile or the tuning table) may still pick 1 or 4.
+    // One workgroup per tile and 256 CUs.  The 128 x 128 tile on 8 waves is the
+    // fastest protected configuration measured at large sizes (half the
+    // accumulators per wave leave room for the checksum state), so it is the
+    // default once it fills the chip; mid sizes take the 4-wave 128 x 128 tile
+    // and small problems 64 x 64.  Explicit choices (config tile or the tuning
+    // table) may pick any configuration.
     auto tiles = [&](int bm, int bn) { return ((m + bm - 1) / bm) * ((n + bn - 1) / bn); };
     (void)k;
     (void)need_intervals;
+    if (tiles(128, 128) >= 256) return 5;
     if (tiles(128, 128) >= 128) return 2;
     return 3;
 }
@@ -160,6 +162,28 @@ bool make_inject(const ftg_inject* in, int64_t m, int64_t n, int64_t k, int64_t 
 }
 
 }  // namespace ftg
+
+// ---------------------------------------------------------------- workspace
+namespace {
+
+// Grows the handle's device workspace to `bytes` (allocation is not allowed
+// under stream capture: warm up with the largest shape first).
+ftg_status ensure_work(ftg_handle h, size_t bytes, hipStream_t s)
+{
+    if (bytes <= h->work_bytes) return FTG_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+        return FTG_ERR_UNSUPPORTED;
+    if (hipDeviceSynchronize() != hipSuccess) return FTG_ERR_HIP;
+    if (h->d_work) hipFree(h->d_work);
+    h->d_work = nullptr;
+    h->work_bytes = 0;
+    if (hipMalloc(&h->d_work, bytes) != hipSuccess) return FTG_ERR_HIP;
+    h->work_bytes = bytes;
+    return FTG_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -333,6 +357,21 @@ ftg_status ftg_dgemm(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n, i
         if (!ftg::make_inject(cfg->inject, m, n, k, slots, 40, 63, &a.inj, 0, false))
             return FTG_ERR_UNSUPPORTED;
     }
+    if (abft && !(cfg && cfg->encode_in_loop)) {
+        // encode pass: checksum row/column of both operands for every tile panel
+        const size_t bytes = (size_t)(a.tiles_m + a.tiles_n) * (size_t)k * 2 * sizeof(double);
+        if ((st = ensure_work(h, bytes, s)) != FTG_OK) return st;
+        double* w = (double*)h->d_work;
+        ftg::DEncArgs e;
+        std::memset(&e, 0, sizeof(e));
+        const int chunks = (int)((k + ftg::kDEncChunk - 1) / ftg::kDEncChunk);
+        e.op[0] = ftg::DEncOperand{A, lda, (int)m, (int)k, ta == FTG_OP_T, bm, a.tiles_m, chunks, w};
+        e.op[1] = ftg::DEncOperand{B, ldb, (int)n, (int)k, tb == FTG_OP_N, bn, a.tiles_n, chunks,
+                                   w + (size_t)a.tiles_m * k * 2};
+        if (ftg::launch_dencode(e, std::max(a.tiles_m, a.tiles_n) * chunks, s) != hipSuccess) return FTG_ERR_HIP;
+        a.asp = e.op[0].out;
+        a.bsp = e.op[1].out;
+    }
     hipError_t e = ftg::launch_dgemm(a, tile, abft, s);
     if (e == hipSuccess && abft) {
         ftg::RepairProblem rp;
@@ -346,6 +385,7 @@ ftg_status ftg_dgemm(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n, i
     }
     return e == hipSuccess ? FTG_OK : FTG_ERR_HIP;
 }
+
 
 // ---------------------------------------------------------------- low precision
 namespace {
@@ -433,17 +473,7 @@ ftg_status ftg_gemm_ex(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n,
 
     // workspace (grows; allocation is not allowed under stream capture)
     const LowpLayout L = lowp_layout(m, n, k);
-    if (L.total > h->work_bytes) {
-        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
-            return FTG_ERR_UNSUPPORTED;
-        if (hipDeviceSynchronize() != hipSuccess) return FTG_ERR_HIP;
-        if (h->d_work) hipFree(h->d_work);
-        h->d_work = nullptr;
-        h->work_bytes = 0;
-        if (hipMalloc(&h->d_work, L.total) != hipSuccess) return FTG_ERR_HIP;
-        h->work_bytes = L.total;
-    }
+    if ((st = ensure_work(h, L.total, s)) != FTG_OK) return st;
     unsigned char* w = h->d_work;
     const int chunks = (int)((k + ftg::kLowpChunk - 1) / ftg::kLowpChunk);
 

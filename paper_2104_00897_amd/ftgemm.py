@@ -39,7 +39,7 @@ class Inject(ct.Structure):
 class Config(ct.Structure):
     _fields_ = [("abft", ct.c_int32), ("interval_k", ct.c_int32), ("lam", ct.c_double),
                 ("correct_policy", ct.c_int32), ("uncorrectable_policy", ct.c_int32),
-                ("tile", ct.c_int32), ("reserved", ct.c_int32), ("inject", ct.POINTER(Inject))]
+                ("tile", ct.c_int32), ("encode_in_loop", ct.c_int32), ("inject", ct.POINTER(Inject))]
 
 
 class FaultRecord(ct.Structure):
@@ -130,8 +130,9 @@ class Report:
 
 def make_config(abft=True, interval_k=0, lam=0.0, correct_policy=0, uncorrectable_policy=0,
                 tile=0, seed=None, n_faults=0, per_mac_rate=0.0, bit_lo=0, bit_hi=0,
-                target=TARGET_ACC):
-    cfg = Config(int(abft), interval_k, lam, correct_policy, uncorrectable_policy, tile, 0, None)
+                target=TARGET_ACC, encode_in_loop=False):
+    cfg = Config(int(abft), interval_k, lam, correct_policy, uncorrectable_policy, tile,
+                 int(encode_in_loop), None)
     inj = None
     if seed is not None and (n_faults > 0 or per_mac_rate > 0.0):
         inj = Inject(seed & (2**64 - 1), n_faults, target, per_mac_rate, bit_lo, bit_hi)

@@ -298,3 +298,23 @@ def test_recompute_in_other_waves_with_beta(env, tile):
         got = sorted((r["row"], r["col"], r["kind"]) for r in rep.records)
         assert got == sorted((r.row, r.col, r.kind) for r in orecs)
         assert_close_f64(out, ref, M, k)
+
+
+@pytest.mark.parametrize("tile", [2, 3, 5])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 1)])
+def test_encode_pass_and_in_loop_encode_agree(env, tile, ta, tb):
+    """The checksum row/column summed by the separate encode pass (default) and
+    inside the k loop (encode_in_loop) locate the same faults; both match the oracle."""
+    ftgemm = env[0]
+    m, n, k = 333, 290, 410
+    A, B, C = inputs.gemm_operands_f64(m, n, k, seed=13, ta=ta, tb=tb)
+    ref = oracle.gemm(A, B, C, 1.5, 0.5, ta, tb)
+    M = magnitude(A, B, C, 1.5, 0.5, ta, tb)
+    got = []
+    for in_loop in (False, True):
+        cfg = ftgemm.make_config(tile=tile, seed=17, n_faults=6, bit_lo=52, bit_hi=62, encode_in_loop=in_loop)
+        out, rep = run(env, A, B, C, 1.5, 0.5, ta, tb, cfg)
+        assert rep.injected == 6 and rep.corrected_subtract + rep.corrected_recompute == 6
+        assert_close_f64(out, ref, M, k)
+        got.append(sorted((r["row"], r["col"], r["kind"]) for r in rep.records))
+    assert got[0] == got[1]
