@@ -833,7 +833,7 @@ __global__ __launch_bounds__(WGM* WGN * 64, MINB) void dgemm_abft_kernel(DGemmAr
 // starts with item blockIdx.x and then takes the next free item from a
 // device counter until none is left; the last workgroup to finish resets the
 // counter for the next launch.
-template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool ABFT, bool IVL, int MINB>
+template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool ABFT, bool IVL, int MINB, bool PRE>
 __global__ __launch_bounds__(WGM* WGN * 64, MINB) void dgemm_batched_kernel(BatchLaunch L)
 {
     __shared__ int s_item;
@@ -851,7 +851,7 @@ __global__ __launch_bounds__(WGM* WGN * 64, MINB) void dgemm_batched_kernel(Batc
         const int local = item - L.first[p];
         const int tm = __builtin_amdgcn_readfirstlane(local % a.tiles_m);
         const int tn = __builtin_amdgcn_readfirstlane(local / a.tiles_m);
-        dgemm_tile<BM, BN, WGM, WGN, TA, TB, ABFT, IVL, false>(a, tm, tn);
+        dgemm_tile<BM, BN, WGM, WGN, TA, TB, ABFT, IVL, PRE>(a, tm, tn);
         // all LDS use of this tile ends before the next item is published
         __syncthreads();
         if (threadIdx.x == 0) s_item = (int)gridDim.x + (int)atomicAdd(&L.queue[0], 1u);
@@ -901,7 +901,7 @@ hipError_t launch_tile(const DGemmArgs& a, bool abft, hipStream_t s)
 // Persistent grid: as many workgroups as are resident on the device at once
 // (from the kernel's register and LDS use), never more than there are work
 // items.  Queried once per kernel instantiation.
-template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool AB, bool IV, int MINB>
+template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool AB, bool IV, int MINB, bool PR>
 int batched_grid(int total)
 {
     static int resident = 0;
@@ -910,7 +910,7 @@ int batched_grid(int total)
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, dgemm_batched_kernel<BM, BN, WGM, WGN, TA, TB, AB, IV, MINB>, WGM * WGN * 64, 0) !=
+                &per_cu, dgemm_batched_kernel<BM, BN, WGM, WGN, TA, TB, AB, IV, MINB, PR>, WGM * WGN * 64, 0) !=
                 hipSuccess)
             return std::min(total, 256);
         resident = std::max(1, cus) * std::max(1, per_cu);
@@ -919,25 +919,30 @@ int batched_grid(int total)
 }
 
 template <int BM, int BN, int WGM, int WGN, bool IVL_OK, int MINB>
-hipError_t launch_batched(const BatchLaunch& L, int ta, int tb, bool abft, bool ivl, hipStream_t s)
+hipError_t launch_batched(const BatchLaunch& L, int ta, int tb, bool abft, bool ivl, bool pre, hipStream_t s)
 {
     if (L.total <= 0) return hipSuccess;
     if (ivl && !IVL_OK) return hipErrorInvalidValue;
     const dim3 block(WGM * WGN * 64);
-#define FTG_L(TA_, TB_, AB_, IV_)                                                                         \
-    hipLaunchKernelGGL((dgemm_batched_kernel<BM, BN, WGM, WGN, TA_, TB_, AB_, IV_, MINB>),                  \
-                       dim3(batched_grid<BM, BN, WGM, WGN, TA_, TB_, AB_, IV_, MINB>(L.total)), block, 0, s, \
+#define FTG_L(TA_, TB_, AB_, IV_, PR_)                                                                         \
+    hipLaunchKernelGGL((dgemm_batched_kernel<BM, BN, WGM, WGN, TA_, TB_, AB_, IV_, MINB, PR_>),                  \
+                       dim3(batched_grid<BM, BN, WGM, WGN, TA_, TB_, AB_, IV_, MINB, PR_>(L.total)), block, 0, s, \
                        L)
-#define FTG_T(AB_, IV_)                                  \
-    do {                                                 \
-        if (!ta && !tb) FTG_L(false, false, AB_, IV_);   \
-        else if (ta && !tb) FTG_L(true, false, AB_, IV_); \
-        else if (!ta && tb) FTG_L(false, true, AB_, IV_); \
-        else FTG_L(true, true, AB_, IV_);                \
+#define FTG_T(AB_, IV_, PR_)                                  \
+    do {                                                      \
+        if (!ta && !tb) FTG_L(false, false, AB_, IV_, PR_);   \
+        else if (ta && !tb) FTG_L(true, false, AB_, IV_, PR_); \
+        else if (!ta && tb) FTG_L(false, true, AB_, IV_, PR_); \
+        else FTG_L(true, true, AB_, IV_, PR_);                \
     } while (0)
-    if (!abft) FTG_T(false, false);
-    else if (!ivl) FTG_T(true, false);
-    else if constexpr (IVL_OK) FTG_T(true, true);
+    if (!abft) FTG_T(false, false, false);
+    else if (!ivl) {
+        if (pre) FTG_T(true, false, true);
+        else FTG_T(true, false, false);
+    } else if constexpr (IVL_OK) {
+        if (pre) FTG_T(true, true, true);
+        else FTG_T(true, true, false);
+    }
 #undef FTG_T
 #undef FTG_L
     return hipGetLastError();

@@ -35,11 +35,8 @@ hipError_t launch_dscale(double* C, int64_t m, int64_t n, int64_t ldc, double be
 // threshold.  One workgroup per (panel, 16 steps); the panel is staged in LDS
 // with loads along the contiguous dimension, then 16 lanes per step sum
 // interleaved rows and one lane adds the 16 partial sums in order.
-__global__ __launch_bounds__(256) void dgemm_encode_kernel(DEncArgs args)
+__device__ __attribute__((always_inline)) inline void dencode_block(const DEncOperand& E, int pi, int c)
 {
-    const DEncOperand& E = args.op[blockIdx.y];
-    const int pi = blockIdx.x / E.chunks, c = blockIdx.x % E.chunks;
-    if (pi >= E.panels) return;
     __shared__ double t[256][kDEncChunk + 1];
     __shared__ double part[16][kDEncChunk][2];
     const int tid = threadIdx.x;
@@ -78,9 +75,47 @@ __global__ __launch_bounds__(256) void dgemm_encode_kernel(DEncArgs args)
     }
 }
 
+__global__ __launch_bounds__(256) void dgemm_encode_kernel(DEncArgs args)
+{
+    const DEncOperand& E = args.op[blockIdx.y];
+    const int pi = blockIdx.x / E.chunks, c = blockIdx.x % E.chunks;
+    if (pi >= E.panels) return;
+    dencode_block(E, pi, c);
+}
+
+__global__ __launch_bounds__(256) void dgemm_encode_batched_kernel(const DGemmArgs* __restrict__ desc,
+                                                                   const int* __restrict__ efirst, int count)
+{
+    const int item = blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (efirst[mid] <= item) lo = mid; else hi = mid - 1;
+    }
+    const DGemmArgs& a = desc[lo];
+    const int chunks = (a.k + kDEncChunk - 1) / kDEncChunk;
+    const int local = item - efirst[lo];
+    const int q = local / chunks, c = local % chunks;
+    DEncOperand E;
+    if (q < a.tiles_m) {
+        E = DEncOperand{a.A, a.lda, a.m, a.k, a.ta, a.bm, a.tiles_m, chunks, const_cast<double*>(a.asp)};
+        dencode_block(E, q, c);
+    } else {
+        E = DEncOperand{a.B, a.ldb, a.n, a.k, !a.tb, a.bn, a.tiles_n, chunks, const_cast<double*>(a.bsp)};
+        dencode_block(E, q - a.tiles_m, c);
+    }
+}
+
 hipError_t launch_dencode(const DEncArgs& e, int grid_x, hipStream_t s)
 {
     hipLaunchKernelGGL(dgemm_encode_kernel, dim3(grid_x, 2), dim3(256), 0, s, e);
+    return hipGetLastError();
+}
+
+hipError_t launch_dencode_batched(const DGemmArgs* desc, const int* efirst, int count, int total, hipStream_t s)
+{
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dgemm_encode_batched_kernel, dim3(total), dim3(256), 0, s, desc, efirst, count);
     return hipGetLastError();
 }
 

@@ -27,6 +27,7 @@ struct DGemmArgs {
     // for the tile's columns; NULL = encode inside the k loop
     const double* asp;
     const double* bsp;
+    int bm, bn;  // tile extent (panel rows of the encode pass)
 };
 
 // Encode pass of one FP64 operand: rows r (i of op(A) or j of op(B)) grouped in
@@ -43,6 +44,11 @@ struct DEncArgs {
 };
 constexpr int kDEncChunk = 16;  // steps per encode workgroup
 hipError_t launch_dencode(const DEncArgs& e, int grid_x, hipStream_t s);
+// Encode pass of every problem of a batched call: work item w is chunk c of
+// panel q of the problem with efirst[p] <= w < efirst[p + 1] (panels 0 ..
+// tiles_m - 1 of A, then tiles_n panels of B), writing desc[p].asp / bsp.
+hipError_t launch_dencode_batched(const DGemmArgs* desc, const int* efirst, int count, int total,
+                                  hipStream_t s);
 
 // One persistent launch over the problems of a batched call that share a tile
 // configuration and transposes (device tables written by the host).
@@ -79,19 +85,19 @@ inline hipError_t launch_dgemm(const DGemmArgs& a, int tile_id, bool abft, hipSt
     }
 }
 template <int BM, int BN, int WGM, int WGN, bool IVL_OK, int MINB>
-hipError_t launch_batched(const BatchLaunch& L, int ta, int tb, bool abft, bool ivl, hipStream_t s);
+hipError_t launch_batched(const BatchLaunch& L, int ta, int tb, bool abft, bool ivl, bool pre, hipStream_t s);
 extern template hipError_t launch_batched<128, 128, 2, 2, true, 2>(const BatchLaunch&, int, int, bool, bool,
-                                                                   hipStream_t);
+                                                                   bool, hipStream_t);
 extern template hipError_t launch_batched<64, 64, 2, 2, true, 2>(const BatchLaunch&, int, int, bool, bool,
-                                                                 hipStream_t);
+                                                                 bool, hipStream_t);
 
 // Batched launches exist for the configurations with verification intervals.
 inline hipError_t launch_dgemm_batched(const BatchLaunch& L, int tile_id, int ta, int tb, bool abft,
-                                       bool ivl, hipStream_t s)
+                                       bool ivl, bool pre, hipStream_t s)
 {
     switch (tile_id) {
-    case 2: return launch_batched<128, 128, 2, 2, true, 2>(L, ta, tb, abft, ivl, s);
-    case 3: return launch_batched<64, 64, 2, 2, true, 2>(L, ta, tb, abft, ivl, s);
+    case 2: return launch_batched<128, 128, 2, 2, true, 2>(L, ta, tb, abft, ivl, pre, s);
+    case 3: return launch_batched<64, 64, 2, 2, true, 2>(L, ta, tb, abft, ivl, pre, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -350,6 +350,8 @@ ftg_status ftg_dgemm(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n, i
     a.uncorrectable_policy = cfg ? cfg->uncorrectable_policy : 0;
     a.problem = 0;
     a.rep = h->rep;
+    a.bm = bm;
+    a.bn = bn;
     const int64_t n_int = (k + kc - 1) / kc;
     if (abft && cfg && cfg->inject) {
         if (n_int > ftg::kMaxIntervals) return FTG_ERR_UNSUPPORTED;
@@ -543,10 +545,11 @@ constexpr int kMaxGroups = 8;  // (tile 2 or 3) x 4 transpose pairs
 
 // Bytes of the batched table for `count` problems: descriptors, first-tile
 // tables of up to kMaxGroups groups, repair table.
-void blob_layout(int64_t count, size_t* off_first, size_t* off_rep, size_t* total)
+void blob_layout(int64_t count, size_t* off_first, size_t* off_efirst, size_t* off_rep, size_t* total)
 {
     *off_first = align256((size_t)count * sizeof(ftg::DGemmArgs));
-    *off_rep = align256(*off_first + (size_t)(count + kMaxGroups) * sizeof(int));
+    *off_efirst = align256(*off_first + (size_t)(count + kMaxGroups) * sizeof(int));
+    *off_rep = align256(*off_efirst + (size_t)(count + 1) * sizeof(int));
     *total = *off_rep + (size_t)count * sizeof(ftg::RepairProblem);
 }
 
@@ -557,8 +560,8 @@ ftg_status ftg_batched_reserve(ftg_handle h, int64_t capacity)
     if (!h || capacity < 0 || capacity > (int64_t(1) << 24)) return FTG_ERR_INVALID_ARG;
     if (capacity <= h->batch_cap && h->d_blob) return FTG_OK;
     if (hipDeviceSynchronize() != hipSuccess) return FTG_ERR_HIP;
-    size_t of, orp, bytes;
-    blob_layout(std::max<int64_t>(1, capacity), &of, &orp, &bytes);
+    size_t of, oe, orp, bytes;
+    blob_layout(std::max<int64_t>(1, capacity), &of, &oe, &orp, &bytes);
     if (h->d_blob) { hipFree(h->d_blob); h->d_blob = nullptr; }
     for (int i = 0; i < 3; ++i)
         if (h->h_blob[i]) { hipHostFree(h->h_blob[i]); h->h_blob[i] = nullptr; }
@@ -631,11 +634,28 @@ ftg_status ftg_dgemm_batched_uneven(ftg_handle h, int64_t count, const ftg_op* t
         if (h->blob_pending[slot] && hipEventSynchronize(h->blob_ev[slot]) != hipSuccess) return FTG_ERR_HIP;
         h->next_slot ^= 1;
     }
-    size_t off_first, off_rep, bytes;
-    blob_layout(count, &off_first, &off_rep, &bytes);
+    size_t off_first, off_efirst, off_rep, bytes;
+    blob_layout(count, &off_first, &off_efirst, &off_rep, &bytes);
     unsigned char* hb = h->h_blob[slot];
     auto* hdesc = (ftg::DGemmArgs*)hb;
     auto* hfirst = (int*)(hb + off_first);
+    auto* hefirst = (int*)(hb + off_efirst);
+
+    // encode pass workspace: per problem, both operands' panel sums
+    const bool pre = abft && !(cfg && cfg->encode_in_loop);
+    size_t enc_doubles = 0;
+    if (pre) {
+        for (int64_t it = 0; it < n_items; ++it) {
+            int ebm, ebn, ebk;
+            ftg::dgemm_tile_shape(items[it].group / 4 + 2, &ebm, &ebn, &ebk);
+            const int64_t p = items[it].p, kk = items[it].k;
+            enc_doubles += (size_t)(((m[p] + ebm - 1) / ebm) + ((n[p] + ebn - 1) / ebn)) * (size_t)kk * 2;
+        }
+        const ftg_status ws = ensure_work(h, std::max<size_t>(enc_doubles, 1) * sizeof(double), s);
+        if (ws != FTG_OK) return ws;
+    }
+    size_t enc_off = 0;
+    int64_t enc_items = 0;
     auto* hrep = (ftg::RepairProblem*)(hb + off_rep);
     std::memset(hrep, 0, (size_t)count * sizeof(ftg::RepairProblem));
 
@@ -677,6 +697,17 @@ ftg_status ftg_dgemm_batched_uneven(ftg_handle h, int64_t count, const ftg_op* t
         a.uncorrectable_policy = cfg ? cfg->uncorrectable_policy : 0;
         a.problem = (int)p;
         a.rep = h->rep;
+        a.bm = bm;
+        a.bn = bn;
+        hefirst[it] = (int)enc_items;
+        if (pre && kk > 0) {
+            double* w = (double*)h->d_work + enc_off;
+            a.asp = w;
+            a.bsp = w + (size_t)a.tiles_m * kk * 2;
+            enc_off += (size_t)(a.tiles_m + a.tiles_n) * kk * 2;
+            enc_items += (int64_t)(a.tiles_m + a.tiles_n) * ((kk + ftg::kDEncChunk - 1) / ftg::kDEncChunk);
+            if (enc_items >= (int64_t(1) << 31)) return FTG_ERR_UNSUPPORTED;
+        }
         if (kc < kk) G.ivl = true;
         const int64_t n_int = (kk + kc - 1) / kc;
         if (abft && cfg && cfg->inject && kk > 0) {
@@ -700,6 +731,7 @@ ftg_status ftg_dgemm_batched_uneven(ftg_handle h, int64_t count, const ftg_op* t
         rp.alpha = alpha[p]; rp.beta = beta[p]; rp.scale_a = rp.scale_b = nullptr;
     }
     hfirst[nfirst++] = (int)total;
+    hefirst[n_items] = (int)enc_items;
 
     if (hipMemcpyAsync(h->d_blob, hb, bytes, hipMemcpyHostToDevice, s) != hipSuccess) return FTG_ERR_HIP;
     if (!capturing) {
@@ -708,6 +740,10 @@ ftg_status ftg_dgemm_batched_uneven(ftg_handle h, int64_t count, const ftg_op* t
     }
     const auto* ddesc = (const ftg::DGemmArgs*)h->d_blob;
     const auto* dfirst = (const int*)(h->d_blob + off_first);
+    if (pre && enc_items > 0 &&
+        ftg::launch_dencode_batched(ddesc, (const int*)(h->d_blob + off_efirst), (int)n_items, (int)enc_items, s) !=
+            hipSuccess)
+        return FTG_ERR_HIP;
     for (int g = 0; g < ng; ++g) {
         const Group& G = groups[g];
         ftg::BatchLaunch L;
@@ -716,7 +752,7 @@ ftg_status ftg_dgemm_batched_uneven(ftg_handle h, int64_t count, const ftg_op* t
         L.count = (int)(G.d1 - G.d0);
         L.total = hfirst[G.f0 + L.count];
         L.queue = h->d_queue;
-        hipError_t e = ftg::launch_dgemm_batched(L, G.tile, G.ta, G.tb, abft, abft && G.ivl, s);
+        hipError_t e = ftg::launch_dgemm_batched(L, G.tile, G.ta, G.tb, abft, abft && G.ivl, pre, s);
         if (e != hipSuccess) return FTG_ERR_HIP;
     }
     if (abft) {

@@ -293,3 +293,24 @@ def test_batched_cfg5_full_size_sampled(env):
     # F_p is capped by the problem's slot count (one-tile problems take at most one)
     expect = sum(min(int(f), -(-m // 64) * -(-n // 64)) for f, (m, n, *_) in zip(faults, specs))
     assert rep.injected == n_inj == expect
+
+
+def test_batched_encode_pass_and_in_loop_agree(env):
+    """Batched calls with the encode pass (default) and with the encode inside the
+    k loop locate the same faults and both match the oracle."""
+    ftgemm = env[0]
+    rng = np.random.default_rng(21)
+    specs = [(int(rng.integers(70, 300)), int(rng.integers(70, 300)), int(rng.integers(1, 400)),
+              int(rng.integers(0, 2)), int(rng.integers(0, 2)), 1.5, 0.5) for _ in range(20)]
+    faults = rng.integers(0, 3, size=len(specs))
+    batch = Batch(env, specs, seed=10)
+    got = []
+    for in_loop in (False, True):
+        cfg = ftgemm.make_config(tile=3, seed=3, n_faults=1, bit_lo=52, bit_hi=62, encode_in_loop=in_loop)
+        outs, rep = run(env, batch, cfg, faults)
+        assert rep.injected == rep.corrected_subtract + rep.corrected_recompute
+        for q, (m, n, k, ta, tb, alpha, beta) in enumerate(specs):
+            A, B, C = batch.host[q]
+            assert_close_f64(outs[q], batch.reference(q), magnitude(A, B, C, alpha, beta, ta, tb), k)
+        got.append(sorted((r["problem"], r["row"], r["col"], r["kind"]) for r in rep.records))
+    assert got[0] == got[1]
