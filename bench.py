@@ -27,6 +27,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_F64_MFMA = 78.6  # TFLOP/s, MI355X dense FP64 matrix
+# HBM bytes per launch of the protected product kernel (tile configuration 5,
+# encode pass) at n = 8192 from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled
+# by a plain-copy calibration (profiles/dgemm_abft_n8192_traffic.md); it must be
+# re-measured whenever that kernel changes
+TRAFFIC_F64_N8192 = 14.77e9
 
 
 def parse():
@@ -50,11 +55,16 @@ def device_operands(torch, ftgemm, m, n, k, seed, ta=0, tb=0):
     return ftgemm.to_device(A), ftgemm.to_device(B), ftgemm.to_device(C), (A, B, C)
 
 
-def time_calls(torch, fn, steps, warmup):
+def time_calls(torch, fn, steps, warmup, kernel_timer=None):
+    """ms per call over `steps` calls (HIP events on the current stream).  With a
+    handle as kernel_timer, the library also times its product kernel launches
+    (events on the same stream) and the list kernel_timer_out gets their mean."""
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    if kernel_timer is not None:
+        kernel_timer.timing(True)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
@@ -62,7 +72,14 @@ def time_calls(torch, fn, steps, warmup):
         fn()
     e1.record(stream)
     torch.cuda.synchronize()
+    if kernel_timer is not None:
+        n, t = kernel_timer.timing_read()
+        kernel_timer.timing(False)
+        KERNEL_MS.append(t / max(1, n))
     return e0.elapsed_time(e1) / steps  # ms per call
+
+
+KERNEL_MS: list = []  # mean product-kernel duration of each timed run with a kernel timer
 
 
 def measure(torch, ftgemm, h, m, n, k, alpha, beta, ta, tb, steps, warmup, tile, seed=0):
@@ -79,10 +96,12 @@ def measure(torch, ftgemm, h, m, n, k, alpha, beta, ta, tb, steps, warmup, tile,
     # alternate protected / unprotected to cancel clock drift
     tp, tu, t0 = [], [], []
     h.reset()
+    KERNEL_MS.clear()
     for _ in range(2):
-        tp.append(time_calls(torch, call(cfg_p), steps, warmup))
+        tp.append(time_calls(torch, call(cfg_p), steps, warmup, kernel_timer=h))
         tu.append(time_calls(torch, call(cfg_u), steps, warmup))
         t0.append(time_calls(torch, call(cfg_0), steps, warmup))
+    kernel_ms = float(np.median(KERNEL_MS))
     rep = h.read()
     flops = 2.0 * m * n * k
     ms_p, ms_u, ms_0 = float(np.median(tp)), float(np.median(tu)), float(np.median(t0))
@@ -95,6 +114,7 @@ def measure(torch, ftgemm, h, m, n, k, alpha, beta, ta, tb, steps, warmup, tile,
         "tflops_protected_no_faults": flops / ms_0 / 1e9,
         "overhead_pct": 100.0 * (ms_p / ms_u - 1.0),
         "overhead_no_faults_pct": 100.0 * (ms_0 / ms_u - 1.0),
+        "kernel_ms_protected": kernel_ms,
         "faults_per_call": faults,
         "injected": rep.injected, "corrected": rep.corrected_subtract + rep.corrected_recompute,
         "uncorrectable": rep.uncorrectable, "detected": rep.detected,
@@ -261,6 +281,9 @@ def main():
     res, host = measure(torch, ftgemm, h, n, n, n, 1.5, 0.5, 0, 0, args.steps, args.warmup, args.tile)
     flops = 2.0 * n ** 3
     achieved = res["tflops_protected"]
+    # roofline of the protected product kernel itself: algorithmic flops per
+    # launch (2 n^3) over its mean launch duration (library-recorded events)
+    kernel_tf = flops / res["kernel_ms_protected"] / 1e9
     line = {
         "metric": "FT-GEMM TFLOP/s & ABFT overhead % vs unprotected, faults injected, 1 GPU",
         "value": round(achieved, 3),
@@ -282,9 +305,11 @@ def main():
         "unprotected_tflops": round(res["tflops_unprotected"], 3),
         "faults": {"injected": res["injected"], "corrected": res["corrected"],
                    "uncorrectable": res["uncorrectable"]},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_F64_MFMA,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64_MFMA, 4),
-                     "traffic": None},
+        "roofline": {"bound": "mfma", "achieved": round(kernel_tf, 3), "peak": PEAK_F64_MFMA,
+                     "unit": "TFLOP/s", "frac": round(kernel_tf / PEAK_F64_MFMA, 4),
+                     "traffic": TRAFFIC_F64_N8192 if n == 8192 else None,
+                     "kernel": "protected FP64 product kernel (128x128 tile, 8 waves)",
+                     "kernel_ms": round(res["kernel_ms_protected"], 4)},
     }
     if args.tiles:
         for t in (1, 2, 3, 4, 5):

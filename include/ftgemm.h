@@ -251,6 +251,18 @@ ftg_status ftg_tune_set(ftg_handle h, ftg_dtype ab_type, int64_t m, int64_t n, i
                         int32_t id);
 int32_t ftg_tune_get(ftg_handle h, ftg_dtype ab_type, int64_t m, int64_t n, int64_t k);
 
+/* Optional timing of the product kernels.  With on = 1, every following
+ * call records a pair of HIP events on its stream around its main GEMM
+ * launch (the protected or unprotected product kernel; for a batched call
+ * all of its persistent launches), up to 256 launches between reads and
+ * never under stream capture; on = 0 stops.  Either resets the record
+ * (creates the events on first use). */
+ftg_status ftg_timing_enable(ftg_handle h, int on);
+
+/* Waits for the recorded launches, returns their count and total duration
+ * in milliseconds, and clears the record. */
+ftg_status ftg_timing_read(ftg_handle h, int32_t* launches, double* total_ms);
+
 /* Human-readable name of a status code (static storage). */
 const char* ftg_status_string(ftg_status s);
 

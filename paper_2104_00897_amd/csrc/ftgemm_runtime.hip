@@ -49,6 +49,10 @@ struct ftg_handle_s {
     // products, magnitude bounds); grows to the largest shape seen
     unsigned char* d_work = nullptr;
     size_t work_bytes = 0;
+    // optional timing of the product launches: event pairs on the call's stream
+    bool timing = false;
+    hipEvent_t tev[2 * 256] = {};
+    int tev_used = 0;  // pairs recorded since the last read
     // tuning table: configuration id per (dtype, bucket m, n, k); 0 = heuristic
     int8_t tune[kDtypes][kTuneBuckets][kTuneBuckets][kTuneBuckets];
 };
@@ -176,12 +180,35 @@ ftg_status ensure_work(ftg_handle h, size_t bytes, hipStream_t s)
         return FTG_ERR_UNSUPPORTED;
     if (hipDeviceSynchronize() != hipSuccess) return FTG_ERR_HIP;
     if (h->d_work) hipFree(h->d_work);
+    for (auto& e : h->tev)
+        if (e) hipEventDestroy(e);
     h->d_work = nullptr;
     h->work_bytes = 0;
     if (hipMalloc(&h->d_work, bytes) != hipSuccess) return FTG_ERR_HIP;
     h->work_bytes = bytes;
     return FTG_OK;
 }
+
+// Records an event pair around one product launch when timing is on (not
+// under stream capture, and only while pairs are free).
+struct LaunchTimer {
+    ftg_handle h;
+    hipStream_t s;
+    int pair = -1;
+    LaunchTimer(ftg_handle h_, hipStream_t s_) : h(h_), s(s_)
+    {
+        if (!h->timing || h->tev_used >= 256) return;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+        pair = h->tev_used++;
+        hipEventRecord(h->tev[2 * pair], s);
+    }
+    void end()
+    {
+        if (pair >= 0) hipEventRecord(h->tev[2 * pair + 1], s);
+        pair = -1;
+    }
+};
 
 }  // namespace
 
@@ -239,6 +266,8 @@ ftg_status ftg_destroy(ftg_handle h)
     if (h->d_blob) hipFree(h->d_blob);
     if (h->d_queue) hipFree(h->d_queue);
     if (h->d_work) hipFree(h->d_work);
+    for (auto& e : h->tev)
+        if (e) hipEventDestroy(e);
     for (int i = 0; i < 3; ++i)
         if (h->h_blob[i]) hipHostFree(h->h_blob[i]);
     for (int i = 0; i < 2; ++i)
@@ -374,7 +403,9 @@ ftg_status ftg_dgemm(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n, i
         a.asp = e.op[0].out;
         a.bsp = e.op[1].out;
     }
+    LaunchTimer timer(h, s);
     hipError_t e = ftg::launch_dgemm(a, tile, abft, s);
+    timer.end();
     if (e == hipSuccess && abft) {
         ftg::RepairProblem rp;
         std::memset(&rp, 0, sizeof(rp));
@@ -470,8 +501,12 @@ ftg_status ftg_gemm_ex(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n,
     a.scale_b = ab_type == FTG_F8_E4M3 ? scale_b : nullptr;
     a.rep = h->rep;
     const int ita = ta == FTG_OP_T, itb = tb == FTG_OP_T;
-    if (!abft)
-        return ftg::launch_lowp_gemm(a, ab_type, ab_type, ita, itb, 0, s) == hipSuccess ? FTG_OK : FTG_ERR_HIP;
+    if (!abft) {
+        LaunchTimer timer(h, s);
+        const hipError_t e = ftg::launch_lowp_gemm(a, ab_type, ab_type, ita, itb, 0, s);
+        timer.end();
+        return e == hipSuccess ? FTG_OK : FTG_ERR_HIP;
+    }
 
     // workspace (grows; allocation is not allowed under stream capture)
     const LowpLayout L = lowp_layout(m, n, k);
@@ -526,7 +561,12 @@ ftg_status ftg_gemm_ex(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n,
         const int64_t slots = (int64_t)a.tiles_m * a.tiles_n;
         if (!ftg::make_inject(cfg->inject, m, n, k, slots, 13, 31, &a.inj, 0, false)) return FTG_ERR_UNSUPPORTED;
     }
-    if (ftg::launch_lowp_gemm(a, ab_type, ab_type, ita, itb, 1, s) != hipSuccess) return FTG_ERR_HIP;
+    {
+        LaunchTimer timer(h, s);
+        const hipError_t e = ftg::launch_lowp_gemm(a, ab_type, ab_type, ita, itb, 1, s);
+        timer.end();
+        if (e != hipSuccess) return FTG_ERR_HIP;
+    }
     ftg::RepairProblem rp;
     std::memset(&rp, 0, sizeof(rp));
     rp.A = A; rp.B = B; rp.C = C;
@@ -744,6 +784,7 @@ ftg_status ftg_dgemm_batched_uneven(ftg_handle h, int64_t count, const ftg_op* t
         ftg::launch_dencode_batched(ddesc, (const int*)(h->d_blob + off_efirst), (int)n_items, (int)enc_items, s) !=
             hipSuccess)
         return FTG_ERR_HIP;
+    LaunchTimer timer(h, s);
     for (int g = 0; g < ng; ++g) {
         const Group& G = groups[g];
         ftg::BatchLaunch L;
@@ -755,12 +796,41 @@ ftg_status ftg_dgemm_batched_uneven(ftg_handle h, int64_t count, const ftg_op* t
         hipError_t e = ftg::launch_dgemm_batched(L, G.tile, G.ta, G.tb, abft, abft && G.ivl, pre, s);
         if (e != hipSuccess) return FTG_ERR_HIP;
     }
+    timer.end();
     if (abft) {
         ftg::RepairProblem none;
         std::memset(&none, 0, sizeof(none));
         if (ftg::launch_repair(h->rep, none, (const ftg::RepairProblem*)(h->d_blob + off_rep), s) != hipSuccess)
             return FTG_ERR_HIP;
     }
+    return FTG_OK;
+}
+
+ftg_status ftg_timing_enable(ftg_handle h, int on)
+{
+    if (!h) return FTG_ERR_INVALID_ARG;
+    if (on && !h->tev[0]) {
+        for (auto& e : h->tev)
+            if (hipEventCreate(&e) != hipSuccess) return FTG_ERR_HIP;
+    }
+    h->timing = on != 0;
+    h->tev_used = 0;
+    return FTG_OK;
+}
+
+ftg_status ftg_timing_read(ftg_handle h, int32_t* launches, double* total_ms)
+{
+    if (!h || !launches || !total_ms) return FTG_ERR_INVALID_ARG;
+    double t = 0.0;
+    for (int i = 0; i < h->tev_used; ++i) {
+        if (hipEventSynchronize(h->tev[2 * i + 1]) != hipSuccess) return FTG_ERR_HIP;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, h->tev[2 * i], h->tev[2 * i + 1]) != hipSuccess) return FTG_ERR_HIP;
+        t += ms;
+    }
+    *launches = h->tev_used;
+    *total_ms = t;
+    h->tev_used = 0;
     return FTG_OK;
 }
 

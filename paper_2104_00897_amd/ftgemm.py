@@ -68,7 +68,8 @@ class FaultReport(ct.Structure):
 EXPORTS = [
     "ftg_create", "ftg_destroy", "ftg_dgemm", "ftg_gemm_ex", "ftg_dgemm_batched_uneven",
     "ftg_batched_reserve", "ftg_report_read", "ftg_report_reset", "ftg_last_error_arg",
-    "ftg_tile_info", "ftg_tune_set", "ftg_tune_get", "ftg_status_string",
+    "ftg_tile_info", "ftg_tune_set", "ftg_tune_get", "ftg_timing_enable", "ftg_timing_read",
+    "ftg_status_string",
 ]
 
 _lib = None
@@ -99,6 +100,8 @@ def load() -> ct.CDLL:
     lib.ftg_tile_info.argtypes = [i32, i32, ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(i32)]
     lib.ftg_tune_set.argtypes = [h, i32, i64, i64, i64, i32]
     lib.ftg_tune_get.argtypes = [h, i32, i64, i64, i64]
+    lib.ftg_timing_enable.argtypes = [h, ct.c_int]
+    lib.ftg_timing_read.argtypes = [h, ct.POINTER(i32), ct.POINTER(ct.c_double)]
     lib.ftg_status_string.argtypes = [i32]
     lib.ftg_status_string.restype = ct.c_char_p
     for name in EXPORTS:
@@ -215,6 +218,15 @@ class Handle:
 
     def batched_reserve(self, capacity: int):
         self._check(self.lib.ftg_batched_reserve(self.h, capacity), "ftg_batched_reserve")
+
+    def timing(self, on: bool = True):
+        self._check(self.lib.ftg_timing_enable(self.h, int(on)), "ftg_timing_enable")
+
+    def timing_read(self):
+        """(launches, total ms) of the product kernels recorded since the last read."""
+        n, t = ct.c_int32(), ct.c_double()
+        self._check(self.lib.ftg_timing_read(self.h, ct.byref(n), ct.byref(t)), "ftg_timing_read")
+        return n.value, t.value
 
     def tune_set(self, dtype, m, n, k, tile_id):
         self._check(self.lib.ftg_tune_set(self.h, dtype, m, n, k, tile_id), "ftg_tune_set")
