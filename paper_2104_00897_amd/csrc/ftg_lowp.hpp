@@ -46,6 +46,11 @@ struct LowpArgs {
     int problem, pad;
     InjectParams inj;
     DevReport* rep;
+    // plain mode: the k range split in `ksplit` slices (one workgroup per tile
+    // and slice), slice s writing C + s cslice; protected mode: ER and EC hold
+    // `slices` / `slices_c` such partial products, er_stride / ec_stride apart
+    int ksplit, slices, slices_c, pad2;
+    int64_t cslice, er_stride, ec_stride;
 };
 
 // Encode pass over one operand.  // One operand X with rows r (i of op(A), or j of op(B)) and steps p:

@@ -427,7 +427,16 @@ struct LowpLayout {
     size_t xs_a, xs_b, xrp_a, xrp_b, xmp_a, xmp_b, ra, cb, ma, mb, er, ec, total;
 };
 
-LowpLayout lowp_layout(int64_t m, int64_t n, int64_t k)
+// k slices of the checksum products: enough workgroups to fill the chip twice,
+// each slice at least 512 steps long
+int lowp_ksplit(int64_t tiles, int64_t k)
+{
+    int s = (int)std::min<int64_t>(16, std::max<int64_t>(1, (512 + tiles - 1) / std::max<int64_t>(1, tiles)));
+    while (s > 1 && k / s < 512) --s;
+    return s;
+}
+
+LowpLayout lowp_layout(int64_t m, int64_t n, int64_t k, int ks_r, int ks_c)
 {
     const int64_t tm = (m + ftg::kLowpTile - 1) / ftg::kLowpTile, tn = (n + ftg::kLowpTile - 1) / ftg::kLowpTile;
     const int64_t ch = (k + ftg::kLowpChunk - 1) / ftg::kLowpChunk;
@@ -444,8 +453,8 @@ LowpLayout lowp_layout(int64_t m, int64_t n, int64_t k)
     L.cb = take((size_t)n * 4);
     L.ma = take((size_t)tm * 4);
     L.mb = take((size_t)tn * 4);
-    L.er = take((size_t)(m * 3 * tn) * 4);
-    L.ec = take((size_t)(3 * tm * n) * 4);
+    L.er = take((size_t)ks_r * (size_t)(m * 3 * tn) * 4);
+    L.ec = take((size_t)ks_c * (size_t)(3 * tm * n) * 4);
     L.total = o;
     return L;
 }
@@ -509,7 +518,10 @@ ftg_status ftg_gemm_ex(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n,
     }
 
     // workspace (grows; allocation is not allowed under stream capture)
-    const LowpLayout L = lowp_layout(m, n, k);
+    const int64_t chk_tiles_r = (int64_t)a.tiles_m * ((3 * a.tiles_n + bn - 1) / bn);
+    const int64_t chk_tiles_c = (int64_t)((3 * a.tiles_m + bm - 1) / bm) * a.tiles_n;
+    const int ks_r = lowp_ksplit(chk_tiles_r, k), ks_c = lowp_ksplit(chk_tiles_c, k);
+    const LowpLayout L = lowp_layout(m, n, k, ks_r, ks_c);
     if ((st = ensure_work(h, L.total, s)) != FTG_OK) return st;
     unsigned char* w = h->d_work;
     const int chunks = (int)((k + ftg::kLowpChunk - 1) / ftg::kLowpChunk);
@@ -540,6 +552,7 @@ ftg_status ftg_gemm_ex(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n,
     c1.tiles_m = a.tiles_m; c1.tiles_n = (c1.n + bn - 1) / bn;
     c1.vec_a = a.vec_a; c1.vec_b = vec_ok(c1.B, k, 2);
     c1.alpha = 1.0f; c1.beta = 0.0f;
+    c1.ksplit = ks_r; c1.cslice = (int64_t)m * 3 * a.tiles_n;
     if (ftg::launch_lowp_gemm(c1, ab_type, FTG_BF16, ita, 0, 0, s) != hipSuccess) return FTG_ERR_HIP;
     ftg::LowpArgs c2;
     std::memset(&c2, 0, sizeof(c2));
@@ -549,11 +562,16 @@ ftg_status ftg_gemm_ex(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n,
     c2.tiles_m = (c2.m + bm - 1) / bm; c2.tiles_n = a.tiles_n;
     c2.vec_a = vec_ok(c2.A, k, 2); c2.vec_b = a.vec_b;
     c2.alpha = 1.0f; c2.beta = 0.0f;
+    c2.ksplit = ks_c; c2.cslice = (int64_t)3 * a.tiles_m * n;
     if (ftg::launch_lowp_gemm(c2, FTG_BF16, ab_type, 1, itb, 0, s) != hipSuccess) return FTG_ERR_HIP;
 
     // protected product
     a.ER = c1.C; a.lder = (int)m;
     a.EC = c2.C; a.ldec = 3 * a.tiles_m;
+    a.slices = ks_r;
+    a.slices_c = ks_c;
+    a.er_stride = c1.cslice;
+    a.ec_stride = c2.cslice;
     a.RA = ea.XR; a.MA = ea.XM; a.CB = eb_.XR; a.MB = eb_.XM;
     a.lambda = (cfg && cfg->lambda > 0.0) ? cfg->lambda : 4.0;
     a.problem = 0;

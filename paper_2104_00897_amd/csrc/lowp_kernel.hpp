@@ -202,17 +202,31 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
     const int wm0 = wr * WM, wn0 = wc * WN;
     const int l16 = lane & 15, lq = lane >> 4;
 
+    // split k (plain mode): workgroup -> (slice, tile)
+    const int ntiles = args.tiles_m * args.tiles_n;
+    int bid = blockIdx.x, nb = gridDim.x;
+    int64_t kbeg = 0, kend = args.k;
+    float* Cbase = args.C;
+    if (MODE == 0 && args.ksplit > 1) {
+        const int slice = bid / ntiles;
+        bid -= slice * ntiles;
+        nb = ntiles;
+        const int64_t kchunk = ((args.k + args.ksplit - 1) / args.ksplit + BK - 1) / BK * BK;
+        kbeg = min((int64_t)args.k, (int64_t)slice * kchunk);
+        kend = min((int64_t)args.k, kbeg + kchunk);
+        Cbase += slice * args.cslice;
+    }
     int tm, tn;
-    tile_of_block(blockIdx.x, gridDim.x, args.tiles_m, args.tiles_n, 4, &tm, &tn);
+    tile_of_block(bid, nb, args.tiles_m, args.tiles_n, 4, &tm, &tn);
     const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
     const int R = (int)min((int64_t)BM, (int64_t)args.m - m0);
     const int Q = (int)min((int64_t)BN, (int64_t)args.n - n0);
-    const int64_t K = args.k;
+    const int64_t K = kend - kbeg;
     const int nkb = (int)((K + BK - 1) / BK);
     const int64_t lda = args.lda, ldb = args.ldb;
 
-    const typename STA::T* A = (const typename STA::T*)args.A;
-    const typename STB::T* B = (const typename STB::T*)args.B;
+    const typename STA::T* A = (const typename STA::T*)args.A + (Cf::AKC ? kbeg : kbeg * lda);
+    const typename STB::T* B = (const typename STB::T*)args.B + (Cf::BKC ? kbeg : kbeg * ldb);
 
     // ---- staging map: thread t, vector q -> (row, k) of the operand tile
     auto a_rp = [&](int q, int* r, int* p) __attribute__((always_inline)) {
@@ -428,7 +442,7 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
     const int64_t ldc = args.ldc;
     const float as = args.alpha * (args.scale_a ? *args.scale_a : 1.0f) * (args.scale_b ? *args.scale_b : 1.0f);
     const bool cin = args.beta != 0.0f;
-    const __amdgpu_buffer_rsrc_t rc = make_rsrc(args.C + m0 + n0 * ldc);
+    const __amdgpu_buffer_rsrc_t rc = make_rsrc(Cbase + m0 + n0 * ldc);
     const int c_voff = (int)((wm0 + 4 * lq + (int64_t)(wn0 + l16) * ldc) * 4);
     const int c_hstep = (int)(16 * ldc * 4);
     const bool full_mn = R == BM && Q == BN;
@@ -510,7 +524,11 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
             if (isrow) {
                 ref = V.rsum[0][x] + V.rsum[1][x];
                 const float* er = args.ER + (m0 + x) + (int64_t)(3 * tn) * args.lder;
-                double e = (double)er[0] + (double)er[args.lder] + (double)er[2 * args.lder];
+                double e = 0.0;
+                for (int sl = 0; sl < args.slices; ++sl) {
+                    const float* es = er + sl * args.er_stride;
+                    e += (double)es[0] + (double)es[args.lder] + (double)es[2 * args.lder];
+                }
                 if (inj && args.inj.target == FTG_TARGET_CHECKSUM) {
                     for (int q = 0; q < nflt; ++q)
                         if (flt[q][0] == x) {
@@ -527,7 +545,12 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
             } else {
                 ref = V.csum[0][x] + V.csum[1][x];
                 const float* ec = args.EC + (int64_t)(3 * tm) + (n0 + x) * args.ldec;
-                ex = asd * ((double)ec[0] + (double)ec[1] + (double)ec[2]);
+                double e = 0.0;
+                for (int sl = 0; sl < args.slices_c; ++sl) {
+                    const float* es = ec + sl * args.ec_stride;
+                    e += (double)es[0] + (double)es[1] + (double)es[2];
+                }
+                ex = asd * e;
                 mag = fabs(asd) * (double)args.CB[n0 + x] * (double)args.MA[tm];
                 if (cin) { ex += bd * (V.cic[0][x] + V.cic[1][x]); mag += fabs(bd) * (V.cica[0][x] + V.cica[1][x]); }
             }
@@ -576,7 +599,7 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
 template <typename STA, typename STB, bool F8MMA, int MODE>
 hipError_t launch_lowp_t(const LowpArgs& a, int ta, int tb, hipStream_t s)
 {
-    const dim3 grid(a.tiles_m * a.tiles_n), block(256);
+    const dim3 grid(a.tiles_m * a.tiles_n * (MODE == 0 && a.ksplit > 1 ? a.ksplit : 1)), block(256);
     if (!ta && !tb) hipLaunchKernelGGL((lowp_gemm_kernel<STA, STB, F8MMA, false, false, MODE>), grid, block, 0, s, a);
     else if (ta && !tb) hipLaunchKernelGGL((lowp_gemm_kernel<STA, STB, F8MMA, true, false, MODE>), grid, block, 0, s, a);
     else if (!ta && tb) hipLaunchKernelGGL((lowp_gemm_kernel<STA, STB, F8MMA, false, true, MODE>), grid, block, 0, s, a);
