@@ -98,48 +98,27 @@ struct LCfg {
     static_assert(BKC || (BN / 8) * (BK / 4) == NT, "column staging map");
 };
 
-// Writes VEC stored elements (16 bytes in `v`) to the LDS tile of MFMA type,
-// either along k of one row (kc) or down VEC rows at one k.
+// Writes one 16-byte load of k-contiguous stored elements (row r, steps p ..)
+// to the k-contiguous LDS tile of the MFMA type (fp8 staged as bf16 when the
+// product runs on the bf16 MFMA).
 template <typename ST, bool F8MMA, int PITCH>
-__device__ __attribute__((always_inline)) inline void lds_put16(unsigned char* tile, int r, int p, bool kc,
-                                                                const u32x4_t v)
+__device__ __attribute__((always_inline)) inline void lds_put16(unsigned char* tile, int r, int p, const u32x4_t v)
 {
-    constexpr int VEC = 16 / ST::bytes;
     if constexpr (F8MMA || ST::bytes == 2) {
-        // MFMA type == storage type
         constexpr int MBY = F8MMA ? 1 : 2;
-        if (kc) {
-            *(u32x4_t*)(tile + r * PITCH + p * MBY) = v;
-        } else {
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                if constexpr (MBY == 2) {
-                    const uint16_t x = (uint16_t)(v[e / 2] >> (16 * (e % 2)));
-                    *(uint16_t*)(tile + (r + e) * PITCH + p * 2) = x;
-                } else {
-                    const uint8_t x = (uint8_t)(v[e / 4] >> (8 * (e % 4)));
-                    tile[(r + e) * PITCH + p] = x;
-                }
-            }
-        }
+        *(u32x4_t*)(tile + r * PITCH + p * MBY) = v;
     } else {
-        // fp8 storage staged as bf16
         uint16_t h[16];
 #pragma unroll
         for (int e = 0; e < 16; ++e) h[e] = e4m3_to_bf16((v[e / 4] >> (8 * (e % 4))) & 0xFFu);
-        if (kc) {
-            u32x4_t w0, w1;
+        u32x4_t w0, w1;
 #pragma unroll
-            for (int d = 0; d < 4; ++d) {
-                w0[d] = (uint32_t)h[2 * d] | ((uint32_t)h[2 * d + 1] << 16);
-                w1[d] = (uint32_t)h[8 + 2 * d] | ((uint32_t)h[8 + 2 * d + 1] << 16);
-            }
-            *(u32x4_t*)(tile + r * PITCH + p * 2) = w0;
-            *(u32x4_t*)(tile + r * PITCH + p * 2 + 16) = w1;
-        } else {
-#pragma unroll
-            for (int e = 0; e < 16; ++e) *(uint16_t*)(tile + (r + e) * PITCH + p * 2) = h[e];
+        for (int d = 0; d < 4; ++d) {
+            w0[d] = (uint32_t)h[2 * d] | ((uint32_t)h[2 * d + 1] << 16);
+            w1[d] = (uint32_t)h[8 + 2 * d] | ((uint32_t)h[8 + 2 * d + 1] << 16);
         }
+        *(u32x4_t*)(tile + r * PITCH + p * 2) = w0;
+        *(u32x4_t*)(tile + r * PITCH + p * 2 + 16) = w1;
     }
 }
 
@@ -312,7 +291,7 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
             for (int q = 0; q < Cf::NVA; ++q) {
                 int r, p;
                 a_rp(q, &r, &p);
-                lds_put16<STA, F8MMA, PITCH>(ta, r, p, true, ra[q]);
+                lds_put16<STA, F8MMA, PITCH>(ta, r, p, ra[q]);
             }
         } else {
             int r, p;
@@ -324,7 +303,7 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
             for (int q = 0; q < Cf::NVB; ++q) {
                 int r, p;
                 b_rp(q, &r, &p);
-                lds_put16<STB, F8MMA, PITCH>(tb, r, p, true, rb[q]);
+                lds_put16<STB, F8MMA, PITCH>(tb, r, p, rb[q]);
             }
         } else {
             int r, p;
