@@ -3,5 +3,5 @@
 #include "dgemm_kernel.hpp"
 
 namespace ftg {
-template hipError_t launch_batched<64, 64, 2, 2, true, 2>(const BatchLaunch&, int, int, bool, bool, bool, hipStream_t);
+template hipError_t launch_batched<64, 64, 2, 2, true, 2>(const BatchLaunch&, int, int, bool, bool, bool, bool, hipStream_t);
 }  // namespace ftg

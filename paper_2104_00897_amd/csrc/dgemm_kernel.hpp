@@ -47,11 +47,15 @@ struct DCfg {
     static constexpr int NT = NW * 64;
     static constexpr int WM = BM / WGM, WN = BN / WGN;
     static constexpr int FM = WM / 16, FN = WN / 16;
-    // LDS layouts: A as [p][i] (TA = 0) or [i][p] (TA = 1); B as [p][j] (TB = 1) or [j][p]
+    // LDS layouts: A as [p][i] (TA = 0) or [i][p] (TA = 1); B as [p][j] (TB = 1)
+    // or [j][p], padded pitches.  Both are made of whole 16-byte slots (BK + 2 =
+    // 9 slots per line along k), the unit of a direct global-to-LDS load.
     static constexpr int SA = TA ? (BK + 2) : (BM + 16);
     static constexpr int SB = TB ? (BN + 16) : (BK + 2);
     static constexpr int A_ELEMS = TA ? BM * SA : BK * SA;
     static constexpr int B_ELEMS = TB ? BK * SB : BN * SB;
+    // direct-to-LDS staging: 1 KB (64 lanes x 16 bytes) per wave load
+    static constexpr bool DIRECT = BM % 128 == 0 && BN % 128 == 0 && BK == 16;
     static constexpr int NA = BM * BK / NT, NB = BN * BK / NT;  // loads per thread
     static constexpr int PPW = BK / NW, LPP = 64 / PPW;        // encode: p's per wave, lanes per p
     static constexpr int GSH = FM / WGN, HSH = FN / WGM;        // checksum FMA shares per wave
@@ -78,7 +82,10 @@ struct VerifyLds {
 // PRE: the checksum row/column of the encoded operands come from the encode
 // pass (args.asp / args.bsp) and are staged with the operands; otherwise they
 // are summed from the staged panels inside the k loop.
-template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool ABFT, bool IVL, bool PRE>
+// DIR: full k-blocks of interior tiles are loaded straight into LDS (operands
+// 16-byte aligned with even leading dimensions); otherwise every block is
+// prefetched into registers one block ahead and stored after the MFMAs.
+template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool ABFT, bool IVL, bool PRE, bool DIR>
 __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs& args, const int tm,
                                                                  const int tn)
 {
@@ -86,10 +93,19 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
     constexpr int BK = Cf::BK, NT = Cf::NT, FM = Cf::FM, FN = Cf::FN;
     constexpr int WM = Cf::WM, WN = Cf::WN;
 
-    __shared__ double As[2][Cf::A_ELEMS];
-    __shared__ double Bs[2][Cf::B_ELEMS];
-    __shared__ double sums[2][BK][4];  // e^T A_I, |A_I|, B_J e, |B_J| per step p
-    __shared__ VerifyLds<BM, BN, WGM, WGN> V;
+    // Two staging buffers, each holding the A panel followed by the B panel of
+    // one k-block.  The verification bookkeeping (VerifyLds) lives in a stage
+    // that holds no live panel at the time (both after the k loop, the one not
+    // holding the next block at an interval end), which keeps the workgroup's
+    // LDS at the staging size and lets two workgroups share a CU.
+    constexpr int SE = Cf::A_ELEMS + Cf::B_ELEMS;  // doubles per stage
+    using VL = VerifyLds<BM, BN, WGM, WGN>;
+    static_assert(sizeof(VL) <= SE * sizeof(double), "verification data must fit in one stage");
+    __shared__ double stg[2][SE];
+    __shared__ double sums[2][2][BK][2];  // [stage][A, B][p]: (e^T A_I, |A_I|), (B_J e, |B_J|)
+    auto As = [&](int st) __attribute__((always_inline)) { return &stg[st][0]; };
+    auto Bs = [&](int st) __attribute__((always_inline)) { return &stg[st][Cf::A_ELEMS]; };
+    VL* Vp = reinterpret_cast<VL*>(&stg[0][0]);
     __shared__ int flt[kMaxIntervals][2][4];  // per interval: up to two faults (row, col, pflip, bit)
     __shared__ int fltn[kMaxIntervals];
 
@@ -140,26 +156,33 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
     constexpr int APT = TA ? BK * BM / NT : BM / LPT;   // elements per thread
     constexpr int BPT = TB ? BN / LPT : BK * BN / NT;
     static_assert(APT == Cf::NA && BPT == Cf::NB, "staging count");
-    // A: TA=0 -> (i = tid%LPT + LPT q, p = tid/LPT); TA=1 -> (i = tid%BM, p = (tid/BM)*APT + q)
-    const int ai0 = TA ? tid % BM : tid % LPT;
-    const int ap0 = TA ? (tid / BM) * APT : tid / LPT;
-    // B: TB=1 -> (j = tid%LPT + LPT q, p = tid/LPT); TB=0 -> (j = tid%BN, p = (tid/BN)*BPT + q)
-    const int bj0 = TB ? tid % LPT : tid % BN;
-    const int bp0 = TB ? tid / LPT : (tid / BN) * BPT;
-    auto a_ip = [&](int q, int* i, int* p) __attribute__((always_inline)) {
-        if (TA) { *i = ai0; *p = ap0 + q; } else { *i = ai0 + LPT * q; *p = ap0; }
-    };
-    auto b_jp = [&](int q, int* j, int* p) __attribute__((always_inline)) {
-        if (TB) { *j = bj0 + LPT * q; *p = bp0; } else { *j = bj0; *p = bp0 + q; }
-    };
     const int64_t lda = args.lda, ldb = args.ldb;
-    const int a_voff = (int)((TA ? (ap0 + (int64_t)ai0 * lda) : (ai0 + (int64_t)ap0 * lda)) * 8);
-    const int b_voff = (int)((TB ? (bj0 + (int64_t)bp0 * ldb) : (bp0 + (int64_t)bj0 * ldb)) * 8);
+    // the staging map of thread t_ (its first element of each panel)
+    struct SMap { int ai0, ap0, bj0, bp0, a_voff, b_voff; };
+    auto smap = [&](int t_) __attribute__((always_inline)) {
+        SMap m;
+        // A: TA=0 -> (i = t%LPT + LPT q, p = t/LPT); TA=1 -> (i = t%BM, p = (t/BM)*APT + q)
+        m.ai0 = TA ? t_ % BM : t_ % LPT;
+        m.ap0 = TA ? (t_ / BM) * APT : t_ / LPT;
+        // B: TB=1 -> (j = t%LPT + LPT q, p = t/LPT); TB=0 -> (j = t%BN, p = (t/BN)*BPT + q)
+        m.bj0 = TB ? t_ % LPT : t_ % BN;
+        m.bp0 = TB ? t_ / LPT : (t_ / BN) * BPT;
+        m.a_voff = (int)((TA ? (m.ap0 + (int64_t)m.ai0 * lda) : (m.ai0 + (int64_t)m.ap0 * lda)) * 8);
+        m.b_voff = (int)((TB ? (m.bj0 + (int64_t)m.bp0 * ldb) : (m.bp0 + (int64_t)m.bj0 * ldb)) * 8);
+        return m;
+    };
+    auto a_ip = [&](const SMap& M, int q, int* i, int* p) __attribute__((always_inline)) {
+        if (TA) { *i = M.ai0; *p = M.ap0 + q; } else { *i = M.ai0 + LPT * q; *p = M.ap0; }
+    };
+    auto b_jp = [&](const SMap& M, int q, int* j, int* p) __attribute__((always_inline)) {
+        if (TB) { *j = M.bj0 + LPT * q; *p = M.bp0; } else { *j = M.bj0; *p = M.bp0 + q; }
+    };
     constexpr int a_qstep = TA ? 8 : 8 * LPT, b_qstep = TB ? 8 * LPT : 8;  // bytes per q
     const bool full_mn = (R == BM) && (Q == BN);
+    const SMap M0 = smap(tid);  // register staging outside the direct kernels
 
     double rsum = 0.0;  // encode-pass value staged by threads tid < 4 BK
-    auto load_global = [&](int kb) __attribute__((always_inline)) {
+    auto load_global = [&](int kb, const SMap& M) __attribute__((always_inline)) {
         const int64_t k0 = (int64_t)kb * BK;
         const int kv = (int)min((int64_t)BK, K - k0);
         if constexpr (ABFT && PRE) {
@@ -174,39 +197,115 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
         const __amdgpu_buffer_rsrc_t rb_ = make_rsrc(TB ? B + n0 + k0 * ldb : B + k0 + n0 * ldb);
         if (full_mn && kv == BK) {
 #pragma unroll
-            for (int q = 0; q < APT; ++q) ra[q] = buf_load_f64(ra_, a_voff + q * a_qstep, 0);
+            for (int q = 0; q < APT; ++q) ra[q] = buf_load_f64(ra_, M.a_voff + q * a_qstep, 0);
 #pragma unroll
-            for (int q = 0; q < BPT; ++q) rb[q] = buf_load_f64(rb_, b_voff + q * b_qstep, 0);
+            for (int q = 0; q < BPT; ++q) rb[q] = buf_load_f64(rb_, M.b_voff + q * b_qstep, 0);
         } else {
 #pragma unroll
             for (int q = 0; q < APT; ++q) {
                 int i, p;
-                a_ip(q, &i, &p);
-                ra[q] = buf_load_f64(ra_, (i < R && p < kv) ? a_voff + q * a_qstep : kOOB, 0);
+                a_ip(M, q, &i, &p);
+                ra[q] = buf_load_f64(ra_, (i < R && p < kv) ? M.a_voff + q * a_qstep : kOOB, 0);
             }
 #pragma unroll
             for (int q = 0; q < BPT; ++q) {
                 int j, p;
-                b_jp(q, &j, &p);
-                rb[q] = buf_load_f64(rb_, (j < Q && p < kv) ? b_voff + q * b_qstep : kOOB, 0);
+                b_jp(M, q, &j, &p);
+                rb[q] = buf_load_f64(rb_, (j < Q && p < kv) ? M.b_voff + q * b_qstep : kOOB, 0);
             }
         }
     };
-    auto store_lds = [&](int st) __attribute__((always_inline)) {
+    auto store_lds = [&](int st, const SMap& M) __attribute__((always_inline)) {
         if constexpr (ABFT && PRE) {
-            if (tid < 4 * BK) sums[st][tid >> 2][tid & 3] = rsum;
+            if (tid < 4 * BK) sums[st][(tid & 3) >> 1][tid >> 2][tid & 1] = rsum;
         }
 #pragma unroll
         for (int q = 0; q < APT; ++q) {
             int i, p;
-            a_ip(q, &i, &p);
-            As[st][Cf::a_idx(i, p)] = ra[q];
+            a_ip(M, q, &i, &p);
+            As(st)[Cf::a_idx(i, p)] = ra[q];
         }
 #pragma unroll
         for (int q = 0; q < BPT; ++q) {
             int j, p;
-            b_jp(q, &j, &p);
-            Bs[st][Cf::b_idx(p, j)] = rb[q];
+            b_jp(M, q, &j, &p);
+            Bs(st)[Cf::b_idx(p, j)] = rb[q];
+        }
+    };
+    // Direct staging of full k-block kb of an interior tile into stage st: each
+    // active lane's 16-byte load lands in LDS at the wave load's base plus
+    // 16 * lane, with no registers in between (the loads complete by the
+    // barrier that publishes the stage).
+    //   lines along the tile ([p][x], pitch X + 16): one wave load per 128
+    //   elements of a step, all lanes active;
+    //   lines along k ([x][p], 9 slots per line): wave load I covers slots
+    //   64 I .. 64 I + 63, lane l slot s = 64 I + l = line s / 9, step pair
+    //   s % 9, the ninth (padding) slot of each line masked off.
+    typedef __attribute__((address_space(3))) void* lds_ptr;
+    auto direct_operand = [&]<bool KC, int X>(const double* base, int64_t ld, double* dst, int pitch)
+        __attribute__((always_inline)) {
+        const __amdgpu_buffer_rsrc_t r = make_rsrc(base);
+        if constexpr (KC) {
+            constexpr int NI = X * (BK / 2 + 1) / 64;  // wave loads per operand
+            static_assert(X * (BK / 2 + 1) % 64 == 0, "whole wave loads");
+#pragma unroll
+            for (int q = 0; q < (NI + Cf::NW - 1) / Cf::NW; ++q) {
+                const int I = wave + q * Cf::NW;
+                if (I < NI) {
+                    const int sl = 64 * I + lane;
+                    const int x = sl / (BK / 2 + 1), pair = sl - x * (BK / 2 + 1);
+                    if (pair < BK / 2)
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)(dst + 128 * I), 16,
+                                                                 (int)(((int64_t)x * ld + 2 * pair) * 8), 0, 0, 0);
+                }
+            }
+        } else {
+            constexpr int PER = X / 128;  // wave loads per step
+            constexpr int NL = BK * PER / Cf::NW;
+            static_assert(BK * PER % Cf::NW == 0, "equal shares of wave loads");
+#pragma unroll
+            for (int q = 0; q < NL; ++q) {
+                const int L = wave * NL + q;
+                const int p = L / PER, part = L % PER;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)(dst + p * pitch + part * 128), 16, lane * 16,
+                                                         (int)(((int64_t)p * ld + part * 128) * 8), 0, 0);
+            }
+        }
+    };
+    auto direct_block = [&](int kb, int st) __attribute__((always_inline)) {
+        const int64_t k0 = (int64_t)kb * BK;
+        if constexpr (TA) direct_operand.template operator()<true, BM>(A + k0 + m0 * lda, lda, As(st), 0);
+        else direct_operand.template operator()<false, BM>(A + m0 + k0 * lda, lda, As(st), Cf::SA);
+        if constexpr (TB) direct_operand.template operator()<false, BN>(B + n0 + k0 * ldb, ldb, Bs(st), Cf::SB);
+        else direct_operand.template operator()<true, BN>(B + k0 + n0 * ldb, ldb, Bs(st), 0);
+        if constexpr (ABFT && PRE) {
+            // encode-pass sums of the block's 16 steps: 16 lanes per operand
+            if (wave == 0 && lane < BK) {
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(make_rsrc(args.asp + ((int64_t)tm * K + k0) * 2),
+                                                         (lds_ptr)&sums[st][0][0][0], 16, lane * 16, 0, 0, 0);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(make_rsrc(args.bsp + ((int64_t)tn * K + k0) * 2),
+                                                         (lds_ptr)&sums[st][1][0][0], 16, lane * 16, 0, 0, 0);
+            }
+        }
+    };
+    // full k-blocks, and whether this tile stages them directly
+    const int full_kb = (int)(K / BK);
+    static_assert(!DIR || (Cf::DIRECT && (!ABFT || PRE)), "direct staging configuration");
+    const bool direct = DIR && full_mn;
+    // stage block kb into st before any MFMA of the current block: directly, or
+    // (edge tiles, the k tail) through registers whose live range ends here
+    auto stage_now = [&](int kb, int st) __attribute__((always_inline)) {
+        if (direct && kb < full_kb) {
+            direct_block(kb, st);
+        } else {
+            // the staging map is rebuilt here from an opaque copy of the thread
+            // id, so that none of it is hoisted into registers held across the
+            // k loop (this path is rare: edge tiles and the k tail)
+            int t_ = tid;
+            asm volatile("" : "+v"(t_));
+            const SMap M = smap(t_);
+            load_global(kb, M);
+            store_lds(st, M);
         }
     };
     // ---- a1: checksum row/column of the encoded operands for the staged k-block
@@ -224,20 +323,20 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
             e.sa = e.saa = e.sb = e.sba = 0.0;
 #pragma unroll
             for (int u = 0; u < UA / 2; ++u) {
-                const double v = As[st][Cf::a_idx(sub + u * Cf::LPP, p)];
+                const double v = As(st)[Cf::a_idx(sub + u * Cf::LPP, p)];
                 e.sa += v;
                 e.saa += fabs(v);
             }
         } else if (slice == 1) {
 #pragma unroll
             for (int u = UA / 2; u < UA; ++u) {
-                const double v = As[st][Cf::a_idx(sub + u * Cf::LPP, p)];
+                const double v = As(st)[Cf::a_idx(sub + u * Cf::LPP, p)];
                 e.sa += v;
                 e.saa += fabs(v);
             }
 #pragma unroll
             for (int u = 0; u < UB; ++u) {
-                const double v = Bs[st][Cf::b_idx(p, sub + u * Cf::LPP)];
+                const double v = Bs(st)[Cf::b_idx(p, sub + u * Cf::LPP)];
                 e.sb += v;
                 e.sba += fabs(v);
             }
@@ -248,10 +347,10 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
             e.sb = group_sum<Cf::LPP>(e.sb);
             e.sba = group_sum<Cf::LPP>(e.sba);
             if (sub == 0) {
-                sums[st][p][0] = e.sa;
-                sums[st][p][1] = e.saa;
-                sums[st][p][2] = e.sb;
-                sums[st][p][3] = e.sba;
+                sums[st][0][p][0] = e.sa;
+                sums[st][0][p][1] = e.saa;
+                sums[st][1][p][0] = e.sb;
+                sums[st][1][p][1] = e.sba;
             }
         }
     };
@@ -264,48 +363,84 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
     // the next rank-4 step are read from LDS while the current step's MFMAs run;
     // the scheduling fence keeps the compiler from hoisting further reads.
     // WRc, WCc: this wave's position, as compile-time constants so that its
-    // share of the checksum updates is fixed at compile time (no selects).
+    // share of the checksum updates is fixed at compile time (no selects), or
+    // -1: one copy of the loop for all waves (its loop-invariant addresses do
+    // not multiply), which reads the step's sums and its share's fragments
+    // from LDS where the checksum updates use them (fewer live registers).
     auto mfma_block = [&]<int WRc, int WCc, bool ENC>(int st) __attribute__((always_inline)) {
         EncAcc enc;
         constexpr int NS = BK / 4;
         double a[2][FM], b[2][FN], sm[2][4];
+        // the layouts are linear in both indices: one per-lane base per operand
+        // and compile-time offsets for the fragment (g, h) and step s_
+        const double* abase = As(st) + Cf::a_idx(wm0 + l16, lq);
+        const double* bbase = Bs(st) + Cf::b_idx(lq, wn0 + l16);
         auto load_frag = [&](int s_, int buf) __attribute__((always_inline)) {
             const int p = 4 * s_ + lq;
 #pragma unroll
-            for (int g = 0; g < FM; ++g) a[buf][g] = As[st][Cf::a_idx(wm0 + 16 * g + l16, p)];
+            for (int g = 0; g < FM; ++g) a[buf][g] = abase[Cf::a_idx(16 * g, 4 * s_)];
 #pragma unroll
-            for (int h = 0; h < FN; ++h) b[buf][h] = Bs[st][Cf::b_idx(p, wn0 + 16 * h + l16)];
-            if (ABFT) {
+            for (int h = 0; h < FN; ++h) b[buf][h] = bbase[Cf::b_idx(4 * s_, 16 * h)];
+            if (ABFT && WRc >= 0) {
 #pragma unroll
-                for (int c = 0; c < 4; ++c) sm[buf][c] = sums[st][p][c];
+                for (int c = 0; c < 4; ++c) sm[buf][c] = sums[st][c >> 1][p][c & 1];
             }
         };
-        load_frag(0, 0);
+        // one-copy loop (run at four waves per SIMD): each step's fragments are
+        // read at its start, the other waves' MFMAs cover the LDS latency;
+        // otherwise the next step's fragments are read during this step's MFMAs
+        constexpr bool JIT = WRc < 0;
+        if (!JIT) load_frag(0, 0);
 #pragma unroll
         for (int s_ = 0; s_ < NS; ++s_) {
-            const int cur = s_ & 1;
-            if (s_ + 1 < NS) load_frag(s_ + 1, cur ^ 1);
+            const int cur = JIT ? 0 : (s_ & 1);
+            if (JIT) load_frag(s_, 0);
+            else if (s_ + 1 < NS) load_frag(s_ + 1, cur ^ 1);
 #pragma unroll
             for (int g = 0; g < FM; ++g)
 #pragma unroll
                 for (int h = 0; h < FN; ++h)
                     acc[g][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[cur][g], b[cur][h], acc[g][h], 0, 0, 0);
             if (ABFT) {
-                const double as_ = sm[cur][0], asa = sm[cur][1], bs_ = sm[cur][2], bsa = sm[cur][3];
                 // this wave's share of the rows (columns) that the waves of its
                 // wave-row (wave-column) have in common
+                if constexpr (WRc < 0) {
+                    const double* sp = &sums[st][0][lq][0] + 8 * s_;  // step 4 s_ + lq
+                    const double as_ = sp[0], asa = sp[1];
+                    const double bs_ = sp[2 * BK], bsa = sp[2 * BK + 1];
 #pragma unroll
-                for (int g = 0; g < FM; ++g)
-                    if (g % WGN == WCc) {
-                        er[g / WGN] = fma(a[cur][g], bs_, er[g / WGN]);
-                        mr[g / WGN] = fma(fabs(a[cur][g]), bsa, mr[g / WGN]);
+                    for (int q = 0; q < Cf::GSH; ++q) {
+                        const double x = abase[Cf::a_idx(16 * (q * WGN + wc), 4 * s_)];
+                        er[q] = fma(x, bs_, er[q]);
+                        mr[q] = fma(fabs(x), bsa, mr[q]);
                     }
 #pragma unroll
-                for (int h = 0; h < FN; ++h)
-                    if (h % WGM == WRc) {
-                        ec[h / WGM] = fma(as_, b[cur][h], ec[h / WGM]);
-                        mc[h / WGM] = fma(asa, fabs(b[cur][h]), mc[h / WGM]);
+                    for (int q = 0; q < Cf::HSH; ++q) {
+                        const double y = bbase[Cf::b_idx(4 * s_, 16 * (q * WGM + wr))];
+                        ec[q] = fma(as_, y, ec[q]);
+                        mc[q] = fma(asa, fabs(y), mc[q]);
                     }
+                    // keep the updates in this step (sinking them out of the
+                    // k-block would hold every step's operands live)
+#pragma unroll
+                    for (int q = 0; q < Cf::GSH; ++q) asm volatile("" : "+v"(er[q]), "+v"(mr[q]));
+#pragma unroll
+                    for (int q = 0; q < Cf::HSH; ++q) asm volatile("" : "+v"(ec[q]), "+v"(mc[q]));
+                } else {
+                    const double as_ = sm[cur][0], asa = sm[cur][1], bs_ = sm[cur][2], bsa = sm[cur][3];
+#pragma unroll
+                    for (int g = 0; g < FM; ++g)
+                        if (g % WGN == WCc) {
+                            er[g / WGN] = fma(a[cur][g], bs_, er[g / WGN]);
+                            mr[g / WGN] = fma(fabs(a[cur][g]), bsa, mr[g / WGN]);
+                        }
+#pragma unroll
+                    for (int h = 0; h < FN; ++h)
+                        if (h % WGM == WRc) {
+                            ec[h / WGM] = fma(as_, b[cur][h], ec[h / WGM]);
+                            mc[h / WGM] = fma(asa, fabs(b[cur][h]), mc[h / WGM]);
+                        }
+                }
             }
             if (ENC) encode_slice(st ^ 1, s_, enc);
             __builtin_amdgcn_sched_barrier(0);
@@ -371,9 +506,9 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
                         f.bit, ck ? FTG_TARGET_CHECKSUM : FTG_TARGET_ACC, oldv, newv);
     };
 
-    // ---- a4 + a5 + a6: reductions and flags; results in V.nfr / V.nfc (and the
+    // ---- a4 + a5 + a6: reductions and flags; results in Vp->nfr / Vp->nfc (and the
     // first flagged row/column with its delta and tau).  On a final check acc
-    // holds C_out and the C_in sums are in V.
+    // holds C_out and the C_in sums are in Vp->
     auto reduce_and_flag = [&](bool final, int64_t pend) __attribute__((always_inline)) {
 #pragma unroll
         for (int g = 0; g < FM; ++g) {
@@ -383,7 +518,7 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
 #pragma unroll
                 for (int h = 0; h < FN; ++h) s += acc[g][h][r];
                 s = group_sum<16>(s);
-                if (l16 == 0) V.rsum[wc][wm0 + 16 * g + 4 * r + lq] = s;
+                if (l16 == 0) Vp->rsum[wc][wm0 + 16 * g + 4 * r + lq] = s;
             }
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -395,7 +530,7 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
 #pragma unroll
                 for (int r = 0; r < 4; ++r) s += acc[g][h][r];
             s = quarter_sum(s);
-            if (lq == 0) V.csum[wr][wn0 + 16 * h + l16] = s;
+            if (lq == 0) Vp->csum[wr][wn0 + 16 * h + l16] = s;
         }
         // maintained checksums: complete after summing the four p lanes
 #pragma unroll
@@ -403,8 +538,8 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
             const double e = quarter_sum(er[q]), mm = quarter_sum(mr[q]);
             if (lq == 0) {
                 const int row = wm0 + 16 * (q * WGN + wc) + l16;
-                V.er[row] = e;
-                V.mr[row] = mm;
+                Vp->er[row] = e;
+                Vp->mr[row] = mm;
             }
         }
 #pragma unroll
@@ -412,11 +547,11 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
             const double e = quarter_sum(ec[q]), mm = quarter_sum(mc[q]);
             if (lq == 0) {
                 const int col = wn0 + 16 * (q * WGM + wr) + l16;
-                V.ec[col] = e;
-                V.mc[col] = mm;
+                Vp->ec[col] = e;
+                Vp->mc[col] = mm;
             }
         }
-        if (tid == 0) { V.nfr = 0; V.nfc = 0; }
+        if (tid == 0) { Vp->nfr = 0; Vp->nfc = 0; }
         __syncthreads();
         const bool cin = final && args.beta != 0.0;
         for (int line = tid; line < BM + BN; line += NT) {
@@ -427,18 +562,18 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
             if (isrow) {
 #pragma unroll
                 for (int w = 0; w < WGN; ++w) {
-                    ref += V.rsum[w][x];
-                    if (cin) { ci += V.cir[w][x]; cia += V.cira[w][x]; }
+                    ref += Vp->rsum[w][x];
+                    if (cin) { ci += Vp->cir[w][x]; cia += Vp->cira[w][x]; }
                 }
             } else {
 #pragma unroll
                 for (int w = 0; w < WGM; ++w) {
-                    ref += V.csum[w][x];
-                    if (cin) { ci += V.cic[w][x]; cia += V.cica[w][x]; }
+                    ref += Vp->csum[w][x];
+                    if (cin) { ci += Vp->cic[w][x]; cia += Vp->cica[w][x]; }
                 }
             }
-            double ex = isrow ? V.er[x] : V.ec[x];
-            double mag = isrow ? V.mr[x] : V.mc[x];
+            double ex = isrow ? Vp->er[x] : Vp->ec[x];
+            double mag = isrow ? Vp->mr[x] : Vp->mc[x];
             if (final) {
                 ex = args.alpha * ex;
                 mag = fabs(args.alpha) * mag;
@@ -448,9 +583,9 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
             const double tau = tau_of(0, 0.0, pend + (isrow ? Q : R) + 8, mag);
             if (flagged(d, tau)) {
                 if (isrow) {
-                    if (atomicAdd(&V.nfr, 1) == 0) { V.fi = x; V.dfi = d; V.tfi = tau; }
+                    if (atomicAdd(&Vp->nfr, 1) == 0) { Vp->fi = x; Vp->dfi = d; Vp->tfi = tau; }
                 } else {
-                    if (atomicAdd(&V.nfc, 1) == 0) { V.fj = x; V.dfj = d; V.tfj = tau; }
+                    if (atomicAdd(&Vp->nfc, 1) == 0) { Vp->fj = x; Vp->dfj = d; Vp->tfj = tau; }
                 }
             }
         }
@@ -468,10 +603,10 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
                 s = fma(a, b, s);
             }
             s = group_sum<64>(s);
-            if (lane == 0) V.dotv = s;
+            if (lane == 0) Vp->dotv = s;
         }
         __syncthreads();
-        return V.dotv;
+        return Vp->dotv;
     };
 
     // ---- a7: verification of one slot (a small state machine around one
@@ -488,55 +623,55 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
         double dfi = 0.0, tfi = 0.0, xold = 0.0;
         for (;;) {
             reduce_and_flag(final, pend);
-            const int nr = __builtin_amdgcn_readfirstlane(V.nfr);
-            const int nc = __builtin_amdgcn_readfirstlane(V.nfc);
+            const int nr = __builtin_amdgcn_readfirstlane(Vp->nfr);
+            const int nc = __builtin_amdgcn_readfirstlane(Vp->nfc);
             int kind = 0;  // outcome to record; 0 = try the recompute next
             if (stage == 0) {
                 if (nr == 0 && nc == 0) return false;
                 if (tid == 0) atomicAdd(&args.rep->cnt[kDetected], 1ull);
                 if (nr == 1 && nc == 1) {
-                    fi = __builtin_amdgcn_readfirstlane(V.fi);
-                    fj = __builtin_amdgcn_readfirstlane(V.fj);
-                    dfi = V.dfi;
-                    tfi = V.tfi;
+                    fi = __builtin_amdgcn_readfirstlane(Vp->fi);
+                    fj = __builtin_amdgcn_readfirstlane(Vp->fj);
+                    dfi = Vp->dfi;
+                    tfi = Vp->tfi;
                     own = owner_of(fi, fj);
                     idx = __builtin_amdgcn_readfirstlane(elem_index(fi, fj));
                     const double x = get_elem(idx);
                     __syncthreads();
-                    if (own) { V.xold = x; V.xfinite = isfinite(x) ? 1 : 0; }
+                    if (own) { Vp->xold = x; Vp->xfinite = isfinite(x) ? 1 : 0; }
                     __syncthreads();
-                    xold = V.xold;
+                    xold = Vp->xold;
                     stage = 1;
                     if (args.correct_policy == 0 && isfinite(dfi) &&
-                        __builtin_amdgcn_readfirstlane(V.xfinite) && !absorbed(false, xold, tfi, Q)) {
+                        __builtin_amdgcn_readfirstlane(Vp->xfinite) && !absorbed(false, xold, tfi, Q)) {
                         set_elem(idx, xold - dfi, own);  // subtract the error (§6.3)
                         continue;
                     }
                 } else if (nr + nc == 1) {
                     // one direction only: the maintained checksum is the faulty value;
                     // re-base it on the data for the following intervals
-                    const int fr = __builtin_amdgcn_readfirstlane(V.fi);
-                    const int fc = __builtin_amdgcn_readfirstlane(V.fj);
+                    const int fr = __builtin_amdgcn_readfirstlane(Vp->fi);
+                    const int fc = __builtin_amdgcn_readfirstlane(Vp->fj);
                     if (!final) {
                         if (nr) {
                             const int g = (fr % WM) / 16;
 #pragma unroll
                             for (int q = 0; q < Cf::GSH; ++q)
                                 if (q == g / WGN && fr / WM == wr && g % WGN == wc && lane == fr % 16)
-                                    er[q] += V.dfi;
+                                    er[q] += Vp->dfi;
                         } else {
                             const int h = (fc % WN) / 16;
 #pragma unroll
                             for (int q = 0; q < Cf::HSH; ++q)
                                 if (q == h / WGM && fc / WN == wc && h % WGM == wr && lane == fc % 16)
-                                    ec[q] += V.dfj;
+                                    ec[q] += Vp->dfj;
                         }
                     }
                     if (tid == 0) {
                         atomicAdd(&args.rep->cnt[kChecksumOnly], 1ull);
                         push_record(args.rep, args.problem, tm, tn, t, nr ? m0 + fr : -1,
-                                    nr ? -1 : n0 + fc, FTG_KIND_CHECKSUM_ONLY, nr ? V.dfi : V.dfj,
-                                    nr ? V.tfi : V.tfj);
+                                    nr ? -1 : n0 + fc, FTG_KIND_CHECKSUM_ONLY, nr ? Vp->dfi : Vp->dfj,
+                                    nr ? Vp->tfi : Vp->tfj);
                     }
                     __syncthreads();
                     return false;
@@ -572,8 +707,8 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
                 if (kind >= FTG_KIND_UNCORRECTABLE) atomicAdd(&args.rep->cnt[kUncorrectable], 1ull);
                 if (kind == FTG_KIND_TILE_RECOMPUTED) atomicAdd(&args.rep->cnt[kTilesRecomputed], 1ull);
                 const bool loc = kind == FTG_KIND_SUBTRACT || kind == FTG_KIND_RECOMPUTE;
-                const double d = (stage > 0) ? dfi : (nr ? V.dfi : V.dfj);
-                const double tt = (stage > 0) ? tfi : (nr ? V.tfi : V.tfj);
+                const double d = (stage > 0) ? dfi : (nr ? Vp->dfi : Vp->dfj);
+                const double tt = (stage > 0) ? tfi : (nr ? Vp->tfi : Vp->tfj);
                 push_record(args.rep, args.problem, tm, tn, t, loc ? m0 + fi : -1, loc ? n0 + fj : -1,
                             kind, d, tt);
             }
@@ -620,8 +755,8 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
                     s = group_sum<16>(s);
                     sa = group_sum<16>(sa);
                     if (l16 == 0) {
-                        V.cir[wc][wm0 + 16 * g + 4 * r + lq] = s;
-                        V.cira[wc][wm0 + 16 * g + 4 * r + lq] = sa;
+                        Vp->cir[wc][wm0 + 16 * g + 4 * r + lq] = s;
+                        Vp->cira[wc][wm0 + 16 * g + 4 * r + lq] = sa;
                     }
                 }
                 __builtin_amdgcn_sched_barrier(0);
@@ -630,7 +765,7 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
 #pragma unroll
             for (int h = 0; h < FN; ++h) {
                 const double s = quarter_sum(cs[h]), sa = quarter_sum(csa[h]);
-                if (lq == 0) { V.cic[wr][wn0 + 16 * h + l16] = s; V.cica[wr][wn0 + 16 * h + l16] = sa; }
+                if (lq == 0) { Vp->cic[wr][wn0 + 16 * h + l16] = s; Vp->cica[wr][wn0 + 16 * h + l16] = sa; }
             }
         }
     };
@@ -681,12 +816,15 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
     for (;;) {
         zero_state();
         t = 0;
-        load_global(0);
-        store_lds(0);
+        if constexpr (DIR) stage_now(0, 0);
+        else {
+            load_global(0, M0);
+            store_lds(0, M0);
+        }
         __syncthreads();
         if (ABFT && !PRE) {
             encode(0);
-            if (nkb > 1) load_global(1);
+            if (nkb > 1) load_global(1, M0);
             __syncthreads();
         }
         bool restart = false;
@@ -701,34 +839,44 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
                     if (fkb >= kb && fkb + 1 < seg) seg = fkb + 1;
                 }
             }
-            // the hot loop, instantiated per wave position (uniform dispatch)
+            // the hot loop, instantiated per wave position (uniform dispatch), or
+            // once for all waves (W = -1) with direct staging
             auto hot = [&]<int W>() __attribute__((always_inline)) {
+                constexpr int WR = W < 0 ? -1 : W / WGN, WC = W < 0 ? -1 : W % WGN;
                 for (; kb < seg; ++kb) {
                     const int st = kb & 1;
-                    if (!ABFT || PRE) {
+                    if (DIR) {
+                        if (kb + 1 < nkb) stage_now(kb + 1, st ^ 1);
+                        mfma_block.template operator()<WR, WC, false>(st);
+                        if (kb + 1 < nkb) __syncthreads();
+                    } else if (!ABFT || PRE) {
                         // (with the encode pass, the checksum updates need no
                         // extra barrier: the sums travel with the operands)
-                        if (kb + 1 < nkb) load_global(kb + 1);
-                        mfma_block.template operator()<W / WGN, W % WGN, false>(st);
+                        if (kb + 1 < nkb) load_global(kb + 1, M0);
+                        mfma_block.template operator()<WR, WC, false>(st);
                         if (kb + 1 < nkb) {
-                            store_lds(st ^ 1);
+                            store_lds(st ^ 1, M0);
                             __syncthreads();
                         }
                     } else if (kb + 1 < nkb) {
                         // block kb+1: staged now, encoded while block kb's MFMAs run
-                        store_lds(st ^ 1);
+                        store_lds(st ^ 1, M0);
                         __syncthreads();
-                        if (kb + 2 < nkb) load_global(kb + 2);
-                        mfma_block.template operator()<W / WGN, W % WGN, true>(st);
+                        if (kb + 2 < nkb) load_global(kb + 2, M0);
+                        mfma_block.template operator()<WR, WC, true>(st);
                         __syncthreads();
                     } else {
-                        mfma_block.template operator()<W / WGN, W % WGN, false>(st);
+                        mfma_block.template operator()<WR, WC, false>(st);
                     }
                 }
             };
-            [&]<int... W>(std::integer_sequence<int, W...>) __attribute__((always_inline)) {
-                ((wave == W ? (hot.template operator()<W>(), 0) : 0), ...);
-            }(std::make_integer_sequence<int, WGM * WGN>{});
+            if constexpr (DIR) {
+                hot.template operator()<-1>();
+            } else {
+                [&]<int... W>(std::integer_sequence<int, W...>) __attribute__((always_inline)) {
+                    ((wave == W ? (hot.template operator()<W>(), 0) : 0), ...);
+                }(std::make_integer_sequence<int, WGM * WGN>{});
+            }
             if (!ABFT) continue;
             // accumulators now hold the sum over steps [0, kb * BK)
             if (inj) {
@@ -738,7 +886,9 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
                         apply_fault(load_fault(t, q), t);
             }
             if (IVL && kb < nkb && kb % kb_per_int == 0) {
-                // a10: online verification of the accumulators at the interval end
+                // a10: online verification of the accumulators at the interval end.
+                // Stage kb & 1 holds block kb; the other stage is free.
+                Vp = reinterpret_cast<VL*>(&stg[(kb - 1) & 1][0]);
                 if (verify(false, (int64_t)kb * BK, t)) {
                     --redo_budget;
                     inj_from = t + 1;  // replay intervals 0..t fault-free
@@ -746,17 +896,23 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
                     break;
                 }
                 ++t;
+                __syncthreads();  // every read of the bookkeeping ends before the stage is refilled
             }
         }
         if (restart) { __syncthreads(); continue; }
+        if (ABFT) {
+            // the last block's fragment reads end before the bookkeeping reuses stage 0
+            Vp = reinterpret_cast<VL*>(&stg[0][0]);
+            __syncthreads();
+        }
         finalize_output();
         if (!ABFT) break;
         // a5-a7 on the output: flags in registers; a located element is repaired
         // after the store, from global memory
         __syncthreads();
         reduce_and_flag(true, K);
-        const int nr = __builtin_amdgcn_readfirstlane(V.nfr);
-        const int nc = __builtin_amdgcn_readfirstlane(V.nfc);
+        const int nr = __builtin_amdgcn_readfirstlane(Vp->nfr);
+        const int nc = __builtin_amdgcn_readfirstlane(Vp->nfc);
         if (nr == 0 && nc == 0) break;
         const bool many = nr > 1 || nc > 1;
         if (many && args.uncorrectable_policy == 1 && redo_budget > 0) {
@@ -766,7 +922,7 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
                 atomicAdd(&args.rep->cnt[kUncorrectable], 1ull);
                 atomicAdd(&args.rep->cnt[kTilesRecomputed], 1ull);
                 push_record(args.rep, args.problem, tm, tn, t, -1, -1, FTG_KIND_TILE_RECOMPUTED,
-                            nr ? V.dfi : V.dfj, nr ? V.tfi : V.tfj);
+                            nr ? Vp->dfi : Vp->dfj, nr ? Vp->tfi : Vp->tfj);
             }
             __syncthreads();
             --redo_budget;
@@ -778,23 +934,23 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
         if (tid == 0) {
             RepairReq q;
             q.problem = args.problem; q.tm = tm; q.tn = tn; q.interval = t;
-            q.nr = nr; q.nc = nc; q.fi = V.fi; q.fj = V.fj; q.R = R; q.Q = Q;
+            q.nr = nr; q.nc = nc; q.fi = Vp->fi; q.fj = Vp->fj; q.R = R; q.Q = Q;
             q.pad0 = q.pad1 = 0; q.m0 = m0; q.n0 = n0;
-            q.dfi = V.dfi; q.tfi = V.tfi; q.dfj = V.dfj; q.tfj = V.tfj;
+            q.dfi = Vp->dfi; q.tfi = Vp->tfi; q.dfj = Vp->dfj; q.tfj = Vp->tfj;
             const bool cin = args.beta != 0.0;
             double cr = 0.0, cc = 0.0;
             q.exp_row = q.exp_col = 0.0;
             if (nr) {
 #pragma unroll
-                for (int w = 0; w < WGN; ++w) cr += V.cir[w][V.fi];
-                q.exp_row = args.alpha * V.er[V.fi] + (cin ? args.beta * cr : 0.0);
+                for (int w = 0; w < WGN; ++w) cr += Vp->cir[w][Vp->fi];
+                q.exp_row = args.alpha * Vp->er[Vp->fi] + (cin ? args.beta * cr : 0.0);
             }
             if (nc) {
 #pragma unroll
-                for (int w = 0; w < WGM; ++w) cc += V.cic[w][V.fj];
-                q.exp_col = args.alpha * V.ec[V.fj] + (cin ? args.beta * cc : 0.0);
+                for (int w = 0; w < WGM; ++w) cc += Vp->cic[w][Vp->fj];
+                q.exp_col = args.alpha * Vp->ec[Vp->fj] + (cin ? args.beta * cc : 0.0);
             }
-            q.cin = (cin && nr == 1 && nc == 1) ? args.C[(m0 + V.fi) + (n0 + V.fj) * ldc] : 0.0;
+            q.cin = (cin && nr == 1 && nc == 1) ? args.C[(m0 + Vp->fi) + (n0 + Vp->fj) * ldc] : 0.0;
             push_repair(args.rep, q);
         }
         // C_in at the located element is read above before any wave stores
@@ -816,14 +972,25 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
     }
 }
 
+// Occupancy target of a kernel (the second launch bound: waves per SIMD the
+// register allocation must allow).  Direct-staging kernels whose accumulators
+// take at most 64 registers per lane aim at two workgroups per CU (their LDS
+// fits twice in 160 KB); the others use the configuration's MINB.
+template <int BM, int BN, int WGM, int WGN, int MINB, bool DIR>
+constexpr int waves_per_simd()
+{
+    constexpr int NW = WGM * WGN;
+    return (DIR && 2 * BM * BN / (NW * 64) <= 64 && NW % 2 == 0) ? NW / 2 : MINB;
+}
+
 // One problem, one workgroup per output tile.
-// MINB: workgroups per CU the register allocation must allow (occupancy target).
-template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool ABFT, bool IVL, int MINB, bool PRE>
-__global__ __launch_bounds__(WGM* WGN * 64, MINB) void dgemm_abft_kernel(DGemmArgs args)
+template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool ABFT, bool IVL, int MINB, bool PRE, bool DIR>
+__global__ __launch_bounds__(WGM* WGN * 64, (waves_per_simd<BM, BN, WGM, WGN, MINB, DIR>())) void dgemm_abft_kernel(
+    DGemmArgs args)
 {
     int tm, tn;
     tile_of_block(blockIdx.x, gridDim.x, args.tiles_m, args.tiles_n, 4, &tm, &tn);
-    dgemm_tile<BM, BN, WGM, WGN, TA, TB, ABFT, IVL, PRE>(args, tm, tn);
+    dgemm_tile<BM, BN, WGM, WGN, TA, TB, ABFT, IVL, PRE, DIR>(args, tm, tn);
 }
 
 // Many problems in one persistent launch.  Work item w is tile
@@ -833,8 +1000,9 @@ __global__ __launch_bounds__(WGM* WGN * 64, MINB) void dgemm_abft_kernel(DGemmAr
 // starts with item blockIdx.x and then takes the next free item from a
 // device counter until none is left; the last workgroup to finish resets the
 // counter for the next launch.
-template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool ABFT, bool IVL, int MINB, bool PRE>
-__global__ __launch_bounds__(WGM* WGN * 64, MINB) void dgemm_batched_kernel(BatchLaunch L)
+template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool ABFT, bool IVL, int MINB, bool PRE, bool DIR>
+__global__ __launch_bounds__(WGM* WGN * 64, (waves_per_simd<BM, BN, WGM, WGN, MINB, DIR>())) void dgemm_batched_kernel(
+    BatchLaunch L)
 {
     __shared__ int s_item;
     int item = blockIdx.x;
@@ -851,7 +1019,7 @@ __global__ __launch_bounds__(WGM* WGN * 64, MINB) void dgemm_batched_kernel(Batc
         const int local = item - L.first[p];
         const int tm = __builtin_amdgcn_readfirstlane(local % a.tiles_m);
         const int tn = __builtin_amdgcn_readfirstlane(local / a.tiles_m);
-        dgemm_tile<BM, BN, WGM, WGN, TA, TB, ABFT, IVL, PRE>(a, tm, tn);
+        dgemm_tile<BM, BN, WGM, WGN, TA, TB, ABFT, IVL, PRE, DIR>(a, tm, tn);
         // all LDS use of this tile ends before the next item is published
         __syncthreads();
         if (threadIdx.x == 0) s_item = (int)gridDim.x + (int)atomicAdd(&L.queue[0], 1u);
@@ -876,22 +1044,33 @@ hipError_t launch_tile(const DGemmArgs& a, bool abft, hipStream_t s)
     const bool ivl = abft && a.kc < a.k;
     if (ivl && !IVL_OK) return hipErrorInvalidValue;
     const bool pre = abft && a.asp != nullptr;
-#define FTG_L(TA_, TB_, AB_, IV_, PR_) \
-    hipLaunchKernelGGL((dgemm_abft_kernel<BM, BN, WGM, WGN, TA_, TB_, AB_, IV_, MINB, PR_>), grid, block, 0, s, a)
-#define FTG_T(AB_, IV_, PR_)                                       \
-    do {                                                           \
-        if (!a.ta && !a.tb) FTG_L(false, false, AB_, IV_, PR_);    \
-        else if (a.ta && !a.tb) FTG_L(true, false, AB_, IV_, PR_); \
-        else if (!a.ta && a.tb) FTG_L(false, true, AB_, IV_, PR_); \
-        else FTG_L(true, true, AB_, IV_, PR_);                     \
+    constexpr bool DOK = DCfg<BM, BN, WGM, WGN, false, false>::DIRECT;
+    const bool dir = DOK && a.lds_direct && (!abft || (pre && !ivl));
+#define FTG_L(TA_, TB_, AB_, IV_, PR_, DR_)                                                                 \
+    hipLaunchKernelGGL((dgemm_abft_kernel<BM, BN, WGM, WGN, TA_, TB_, AB_, IV_, MINB, PR_, DR_>), grid, block, 0, \
+                       s, a)
+#define FTG_T(AB_, IV_, PR_, DR_)                                       \
+    do {                                                                \
+        if (!a.ta && !a.tb) FTG_L(false, false, AB_, IV_, PR_, DR_);    \
+        else if (a.ta && !a.tb) FTG_L(true, false, AB_, IV_, PR_, DR_); \
+        else if (!a.ta && a.tb) FTG_L(false, true, AB_, IV_, PR_, DR_); \
+        else FTG_L(true, true, AB_, IV_, PR_, DR_);                     \
     } while (0)
-    if (!abft) FTG_T(false, false, false);
-    else if (!ivl) {
-        if (pre) FTG_T(true, false, true);
-        else FTG_T(true, false, false);
+    if (!abft) {
+        if constexpr (DOK) {
+            if (dir) FTG_T(false, false, false, true);
+            else FTG_T(false, false, false, false);
+        } else FTG_T(false, false, false, false);
+    } else if (!ivl) {
+        if (pre) {
+            if constexpr (DOK) {
+                if (dir) FTG_T(true, false, true, true);
+                else FTG_T(true, false, true, false);
+            } else FTG_T(true, false, true, false);
+        } else FTG_T(true, false, false, false);
     } else if constexpr (IVL_OK) {
-        if (pre) FTG_T(true, true, true);
-        else FTG_T(true, true, false);
+        if (pre) FTG_T(true, true, true, false);
+        else FTG_T(true, true, false, false);
     }
 #undef FTG_T
 #undef FTG_L
@@ -901,7 +1080,7 @@ hipError_t launch_tile(const DGemmArgs& a, bool abft, hipStream_t s)
 // Persistent grid: as many workgroups as are resident on the device at once
 // (from the kernel's register and LDS use), never more than there are work
 // items.  Queried once per kernel instantiation.
-template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool AB, bool IV, int MINB, bool PR>
+template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool AB, bool IV, int MINB, bool PR, bool DR>
 int batched_grid(int total)
 {
     static int resident = 0;
@@ -910,7 +1089,7 @@ int batched_grid(int total)
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, dgemm_batched_kernel<BM, BN, WGM, WGN, TA, TB, AB, IV, MINB, PR>, WGM * WGN * 64, 0) !=
+                &per_cu, dgemm_batched_kernel<BM, BN, WGM, WGN, TA, TB, AB, IV, MINB, PR, DR>, WGM * WGN * 64, 0) !=
                 hipSuccess)
             return std::min(total, 256);
         resident = std::max(1, cus) * std::max(1, per_cu);
@@ -919,29 +1098,40 @@ int batched_grid(int total)
 }
 
 template <int BM, int BN, int WGM, int WGN, bool IVL_OK, int MINB>
-hipError_t launch_batched(const BatchLaunch& L, int ta, int tb, bool abft, bool ivl, bool pre, hipStream_t s)
+hipError_t launch_batched(const BatchLaunch& L, int ta, int tb, bool abft, bool ivl, bool pre, bool lds_direct,
+                          hipStream_t s)
 {
     if (L.total <= 0) return hipSuccess;
     if (ivl && !IVL_OK) return hipErrorInvalidValue;
     const dim3 block(WGM * WGN * 64);
-#define FTG_L(TA_, TB_, AB_, IV_, PR_)                                                                         \
-    hipLaunchKernelGGL((dgemm_batched_kernel<BM, BN, WGM, WGN, TA_, TB_, AB_, IV_, MINB, PR_>),                  \
-                       dim3(batched_grid<BM, BN, WGM, WGN, TA_, TB_, AB_, IV_, MINB, PR_>(L.total)), block, 0, s, \
-                       L)
-#define FTG_T(AB_, IV_, PR_)                                  \
-    do {                                                      \
-        if (!ta && !tb) FTG_L(false, false, AB_, IV_, PR_);   \
-        else if (ta && !tb) FTG_L(true, false, AB_, IV_, PR_); \
-        else if (!ta && tb) FTG_L(false, true, AB_, IV_, PR_); \
-        else FTG_L(true, true, AB_, IV_, PR_);                \
+    constexpr bool DOK = DCfg<BM, BN, WGM, WGN, false, false>::DIRECT;
+    const bool dir = DOK && lds_direct && (!abft || (pre && !ivl));
+#define FTG_L(TA_, TB_, AB_, IV_, PR_, DR_)                                                                        \
+    hipLaunchKernelGGL((dgemm_batched_kernel<BM, BN, WGM, WGN, TA_, TB_, AB_, IV_, MINB, PR_, DR_>),                 \
+                       dim3(batched_grid<BM, BN, WGM, WGN, TA_, TB_, AB_, IV_, MINB, PR_, DR_>(L.total)), block, 0, \
+                       s, L)
+#define FTG_T(AB_, IV_, PR_, DR_)                                  \
+    do {                                                           \
+        if (!ta && !tb) FTG_L(false, false, AB_, IV_, PR_, DR_);   \
+        else if (ta && !tb) FTG_L(true, false, AB_, IV_, PR_, DR_); \
+        else if (!ta && tb) FTG_L(false, true, AB_, IV_, PR_, DR_); \
+        else FTG_L(true, true, AB_, IV_, PR_, DR_);                \
     } while (0)
-    if (!abft) FTG_T(false, false, false);
-    else if (!ivl) {
-        if (pre) FTG_T(true, false, true);
-        else FTG_T(true, false, false);
+    if (!abft) {
+        if constexpr (DOK) {
+            if (dir) FTG_T(false, false, false, true);
+            else FTG_T(false, false, false, false);
+        } else FTG_T(false, false, false, false);
+    } else if (!ivl) {
+        if (pre) {
+            if constexpr (DOK) {
+                if (dir) FTG_T(true, false, true, true);
+                else FTG_T(true, false, true, false);
+            } else FTG_T(true, false, true, false);
+        } else FTG_T(true, false, false, false);
     } else if constexpr (IVL_OK) {
-        if (pre) FTG_T(true, true, true);
-        else FTG_T(true, true, false);
+        if (pre) FTG_T(true, true, true, false);
+        else FTG_T(true, true, false, false);
     }
 #undef FTG_T
 #undef FTG_L

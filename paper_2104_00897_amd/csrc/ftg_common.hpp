@@ -166,6 +166,7 @@ __device__ inline bool absorbed(bool acc32, double x, double tau, int q)
 // elements outside the matrix are zero-filled without branches.
 constexpr int kOOB = (int)0x80000000u;
 
+
 __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* base)
 {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, 0x7FFFFFFF,

@@ -28,7 +28,16 @@ struct DGemmArgs {
     const double* asp;
     const double* bsp;
     int bm, bn;  // tile extent (panel rows of the encode pass)
+    // 1: A and B are 16-byte aligned with even lda, ldb, so the 16-byte slots of
+    // the operand panels can be loaded straight into LDS
+    int lds_direct;
+    int pad_;
 };
+
+inline int lds_direct_ok(const void* A, int64_t lda, const void* B, int64_t ldb)
+{
+    return ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0) && lda % 2 == 0 && ldb % 2 == 0;
+}
 
 // Encode pass of one FP64 operand: rows r (i of op(A) or j of op(B)) grouped in
 // panels of `panel` rows (the output-tile extent), steps p; element (r, p) at
@@ -85,19 +94,20 @@ inline hipError_t launch_dgemm(const DGemmArgs& a, int tile_id, bool abft, hipSt
     }
 }
 template <int BM, int BN, int WGM, int WGN, bool IVL_OK, int MINB>
-hipError_t launch_batched(const BatchLaunch& L, int ta, int tb, bool abft, bool ivl, bool pre, hipStream_t s);
+hipError_t launch_batched(const BatchLaunch& L, int ta, int tb, bool abft, bool ivl, bool pre, bool lds_direct,
+                          hipStream_t s);
 extern template hipError_t launch_batched<128, 128, 2, 2, true, 2>(const BatchLaunch&, int, int, bool, bool,
-                                                                   bool, hipStream_t);
+                                                                   bool, bool, hipStream_t);
 extern template hipError_t launch_batched<64, 64, 2, 2, true, 2>(const BatchLaunch&, int, int, bool, bool,
-                                                                 bool, hipStream_t);
+                                                                 bool, bool, hipStream_t);
 
 // Batched launches exist for the configurations with verification intervals.
 inline hipError_t launch_dgemm_batched(const BatchLaunch& L, int tile_id, int ta, int tb, bool abft,
-                                       bool ivl, bool pre, hipStream_t s)
+                                       bool ivl, bool pre, bool lds_direct, hipStream_t s)
 {
     switch (tile_id) {
-    case 2: return launch_batched<128, 128, 2, 2, true, 2>(L, ta, tb, abft, ivl, pre, s);
-    case 3: return launch_batched<64, 64, 2, 2, true, 2>(L, ta, tb, abft, ivl, pre, s);
+    case 2: return launch_batched<128, 128, 2, 2, true, 2>(L, ta, tb, abft, ivl, pre, lds_direct, s);
+    case 3: return launch_batched<64, 64, 2, 2, true, 2>(L, ta, tb, abft, ivl, pre, lds_direct, s);
     default: return hipErrorInvalidValue;
     }
 }

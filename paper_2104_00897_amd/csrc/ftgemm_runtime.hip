@@ -381,6 +381,7 @@ ftg_status ftg_dgemm(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n, i
     a.rep = h->rep;
     a.bm = bm;
     a.bn = bn;
+    a.lds_direct = ftg::lds_direct_ok(A, lda, B, ldb);
     const int64_t n_int = (k + kc - 1) / kc;
     if (abft && cfg && cfg->inject) {
         if (n_int > ftg::kMaxIntervals) return FTG_ERR_UNSUPPORTED;
@@ -717,7 +718,7 @@ ftg_status ftg_dgemm_batched_uneven(ftg_handle h, int64_t count, const ftg_op* t
     auto* hrep = (ftg::RepairProblem*)(hb + off_rep);
     std::memset(hrep, 0, (size_t)count * sizeof(ftg::RepairProblem));
 
-    struct Group { int64_t d0, d1; int f0; int tile, ta, tb; bool ivl; };
+    struct Group { int64_t d0, d1; int f0; int tile, ta, tb; bool ivl, direct; };
     Group groups[kMaxGroups];
     int ng = 0;
     int nfirst = 0;
@@ -730,6 +731,7 @@ ftg_status ftg_dgemm_batched_uneven(ftg_handle h, int64_t count, const ftg_op* t
             G.d0 = it; G.d1 = it; G.f0 = nfirst;
             G.tile = items[it].group / 4 + 2; G.ta = (items[it].group >> 1) & 1; G.tb = items[it].group & 1;
             G.ivl = false;
+            G.direct = true;
             total = 0;
         }
         Group& G = groups[ng - 1];
@@ -757,6 +759,8 @@ ftg_status ftg_dgemm_batched_uneven(ftg_handle h, int64_t count, const ftg_op* t
         a.rep = h->rep;
         a.bm = bm;
         a.bn = bn;
+        a.lds_direct = ftg::lds_direct_ok(a.A, a.lda, a.B, a.ldb);
+        G.direct = G.direct && a.lds_direct;
         hefirst[it] = (int)enc_items;
         if (pre && kk > 0) {
             double* w = (double*)h->d_work + enc_off;
@@ -811,7 +815,7 @@ ftg_status ftg_dgemm_batched_uneven(ftg_handle h, int64_t count, const ftg_op* t
         L.count = (int)(G.d1 - G.d0);
         L.total = hfirst[G.f0 + L.count];
         L.queue = h->d_queue;
-        hipError_t e = ftg::launch_dgemm_batched(L, G.tile, G.ta, G.tb, abft, abft && G.ivl, pre, s);
+        hipError_t e = ftg::launch_dgemm_batched(L, G.tile, G.ta, G.tb, abft, abft && G.ivl, pre, G.direct, s);
         if (e != hipSuccess) return FTG_ERR_HIP;
     }
     timer.end();
