@@ -132,16 +132,18 @@ def timed_ab(torch, fns, steps, warmup, rounds=2):
 
 def cfg1_latency(torch, ftgemm, h, steps):
     """256^3 FP64, alpha = 1, beta = 0, U[-1,1] seed 0, 4 flips in distinct slots
-    (128 x 128 tiles): microseconds per protected call (launch-latency bound)."""
+    (the library's default tile for this shape, 64 x 64: 16 slots): microseconds
+    per protected call (launch-latency bound)."""
     from paper_2104_00897_amd import inputs
     A, B, _ = inputs.gemm_operands_f64(256, 256, 256, seed=0, with_c=False)
     dA, dB = ftgemm.to_device(A), ftgemm.to_device(B)
     dC = torch.zeros((256, 256), dtype=torch.float64, device="cuda")
-    cp = ftgemm.make_config(tile=2, seed=0, n_faults=4)
-    cu = ftgemm.make_config(abft=False, tile=2)
+    cp = ftgemm.make_config(seed=0, n_faults=4)
+    cu = ftgemm.make_config(abft=False)
     t = timed_ab(torch, {"p": lambda: ftgemm.gemm_f64(h, dA, dB, dC, 1.0, 0.0, cfg=cp),
                          "u": lambda: ftgemm.gemm_f64(h, dA, dB, dC, 1.0, 0.0, cfg=cu)}, steps * 10, 5)
-    return {"workload": "FP64 256^3 NN, 4 flips", "us_protected": 1e3 * t["p"], "us_unprotected": 1e3 * t["u"]}
+    return {"workload": "FP64 256^3 NN, 4 flips", "tile": h.tune_get(ftgemm.F64, 256, 256, 256),
+            "us_protected": 1e3 * t["p"], "us_unprotected": 1e3 * t["u"]}
 
 
 def lowp_operands(torch, kind, rows, cols, seed, std=1.0):

@@ -51,9 +51,10 @@ struct DEncOperand {
 struct DEncArgs {
     DEncOperand op[2];
 };
-constexpr int kDEncChunk = 16;  // steps per encode workgroup
-hipError_t launch_dencode(const DEncArgs& e, int grid_x, hipStream_t s);
-// Encode pass of every problem of a batched call: work item w is chunk c of
+constexpr int kDEncChunk = 64;  // steps per encode workgroup
+// items: workgroup items of the larger operand (panels * chunks)
+hipError_t launch_dencode(const DEncArgs& e, int items, hipStream_t s);
+// Encode pass of every problem of a batched call: workgroup item w is chunk c of
 // panel q of the problem with efirst[p] <= w < efirst[p + 1] (panels 0 ..
 // tiles_m - 1 of A, then tiles_n panels of B), writing desc[p].asp / bsp.
 hipError_t launch_dencode_batched(const DGemmArgs* desc, const int* efirst, int count, int total,
