@@ -497,9 +497,18 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
         } else {
             own = owner_of(f.row, f.col);
             const int idx = __builtin_amdgcn_readfirstlane(elem_index(f.row, f.col));
-            oldv = get_elem(idx);
-            newv = flip_f64(oldv, f.bit);
-            set_elem(idx, newv, own);
+            // a uniform test per element (no select chains over all accumulators)
+#pragma unroll
+            for (int g = 0; g < FM; ++g)
+#pragma unroll
+                for (int h = 0; h < FN; ++h)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if ((g * FN + h) * 4 + r == idx) {
+                            oldv = acc[g][h][r];
+                            newv = flip_f64(oldv, f.bit);
+                            if (own) acc[g][h][r] = newv;
+                        }
         }
         if (own)
             push_inject(args.rep, args.problem, tm, tn, t, m0 + f.row, ck ? -1 : n0 + f.col, f.pflip,
@@ -510,6 +519,9 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
     // first flagged row/column with its delta and tau).  On a final check acc
     // holds C_out and the C_in sums are in Vp->
     auto reduce_and_flag = [&](bool final, int64_t pend) __attribute__((always_inline)) {
+        // (on the final check the row and column sums of C_out were taken by
+        // finalize_output in the same pass that formed C_out)
+        if (!final) {
 #pragma unroll
         for (int g = 0; g < FM; ++g) {
 #pragma unroll
@@ -531,6 +543,7 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
                 for (int r = 0; r < 4; ++r) s += acc[g][h][r];
             s = quarter_sum(s);
             if (lq == 0) Vp->csum[wr][wn0 + 16 * h + l16] = s;
+        }
         }
         // maintained checksums: complete after summing the four p lanes
 #pragma unroll
@@ -729,43 +742,92 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
     auto c_ok = [&](int g, int h, int r) __attribute__((always_inline)) {
         return full_mn || ((wm0 + 16 * g + 4 * r + lq < R) && (wn0 + 16 * h + l16 < Q));
     };
+    // C_out = alpha acc + beta C_in, and with ABFT the row and column sums of
+    // C_in (a4) and of C_out (a5) into LDS.  Two passes, each with few values
+    // live beside the accumulators: the C_in sums, then C_out with its sums
+    // (the second pass re-reads C_in, from L2).  The C_in offset goes through
+    // an opaque copy made here, so that the loads are issued after the k loop
+    // (hoisted above it, their values would be held in scratch across the
+    // whole loop); two rows of each fragment (2 FN values) load at a time.
     auto finalize_output = [&]() __attribute__((always_inline)) {
         const bool cin = args.beta != 0.0;
+        int cvo = c_voff;
+        asm volatile("" : "+v"(cvo));
         const __amdgpu_buffer_rsrc_t rc = make_rsrc(args.C + m0 + n0 * ldc);
-        double cs[FN], csa[FN];
+        auto load_c = [&](double (&c)[2][FN], int g, int r0) __attribute__((always_inline)) {
 #pragma unroll
-        for (int h = 0; h < FN; ++h) cs[h] = csa[h] = 0.0;
+            for (int rr = 0; rr < 2; ++rr)
 #pragma unroll
-        for (int g = 0; g < FM; ++g)
+                for (int h = 0; h < FN; ++h)
+                    c[rr][h] = buf_load_f64(rc, c_ok(g, h, r0 + rr) ? cvo + (16 * g + 4 * (r0 + rr)) * 8 : kOOB,
+                                            h * c_hstep);
+        };
+        if (ABFT && cin) {
+            double cs[FN], csa[FN];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                double s = 0.0, sa = 0.0;
+            for (int h = 0; h < FN; ++h) cs[h] = csa[h] = 0.0;
 #pragma unroll
-                for (int h = 0; h < FN; ++h) {
-                    double c = 0.0;
-                    if (cin) c = buf_load_f64(rc, c_vo(g, r, c_ok(g, h, r)), h * c_hstep);
-                    acc[g][h][r] = cin ? args.alpha * acc[g][h][r] + args.beta * c
-                                       : args.alpha * acc[g][h][r];
-                    s += c;
-                    sa += fabs(c);
-                    cs[h] += c;
-                    csa[h] += fabs(c);
-                }
-                if (ABFT && cin) {
+            for (int gr = 0; gr < 2 * FM; ++gr) {
+                const int g = gr / 2, r0 = 2 * (gr % 2);
+                double c[2][FN];
+                load_c(c, g, r0);
+#pragma unroll
+                for (int rr = 0; rr < 2; ++rr) {
+                    double s = 0.0, sa = 0.0;
+#pragma unroll
+                    for (int h = 0; h < FN; ++h) {
+                        s += c[rr][h];
+                        sa += fabs(c[rr][h]);
+                        cs[h] += c[rr][h];
+                        csa[h] += fabs(c[rr][h]);
+                    }
                     s = group_sum<16>(s);
                     sa = group_sum<16>(sa);
                     if (l16 == 0) {
-                        Vp->cir[wc][wm0 + 16 * g + 4 * r + lq] = s;
-                        Vp->cira[wc][wm0 + 16 * g + 4 * r + lq] = sa;
+                        const int row = wm0 + 16 * g + 4 * (r0 + rr) + lq;
+                        Vp->cir[wc][row] = s;
+                        Vp->cira[wc][row] = sa;
                     }
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
-        if (ABFT && cin) {
 #pragma unroll
             for (int h = 0; h < FN; ++h) {
                 const double s = quarter_sum(cs[h]), sa = quarter_sum(csa[h]);
                 if (lq == 0) { Vp->cic[wr][wn0 + 16 * h + l16] = s; Vp->cica[wr][wn0 + 16 * h + l16] = sa; }
+            }
+        }
+        double os[FN];
+#pragma unroll
+        for (int h = 0; h < FN; ++h) os[h] = 0.0;
+#pragma unroll
+        for (int gr = 0; gr < 2 * FM; ++gr) {
+            const int g = gr / 2, r0 = 2 * (gr % 2);
+            double c[2][FN];
+            if (cin) load_c(c, g, r0);
+#pragma unroll
+            for (int rr = 0; rr < 2; ++rr) {
+                const int r = r0 + rr;
+                double o = 0.0;
+#pragma unroll
+                for (int h = 0; h < FN; ++h) {
+                    const double v = cin ? args.alpha * acc[g][h][r] + args.beta * c[rr][h] : args.alpha * acc[g][h][r];
+                    acc[g][h][r] = v;
+                    o += v;
+                    os[h] += v;
+                }
+                if (ABFT) {
+                    o = group_sum<16>(o);
+                    if (l16 == 0) Vp->rsum[wc][wm0 + 16 * g + 4 * r + lq] = o;
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (ABFT) {
+#pragma unroll
+            for (int h = 0; h < FN; ++h) {
+                const double o = quarter_sum(os[h]);
+                if (lq == 0) Vp->csum[wr][wn0 + 16 * h + l16] = o;
             }
         }
     };
@@ -924,10 +986,27 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
                 push_record(args.rep, args.problem, tm, tn, t, -1, -1, FTG_KIND_TILE_RECOMPUTED,
                             nr ? Vp->dfi : Vp->dfj, nr ? Vp->tfi : Vp->tfj);
             }
-            __syncthreads();
-            --redo_budget;
-            inj_from = n_int;
-            continue;
+            if constexpr (IVL) {
+                __syncthreads();
+                --redo_budget;
+                inj_from = n_int;
+                continue;
+            } else {
+                // Without intervals the tile is recomputed by the repair kernel,
+                // from the operands and C_in, which stays in place: the tile is
+                // not stored.  (A restart here would make the k loop a loop body
+                // whose invariants stay live through this epilogue.)
+                if (tid == 0) {
+                    RepairReq q;
+                    q.problem = args.problem; q.tm = tm; q.tn = tn; q.interval = t;
+                    q.nr = nr; q.nc = nc; q.fi = q.fj = 0; q.R = R; q.Q = Q;
+                    q.whole = 1; q.pad1 = 0; q.m0 = m0; q.n0 = n0;
+                    q.dfi = q.tfi = q.dfj = q.tfj = q.exp_row = q.exp_col = q.cin = 0.0;
+                    push_repair(args.rep, q);
+                }
+                __syncthreads();
+                return;
+            }
         }
         // hand the slot to the repair kernel (it runs after this kernel on the
         // same stream and works on the stored tile in global memory)
@@ -935,7 +1014,7 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
             RepairReq q;
             q.problem = args.problem; q.tm = tm; q.tn = tn; q.interval = t;
             q.nr = nr; q.nc = nc; q.fi = Vp->fi; q.fj = Vp->fj; q.R = R; q.Q = Q;
-            q.pad0 = q.pad1 = 0; q.m0 = m0; q.n0 = n0;
+            q.whole = q.pad1 = 0; q.m0 = m0; q.n0 = n0;
             q.dfi = Vp->dfi; q.tfi = Vp->tfi; q.dfj = Vp->dfj; q.tfj = Vp->tfj;
             const bool cin = args.beta != 0.0;
             double cr = 0.0, cc = 0.0;

@@ -21,7 +21,9 @@ constexpr int kMaxIntervals = 128;
 struct RepairReq {
     int problem, tm, tn, interval;
     int nr, nc, fi, fj;  // flagged row/column counts, first flagged row/column
-    int R, Q, pad0, pad1;
+    int R, Q;
+    int whole;  // 1: recompute the whole tile (not stored: C still holds C_in)
+    int pad1;
     int64_t m0, n0;
     double dfi, tfi, dfj, tfj, exp_row, exp_col, cin;
 };

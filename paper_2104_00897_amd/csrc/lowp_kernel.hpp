@@ -551,7 +551,7 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
                 RepairReq q;
                 q.problem = args.problem; q.tm = tm; q.tn = tn; q.interval = 0;
                 q.nr = nr; q.nc = nc; q.fi = V.fi; q.fj = V.fj; q.R = R; q.Q = Q;
-                q.pad0 = q.pad1 = 0; q.m0 = m0; q.n0 = n0;
+                q.whole = q.pad1 = 0; q.m0 = m0; q.n0 = n0;
                 q.dfi = V.dfi; q.tfi = V.tfi; q.dfj = V.dfj; q.tfj = V.tfj;
                 q.exp_row = nr ? V.exi : 0.0;
                 q.exp_col = nc ? V.exj : 0.0;

@@ -72,6 +72,22 @@ __global__ __launch_bounds__(256) void repair_kernel(DevReport* rep, RepairProbl
     for (unsigned int r = gwave; r < n; r += nwaves) {
         const RepairReq q = rep->rq[r];
         const RepairProblem P = table ? table[q.problem] : single;
+        if (q.whole) {
+            // policy 1, several errors in the final slot of a tile that was left
+            // unstored: every element from a fresh dot product and C_in (the
+            // kernel has counted and recorded the slot)
+            const double scale =
+                (double)(P.scale_a ? *P.scale_a : 1.0f) * (double)(P.scale_b ? *P.scale_b : 1.0f);
+            for (int e = lane; e < q.R * q.Q; e += 64) {
+                const int64_t gi = q.m0 + e % q.R, gj = q.n0 + e / q.R;
+                double s = 0.0;
+                for (int64_t p = 0; p < P.k; ++p) s = fma(opnd(P, true, gi, p), opnd(P, false, p, gj), s);
+                double v = P.alpha * s * scale;
+                if (P.beta != 0.0) v += P.beta * c_get(P, gi, gj);
+                c_set(P, gi, gj, v);
+            }
+            continue;
+        }
         int kind;
         int64_t row = -1, col = -1;
         double d = q.nr ? q.dfi : q.dfj, tau = q.nr ? q.tfi : q.tfj;
