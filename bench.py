@@ -31,7 +31,7 @@ PEAK_F64_MFMA = 78.6  # TFLOP/s, MI355X dense FP64 matrix
 # encode pass) at n = 8192 from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled
 # by a plain-copy calibration (profiles/dgemm_abft_n8192_traffic.md); it must be
 # re-measured whenever that kernel changes
-TRAFFIC_F64_N8192 = None
+TRAFFIC_F64_N8192 = 1.729e10
 
 
 def parse():
