@@ -80,6 +80,11 @@ constexpr int kLowpChunk = 64;   // k steps per encode block
 hipError_t launch_lowp_gemm(const LowpArgs& a, ftg_dtype sta, ftg_dtype stb, int ta, int tb, int mode,
                             hipStream_t s);
 hipError_t launch_lowp_encode(const EncArgs& e, ftg_dtype st, int grid_x, int finish_x, hipStream_t s);
+// k-major copy P[p + r ldp] of an operand with contiguous rows X[r + p ld]
+// (eb = element bytes, ldp a multiple of 16, P 16-byte aligned; vec: X rows
+// allow 16-byte loads)
+hipError_t launch_lowp_pack(const void* X, int64_t ld, int64_t rows, int64_t K, int eb, void* P, int64_t ldp,
+                            int vec, hipStream_t s);
 hipError_t launch_sscale(float* C, int64_t m, int64_t n, int64_t ldc, float beta, hipStream_t s);
 
 template <typename STA, typename STB, bool F8MMA, int MODE>

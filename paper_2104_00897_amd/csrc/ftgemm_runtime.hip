@@ -510,33 +510,55 @@ ftg_status ftg_gemm_ex(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n,
     a.scale_a = ab_type == FTG_F8_E4M3 ? scale_a : nullptr;
     a.scale_b = ab_type == FTG_F8_E4M3 ? scale_b : nullptr;
     a.rep = h->rep;
-    const int ita = ta == FTG_OP_T, itb = tb == FTG_OP_T;
+    // Operands whose rows are contiguous (op(A) = A, op(B) = B^T) are first
+    // packed into k-major copies in the workspace: the product kernels stage
+    // k-contiguous operands without register transposes (about twice as fast).
+    // Everything after the pack (encode, checksum products, product) reads the
+    // packed copies; the repair kernel reads the caller's operands.
+    const int ita0 = ta == FTG_OP_T, itb0 = tb == FTG_OP_T;
+    const bool pack_a = !ita0, pack_b = itb0 != 0;
+    const int64_t ldp = (k + 15) / 16 * 16;
+    if ((pack_a || pack_b) && ldp >= (1 << 20)) return FTG_ERR_UNSUPPORTED;
+    const size_t pa_bytes = pack_a ? align256((size_t)m * ldp * eb) : 0;
+    const size_t pb_bytes = pack_b ? align256((size_t)n * ldp * eb) : 0;
+    size_t work_base = 0;  // workspace bytes before the packed copies
+    const int64_t chk_tiles_r = (int64_t)a.tiles_m * ((3 * a.tiles_n + bn - 1) / bn);
+    const int64_t chk_tiles_c = (int64_t)((3 * a.tiles_m + bm - 1) / bm) * a.tiles_n;
+    const int ks_r = lowp_ksplit(chk_tiles_r, k), ks_c = lowp_ksplit(chk_tiles_c, k);
+    const LowpLayout L = lowp_layout(m, n, k, ks_r, ks_c);
+    if (abft) work_base = align256(L.total);
+    // workspace (grows; allocation is not allowed under stream capture)
+    if ((st = ensure_work(h, work_base + pa_bytes + pb_bytes, s)) != FTG_OK) return st;
+    unsigned char* w = h->d_work;
+    if (pack_a) {
+        void* P = w + work_base;
+        if (ftg::launch_lowp_pack(A, lda, m, k, eb, P, ldp, a.vec_a, s) != hipSuccess) return FTG_ERR_HIP;
+        a.A = P; a.lda = (int)ldp; a.vec_a = vec_ok(P, ldp, eb);
+    }
+    if (pack_b) {
+        void* P = w + work_base + pa_bytes;
+        if (ftg::launch_lowp_pack(B, ldb, n, k, eb, P, ldp, a.vec_b, s) != hipSuccess) return FTG_ERR_HIP;
+        a.B = P; a.ldb = (int)ldp; a.vec_b = vec_ok(P, ldp, eb);
+    }
+    const int ita = 1, itb = 0;  // op(A) rows and op(B) columns are k-contiguous from here on
     if (!abft) {
         LaunchTimer timer(h, s);
         const hipError_t e = ftg::launch_lowp_gemm(a, ab_type, ab_type, ita, itb, 0, s);
         timer.end();
         return e == hipSuccess ? FTG_OK : FTG_ERR_HIP;
     }
-
-    // workspace (grows; allocation is not allowed under stream capture)
-    const int64_t chk_tiles_r = (int64_t)a.tiles_m * ((3 * a.tiles_n + bn - 1) / bn);
-    const int64_t chk_tiles_c = (int64_t)((3 * a.tiles_m + bm - 1) / bm) * a.tiles_n;
-    const int ks_r = lowp_ksplit(chk_tiles_r, k), ks_c = lowp_ksplit(chk_tiles_c, k);
-    const LowpLayout L = lowp_layout(m, n, k, ks_r, ks_c);
-    if ((st = ensure_work(h, L.total, s)) != FTG_OK) return st;
-    unsigned char* w = h->d_work;
     const int chunks = (int)((k + ftg::kLowpChunk - 1) / ftg::kLowpChunk);
 
     // encode: checksum pieces and magnitude sums of both operands
     ftg::EncArgs e;
     std::memset(&e, 0, sizeof(e));
     ftg::EncOperand& ea = e.op[0];
-    ea.X = A; ea.ld = lda; ea.rows = (int)m; ea.K = (int)k; ea.kcontig = ita; ea.vec = a.vec_a;
+    ea.X = a.A; ea.ld = a.lda; ea.rows = (int)m; ea.K = (int)k; ea.kcontig = ita; ea.vec = a.vec_a;
     ea.panels = a.tiles_m; ea.chunks = chunks;
     ea.XS = (uint16_t*)(w + L.xs_a); ea.XRp = (float*)(w + L.xrp_a); ea.XMp = (float*)(w + L.xmp_a);
     ea.XR = (float*)(w + L.ra); ea.XM = (float*)(w + L.ma);
     ftg::EncOperand& eb_ = e.op[1];
-    eb_.X = B; eb_.ld = ldb; eb_.rows = (int)n; eb_.K = (int)k; eb_.kcontig = !itb; eb_.vec = a.vec_b;
+    eb_.X = a.B; eb_.ld = a.ldb; eb_.rows = (int)n; eb_.K = (int)k; eb_.kcontig = !itb; eb_.vec = a.vec_b;
     eb_.panels = a.tiles_n; eb_.chunks = chunks;
     eb_.XS = (uint16_t*)(w + L.xs_b); eb_.XRp = (float*)(w + L.xrp_b); eb_.XMp = (float*)(w + L.xmp_b);
     eb_.XR = (float*)(w + L.cb); eb_.XM = (float*)(w + L.mb);
@@ -547,7 +569,7 @@ ftg_status ftg_gemm_ex(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n,
     // checksum products: ER = op(A) [B_J e pieces], EC = [e^T A_I pieces]^T op(B)
     ftg::LowpArgs c1;
     std::memset(&c1, 0, sizeof(c1));
-    c1.A = A; c1.lda = (int)lda; c1.B = eb_.XS; c1.ldb = (int)k;
+    c1.A = a.A; c1.lda = a.lda; c1.B = eb_.XS; c1.ldb = (int)k;
     c1.C = (float*)(w + L.er); c1.ldc = (int)m;
     c1.m = (int)m; c1.n = 3 * a.tiles_n; c1.k = (int)k;
     c1.tiles_m = a.tiles_m; c1.tiles_n = (c1.n + bn - 1) / bn;
@@ -557,7 +579,7 @@ ftg_status ftg_gemm_ex(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n,
     if (ftg::launch_lowp_gemm(c1, ab_type, FTG_BF16, ita, 0, 0, s) != hipSuccess) return FTG_ERR_HIP;
     ftg::LowpArgs c2;
     std::memset(&c2, 0, sizeof(c2));
-    c2.A = ea.XS; c2.lda = (int)k; c2.B = B; c2.ldb = (int)ldb;
+    c2.A = ea.XS; c2.lda = (int)k; c2.B = a.B; c2.ldb = a.ldb;
     c2.C = (float*)(w + L.ec); c2.ldc = 3 * a.tiles_m;
     c2.m = 3 * a.tiles_m; c2.n = (int)n; c2.k = (int)k;
     c2.tiles_m = (c2.m + bm - 1) / bm; c2.tiles_n = a.tiles_n;
@@ -590,7 +612,7 @@ ftg_status ftg_gemm_ex(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n,
     std::memset(&rp, 0, sizeof(rp));
     rp.A = A; rp.B = B; rp.C = C;
     rp.lda = lda; rp.ldb = ldb; rp.ldc = ldc; rp.k = k;
-    rp.ta = ita; rp.tb = itb; rp.correct_policy = cfg ? cfg->correct_policy : 0;
+    rp.ta = ita0; rp.tb = itb0; rp.correct_policy = cfg ? cfg->correct_policy : 0;
     rp.ab_type = ab_type; rp.c_type = FTG_F32;
     rp.alpha = alpha; rp.beta = beta;
     rp.scale_a = a.scale_a; rp.scale_b = a.scale_b;

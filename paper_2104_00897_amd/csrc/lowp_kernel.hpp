@@ -239,6 +239,12 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
                     const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(rsa, off, 0, 0);
                     ra[q] = (u32x4_t){w[0], w[1], 0u, 0u};
                 }
+            } else if ((Cf::AKC || STA::bytes == 2) && args.vec_a && r + (Cf::AKC ? 1 : Cf::VA) <= R &&
+                       p + (Cf::AKC ? Cf::VA : 1) <= kv) {
+                // a whole vector inside the matrix (edge tiles)
+                ra[q] = __builtin_amdgcn_raw_buffer_load_b128(rsa, off, 0, 0);
+            } else if (r >= R || p >= kv) {
+                ra[q] = (u32x4_t){0u, 0u, 0u, 0u};  // entirely outside
             } else {
                 // element by element, zero outside the matrix
                 uint32_t w[4] = {0u, 0u, 0u, 0u};
@@ -267,6 +273,11 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
                     const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(rsb, off, 0, 0);
                     rb[q] = (u32x4_t){w[0], w[1], 0u, 0u};
                 }
+            } else if ((Cf::BKC || STB::bytes == 2) && args.vec_b && r + (Cf::BKC ? 1 : Cf::VB) <= Q &&
+                       p + (Cf::BKC ? Cf::VB : 1) <= kv) {
+                rb[q] = __builtin_amdgcn_raw_buffer_load_b128(rsb, off, 0, 0);
+            } else if (r >= Q || p >= kv) {
+                rb[q] = (u32x4_t){0u, 0u, 0u, 0u};
             } else {
                 uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll

@@ -88,6 +88,130 @@ __global__ __launch_bounds__(256, 4) void lowp_encode_kernel(EncArgs args)
     }
 }
 
+// The same encode for an operand whose steps are contiguous (element (r, p)
+// at X[p + r ld]; packed operands always are).  Thread t takes steps
+// V (t % SG) .. + V - 1 (V = 8) of rows RPT (t / SG) .. + RPT - 1 of the
+// block (kLowpTile rows x kLowpChunk steps) with RPT loads issued together.
+// Column sums: per thread over its rows, then a fixed xor butterfly over the
+// lanes of a wave that share its steps, then the four waves in order through
+// LDS.  Row sums of |x|: per thread over its steps, then a fixed butterfly
+// over the SG lanes that share its rows.
+template <typename ST>
+__global__ __launch_bounds__(256) void lowp_encode_k_kernel(EncArgs args)
+{
+    const EncOperand& E = args.op[blockIdx.y];
+    const int pi = blockIdx.x / E.chunks, c = blockIdx.x % E.chunks;
+    if (pi >= E.panels) return;
+    constexpr int LB = ST::bytes == 2 ? 16 : 8;    // bytes per load: 8 steps of either type
+    constexpr int V = LB / ST::bytes;              // steps per load
+    constexpr int SG = kLowpChunk / V;             // step groups
+    constexpr int RG = 256 / SG;                   // row groups
+    constexpr int RPT = kLowpTile / RG;            // rows per thread
+    static_assert(kLowpTile % RG == 0 && 64 % SG == 0, "encode map");
+    __shared__ double cpart[4][kLowpChunk][2];
+    __shared__ float pmax[kLowpChunk];
+    __shared__ float lut[256];  // e4m3 code -> value (FP8 operands)
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if constexpr (ST::bytes == 1) {
+        lut[tid] = bf16_bits_to_f32(e4m3_to_bf16((uint32_t)tid));
+        __syncthreads();
+    }
+    const int sg = tid % SG, rg = tid / SG;
+    const int64_t r0 = (int64_t)pi * kLowpTile, p0 = (int64_t)c * kLowpChunk;
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc((const unsigned char*)E.X + (r0 * E.ld + p0) * ST::bytes);
+    const bool full = E.vec && r0 + kLowpTile <= E.rows && p0 + kLowpChunk <= E.K;
+    u32x4_t x[RPT];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+        const int r = rg * RPT + u, pv = sg * V;
+        if (full) {
+            if constexpr (LB == 16) {
+                x[u] = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(((int64_t)r * E.ld + pv) * ST::bytes), 0, 0);
+            } else {
+                const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(((int64_t)r * E.ld + pv) * ST::bytes), 0, 0);
+                x[u] = (u32x4_t){v[0], v[1], 0u, 0u};
+            }
+        } else {
+            uint32_t wv[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const bool ok = r0 + r < E.rows && p0 + pv + e < E.K;
+                const int off = ok ? (int)(((int64_t)r * E.ld + pv + e) * ST::bytes) : kOOB;
+                const uint32_t b = ST::bytes == 2 ? __builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0)
+                                                  : __builtin_amdgcn_raw_buffer_load_b8(rs, off, 0, 0);
+                wv[(e * ST::bytes) / 4] |= b << (8 * ((e * ST::bytes) % 4));
+            }
+            x[u] = (u32x4_t){wv[0], wv[1], wv[2], wv[3]};
+        }
+    }
+    auto val = [&](int u, int e) __attribute__((always_inline)) -> double {
+        const uint32_t raw = (x[u][(e * ST::bytes) / 4] >> (8 * ((e * ST::bytes) % 4))) & (ST::bytes == 2 ? 0xFFFFu : 0xFFu);
+        if constexpr (ST::bytes == 1) return (double)lut[raw];
+        else return (double)bf16_bits_to_f32(raw);
+    };
+    // row sums of |x| over this block's steps
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+        double ra = 0.0;
+#pragma unroll
+        for (int e = 0; e < V; ++e) ra += fabs(val(u, e));
+#pragma unroll
+        for (int off = 1; off < SG; off <<= 1) ra += __shfl_xor(ra, off);
+        const int64_t r = r0 + rg * RPT + u;
+        if (sg == 0 && r < E.rows) E.XRp[(int64_t)c * E.rows + r] = f64_to_f32_up(ra);
+    }
+    // column sums over this block's rows
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+        double cs = 0.0, ca = 0.0;
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) {
+            const double v = val(u, e);
+            cs += v;
+            ca += fabs(v);
+        }
+#pragma unroll
+        for (int off = SG; off < 64; off <<= 1) {
+            cs += __shfl_xor(cs, off);
+            ca += __shfl_xor(ca, off);
+        }
+        if (lane < SG) {
+            cpart[w][sg * V + e][0] = cs;
+            cpart[w][sg * V + e][1] = ca;
+        }
+    }
+    __syncthreads();
+    if (tid < kLowpChunk) {
+        const int p = tid;
+        double s = 0.0, sa = 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            s += cpart[v][p][0];
+            sa += cpart[v][p][1];
+        }
+        pmax[p] = f64_to_f32_up(sa);
+        if (p0 + p < E.K) {
+            // three bf16 pieces: hi + mid + lo = s to within 2^-24 |s|
+            const uint16_t hi = f32_to_bf16_rne((float)s);
+            const double r1 = s - (double)bf16_bits_to_f32(hi);
+            const uint16_t mid = f32_to_bf16_rne((float)r1);
+            const double r2 = r1 - (double)bf16_bits_to_f32(mid);
+            const uint16_t lo = f32_to_bf16_rne((float)r2);
+            uint16_t* o = E.XS + (int64_t)3 * pi * E.K + p0 + p;
+            o[0] = hi;
+            o[E.K] = mid;
+            o[2 * E.K] = lo;
+        }
+    }
+    __syncthreads();
+    if (tid < 64) {
+        float mx = pmax[tid];
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+        if (tid == 0) E.XMp[(int64_t)pi * E.chunks + c] = mx;
+    }
+}
+
 // XR[r] = sum over chunks (binary64, rounded up); XM[panel] = max over chunks.
 __global__ __launch_bounds__(256) void lowp_encode_finish_kernel(EncArgs args)
 {
@@ -95,7 +219,15 @@ __global__ __launch_bounds__(256) void lowp_encode_finish_kernel(EncArgs args)
     const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (x < E.rows) {
         double s = 0.0;
-        for (int c = 0; c < E.chunks; ++c) s += (double)E.XRp[(int64_t)c * E.rows + x];
+        int c = 0;
+        for (; c + 16 <= E.chunks; c += 16) {
+            float v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = E.XRp[(int64_t)(c + u) * E.rows + x];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) s += (double)v[u];
+        }
+        for (; c < E.chunks; ++c) s += (double)E.XRp[(int64_t)c * E.rows + x];
         E.XR[x] = f64_to_f32_up(s);
     }
     if (x < E.panels) {
@@ -126,13 +258,91 @@ hipError_t launch_lowp_gemm(const LowpArgs& a, ftg_dtype sta, ftg_dtype stb, int
 
 hipError_t launch_lowp_encode(const EncArgs& e, ftg_dtype st, int grid_x, int finish_x, hipStream_t s)
 {
-    if (st == FTG_F8_E4M3)
-        hipLaunchKernelGGL(lowp_encode_kernel<StFP8>, dim3(grid_x, 2), dim3(256), 0, s, e);
-    else
-        hipLaunchKernelGGL(lowp_encode_kernel<StBF16>, dim3(grid_x, 2), dim3(256), 0, s, e);
+    // operands with contiguous steps (both, once packed) take the k-major encode
+    const bool kc = e.op[0].kcontig && e.op[1].kcontig;
+    if (st == FTG_F8_E4M3) {
+        if (kc) hipLaunchKernelGGL(lowp_encode_k_kernel<StFP8>, dim3(grid_x, 2), dim3(256), 0, s, e);
+        else hipLaunchKernelGGL(lowp_encode_kernel<StFP8>, dim3(grid_x, 2), dim3(256), 0, s, e);
+    } else {
+        if (kc) hipLaunchKernelGGL(lowp_encode_k_kernel<StBF16>, dim3(grid_x, 2), dim3(256), 0, s, e);
+        else hipLaunchKernelGGL(lowp_encode_kernel<StBF16>, dim3(grid_x, 2), dim3(256), 0, s, e);
+    }
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(lowp_encode_finish_kernel, dim3(finish_x, 2), dim3(256), 0, s, e);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- pack
+// Packs an operand stored with its rows contiguous (element (r, p) at
+// X[r + p ld]) into a copy with the steps contiguous (P[p + r ldp]), the
+// layout the product kernels stage without register transposes (the packing
+// of BLAS-style GEMMs, here with the checksum encode reading the packed copy).
+// One workgroup per tile of 64 rows x TS steps (TS elements = 128 bytes):
+// coalesced 16-byte loads along the rows, the transpose through LDS, then
+// each row's 128 bytes written by 8 neighbouring lanes (whole cache lines).
+template <int EB>
+__global__ __launch_bounds__(256) void lowp_pack_kernel(const unsigned char* __restrict__ X, int64_t ld, int rows,
+                                                        int K, unsigned char* __restrict__ P, int64_t ldp, int vec)
+{
+    constexpr int TR = 64, TS = 128 / EB, V = 16 / EB;  // rows, steps, elements per 16 bytes
+    constexpr int PITCH = 128 + 16;                     // LDS bytes per tile row
+    __shared__ __attribute__((aligned(16))) unsigned char t[TR * PITCH];
+    const int tid = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * TR, p0 = (int64_t)blockIdx.y * TS;
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(X + (r0 + p0 * ld) * EB);
+    const bool full = vec && r0 + TR <= rows && p0 + TS <= K;
+    // load: TS steps x (TR / V) chunks of V rows
+#pragma unroll
+    for (int u = 0; u < TS * (TR / V) / 256; ++u) {
+        const int i = tid + 256 * u;
+        const int p = i / (TR / V), rc = (i % (TR / V)) * V;
+        uint32_t w[4];
+        if (full) {
+            const u32x4_t v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)((rc + p * ld) * EB), 0, 0);
+#pragma unroll
+            for (int d = 0; d < 4; ++d) w[d] = v[d];
+        } else {
+#pragma unroll
+            for (int d = 0; d < 4; ++d) w[d] = 0u;
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const bool ok = r0 + rc + e < rows && p0 + p < K;
+                const int off = ok ? (int)((rc + e + p * ld) * EB) : kOOB;
+                const uint32_t x = EB == 2 ? __builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0)
+                                           : __builtin_amdgcn_raw_buffer_load_b8(rs, off, 0, 0);
+                w[(e * EB) / 4] |= x << (8 * ((e * EB) % 4));
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            const uint32_t x = (w[(e * EB) / 4] >> (8 * ((e * EB) % 4))) & (EB == 2 ? 0xFFFFu : 0xFFu);
+            if constexpr (EB == 2) *(uint16_t*)(t + (rc + e) * PITCH + p * 2) = (uint16_t)x;
+            else t[(rc + e) * PITCH + p] = (unsigned char)x;
+        }
+    }
+    __syncthreads();
+    // store: row r, 16-byte chunk c (8 chunks = the row's 128 bytes)
+#pragma unroll
+    for (int u = 0; u < TR * 8 / 256; ++u) {
+        const int i = tid + 256 * u;
+        const int r = i / 8, c = i % 8;
+        if (r0 + r < rows && p0 + c * V < ldp)
+            *(u32x4_t*)(P + ((r0 + r) * ldp + p0) * EB + c * 16) = *(const u32x4_t*)(t + r * PITCH + c * 16);
+    }
+}
+
+hipError_t launch_lowp_pack(const void* X, int64_t ld, int64_t rows, int64_t K, int eb, void* P, int64_t ldp,
+                            int vec, hipStream_t s)
+{
+    const int TS = 128 / eb;
+    const dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((K + TS - 1) / TS));
+    if (eb == 2)
+        hipLaunchKernelGGL(lowp_pack_kernel<2>, grid, dim3(256), 0, s, (const unsigned char*)X, ld, (int)rows, (int)K,
+                           (unsigned char*)P, ldp, vec);
+    else
+        hipLaunchKernelGGL(lowp_pack_kernel<1>, grid, dim3(256), 0, s, (const unsigned char*)X, ld, (int)rows, (int)K,
+                           (unsigned char*)P, ldp, vec);
     return hipGetLastError();
 }
 

@@ -50,9 +50,12 @@ __device__ inline double opnd(const RepairProblem& P, bool isA, int64_t r, int64
 
 __device__ inline double c_get(const RepairProblem& P, int64_t i, int64_t j)
 {
-    // volatile: other workgroups of the producing kernel wrote C; bypass stale caches
-    if (P.c_type == FTG_F64) return ((volatile const double*)P.C)[i + j * P.ldc];
-    return (double)((volatile const float*)P.C)[i + j * P.ldc];
+    // device-scope atomic loads: not served from a stale vector L1 line (this
+    // kernel's own corrections are re-read), and unlike volatile accesses they
+    // are not serialized, so a wave's loads overlap
+    if (P.c_type == FTG_F64)
+        return __hip_atomic_load((const double*)P.C + i + j * P.ldc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (double)__hip_atomic_load((const float*)P.C + i + j * P.ldc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ inline void c_set(const RepairProblem& P, int64_t i, int64_t j, double v)
