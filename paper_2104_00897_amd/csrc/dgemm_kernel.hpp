@@ -54,8 +54,12 @@ struct DCfg {
     static constexpr int SB = TB ? (BN + 16) : (BK + 2);
     static constexpr int A_ELEMS = TA ? BM * SA : BK * SA;
     static constexpr int B_ELEMS = TB ? BK * SB : BN * SB;
-    // direct-to-LDS staging: 1 KB (64 lanes x 16 bytes) per wave load
-    static constexpr bool DIRECT = BM % 128 == 0 && BN % 128 == 0 && BK == 16;
+    // direct-to-LDS staging: up to 1 KB (64 lanes x 16 bytes) per wave load
+    static constexpr bool DIRECT = BM % 64 == 0 && BN % 64 == 0 && BK == 16;
+    // protected kernels of small tiles run one copy of the k loop for all
+    // waves also with register staging (their prefetch registers are few):
+    // three workgroups per CU
+    static constexpr bool ONE_COPY = BM * BN / NW <= 32 * 32;
     static constexpr int NA = BM * BK / NT, NB = BN * BK / NT;  // loads per thread
     static constexpr int PPW = BK / NW, LPP = 64 / PPW;        // encode: p's per wave, lanes per p
     static constexpr int GSH = FM / WGN, HSH = FN / WGM;        // checksum FMA shares per wave
@@ -237,7 +241,8 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
     // 16 * lane, with no registers in between (the loads complete by the
     // barrier that publishes the stage).
     //   lines along the tile ([p][x], pitch X + 16): one wave load per 128
-    //   elements of a step, all lanes active;
+    //   elements of a step, all lanes active (64-element lines: one load per
+    //   step with 32 lanes active);
     //   lines along k ([x][p], 9 slots per line): wave load I covers slots
     //   64 I .. 64 I + 63, lane l slot s = 64 I + l = line s / 9, step pair
     //   s % 9, the ninth (padding) slot of each line masked off.
@@ -259,7 +264,7 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
                                                                  (int)(((int64_t)x * ld + 2 * pair) * 8), 0, 0, 0);
                 }
             }
-        } else {
+        } else if constexpr (X >= 128) {
             constexpr int PER = X / 128;  // wave loads per step
             constexpr int NL = BK * PER / Cf::NW;
             static_assert(BK * PER % Cf::NW == 0, "equal shares of wave loads");
@@ -269,6 +274,16 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
                 const int p = L / PER, part = L % PER;
                 __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)(dst + p * pitch + part * 128), 16, lane * 16,
                                                          (int)(((int64_t)p * ld + part * 128) * 8), 0, 0);
+            }
+        } else {
+            static_assert(X == 64 && BK % Cf::NW == 0, "64-element lines: one load per step");
+            constexpr int NL = BK / Cf::NW;
+#pragma unroll
+            for (int q = 0; q < NL; ++q) {
+                const int p = wave * NL + q;
+                if (lane < X / 2)
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)(dst + p * pitch), 16, lane * 16,
+                                                             (int)((int64_t)p * ld * 8), 0, 0);
             }
         }
     };
@@ -932,7 +947,7 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
                     }
                 }
             };
-            if constexpr (DIR) {
+            if constexpr ((Cf::ONE_COPY && ABFT) || DIR) {
                 hot.template operator()<-1>();
             } else {
                 [&]<int... W>(std::integer_sequence<int, W...>) __attribute__((always_inline)) {
@@ -1052,19 +1067,23 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
 }
 
 // Occupancy target of a kernel (the second launch bound: waves per SIMD the
-// register allocation must allow).  Direct-staging kernels whose accumulators
-// take at most 64 registers per lane aim at two workgroups per CU (their LDS
-// fits twice in 160 KB); the others use the configuration's MINB.
-template <int BM, int BN, int WGM, int WGN, int MINB, bool DIR>
+// register allocation must allow).  Kernels with one copy of the k loop
+// (direct staging, or protected small tiles) whose accumulators take at most 64
+// registers per lane aim at two workgroups per CU, at most 32 at three (their
+// LDS fits that many times in 160 KB); the others use the configuration's MINB.
+template <int BM, int BN, int WGM, int WGN, int MINB, bool DIR, bool ABFT>
 constexpr int waves_per_simd()
 {
     constexpr int NW = WGM * WGN;
-    return (DIR && 2 * BM * BN / (NW * 64) <= 64 && NW % 2 == 0) ? NW / 2 : MINB;
+    constexpr int accv = 2 * BM * BN / (NW * 64);  // accumulator VGPRs per lane
+    constexpr bool one = DIR || (ABFT && DCfg<BM, BN, WGM, WGN, false, false>::ONE_COPY);
+    constexpr int blocks = !one ? 0 : (accv <= 32 ? 3 : (accv <= 64 ? 2 : 0));
+    return (blocks && (blocks * NW) % 4 == 0) ? blocks * NW / 4 : MINB;
 }
 
 // One problem, one workgroup per output tile.
 template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool ABFT, bool IVL, int MINB, bool PRE, bool DIR>
-__global__ __launch_bounds__(WGM* WGN * 64, (waves_per_simd<BM, BN, WGM, WGN, MINB, DIR>())) void dgemm_abft_kernel(
+__global__ __launch_bounds__(WGM* WGN * 64, (waves_per_simd<BM, BN, WGM, WGN, MINB, DIR, ABFT>())) void dgemm_abft_kernel(
     DGemmArgs args)
 {
     int tm, tn;
@@ -1080,7 +1099,7 @@ __global__ __launch_bounds__(WGM* WGN * 64, (waves_per_simd<BM, BN, WGM, WGN, MI
 // device counter until none is left; the last workgroup to finish resets the
 // counter for the next launch.
 template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool ABFT, bool IVL, int MINB, bool PRE, bool DIR>
-__global__ __launch_bounds__(WGM* WGN * 64, (waves_per_simd<BM, BN, WGM, WGN, MINB, DIR>())) void dgemm_batched_kernel(
+__global__ __launch_bounds__(WGM* WGN * 64, (waves_per_simd<BM, BN, WGM, WGN, MINB, DIR, ABFT>())) void dgemm_batched_kernel(
     BatchLaunch L)
 {
     __shared__ int s_item;
