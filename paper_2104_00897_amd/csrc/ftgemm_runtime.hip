@@ -70,17 +70,18 @@ int bucket(int64_t x)
 
 int heuristic_tile_f64(int64_t m, int64_t n, int64_t k, bool need_intervals)
 {
-    // One workgroup per tile and 256 CUs.  The 128 x 128 tile on 8 waves is the
-    // fastest protected configuration measured at large sizes (half the
-    // accumulators per wave leave room for the checksum state), so it is the
-    // default once it fills the chip; mid sizes take the 4-wave 128 x 128 tile
-    // and small problems 64 x 64.  Explicit choices (config tile or the tuning
-    // table) may pick any configuration.
+    // One workgroup per tile, 256 CUs.  The 128 x 128 tile on 8 waves runs two
+    // workgroups per CU (512 at once), the 64 x 64 tile three (768).  Measured
+    // (protected, 8 waves vs 64 x 64): the large tile wins once it fills the
+    // chip, unless its last round of resident tiles is nearly empty (3072^3:
+    // 576 tiles, the second round one eighth full); otherwise the small tile
+    // wins.  The 4-wave 128 x 128 tile never won; explicit choices (config tile
+    // or the tuning table) may still pick any configuration.
     auto tiles = [&](int bm, int bn) { return ((m + bm - 1) / bm) * ((n + bn - 1) / bn); };
     (void)k;
     (void)need_intervals;
-    if (tiles(128, 128) >= 256) return 5;
-    if (tiles(128, 128) >= 128) return 2;
+    const int64_t t5 = tiles(128, 128), last = t5 % 512;
+    if (t5 >= 256 && (t5 <= 512 || last == 0 || last >= 256)) return 5;
     return 3;
 }
 

@@ -65,6 +65,27 @@ __device__ inline void c_set(const RepairProblem& P, int64_t i, int64_t j, doubl
     __threadfence();
 }
 
+// sum over p = p0, p0 + step, ... < k of op(A)(i, p) op(B)(p, j), accumulated
+// in that order; eight steps' operands are loaded before they are used, so a
+// lane's strided loads overlap instead of forming one round trip per step
+__device__ inline double dot_strided(const RepairProblem& P, int64_t i, int64_t j, int64_t p0, int64_t step)
+{
+    double s = 0.0;
+    int64_t p = p0;
+    for (; p + 7 * step < P.k; p += 8 * step) {
+        double a[8], b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            a[u] = opnd(P, true, i, p + u * step);
+            b[u] = opnd(P, false, p + u * step, j);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s = fma(a[u], b[u], s);
+    }
+    for (; p < P.k; p += step) s = fma(opnd(P, true, i, p), opnd(P, false, p, j), s);
+    return s;
+}
+
 __global__ __launch_bounds__(256) void repair_kernel(DevReport* rep, RepairProblem single,
                                                      const RepairProblem* table)
 {
@@ -83,8 +104,7 @@ __global__ __launch_bounds__(256) void repair_kernel(DevReport* rep, RepairProbl
                 (double)(P.scale_a ? *P.scale_a : 1.0f) * (double)(P.scale_b ? *P.scale_b : 1.0f);
             for (int e = lane; e < q.R * q.Q; e += 64) {
                 const int64_t gi = q.m0 + e % q.R, gj = q.n0 + e / q.R;
-                double s = 0.0;
-                for (int64_t p = 0; p < P.k; ++p) s = fma(opnd(P, true, gi, p), opnd(P, false, p, gj), s);
+                const double s = dot_strided(P, gi, gj, 0, 1);
                 double v = P.alpha * s * scale;
                 if (P.beta != 0.0) v += P.beta * c_get(P, gi, gj);
                 c_set(P, gi, gj, v);
@@ -113,8 +133,7 @@ __global__ __launch_bounds__(256) void repair_kernel(DevReport* rep, RepairProbl
                 if (lines_ok()) kind = FTG_KIND_SUBTRACT;
             }
             if (!kind) {
-                double s = 0.0;
-                for (int64_t p = lane; p < P.k; p += 64) s = fma(opnd(P, true, gi, p), opnd(P, false, p, gj), s);
+                double s = dot_strided(P, gi, gj, lane, 64);
                 s = group_sum<64>(s);
                 const double scale = (double)(P.scale_a ? *P.scale_a : 1.0f) * (double)(P.scale_b ? *P.scale_b : 1.0f);
                 double v = P.alpha * s * scale;
