@@ -77,15 +77,20 @@ __device__ inline float f64_to_f32_up(double x)
 }
 
 // ---------------------------------------------------------------- GEMM
-template <typename STA, typename STB, bool F8MMA, bool TA, bool TB>
+// RING: both operands k-contiguous and stored in the MFMA type; k-blocks of
+// 64 bytes per row go straight from memory to a ring of four LDS stages
+// (three blocks in flight, 80 KB: two workgroups per CU)
+template <typename STA, typename STB, bool F8MMA, bool TA, bool TB, bool RING = false>
 struct LCfg {
-    static constexpr int BM = 128, BN = 128, BK = 64;
+    static constexpr int MB = F8MMA ? 1 : 2;              // bytes of an MFMA operand element
+    static constexpr int BM = 128, BN = 128, BK = RING ? 64 / MB : 64;
+    static constexpr int NSTAGE = RING ? 4 : 2;
     static constexpr int NT = 256, WGM = 2, WGN = 2;
     static constexpr int WM = 64, WN = 64, FM = 4, FN = 4;
-    static constexpr int MB = F8MMA ? 1 : 2;              // bytes of an MFMA operand element
     static constexpr int PITCH = BK * MB + 16;  // LDS row pitch in bytes (16-byte aligned rows)
     static constexpr int A_BYTES = BM * PITCH, B_BYTES = BN * PITCH;
     static constexpr int STAGE = A_BYTES + B_BYTES;
+    static_assert(!RING || (TA && !TB && STA::bytes == MB && STB::bytes == MB && PITCH == 80), "ring staging");
     // operand staging: k-contiguous rows (A with TA=1, B with TB=0) or not
     static constexpr bool AKC = TA, BKC = !TB;
     // k-contiguous: 16-byte loads along k; otherwise each thread stages an
@@ -152,6 +157,14 @@ __device__ __attribute__((always_inline)) inline void lds_put_cols(unsigned char
     }
 }
 
+// One 16-byte load per lane from global memory straight into LDS: lane l
+// writes 16 bytes at dst + 16 l (lanes that do not issue write nothing).
+__device__ __attribute__((always_inline)) inline void lds_dma16(__amdgpu_buffer_rsrc_t r, unsigned char* dst, int voff)
+{
+    typedef __attribute__((address_space(3))) void* lds_ptr;
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)dst, 16, voff, 0, 0, 0);
+}
+
 // Verification bookkeeping (aliases the stage buffers after the k loop).
 struct LVerify {
     double rsum[2][128], csum[2][128];
@@ -162,17 +175,15 @@ struct LVerify {
 
 // MODE 0: C := alpha scale acc + beta C (FP32 C; also the checksum products);
 // MODE 1: the same, protected (injection, reference sums, flags, repair queue).
-template <typename STA, typename STB, bool F8MMA, bool TA, bool TB, int MODE>
+template <typename STA, typename STB, bool F8MMA, bool TA, bool TB, int MODE, bool RING>
 __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
 {
-    using Cf = LCfg<STA, STB, F8MMA, TA, TB>;
+    using Cf = LCfg<STA, STB, F8MMA, TA, TB, RING>;
     constexpr int BM = Cf::BM, BN = Cf::BN, BK = Cf::BK, PITCH = Cf::PITCH;
     constexpr int FM = Cf::FM, FN = Cf::FN, WM = Cf::WM, WN = Cf::WN;
-    static_assert(sizeof(LVerify) <= 2 * Cf::STAGE, "verify alias");
+    static_assert(sizeof(LVerify) <= Cf::NSTAGE * Cf::STAGE, "verify alias");
 
-    __shared__ __attribute__((aligned(16))) unsigned char smem[2 * Cf::STAGE];
-    __shared__ int flt[2][4];
-    __shared__ int fltn;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[Cf::NSTAGE * Cf::STAGE];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -364,31 +375,31 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
         }
     };
 
-    // ---- injection plan of this tile (one slot per tile: the whole k loop)
+    // ---- injection plan of this tile (one slot per tile: the whole k loop),
+    // drawn by every thread (the same values in all lanes)
     const bool inj = MODE == 1 && args.inj.on;
+    int flt[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+    int nflt = 0;
     if (inj) {
-        if (tid == 0) {
-            Fault f2[2];
-            const uint64_t tile_id = (uint64_t)tn * args.tiles_m + tm;
-            const int nf = slot_faults(args.inj, tile_id, R, Q, 0, K, f2);
-            fltn = nf;
-            for (int q = 0; q < 2; ++q) {
-                flt[q][0] = f2[q].row;
-                flt[q][1] = f2[q].col;
-                flt[q][2] = (int)f2[q].pflip;
-                flt[q][3] = f2[q].bit;
+        Fault f2[2];
+        const uint64_t tile_id = (uint64_t)tn * args.tiles_m + tm;
+        nflt = __builtin_amdgcn_readfirstlane(slot_faults(args.inj, tile_id, R, Q, 0, K, f2));
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            if (q < nflt) {
+                flt[q][0] = __builtin_amdgcn_readfirstlane(f2[q].row);
+                flt[q][1] = __builtin_amdgcn_readfirstlane(f2[q].col);
+                flt[q][2] = __builtin_amdgcn_readfirstlane((int)f2[q].pflip);
+                flt[q][3] = __builtin_amdgcn_readfirstlane(f2[q].bit);
             }
-        }
-        __syncthreads();
     }
-    const int nflt = inj ? __builtin_amdgcn_readfirstlane(fltn) : 0;
-    const int fkb0 = nflt > 0 ? __builtin_amdgcn_readfirstlane(flt[0][2]) / BK : -1;
-    const int fkb1 = nflt > 1 ? __builtin_amdgcn_readfirstlane(flt[1][2]) / BK : -1;
+    const int fkb0 = nflt > 0 ? flt[0][2] / BK : -1;
+    const int fkb1 = nflt > 1 ? flt[1][2] / BK : -1;
     auto apply_fault = [&](int q) __attribute__((always_inline)) {
-        const int row = __builtin_amdgcn_readfirstlane(flt[q][0]);
-        const int col = __builtin_amdgcn_readfirstlane(flt[q][1]);
-        const int bit = __builtin_amdgcn_readfirstlane(flt[q][3]);
-        const int pfl = __builtin_amdgcn_readfirstlane(flt[q][2]);
+        const int row = q ? flt[1][0] : flt[0][0];
+        const int col = q ? flt[1][1] : flt[0][1];
+        const int bit = q ? flt[1][3] : flt[0][3];
+        const int pfl = q ? flt[1][2] : flt[0][2];
         const bool ck = args.inj.target == FTG_TARGET_CHECKSUM;
         if (ck) return;  // the checksum target is applied to the expected sum in the epilogue
         const int rr = row % WM, cc = col % WN;
@@ -411,6 +422,72 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
                         (double)oldv, (double)newv);
     };
 
+    if constexpr (RING) {
+        // ---- k loop over a ring of NSTAGE stages, NSTAGE - 1 blocks in flight.
+        // Full blocks of interior tiles go straight to LDS: per stage 2 x 10
+        // wave loads of 64 slots (a row is 4 data slots of 16 bytes and one
+        // padding slot, masked off), five per wave.  Edge tiles and the k tail
+        // stage through registers, written before the block is needed.  The
+        // wait for block kb leaves the later blocks' loads in flight (an
+        // explicit count), then a plain barrier publishes the stage; a
+        // fenced barrier would wait for every outstanding load.
+        constexpr int NS = Cf::NSTAGE;
+        const bool ring = full_a && full_b;
+        const int nfull = (int)(K / BK);
+        auto ring_issue = [&](int kb, int st) __attribute__((always_inline)) {
+            const int64_t k0 = (int64_t)kb * BK;
+            unsigned char* base = smem + st * Cf::STAGE;
+#pragma unroll
+            for (int u = 0; u < 5; ++u) {
+                const int I = wave * 5 + u;     // 0..19: A loads 0..9, B loads 10..19
+                const int J = I % 10;
+                const int sl = 64 * J + lane, x = sl / 5, sub = sl - 5 * x;
+                if (I < 10) {
+                    if (sub < 4)
+                        lds_dma16(make_rsrc(A + k0 + m0 * lda), base + 1024 * J,
+                                  (int)(((int64_t)x * lda) * STA::bytes + 16 * sub));
+                } else {
+                    if (sub < 4)
+                        lds_dma16(make_rsrc(B + k0 + n0 * ldb), base + Cf::A_BYTES + 1024 * J,
+                                  (int)(((int64_t)x * ldb) * STB::bytes + 16 * sub));
+                }
+            }
+        };
+        auto stage_block = [&](int kb) __attribute__((always_inline)) {
+            const int st = kb % NS;
+            if (ring && kb < nfull) {
+                ring_issue(kb, st);
+            } else {
+                load_global(kb);
+                store_lds(st);
+            }
+        };
+        auto sync_for = [&](int kb) __attribute__((always_inline)) {
+            // this wave's loads of later blocks (five per block) may stay in flight
+            const int hi = min(nkb - 1, kb + NS - 2);
+            const int later = ring ? max(0, min(hi, nfull - 1) - kb) : 0;
+            asm volatile("" ::: "memory");
+            // s_waitcnt: vmcnt = later * 5, expcnt unconstrained, lgkmcnt = 0
+            if (later >= 2) __builtin_amdgcn_s_waitcnt(0x7A);
+            else if (later == 1) __builtin_amdgcn_s_waitcnt(0x75);
+            else __builtin_amdgcn_s_waitcnt(0x70);
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+        };
+#pragma unroll 1
+        for (int b = 0; b < NS - 1 && b < nkb; ++b) stage_block(b);
+        for (int kb = 0; kb < nkb; ++kb) {
+            sync_for(kb);
+            // the stage of block kb - 1 is free: every wave is past its MFMAs
+            if (kb + NS - 1 < nkb) stage_block(kb + NS - 1);
+            mfma_block(kb % NS);
+            if (MODE == 1) {
+                if (kb == fkb0) apply_fault(0);
+                if (kb == fkb1) apply_fault(1);
+            }
+        }
+        __syncthreads();
+    } else {
     // ---- k loop: stage kb+1 in registers while block kb multiplies from LDS
     load_global(0);
     store_lds(0);
@@ -425,6 +502,7 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
         }
         if (kb + 1 < nkb) store_lds(st ^ 1);
         __syncthreads();
+    }
     }
 
     // ---- epilogue.  Lane (lq, l16) of fragment (g, h) holds rows
@@ -520,14 +598,18 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
                     e += (double)es[0] + (double)es[args.lder] + (double)es[2 * args.lder];
                 }
                 if (inj && args.inj.target == FTG_TARGET_CHECKSUM) {
-                    for (int q = 0; q < nflt; ++q)
-                        if (flt[q][0] == x) {
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const int fr = q ? flt[1][0] : flt[0][0], fb = q ? flt[1][3] : flt[0][3];
+                        const int fp = q ? flt[1][2] : flt[0][2];
+                        if (q < nflt && fr == x) {
                             const float o = er[0];
-                            const float nv = flip_f32(o, flt[q][3]);
+                            const float nv = flip_f32(o, fb);
                             e += (double)nv - (double)o;
-                            push_inject(args.rep, args.problem, tm, tn, 0, m0 + x, -1, flt[q][2], flt[q][3],
-                                        FTG_TARGET_CHECKSUM, (double)o, (double)nv);
+                            push_inject(args.rep, args.problem, tm, tn, 0, m0 + x, -1, fp, fb, FTG_TARGET_CHECKSUM,
+                                        (double)o, (double)nv);
                         }
+                    }
                 }
                 ex = asd * e;
                 mag = fabs(asd) * (double)args.RA[m0 + x] * (double)args.MB[tn];
@@ -590,10 +672,20 @@ template <typename STA, typename STB, bool F8MMA, int MODE>
 hipError_t launch_lowp_t(const LowpArgs& a, int ta, int tb, hipStream_t s)
 {
     const dim3 grid(a.tiles_m * a.tiles_n * (MODE == 0 && a.ksplit > 1 ? a.ksplit : 1)), block(256);
-    if (!ta && !tb) hipLaunchKernelGGL((lowp_gemm_kernel<STA, STB, F8MMA, false, false, MODE>), grid, block, 0, s, a);
-    else if (ta && !tb) hipLaunchKernelGGL((lowp_gemm_kernel<STA, STB, F8MMA, true, false, MODE>), grid, block, 0, s, a);
-    else if (!ta && tb) hipLaunchKernelGGL((lowp_gemm_kernel<STA, STB, F8MMA, false, true, MODE>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((lowp_gemm_kernel<STA, STB, F8MMA, true, true, MODE>), grid, block, 0, s, a);
+    constexpr bool ring_ok = STA::bytes == (F8MMA ? 1 : 2) && STB::bytes == (F8MMA ? 1 : 2);
+    if (!ta && !tb) hipLaunchKernelGGL((lowp_gemm_kernel<STA, STB, F8MMA, false, false, MODE, false>), grid, block, 0, s, a);
+    else if (ta && !tb) {
+        if constexpr (ring_ok) {
+            if (a.vec_a && a.vec_b)
+                hipLaunchKernelGGL((lowp_gemm_kernel<STA, STB, F8MMA, true, false, MODE, true>), grid, block, 0, s, a);
+            else
+                hipLaunchKernelGGL((lowp_gemm_kernel<STA, STB, F8MMA, true, false, MODE, false>), grid, block, 0, s, a);
+        } else {
+            hipLaunchKernelGGL((lowp_gemm_kernel<STA, STB, F8MMA, true, false, MODE, false>), grid, block, 0, s, a);
+        }
+    }
+    else if (!ta && tb) hipLaunchKernelGGL((lowp_gemm_kernel<STA, STB, F8MMA, false, true, MODE, false>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((lowp_gemm_kernel<STA, STB, F8MMA, true, true, MODE, false>), grid, block, 0, s, a);
     return hipGetLastError();
 }
 
