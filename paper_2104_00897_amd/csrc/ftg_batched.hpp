@@ -19,7 +19,7 @@ struct RepairProblem {
     const float* scale_b;
 };
 
-constexpr int kRepairBlocks = 64;  // 256 waves: one queued slot per wave in most calls
+constexpr int kRepairBlocks = 256;  // one queued request per workgroup, one workgroup per CU
 
 hipError_t launch_report_reset(DevReport* rep, hipStream_t s);
 hipError_t launch_repair(DevReport* rep, const RepairProblem& single, const RepairProblem* table,

@@ -514,8 +514,8 @@ ftg_status ftg_gemm_ex(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n,
     // Operands whose rows are contiguous (op(A) = A, op(B) = B^T) are first
     // packed into k-major copies in the workspace: the product kernels stage
     // k-contiguous operands without register transposes (about twice as fast).
-    // Everything after the pack (encode, checksum products, product) reads the
-    // packed copies; the repair kernel reads the caller's operands.
+    // Everything after the pack (encode, checksum products, product, repair)
+    // reads the packed copies.
     const int ita0 = ta == FTG_OP_T, itb0 = tb == FTG_OP_T;
     const bool pack_a = !ita0, pack_b = itb0 != 0;
     const int64_t ldp = (k + 15) / 16 * 16;
@@ -611,9 +611,9 @@ ftg_status ftg_gemm_ex(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n,
     }
     ftg::RepairProblem rp;
     std::memset(&rp, 0, sizeof(rp));
-    rp.A = A; rp.B = B; rp.C = C;
-    rp.lda = lda; rp.ldb = ldb; rp.ldc = ldc; rp.k = k;
-    rp.ta = ita0; rp.tb = itb0; rp.correct_policy = cfg ? cfg->correct_policy : 0;
+    rp.A = a.A; rp.B = a.B; rp.C = C;  // the packed copies are still in the workspace
+    rp.lda = a.lda; rp.ldb = a.ldb; rp.ldc = ldc; rp.k = k;
+    rp.ta = ita; rp.tb = itb; rp.correct_policy = cfg ? cfg->correct_policy : 0;
     rp.ab_type = ab_type; rp.c_type = FTG_F32;
     rp.alpha = alpha; rp.beta = beta;
     rp.scale_a = a.scale_a; rp.scale_b = a.scale_b;

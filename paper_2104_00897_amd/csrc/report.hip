@@ -86,14 +86,28 @@ __device__ inline double dot_strided(const RepairProblem& P, int64_t i, int64_t 
     return s;
 }
 
+// One workgroup per queued request: the dot product of a recomputed element is
+// split over the 256 threads (thread t takes p = t, t + 256, ...) and the
+// partial sums are combined in a fixed order, so a repair costs a few rounds
+// of strided loads instead of one wave's long chain.  Every branch below
+// depends only on the request and on values all threads read alike, so the
+// barriers are reached uniformly.
 __global__ __launch_bounds__(256) void repair_kernel(DevReport* rep, RepairProblem single,
                                                      const RepairProblem* table)
 {
-    const int lane = threadIdx.x & 63;
-    const int gwave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    __shared__ double red[4];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const unsigned int n = min(rep->rq_count, rep->rq_capacity);
-    for (unsigned int r = gwave; r < n; r += nwaves) {
+    auto block_sum = [&](double v) {
+        v = group_sum<64>(v);
+        if (lane == 0) red[wave] = v;
+        __syncthreads();
+        const double t = (red[0] + red[1]) + (red[2] + red[3]);
+        __syncthreads();
+        return t;
+    };
+    for (unsigned int r = blockIdx.x; r < n; r += gridDim.x) {
         const RepairReq q = rep->rq[r];
         const RepairProblem P = table ? table[q.problem] : single;
         if (q.whole) {
@@ -102,7 +116,7 @@ __global__ __launch_bounds__(256) void repair_kernel(DevReport* rep, RepairProbl
             // kernel has counted and recorded the slot)
             const double scale =
                 (double)(P.scale_a ? *P.scale_a : 1.0f) * (double)(P.scale_b ? *P.scale_b : 1.0f);
-            for (int e = lane; e < q.R * q.Q; e += 64) {
+            for (int e = tid; e < q.R * q.Q; e += 256) {
                 const int64_t gi = q.m0 + e % q.R, gj = q.n0 + e / q.R;
                 const double s = dot_strided(P, gi, gj, 0, 1);
                 double v = P.alpha * s * scale;
@@ -116,32 +130,33 @@ __global__ __launch_bounds__(256) void repair_kernel(DevReport* rep, RepairProbl
         double d = q.nr ? q.dfi : q.dfj, tau = q.nr ? q.tfi : q.tfj;
         if (q.nr == 1 && q.nc == 1) {
             const int64_t gi = q.m0 + q.fi, gj = q.n0 + q.fj;
+            // C's row and column sums over the tile against the expected ones
             auto lines_ok = [&]() {
                 double rs = 0.0, cs = 0.0;
-                for (int j = lane; j < q.Q; j += 64) rs += c_get(P, gi, q.n0 + j);
-                for (int i = lane; i < q.R; i += 64) cs += c_get(P, q.m0 + i, gj);
-                rs = group_sum<64>(rs);
-                cs = group_sum<64>(cs);
+                for (int j = tid; j < q.Q; j += 256) rs += c_get(P, gi, q.n0 + j);
+                for (int i = tid; i < q.R; i += 256) cs += c_get(P, q.m0 + i, gj);
+                rs = block_sum(rs);
+                cs = block_sum(cs);
                 return !flagged(rs - q.exp_row, q.tfi) && !flagged(cs - q.exp_col, q.tfj);
             };
             const double x = c_get(P, gi, gj);
+            __syncthreads();  // every thread holds the stored value before thread 0 changes it
             kind = 0;
             if (P.correct_policy == 0 && isfinite(q.dfi) && isfinite(x) &&
                 !absorbed(P.c_type == FTG_F32, x, q.tfi, q.Q)) {
-                if (lane == 0) c_set(P, gi, gj, x - q.dfi);
-                __threadfence();
+                if (tid == 0) c_set(P, gi, gj, x - q.dfi);
+                __syncthreads();
                 if (lines_ok()) kind = FTG_KIND_SUBTRACT;
             }
             if (!kind) {
-                double s = dot_strided(P, gi, gj, lane, 64);
-                s = group_sum<64>(s);
+                const double s = block_sum(dot_strided(P, gi, gj, tid, 256));
                 const double scale = (double)(P.scale_a ? *P.scale_a : 1.0f) * (double)(P.scale_b ? *P.scale_b : 1.0f);
                 double v = P.alpha * s * scale;
                 if (P.beta != 0.0) v += P.beta * q.cin;
-                if (lane == 0) c_set(P, gi, gj, v);
-                __threadfence();
+                if (tid == 0) c_set(P, gi, gj, v);
+                __syncthreads();
                 kind = lines_ok() ? FTG_KIND_RECOMPUTE : FTG_KIND_UNCORRECTABLE;
-                if (kind == FTG_KIND_UNCORRECTABLE && lane == 0) c_set(P, gi, gj, x);
+                if (kind == FTG_KIND_UNCORRECTABLE && tid == 0) c_set(P, gi, gj, x);
             }
             if (kind != FTG_KIND_UNCORRECTABLE) { row = gi; col = gj; }
             d = q.dfi;
@@ -152,7 +167,7 @@ __global__ __launch_bounds__(256) void repair_kernel(DevReport* rep, RepairProbl
         } else {
             kind = FTG_KIND_UNCORRECTABLE;
         }
-        if (lane == 0) {
+        if (tid == 0) {
             atomicAdd(&rep->cnt[kDetected], 1ull);
             if (kind == FTG_KIND_SUBTRACT) atomicAdd(&rep->cnt[kCorrSub], 1ull);
             else if (kind == FTG_KIND_RECOMPUTE) atomicAdd(&rep->cnt[kCorrRecomp], 1ull);
