@@ -79,7 +79,11 @@ __device__ inline float f64_to_f32_up(double x)
 // ---------------------------------------------------------------- GEMM
 // RING: both operands k-contiguous and stored in the MFMA type; k-blocks of
 // 64 bytes per row go straight from memory to a ring of four LDS stages
-// (three blocks in flight, 80 KB: two workgroups per CU)
+// (three blocks in flight, 64 KB: two workgroups per CU).  Ring rows are not
+// padded: 16-byte chunk c of row r sits at chunk c ^ ((r >> SWS) & 3), with
+// SWS = 1 for the 16-byte bf16 fragment reads and 2 for the 8-byte fp8 ones;
+// measured, these keep the reads free of bank conflicts, while padded 80-byte
+// rows cost four conflict cycles per 16-byte read.
 template <typename STA, typename STB, bool F8MMA, bool TA, bool TB, bool RING = false>
 struct LCfg {
     static constexpr int MB = F8MMA ? 1 : 2;              // bytes of an MFMA operand element
@@ -87,10 +91,12 @@ struct LCfg {
     static constexpr int NSTAGE = RING ? 4 : 2;
     static constexpr int NT = 256, WGM = 2, WGN = 2;
     static constexpr int WM = 64, WN = 64, FM = 4, FN = 4;
-    static constexpr int PITCH = BK * MB + 16;  // LDS row pitch in bytes (16-byte aligned rows)
+    static constexpr bool SWZ = RING;                       // swizzled, unpadded rows
+    static constexpr int SWS = MB == 2 ? 1 : 2;             // row shift of the swizzle
+    static constexpr int PITCH = BK * MB + (SWZ ? 0 : 16);  // LDS row pitch in bytes (16-byte aligned rows)
     static constexpr int A_BYTES = BM * PITCH, B_BYTES = BN * PITCH;
     static constexpr int STAGE = A_BYTES + B_BYTES;
-    static_assert(!RING || (TA && !TB && STA::bytes == MB && STB::bytes == MB && PITCH == 80), "ring staging");
+    static_assert(!RING || (TA && !TB && STA::bytes == MB && STB::bytes == MB && PITCH == 64), "ring staging");
     // operand staging: k-contiguous rows (A with TA=1, B with TB=0) or not
     static constexpr bool AKC = TA, BKC = !TB;
     // k-contiguous: 16-byte loads along k; otherwise each thread stages an
@@ -229,6 +235,11 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
         if (Cf::BKC) { *r = v / (BK / Cf::VB); *p = (v % (BK / Cf::VB)) * Cf::VB; }
         else { *r = (tid % (BN / 8)) * 8; *p = (tid / (BN / 8)) * 4 + q; }
     };
+    // swizzled rows: the step whose 16-byte chunk holds step p of row r
+    auto swz_step = [&](int r, int p) __attribute__((always_inline)) {
+        constexpr int PER = 16 / Cf::MB;  // steps per chunk
+        return ((p / PER) ^ ((r >> Cf::SWS) & 3)) * PER + p % PER;
+    };
     u32x4_t ra[Cf::NVA], rb[Cf::NVB];
     const bool full_a = (R == BM) && args.vec_a;
     const bool full_b = (Q == BN) && args.vec_b;
@@ -313,6 +324,7 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
             for (int q = 0; q < Cf::NVA; ++q) {
                 int r, p;
                 a_rp(q, &r, &p);
+                if constexpr (Cf::SWZ) p = swz_step(r, p);
                 lds_put16<STA, F8MMA, PITCH>(ta, r, p, ra[q]);
             }
         } else {
@@ -325,6 +337,7 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
             for (int q = 0; q < Cf::NVB; ++q) {
                 int r, p;
                 b_rp(q, &r, &p);
+                if constexpr (Cf::SWZ) p = swz_step(r, p);
                 lds_put16<STB, F8MMA, PITCH>(tb, r, p, rb[q]);
             }
         } else {
@@ -346,7 +359,9 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
         const unsigned char* tb = ta + Cf::A_BYTES;
 #pragma unroll
         for (int s = 0; s < BK / 32; ++s) {
-            const int kb_ = (32 * s + 8 * lq) * Cf::MB;
+            int kb_ = (32 * s + 8 * lq) * Cf::MB;
+            // fragment rows are 16g + l16 past a multiple of 16: swizzle (l16 >> SWS) & 3
+            if constexpr (Cf::SWZ) kb_ = (((kb_ >> 4) ^ ((l16 >> Cf::SWS) & 3)) << 4) | (kb_ & 15);
             if constexpr (F8MMA) {
                 long a[FM], b[FN];
 #pragma unroll
@@ -424,9 +439,9 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
 
     if constexpr (RING) {
         // ---- k loop over a ring of NSTAGE stages, NSTAGE - 1 blocks in flight.
-        // Full blocks of interior tiles go straight to LDS: per stage 2 x 10
-        // wave loads of 64 slots (a row is 4 data slots of 16 bytes and one
-        // padding slot, masked off), five per wave.  Edge tiles and the k tail
+        // Full blocks of interior tiles go straight to LDS: per stage 2 x 8
+        // wave loads of 64 slots of 16 bytes, four per wave; slot s holds row
+        // s / 4, chunk (s % 4) ^ ((row >> SWS) & 3).  Edge tiles and the k tail
         // stage through registers, written before the block is needed.  The
         // wait for block kb leaves the later blocks' loads in flight (an
         // explicit count), then a plain barrier publishes the stage; a
@@ -438,19 +453,16 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
             const int64_t k0 = (int64_t)kb * BK;
             unsigned char* base = smem + st * Cf::STAGE;
 #pragma unroll
-            for (int u = 0; u < 5; ++u) {
-                const int I = wave * 5 + u;     // 0..19: A loads 0..9, B loads 10..19
-                const int J = I % 10;
-                const int sl = 64 * J + lane, x = sl / 5, sub = sl - 5 * x;
-                if (I < 10) {
-                    if (sub < 4)
-                        lds_dma16(make_rsrc(A + k0 + m0 * lda), base + 1024 * J,
-                                  (int)(((int64_t)x * lda) * STA::bytes + 16 * sub));
-                } else {
-                    if (sub < 4)
-                        lds_dma16(make_rsrc(B + k0 + n0 * ldb), base + Cf::A_BYTES + 1024 * J,
-                                  (int)(((int64_t)x * ldb) * STB::bytes + 16 * sub));
-                }
+            for (int u = 0; u < 4; ++u) {
+                const int I = wave * 4 + u;     // 0..15: A loads 0..7, B loads 8..15
+                const int J = I % 8;
+                const int sl = 64 * J + lane, x = sl >> 2, c = (sl & 3) ^ ((x >> Cf::SWS) & 3);
+                if (I < 8)
+                    lds_dma16(make_rsrc(A + k0 + m0 * lda), base + 1024 * J,
+                              (int)(((int64_t)x * lda) * STA::bytes + 16 * c));
+                else
+                    lds_dma16(make_rsrc(B + k0 + n0 * ldb), base + Cf::A_BYTES + 1024 * J,
+                              (int)(((int64_t)x * ldb) * STB::bytes + 16 * c));
             }
         };
         auto stage_block = [&](int kb) __attribute__((always_inline)) {
@@ -463,13 +475,13 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
             }
         };
         auto sync_for = [&](int kb) __attribute__((always_inline)) {
-            // this wave's loads of later blocks (five per block) may stay in flight
+            // this wave's loads of later blocks (four per block) may stay in flight
             const int hi = min(nkb - 1, kb + NS - 2);
             const int later = ring ? max(0, min(hi, nfull - 1) - kb) : 0;
             asm volatile("" ::: "memory");
-            // s_waitcnt: vmcnt = later * 5, expcnt unconstrained, lgkmcnt = 0
-            if (later >= 2) __builtin_amdgcn_s_waitcnt(0x7A);
-            else if (later == 1) __builtin_amdgcn_s_waitcnt(0x75);
+            // s_waitcnt: vmcnt = later * 4, expcnt unconstrained, lgkmcnt = 0
+            if (later >= 2) __builtin_amdgcn_s_waitcnt(0x78);
+            else if (later == 1) __builtin_amdgcn_s_waitcnt(0x74);
             else __builtin_amdgcn_s_waitcnt(0x70);
             __builtin_amdgcn_s_barrier();
             asm volatile("" ::: "memory");
