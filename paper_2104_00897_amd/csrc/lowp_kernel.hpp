@@ -439,15 +439,17 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
 
     if constexpr (RING) {
         // ---- k loop over a ring of NSTAGE stages, NSTAGE - 1 blocks in flight.
-        // Full blocks of interior tiles go straight to LDS: per stage 2 x 8
-        // wave loads of 64 slots of 16 bytes, four per wave; slot s holds row
-        // s / 4, chunk (s % 4) ^ ((row >> SWS) & 3).  Edge tiles and the k tail
-        // stage through registers, written before the block is needed.  The
+        // Full k-blocks go straight to LDS: per stage 2 x 8 wave loads of 64
+        // slots of 16 bytes, four per wave; slot s holds row s / 4, chunk
+        // (s % 4) ^ ((row >> SWS) & 3).  The k tail, and in protected mode the
+        // edge tiles, stage through registers, written before the block is needed.  The
         // wait for block kb leaves the later blocks' loads in flight (an
         // explicit count), then a plain barrier publishes the stage; a
         // fenced barrier would wait for every outstanding load.
         constexpr int NS = Cf::NSTAGE;
-        const bool ring = full_a && full_b;
+        // plain mode: edge tiles use the ring too; rows past the matrix load
+        // its last row (they only feed accumulators the epilogue never stores)
+        const bool ring = MODE == 0 ? (args.vec_a && args.vec_b) : (full_a && full_b);
         const int nfull = (int)(K / BK);
         auto ring_issue = [&](int kb, int st) __attribute__((always_inline)) {
             const int64_t k0 = (int64_t)kb * BK;
@@ -459,10 +461,10 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
                 const int sl = 64 * J + lane, x = sl >> 2, c = (sl & 3) ^ ((x >> Cf::SWS) & 3);
                 if (I < 8)
                     lds_dma16(make_rsrc(A + k0 + m0 * lda), base + 1024 * J,
-                              (int)(((int64_t)x * lda) * STA::bytes + 16 * c));
+                              (int)(((int64_t)min(x, R - 1) * lda) * STA::bytes + 16 * c));
                 else
                     lds_dma16(make_rsrc(B + k0 + n0 * ldb), base + Cf::A_BYTES + 1024 * J,
-                              (int)(((int64_t)x * ldb) * STB::bytes + 16 * c));
+                              (int)(((int64_t)min(x, Q - 1) * ldb) * STB::bytes + 16 * c));
             }
         };
         auto stage_block = [&](int kb) __attribute__((always_inline)) {
