@@ -77,13 +77,22 @@ __device__ inline float f64_to_f32_up(double x)
 }
 
 // ---------------------------------------------------------------- GEMM
-// RING: both operands k-contiguous and stored in the MFMA type; k-blocks of
-// 64 bytes per row go straight from memory to a ring of four LDS stages
-// (three blocks in flight, 64 KB: two workgroups per CU).  Ring rows are not
-// padded: 16-byte chunk c of row r sits at chunk c ^ ((r >> SWS) & 3), with
-// SWS = 1 for the 16-byte bf16 fragment reads and 2 for the 8-byte fp8 ones;
-// measured, these keep the reads free of bank conflicts, while padded 80-byte
-// rows cost four conflict cycles per 16-byte read.
+// RING: both operands k-contiguous; k-blocks of BK steps go straight from
+// memory to a ring of four LDS stages (three blocks in flight, two workgroups
+// per CU) in the stored type: 64-byte rows for bf16 (BK = 32) and for fp8 on
+// the fp8 MFMA (BK = 64); an fp8 operand of a bf16 product (the fp8 checksum
+// products) keeps 32-byte rows and is widened to bf16 exactly when its
+// fragments are read.  Ring rows are not padded: 16-byte chunk c of row r sits
+// at chunk c ^ ring_swz(r), chosen per row size and fragment read width;
+// measured, the swizzles keep the reads free of bank conflicts, while padded
+// 80-byte rows cost four conflict cycles per 16-byte read.
+template <int ROWB, int W>
+__device__ __attribute__((always_inline)) inline int ring_swz(int r)
+{
+    if constexpr (ROWB == 64) return (r >> (W == 16 ? 1 : 2)) & 3;
+    else return (r >> 3) & 1;
+}
+
 template <typename STA, typename STB, bool F8MMA, bool TA, bool TB, bool RING = false>
 struct LCfg {
     static constexpr int MB = F8MMA ? 1 : 2;              // bytes of an MFMA operand element
@@ -92,11 +101,18 @@ struct LCfg {
     static constexpr int NT = 256, WGM = 2, WGN = 2;
     static constexpr int WM = 64, WN = 64, FM = 4, FN = 4;
     static constexpr bool SWZ = RING;                       // swizzled, unpadded rows
-    static constexpr int SWS = MB == 2 ? 1 : 2;             // row shift of the swizzle
     static constexpr int PITCH = BK * MB + (SWZ ? 0 : 16);  // LDS row pitch in bytes (16-byte aligned rows)
-    static constexpr int A_BYTES = BM * PITCH, B_BYTES = BN * PITCH;
+    // LDS rows of A and B: the MFMA type, or in the ring the stored type
+    static constexpr int PA = RING ? BK * STA::bytes : PITCH, PB = RING ? BK * STB::bytes : PITCH;
+    static constexpr bool CVA = RING && !F8MMA && STA::bytes == 1;  // fp8 widened at the fragment read
+    static constexpr bool CVB = RING && !F8MMA && STB::bytes == 1;
+    static constexpr int WA = (F8MMA || CVA) ? 8 : 16, WB = (F8MMA || CVB) ? 8 : 16;  // fragment read bytes
+    static constexpr int A_BYTES = BM * PA, B_BYTES = BN * PB;
     static constexpr int STAGE = A_BYTES + B_BYTES;
-    static_assert(!RING || (TA && !TB && STA::bytes == MB && STB::bytes == MB && PITCH == 64), "ring staging");
+    static constexpr int LA = A_BYTES / 1024, LB = B_BYTES / 1024;  // ring: wave loads per stage
+    static constexpr int LPW = (LA + LB) / 4;                        // ring: loads per wave per stage
+    static_assert(!RING || (TA && !TB && (STA::bytes == MB || CVA) && (STB::bytes == MB || CVB) &&
+                            !(CVA && CVB) && (LA + LB) % 4 == 0), "ring staging");
     // operand staging: k-contiguous rows (A with TA=1, B with TB=0) or not
     static constexpr bool AKC = TA, BKC = !TB;
     // k-contiguous: 16-byte loads along k; otherwise each thread stages an
@@ -112,12 +128,12 @@ struct LCfg {
 // Writes one 16-byte load of k-contiguous stored elements (row r, steps p ..)
 // to the k-contiguous LDS tile of the MFMA type (fp8 staged as bf16 when the
 // product runs on the bf16 MFMA).
-template <typename ST, bool F8MMA, int PITCH>
+template <typename ST, bool F8MMA, int PITCH, bool RAW = false>
 __device__ __attribute__((always_inline)) inline void lds_put16(unsigned char* tile, int r, int p, const u32x4_t v)
 {
-    if constexpr (F8MMA || ST::bytes == 2) {
-        constexpr int MBY = F8MMA ? 1 : 2;
-        *(u32x4_t*)(tile + r * PITCH + p * MBY) = v;
+    if constexpr (RAW || F8MMA || ST::bytes == 2) {
+        // the stored type (the MFMA type unless RAW keeps fp8 for a bf16 product)
+        *(u32x4_t*)(tile + r * PITCH + p * ST::bytes) = v;
     } else {
         uint16_t h[16];
 #pragma unroll
@@ -169,6 +185,18 @@ __device__ __attribute__((always_inline)) inline void lds_dma16(__amdgpu_buffer_
 {
     typedef __attribute__((address_space(3))) void* lds_ptr;
     __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)dst, 16, voff, 0, 0, 0);
+}
+
+// Eight e4m3fn codes (k order, lowest byte first) as bf16, exactly: every
+// e4m3fn value, subnormals included, is a bf16 value.
+__device__ __attribute__((always_inline)) inline bf16x8_t widen_fp8x8(u32x2 w)
+{
+    u32x4_t r;
+    r[0] = __builtin_bit_cast(unsigned int, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w[0], 1.0f, false));
+    r[1] = __builtin_bit_cast(unsigned int, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w[0], 1.0f, true));
+    r[2] = __builtin_bit_cast(unsigned int, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w[1], 1.0f, false));
+    r[3] = __builtin_bit_cast(unsigned int, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w[1], 1.0f, true));
+    return __builtin_bit_cast(bf16x8_t, r);
 }
 
 // Verification bookkeeping (aliases the stage buffers after the k loop).
@@ -236,9 +264,13 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
         else { *r = (tid % (BN / 8)) * 8; *p = (tid / (BN / 8)) * 4 + q; }
     };
     // swizzled rows: the step whose 16-byte chunk holds step p of row r
-    auto swz_step = [&](int r, int p) __attribute__((always_inline)) {
-        constexpr int PER = 16 / Cf::MB;  // steps per chunk
-        return ((p / PER) ^ ((r >> Cf::SWS) & 3)) * PER + p % PER;
+    auto swz_a = [&](int r, int p) __attribute__((always_inline)) {
+        constexpr int PER = 16 / STA::bytes;  // steps per chunk
+        return ((p / PER) ^ ring_swz<Cf::PA, Cf::WA>(r)) * PER + p % PER;
+    };
+    auto swz_b = [&](int r, int p) __attribute__((always_inline)) {
+        constexpr int PER = 16 / STB::bytes;
+        return ((p / PER) ^ ring_swz<Cf::PB, Cf::WB>(r)) * PER + p % PER;
     };
     u32x4_t ra[Cf::NVA], rb[Cf::NVB];
     const bool full_a = (R == BM) && args.vec_a;
@@ -324,8 +356,8 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
             for (int q = 0; q < Cf::NVA; ++q) {
                 int r, p;
                 a_rp(q, &r, &p);
-                if constexpr (Cf::SWZ) p = swz_step(r, p);
-                lds_put16<STA, F8MMA, PITCH>(ta, r, p, ra[q]);
+                if constexpr (Cf::SWZ) p = swz_a(r, p);
+                lds_put16<STA, F8MMA, Cf::PA, RING>(ta, r, p, ra[q]);
             }
         } else {
             int r, p;
@@ -337,8 +369,8 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
             for (int q = 0; q < Cf::NVB; ++q) {
                 int r, p;
                 b_rp(q, &r, &p);
-                if constexpr (Cf::SWZ) p = swz_step(r, p);
-                lds_put16<STB, F8MMA, PITCH>(tb, r, p, rb[q]);
+                if constexpr (Cf::SWZ) p = swz_b(r, p);
+                lds_put16<STB, F8MMA, Cf::PB, RING>(tb, r, p, rb[q]);
             }
         } else {
             int r, p;
@@ -359,15 +391,20 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
         const unsigned char* tb = ta + Cf::A_BYTES;
 #pragma unroll
         for (int s = 0; s < BK / 32; ++s) {
-            int kb_ = (32 * s + 8 * lq) * Cf::MB;
-            // fragment rows are 16g + l16 past a multiple of 16: swizzle (l16 >> SWS) & 3
-            if constexpr (Cf::SWZ) kb_ = (((kb_ >> 4) ^ ((l16 >> Cf::SWS) & 3)) << 4) | (kb_ & 15);
+            // byte offsets of the lane's 8 steps in an A / B row; fragment rows
+            // are 16g + l16 past a multiple of 16, so the swizzle depends on l16
+            int oa = (32 * s + 8 * lq) * (RING ? STA::bytes : Cf::MB);
+            int ob = (32 * s + 8 * lq) * (RING ? STB::bytes : Cf::MB);
+            if constexpr (Cf::SWZ) {
+                oa = (((oa >> 4) ^ ring_swz<Cf::PA, Cf::WA>(l16)) << 4) | (oa & 15);
+                ob = (((ob >> 4) ^ ring_swz<Cf::PB, Cf::WB>(l16)) << 4) | (ob & 15);
+            }
             if constexpr (F8MMA) {
                 long a[FM], b[FN];
 #pragma unroll
-                for (int g = 0; g < FM; ++g) a[g] = *(const long*)(ta + (wm0 + 16 * g + l16) * PITCH + kb_);
+                for (int g = 0; g < FM; ++g) a[g] = *(const long*)(ta + (wm0 + 16 * g + l16) * Cf::PA + oa);
 #pragma unroll
-                for (int h = 0; h < FN; ++h) b[h] = *(const long*)(tb + (wn0 + 16 * h + l16) * PITCH + kb_);
+                for (int h = 0; h < FN; ++h) b[h] = *(const long*)(tb + (wn0 + 16 * h + l16) * Cf::PB + ob);
 #pragma unroll
                 for (int g = 0; g < FM; ++g)
 #pragma unroll
@@ -376,11 +413,17 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
             } else {
                 bf16x8_t a[FM], b[FN];
 #pragma unroll
-                for (int g = 0; g < FM; ++g)
-                    a[g] = __builtin_bit_cast(bf16x8_t, *(const u32x4_t*)(ta + (wm0 + 16 * g + l16) * PITCH + kb_));
+                for (int g = 0; g < FM; ++g) {
+                    const unsigned char* q = ta + (wm0 + 16 * g + l16) * Cf::PA + oa;
+                    if constexpr (Cf::CVA) a[g] = widen_fp8x8(*(const u32x2*)q);
+                    else a[g] = __builtin_bit_cast(bf16x8_t, *(const u32x4_t*)q);
+                }
 #pragma unroll
-                for (int h = 0; h < FN; ++h)
-                    b[h] = __builtin_bit_cast(bf16x8_t, *(const u32x4_t*)(tb + (wn0 + 16 * h + l16) * PITCH + kb_));
+                for (int h = 0; h < FN; ++h) {
+                    const unsigned char* q = tb + (wn0 + 16 * h + l16) * Cf::PB + ob;
+                    if constexpr (Cf::CVB) b[h] = widen_fp8x8(*(const u32x2*)q);
+                    else b[h] = __builtin_bit_cast(bf16x8_t, *(const u32x4_t*)q);
+                }
 #pragma unroll
                 for (int g = 0; g < FM; ++g)
 #pragma unroll
@@ -439,9 +482,9 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
 
     if constexpr (RING) {
         // ---- k loop over a ring of NSTAGE stages, NSTAGE - 1 blocks in flight.
-        // Full k-blocks go straight to LDS: per stage 2 x 8 wave loads of 64
-        // slots of 16 bytes, four per wave; slot s holds row s / 4, chunk
-        // (s % 4) ^ ((row >> SWS) & 3).  The k tail, and in protected mode the
+        // Full k-blocks go straight to LDS: per stage LA + LB wave loads of 64
+        // slots of 16 bytes, LPW per wave; slot s of an operand with S slots
+        // per row holds row s / S, chunk (s % S) ^ ring_swz(row).  The k tail, and in protected mode the
         // edge tiles, stage through registers, written before the block is needed.  The
         // wait for block kb leaves the later blocks' loads in flight (an
         // explicit count), then a plain barrier publishes the stage; a
@@ -455,16 +498,22 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
             const int64_t k0 = (int64_t)kb * BK;
             unsigned char* base = smem + st * Cf::STAGE;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int I = wave * 4 + u;     // 0..15: A loads 0..7, B loads 8..15
-                const int J = I % 8;
-                const int sl = 64 * J + lane, x = sl >> 2, c = (sl & 3) ^ ((x >> Cf::SWS) & 3);
-                if (I < 8)
-                    lds_dma16(make_rsrc(A + k0 + m0 * lda), base + 1024 * J,
+            for (int u = 0; u < Cf::LPW; ++u) {
+                const int I = wave * Cf::LPW + u;  // A loads 0 .. LA-1, then B loads
+                if (I < Cf::LA) {
+                    constexpr int SPR = Cf::PA / 16;  // 16-byte slots per row
+                    const int sl = 64 * I + lane, x = sl / SPR;
+                    const int c = (sl % SPR) ^ ring_swz<Cf::PA, Cf::WA>(x);
+                    lds_dma16(make_rsrc(A + k0 + m0 * lda), base + 1024 * I,
                               (int)(((int64_t)min(x, R - 1) * lda) * STA::bytes + 16 * c));
-                else
+                } else {
+                    constexpr int SPR = Cf::PB / 16;
+                    const int J = I - Cf::LA;
+                    const int sl = 64 * J + lane, x = sl / SPR;
+                    const int c = (sl % SPR) ^ ring_swz<Cf::PB, Cf::WB>(x);
                     lds_dma16(make_rsrc(B + k0 + n0 * ldb), base + Cf::A_BYTES + 1024 * J,
                               (int)(((int64_t)min(x, Q - 1) * ldb) * STB::bytes + 16 * c));
+                }
             }
         };
         auto stage_block = [&](int kb) __attribute__((always_inline)) {
@@ -477,13 +526,14 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
             }
         };
         auto sync_for = [&](int kb) __attribute__((always_inline)) {
-            // this wave's loads of later blocks (four per block) may stay in flight
+            // this wave's loads of later blocks (LPW per block) may stay in flight
             const int hi = min(nkb - 1, kb + NS - 2);
             const int later = ring ? max(0, min(hi, nfull - 1) - kb) : 0;
             asm volatile("" ::: "memory");
-            // s_waitcnt: vmcnt = later * 4, expcnt unconstrained, lgkmcnt = 0
-            if (later >= 2) __builtin_amdgcn_s_waitcnt(0x78);
-            else if (later == 1) __builtin_amdgcn_s_waitcnt(0x74);
+            // s_waitcnt: vmcnt = later * LPW, expcnt unconstrained, lgkmcnt = 0
+            static_assert(2 * Cf::LPW <= 15, "vmcnt field");
+            if (later >= 2) __builtin_amdgcn_s_waitcnt(0x70 | (2 * Cf::LPW));
+            else if (later == 1) __builtin_amdgcn_s_waitcnt(0x70 | Cf::LPW);
             else __builtin_amdgcn_s_waitcnt(0x70);
             __builtin_amdgcn_s_barrier();
             asm volatile("" ::: "memory");
@@ -686,7 +736,8 @@ template <typename STA, typename STB, bool F8MMA, int MODE>
 hipError_t launch_lowp_t(const LowpArgs& a, int ta, int tb, hipStream_t s)
 {
     const dim3 grid(a.tiles_m * a.tiles_n * (MODE == 0 && a.ksplit > 1 ? a.ksplit : 1)), block(256);
-    constexpr bool ring_ok = STA::bytes == (F8MMA ? 1 : 2) && STB::bytes == (F8MMA ? 1 : 2);
+    // fp8 product: fp8 x fp8; bf16 product: bf16 x bf16, or one fp8 operand widened at the read
+    constexpr bool ring_ok = F8MMA ? (STA::bytes == 1 && STB::bytes == 1) : (STA::bytes + STB::bytes >= 3);
     if (!ta && !tb) hipLaunchKernelGGL((lowp_gemm_kernel<STA, STB, F8MMA, false, false, MODE, false>), grid, block, 0, s, a);
     else if (ta && !tb) {
         if constexpr (ring_ok) {
