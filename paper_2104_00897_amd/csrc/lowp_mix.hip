@@ -110,12 +110,7 @@ __global__ __launch_bounds__(256) void lowp_encode_k_kernel(EncArgs args)
     static_assert(kLowpTile % RG == 0 && 64 % SG == 0, "encode map");
     __shared__ double cpart[4][kLowpChunk][2];
     __shared__ float pmax[kLowpChunk];
-    __shared__ float lut[256];  // e4m3 code -> value (FP8 operands)
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    if constexpr (ST::bytes == 1) {
-        lut[tid] = bf16_bits_to_f32(e4m3_to_bf16((uint32_t)tid));
-        __syncthreads();
-    }
     const int sg = tid % SG, rg = tid / SG;
     const int64_t r0 = (int64_t)pi * kLowpTile, p0 = (int64_t)c * kLowpChunk;
     const __amdgpu_buffer_rsrc_t rs = make_rsrc((const unsigned char*)E.X + (r0 * E.ld + p0) * ST::bytes);
@@ -144,10 +139,24 @@ __global__ __launch_bounds__(256) void lowp_encode_k_kernel(EncArgs args)
             x[u] = (u32x4_t){wv[0], wv[1], wv[2], wv[3]};
         }
     }
+    // fp8 codes widened to bf16 pairs by the hardware conversion (exact:
+    // every e4m3fn value is a bf16 value), so both types read bf16 halves
+    uint32_t hv[RPT][V / 2];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+        if constexpr (ST::bytes == 1) {
+#pragma unroll
+            for (int q = 0; q < V / 4; ++q) {
+                hv[u][2 * q] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(x[u][q], 1.0f, false));
+                hv[u][2 * q + 1] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(x[u][q], 1.0f, true));
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < V / 2; ++j) hv[u][j] = x[u][j];
+        }
+    }
     auto val = [&](int u, int e) __attribute__((always_inline)) -> double {
-        const uint32_t raw = (x[u][(e * ST::bytes) / 4] >> (8 * ((e * ST::bytes) % 4))) & (ST::bytes == 2 ? 0xFFFFu : 0xFFu);
-        if constexpr (ST::bytes == 1) return (double)lut[raw];
-        else return (double)bf16_bits_to_f32(raw);
+        return (double)bf16_bits_to_f32((hv[u][e / 2] >> (16 * (e % 2))) & 0xFFFFu);
     };
     // row sums of |x| over this block's steps
 #pragma unroll
