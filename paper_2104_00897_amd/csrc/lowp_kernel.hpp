@@ -405,6 +405,10 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
                 for (int g = 0; g < FM; ++g) a[g] = *(const long*)(ta + (wm0 + 16 * g + l16) * Cf::PA + oa);
 #pragma unroll
                 for (int h = 0; h < FN; ++h) b[h] = *(const long*)(tb + (wn0 + 16 * h + l16) * Cf::PB + ob);
+                if constexpr (RING && MODE == 1) {
+#pragma unroll
+                    for (int g = 0; g < FM; ++g) asm volatile("" : "+v"(a[g]));
+                }
 #pragma unroll
                 for (int g = 0; g < FM; ++g)
 #pragma unroll
@@ -423,6 +427,13 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
                     const unsigned char* q = tb + (wn0 + 16 * h + l16) * Cf::PB + ob;
                     if constexpr (Cf::CVB) b[h] = widen_fp8x8(*(const u32x2*)q);
                     else b[h] = __builtin_bit_cast(bf16x8_t, *(const u32x4_t*)q);
+                }
+                if constexpr (RING && MODE == 1) {
+                    // all A fragments of the step live together: at the protected
+                    // kernels' register budget the compiler would otherwise read
+                    // them one at a time, each read waited for before its MFMAs
+#pragma unroll
+                    for (int g = 0; g < FM; ++g) asm volatile("" : "+v"(a[g]));
                 }
 #pragma unroll
                 for (int g = 0; g < FM; ++g)
