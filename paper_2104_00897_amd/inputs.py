@@ -3,7 +3,9 @@
 This module holds none of the method's arithmetic: it only draws random
 operands (numpy PCG64 streams) and rounds them to the operand dtypes.  The
 paper measures square random matrices of 2048^2..10240^2 (§6); the shapes
-used here follow the workloads described in the design doc.
+used here are the benchmark workloads (FP64 8192^3, bf16/fp8 8192^3, a
+transformer-sized linear layer, 512 log-uniform batched problems) and small
+ragged cases for the tests.
 
 All matrices are returned as numpy arrays in Fortran (column-major) order,
 as the BLAS-style interface expects.
