@@ -10,7 +10,13 @@ something other than itself:
   * closed forms (identity, rank-1, all-ones, alpha = 0, beta = 0 with NaN C);
   * the published first outputs of SplitMix64 seeded with 0;
   * bijectivity of the slot permutation (every slot hit exactly once);
-  * rigor of the threshold: rounding alone never trips it on random data.
+  * rigor of the threshold: rounding alone never trips it on random data;
+  * the threshold itself in closed form: all-ones operands fix every line's
+    magnitude by hand (final check with beta, interval check, ragged edge
+    tile, a tile next to one scaled by 10^6), and on random data it stays
+    within a factor 2.2 of the textbook bound gamma_{k+q} |A||B|e;
+  * single-bit flips against the IEEE 754 bit layout (exponent, sign,
+    mantissa bits of binary32 and binary64).
 A plausible slip in the oracle (a dropped beta term, a transposed operand, a
 wrong sign in the correction, a checksum taken over the wrong index) breaks at
 least one of them.
@@ -416,3 +422,98 @@ def test_acc32_absorbing_flip_recomputed_small_flip_subtracted():
         C, recs, cnt = oracle.abft(A, B, bm=64, bn=48, plan=plan, acc32=True, lam=4.0)
         assert [(r.row, r.col, r.kind) for r in recs] == [(7, 9, kind)]
         np.testing.assert_allclose(C, ref, rtol=0, atol=1e-9 * np.abs(A).sum(axis=1).max() * np.abs(B).max())
+
+
+# ----------------------------------------------------------------------------- FP64 threshold, closed form
+U64 = 2.0 ** -53
+
+
+def _gamma_closed(nterms):
+    # the standard-model constant gamma(n) = n u / (1 - n u) of binary64
+    return nterms * U64 / (1.0 - nterms * U64)
+
+
+def test_fp64_threshold_closed_form_all_ones():
+    """All-ones operands fix the row magnitude by hand: for a row i of tile (0,0)
+    with Q columns, M_i = |alpha| k Q + |beta| Q c (c the constant C_in), and the
+    final check sums k + Q terms.  The record of an exponent flip (always far
+    above the threshold) must carry tau = 2 gamma(k + Q + 8) M_i (1 + 2^-20): a
+    tau taken over the whole matrix, with a wrong term count, or without the beta
+    term fails the equality.  The rows of A in tile (1, 0) are scaled by 10^6,
+    which a tile-local magnitude never sees."""
+    m, n, k = 40, 24, 33
+    bm, bn = 32, 16
+    A = np.ones((m, k), order="F")
+    A[bm:, :] = 1e6
+    B = np.ones((k, n), order="F")
+    C = np.full((m, n), 0.75, order="F")
+    alpha, beta = 1.5, -0.5
+    plan = [oracle.Fault(0, 0, 0, 3, 5, k - 1, 62, oracle.TARGET_ACC)]
+    _, recs, cnt = oracle.abft(A, B, C, alpha, beta, bm=bm, bn=bn, plan=plan)
+    assert cnt["detected"] == 1 and len(recs) == 1
+    Q = bn
+    M = abs(alpha) * k * Q + abs(beta) * Q * 0.75
+    want = 2.0 * _gamma_closed(k + Q + 8) * M * (1 + 2.0 ** -20)
+    assert (recs[0].row, recs[0].col) == (3, 5)
+    assert recs[0].tau == want
+    # the ragged edge tile (1, 1): 8 rows of A scaled by 10^6, Q = 8 columns
+    plan = [oracle.Fault(1, 1, 0, 2, 6, k - 1, 62, oracle.TARGET_ACC)]
+    _, recs, cnt = oracle.abft(A, B, C, alpha, beta, bm=bm, bn=bn, plan=plan)
+    Q1 = n - bn
+    M1 = abs(alpha) * 1e6 * k * Q1 + abs(beta) * Q1 * 0.75
+    assert cnt["detected"] == 1
+    assert (recs[0].row, recs[0].col) == (bm + 2, bn + 6)
+    assert recs[0].tau == 2.0 * _gamma_closed(k + Q1 + 8) * M1 * (1 + 2.0 ** -20)
+
+
+def test_fp64_threshold_closed_form_interval():
+    """Interval mode: a check after steps [0, p_end) compares the held accumulator
+    (alpha = 1, beta = 0 mid-way), so for all-ones operands M_i = p_end Q and the
+    term count is p_end + Q + 8."""
+    m, n, k, kc = 32, 16, 48, 16
+    A = np.ones((m, k), order="F")
+    B = np.ones((k, n), order="F")
+    plan = [oracle.Fault(0, 0, 1, 4, 7, 2 * kc - 1, 62, oracle.TARGET_ACC)]
+    _, recs, cnt = oracle.abft(A, B, None, 2.0, 0.0, bm=32, bn=16, kc=kc, plan=plan)
+    assert cnt["detected"] == 1 and recs[0].interval == 1
+    p_end, Q = 2 * kc, 16
+    assert recs[0].tau == 2.0 * _gamma_closed(p_end + Q + 8) * (p_end * Q) * (1 + 2.0 ** -20)
+
+
+def test_fp64_threshold_within_factor_of_rigorous_bound():
+    """Upper pin: tau must not exceed a small multiple of the textbook bound
+    gamma_{k+Q} |alpha| |A_i| |B_J| e for random data (a tau inflated by a wrong
+    term count or a magnitude over the whole matrix would be 10-100x larger)."""
+    rng = np.random.default_rng(5)
+    m, n, k = 96, 64, 200
+    A = np.asfortranarray(rng.uniform(-1, 1, (m, k)))
+    B = np.asfortranarray(rng.uniform(-1, 1, (k, n)))
+    plan = [oracle.Fault(1, 1, 0, 5, 9, k - 1, 62, oracle.TARGET_ACC)]
+    _, recs, cnt = oracle.abft(A, B, None, 1.0, 0.0, bm=48, bn=32, plan=plan)
+    i, J = 48 + 5, slice(32, 64)
+    M = float((np.abs(A[i, :]) * np.abs(B[:, J]).sum(axis=1)).sum())
+    textbook = _gamma_closed(k + 32) * M
+    assert textbook < recs[0].tau <= 2.2 * textbook
+
+
+# ----------------------------------------------------------------------------- bit flips
+@pytest.mark.parametrize("x,bit,want", [
+    (1.0, 23, 0.5),            # lowest exponent bit: 0x3F800000 -> 0x3F000000
+    (1.0, 31, -1.0),           # sign
+    (1.0, 22, 1.5),            # top mantissa bit
+    (1.0, 0, 1.0 + 2.0 ** -23),  # lowest mantissa bit
+    (1.0, 30, float("inf")),   # top exponent bit: 0x7F800000
+    (3.0, 24, 12.0),           # 0x40400000 -> 0x41400000: exponent 128 -> 130
+])
+def test_flip32_bit_patterns(x, bit, want):
+    assert oracle.flip32(x, bit) == want
+    assert oracle.flip32(oracle.flip32(x, bit), bit) == x
+
+
+@pytest.mark.parametrize("x,bit,want", [
+    (1.0, 52, 0.5), (1.0, 63, -1.0), (1.0, 51, 1.5), (1.0, 0, 1.0 + 2.0 ** -52),
+    (1.0, 62, float("inf")), (10.0, 52, 20.0),
+])
+def test_flip64_bit_patterns(x, bit, want):
+    assert oracle.flip64(x, bit) == want
+    assert oracle.flip64(oracle.flip64(x, bit), bit) == x
