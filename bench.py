@@ -1,16 +1,19 @@
 """Benchmark of the checksum-protected FP64 GEMM on one MI355X.
 
-One step = one protected GEMM call C := alpha A B + beta C (fused encode,
+One step = one protected GEMM call C := alpha A B + beta C (encode pass,
 maintained checksums, reference sums, verify, locate/correct) on the square
-FP64 workload n = m = k = 8192, alpha = 1.5, beta = 0.5, A/B/C i.i.d.
-U[-1,1], with seeded bit flips at one per 2^32 multiply-adds (128 faults, at
-most one per tile).  Inputs are resident in HBM before timing starts.
+FP64 workload n = m = k = 16384 (the largest of the FP64 sweep), alpha = 1.5,
+beta = 0.5, A/B/C i.i.d. U[-1,1], with seeded bit flips at one per 2^32
+multiply-adds (1024 faults, at most one per tile).  Inputs are resident in
+HBM before timing starts.
 
 Printed (one JSON line): TFLOP/s of the protected call with faults injected,
 the same kernel with ABFT compiled out, the overhead %, a roofline object for
-the GEMM kernel (FP64 MFMA bound) and the CPU oracle's throughput on a bounded
-sample of the same workload.  Extra sizes of the FP64 sweep and the rank-k
-shapes are reported with --sweep.
+the protected product kernel (FP64 MFMA bound), the rest of the FP64 sweep
+(1024..8192 and the rank-k updates m = n = 16384, k = 128/256/512, NN and
+TN), the other workloads (FP64 256^3 latency, BF16/FP8 8192^3 with the
+false-positive campaign, the FTLinear step, 512 batched problems) and the CPU
+oracle's throughput on a bounded sample of the headline workload.
 """
 from __future__ import annotations
 
@@ -27,11 +30,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_F64_MFMA = 78.6  # TFLOP/s, MI355X dense FP64 matrix
-# HBM bytes per launch of the protected product kernel (tile configuration 5,
-# encode pass) at n = 8192 from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled
-# by a plain-copy calibration (profiles/dgemm_abft_n8192_traffic.md); it must be
-# re-measured whenever that kernel changes
-TRAFFIC_F64_N8192 = 1.729e10
+PEAK_HBM = 8000.0     # GB/s
+# HBM bytes per launch of the protected product kernel by problem size, from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a plain-copy calibration
+# (profiles/dgemm_abft_*_traffic.md); an entry is dropped whenever that kernel
+# changes, and the line then reports null until it is measured again
+TRAFFIC_F64: dict = {}
 
 
 def parse():
@@ -39,12 +43,17 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--n", type=int, default=8192)
+    p.add_argument("--n", type=int, default=16384)
     p.add_argument("--tile", type=int, default=0)
-    p.add_argument("--sweep", action="store_true", help="also time the FP64 size sweep and rank-k shapes")
+    p.add_argument("--no-sweep", action="store_true", help="skip the FP64 size sweep and rank-k shapes")
+    p.add_argument("--fp-calls", type=int, default=1000,
+                   help="fault-free calls of the BF16/FP8 false-positive campaign")
+    p.add_argument("--only", default="", help="comma list of legs to run among cfg1,cfg3,cfg4,cfg5")
     p.add_argument("--tiles", action="store_true", help="time every FP64 tile configuration at --n")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-configs", action="store_true", help="skip the other workloads (cfg 1, 3, 4, 5)")
+    p.add_argument("--calibrate", type=int, default=0,
+                   help="only measure the binary32 threshold noise over this many calls per input family")
     return p.parse_args()
 
 
@@ -105,9 +114,12 @@ def measure(torch, ftgemm, h, m, n, k, alpha, beta, ta, tb, steps, warmup, tile,
     rep = h.read()
     flops = 2.0 * m * n * k
     ms_p, ms_u, ms_0 = float(np.median(tp)), float(np.median(tu)), float(np.median(t0))
+    bytes_alg = 8.0 * (m * k + k * n + 2 * m * n)  # A, B read, C read and written
     return {
         "m": m, "n": n, "k": k, "ta": ta, "tb": tb,
         "tile": tile or h.tune_get(ftgemm.F64, m, n, k),
+        "kernel_frac_of_fp64_peak": flops / kernel_ms / 1e9 / PEAK_F64_MFMA,
+        "kernel_hbm_gbs_algorithmic": bytes_alg / kernel_ms / 1e6,
         "ms_protected": ms_p, "ms_unprotected": ms_u, "ms_protected_no_faults": ms_0,
         "tflops_protected": flops / ms_p / 1e9,
         "tflops_unprotected": flops / ms_u / 1e9,
@@ -146,11 +158,15 @@ def cfg1_latency(torch, ftgemm, h, steps):
             "us_protected": 1e3 * t["p"], "us_unprotected": 1e3 * t["u"]}
 
 
-def lowp_operands(torch, kind, rows, cols, seed, std=1.0):
+def lowp_operands(torch, kind, rows, cols, seed, std=1.0, dist="normal"):
     """Column-major (rows x cols) operand as a (cols x rows) device tensor: N(0, std^2)
-    rounded to bf16, or absmax-scaled e4m3fn codes with their per-tensor scale."""
+    (or U[0, std) with dist="uniform01") rounded to bf16, or absmax-scaled e4m3fn
+    codes with their per-tensor scale."""
     g = torch.Generator(device="cuda").manual_seed(seed)
-    x = torch.randn((cols, rows), generator=g, device="cuda", dtype=torch.float32) * std
+    if dist == "uniform01":
+        x = torch.rand((cols, rows), generator=g, device="cuda", dtype=torch.float32) * std
+    else:
+        x = torch.randn((cols, rows), generator=g, device="cuda", dtype=torch.float32) * std
     if kind == "bf16":
         return x.to(torch.bfloat16).view(torch.int16), None
     s = x.abs().max() / 448.0
@@ -162,9 +178,61 @@ def lowp_operands(torch, kind, rows, cols, seed, std=1.0):
     return q, s.reshape(1).float()
 
 
-def cfg3_lowp(torch, ftgemm, h, kind, steps, n=8192):
+def lowp_values(torch, q, s, kind):
+    """Exact binary64 values (host, rows x cols) of a device operand made by lowp_operands."""
+    if kind == "bf16":
+        return q.view(torch.bfloat16).double().cpu().numpy().T
+    from paper_2104_00897_amd import inputs
+    return inputs.e4m3_table()[q.cpu().numpy()].T
+
+
+def acc32_line_tau(a, b, lam, i, j, bm=128, bn=128):
+    """The binary32 paths' threshold at element (i, j) (alpha = 1, beta = 0), the
+    larger of its tile row's and column's: 2 lam sqrt(k + len + 8) 2^-24 M (1 + 2^-20)
+    with the magnitude bounds the kernels use (sum_p |a_ip|) max_p (sum_{j in J} |b_pj|)
+    and (sum_p |b_pj|) max_p (sum_{i in I} |a_ip|); a, b: |op(A)|, |op(B)|."""
+    m, k = a.shape
+    n = b.shape[1]
+    i0, j0 = (i // bm) * bm, (j // bn) * bn
+    R, Q = min(bm, m - i0), min(bn, n - j0)
+    mr = a[i, :].sum() * b[:, j0:j0 + Q].sum(axis=1).max()
+    mc = b[:, j].sum() * a[i0:i0 + R, :].sum(axis=0).max()
+    g = lambda nt: 2.0 * lam * math.sqrt(nt) * 2.0 ** -24 * (1 + 2.0 ** -20)
+    return max(g(k + Q + 8) * mr, g(k + R + 8) * mc)
+
+
+def fault_classes(rep, a, b, lam, scale=1.0):
+    """Splits the logged injections by the detectability rule: a flip whose error
+    clears 4 tau of its element must be corrected (else it is missed); a smaller
+    one that stays uncorrected is masked.  a, b: |op(A)|, |op(B)| in the stored
+    (code) domain; `scale` carries the FP8 per-tensor scales to the output."""
+    fixed = {(r["row"], r["col"]) for r in rep.records if r["kind"] in (1, 2)}
+    seen, out = set(), {"distinct": 0, "must_correct": 0, "corrected": 0, "masked": 0, "missed": 0}
+    taus = []
+    for g in rep.inject_log:
+        key = (g["row"], g["col"], g["bit"])
+        if key in seen:
+            continue
+        seen.add(key)
+        out["distinct"] += 1
+        tau = scale * acc32_line_tau(a, b, lam, g["row"], g["col"])
+        taus.append(tau / max(1e-300, abs(g["old_val"]) * scale))
+        d = abs(g["new_val"] - g["old_val"]) * scale
+        ok = (g["row"], g["col"]) in fixed
+        out["corrected"] += ok
+        if not math.isfinite(d) or d >= 4.0 * tau:
+            out["must_correct"] += 1
+            out["missed"] += not ok
+        elif not ok:
+            out["masked"] += 1
+    out["median_tau_over_abs_c"] = float(np.median(taus)) if taus else None
+    return out
+
+
+def cfg3_lowp(torch, ftgemm, h, kind, steps, n=8192, fp_calls=1000):
     """8192^3 NN, alpha = 1, beta = 0, N(0,1) operands (bf16, or e4m3fn with absmax
-    scales), 16 flips of FP32 accumulator bits 13..30 per call."""
+    scales), 16 flips of FP32 accumulator bits 13..30 per call; then `fp_calls`
+    fault-free calls (the false-positive campaign) and the detection floor."""
     dA, sa = lowp_operands(torch, kind, n, n, 1)
     dB, sb = lowp_operands(torch, kind, n, n, 2)
     dC = torch.empty((n, n), dtype=torch.float32, device="cuda")
@@ -178,12 +246,58 @@ def cfg3_lowp(torch, ftgemm, h, kind, steps, n=8192):
     rep = h.read()
     fl = 2.0 * n ** 3
     peak = 2500.0 if kind == "bf16" else 5000.0
+    scale = float(sa.item() * sb.item()) if sa is not None else 1.0
+    a = np.abs(lowp_values(torch, dA, sa, kind))
+    b = np.abs(lowp_values(torch, dB, sb, kind))
+    lam = ftgemm.default_lambda()
+    classes = fault_classes(rep, a, b, lam, scale)
+    # false-positive campaign: fault-free calls at the default threshold
+    h.reset()
+    f0 = fns["p0"]
+    for _ in range(fp_calls):
+        f0()
+    torch.cuda.synchronize()
+    fp = h.read()
     return {"workload": f"{kind} {n}^3 NN -> FP32, 16 flips/call", "ms_protected": t["p"],
             "ms_unprotected": t["u"], "ms_protected_no_faults": t["p0"],
             "tflops_protected": fl / t["p"] / 1e9, "tflops_unprotected": fl / t["u"] / 1e9,
             "overhead_pct": 100.0 * (t["p"] / t["u"] - 1.0), "frac_of_peak_protected": fl / t["p"] / 1e9 / peak,
             "faults": {"injected": rep.injected, "corrected": rep.corrected_subtract + rep.corrected_recompute,
-                       "detected": rep.detected, "uncorrectable": rep.uncorrectable}}
+                       "detected": rep.detected, "uncorrectable": rep.uncorrectable,
+                       "per_distinct_flip": classes},
+            "lambda": lam,
+            "false_positives": {"calls": fp_calls, "flagged_slots": fp.detected,
+                                "checks_per_call": 2 * n * (n // 128),
+                                "max_pass_ratio": fp.max_pass_ratio}}
+
+
+def calibrate_lambda(torch, ftgemm, h, calls):
+    """Noise of the binary32 paths against the threshold at lambda = 1: the largest
+    |delta| / tau over `calls` fault-free calls per input family.  Since tau is
+    linear in lambda, that ratio is the smallest lambda with no false positive in
+    the campaign."""
+    n = 8192
+    out = []
+    fams = [("bf16", "normal", 1.0, 1.0), ("fp8", "normal", 1.0, 1.0),
+            ("bf16", "uniform01", 1.0, 1.0), ("fp8", "uniform01", 1.0, 1.0),
+            ("bf16", "normal", 0.02, 1.0)]
+    for kind, dist, sa_std, sb_std in fams:
+        dA, sa = lowp_operands(torch, kind, n, n, 11, sa_std, dist)
+        dB, sb = lowp_operands(torch, kind, n, n, 12, sb_std, dist)
+        dC = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        ab = ftgemm.BF16 if kind == "bf16" else ftgemm.F8_E4M3
+        cfg = ftgemm.make_config(lam=1.0)
+        h.reset()
+        for _ in range(calls):
+            ftgemm.gemm_lowp(h, dA, dB, dC, 1.0, 0.0, 0, 0, ab, sa, sb, cfg)
+        torch.cuda.synchronize()
+        rep = h.read()
+        row = {"kind": kind, "dist": dist, "std": [sa_std, sb_std], "calls": calls,
+               "flagged_at_lambda_1": rep.detected, "max_pass_ratio_at_lambda_1": rep.max_pass_ratio}
+        print(json.dumps({"calibrate": row}), file=sys.stderr, flush=True)
+        out.append(row)
+        del dA, dB, dC
+    return out
 
 
 def cfg4_ftlinear(torch, ftgemm, h, steps):
@@ -214,11 +328,23 @@ def cfg4_ftlinear(torch, ftgemm, h, steps):
                        "uncorrectable": rep.uncorrectable}}
 
 
+def batched_problem_seed(seed: int, p: int) -> int:
+    """Injector seed of problem p of a batched call (the rule documented with
+    ftg_dgemm_batched_uneven): output 2^32 + p of SplitMix64 seeded with `seed`."""
+    m64 = 2 ** 64 - 1
+    z = (seed + (2 ** 32 + p + 1) * 0x9E3779B97F4A7C15) & m64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & m64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & m64
+    return z ^ (z >> 31)
+
+
 def cfg5_batched(torch, ftgemm, h, steps):
     """512 FP64 problems, m, n, k log-uniform in [32, 2048] (seed 7), alpha = 1,
-    beta = 0, U[-1,1] operands, 0-2 flips per problem (U{0,1,2}, seed 7), one
-    persistent launch; eager and hipGraph-replayed."""
-    from paper_2104_00897_amd import inputs
+    beta = 0, U[-1,1] operands, 0-2 flips per problem (U{0,1,2}, seed 7).  The
+    batched call's tiles come from the autotuner (per shape bucket, timed on the
+    GPU first); it runs eager and hipGraph-replayed, and against the same
+    problems as 512 single protected calls (each with its own faults)."""
+    from paper_2104_00897_amd import inputs, tune
     sizes = inputs.log_uniform_sizes(512, 32, 2048, 7)
     faults = np.random.default_rng(7).integers(0, 3, size=len(sizes))
     g = torch.Generator(device="cuda").manual_seed(7)
@@ -230,44 +356,106 @@ def cfg5_batched(torch, ftgemm, h, steps):
         keep.append((A, B, C))
         probs.append(ftgemm.batch_problem(A, B, C, 1.0, 0.0))
     plan = ftgemm.BatchPlan(probs)
-    cp = ftgemm.make_config(tile=3, seed=7, n_faults=1)
-    cu = ftgemm.make_config(abft=False, tile=3)
     stream = ftgemm.current_stream_ptr
     fl = float(sum(2.0 * m * n * k for m, n, k in sizes))
-    h.reset()
-    t = timed_ab(torch, {"p": lambda: h.dgemm_batched(plan, stream(), cp, faults),
-                         "u": lambda: h.dgemm_batched(plan, stream(), cu)}, steps, 2)
-    rep = h.read()
+    # the autotuner fills a handle's table for the batched tiles of every bucket present
+    hb = ftgemm.Handle(capacity=16384)
+    t0 = time.perf_counter()
+    table = tune.autotune_batched(hb, sizes)
+    tune_s = time.perf_counter() - t0
+    picked = {t: sum(1 for m, n, k in sizes if table.get(ftgemm.F64, m, n, k) == t) for t in (2, 3)}
+    cp = ftgemm.make_config(seed=7, n_faults=1)
+    cu = ftgemm.make_config(abft=False)
+    cp3 = ftgemm.make_config(tile=3, seed=7, n_faults=1)
+    cu3 = ftgemm.make_config(abft=False, tile=3)
+    # looped single calls: problem p draws from the seed the batched call gives it
+    singles = [ftgemm.make_config(seed=batched_problem_seed(7, p), n_faults=int(f))
+               for p, f in enumerate(faults)]
+
+    def looped(cfgs):
+        for (A, B, C), c in zip(keep, cfgs):
+            ftgemm.gemm_f64(h, A, B, C, 1.0, 0.0, cfg=c)
+
+    hb.reset()
+    t = timed_ab(torch, {"p": lambda: hb.dgemm_batched(plan, stream(), cp, faults),
+                         "u": lambda: hb.dgemm_batched(plan, stream(), cu),
+                         "p3": lambda: hb.dgemm_batched(plan, stream(), cp3, faults),
+                         "u3": lambda: hb.dgemm_batched(plan, stream(), cu3)}, steps, 2)
+    rep = hb.read()
     gr = torch.cuda.CUDAGraph()
     with torch.cuda.graph(gr):
-        h.dgemm_batched(plan, stream(), cp, faults)
+        hb.dgemm_batched(plan, stream(), cp, faults)
     tg = time_calls(torch, gr.replay, steps, 2)
     torch.cuda.synchronize()
     del gr
-    return {"workload": "512 FP64 problems, m,n,k log-uniform [32, 2048], seed 7, 0-2 flips each",
-            "gflop": fl / 1e9, "ms_protected": t["p"], "ms_unprotected": t["u"], "ms_protected_graph": tg,
-            "tflops_protected": fl / t["p"] / 1e9, "tflops_unprotected": fl / t["u"] / 1e9,
-            "overhead_pct": 100.0 * (t["p"] / t["u"] - 1.0),
-            "faults": {"injected": rep.injected, "corrected": rep.corrected_subtract + rep.corrected_recompute,
-                       "uncorrectable": rep.uncorrectable}}
+    h.reset()
+    tl = timed_ab(torch, {"p": lambda: looped(singles), "u": lambda: looped([cu] * len(keep))},
+                  max(2, steps // 2), 1)
+    rep_l = h.read()
+    requested = int(faults.sum())
+    per_call = rep.injected // (4 * (steps + 2))  # four timed runs of steps + 2 warm-up calls
+    out = {"workload": "512 FP64 problems, m,n,k log-uniform [32, 2048], seed 7, 0-2 flips each",
+           "gflop": fl / 1e9,
+           "autotune": {"seconds": tune_s, "buckets": len(table.entries), "problems_on_tile": picked},
+           "ms_protected": t["p"], "ms_unprotected": t["u"], "ms_protected_graph": tg,
+           "tflops_protected": fl / t["p"] / 1e9, "tflops_unprotected": fl / t["u"] / 1e9,
+           "tflops_protected_graph": fl / tg / 1e9,
+           "overhead_pct": 100.0 * (t["p"] / t["u"] - 1.0),
+           "fixed_tile3": {"ms_protected": t["p3"], "ms_unprotected": t["u3"],
+                           "tflops_protected": fl / t["p3"] / 1e9,
+                           "overhead_pct": 100.0 * (t["p3"] / t["u3"] - 1.0)},
+           "looped_single_calls": {"ms_protected": tl["p"], "ms_unprotected": tl["u"],
+                                   "tflops_protected": fl / tl["p"] / 1e9,
+                                   "tflops_unprotected": fl / tl["u"] / 1e9,
+                                   "batched_speedup_protected": tl["p"] / t["p"]},
+           "faults": {"requested_per_call": requested, "injected_per_call": per_call,
+                      "capped_per_call": requested - per_call,
+                      "injected": rep.injected, "corrected": rep.corrected_subtract + rep.corrected_recompute,
+                      "uncorrectable": rep.uncorrectable,
+                      "looped_injected": rep_l.injected,
+                      "looped_corrected": rep_l.corrected_subtract + rep_l.corrected_recompute}}
+    hb.close()
+    return out
 
 
 def cpu_baseline(host, k):
-    """The oracle's ABFT procedure (single thread) on a bounded sample: the
-    leading 1536 x 1536 block of C with the full k of the workload."""
+    """The oracle on a bounded sample of the headline workload, on the host cores:
+    its plain definition of the product (OpenMP over columns, every thread the
+    process may use) on the leading 1024 x 1024 block of C with the full k, and
+    its simulation of the protected procedure (one thread) on the leading
+    512 x 512 block."""
     import oracle
+    import platform
     A, B, C = host
-    ms = ns = 1536
-    As = np.asfortranarray(A[:ms, :])
-    Bs = np.asfortranarray(B[:, :ns])
-    Cs = np.asfortranarray(C[:ms, :ns])
+    threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    ms = ns = 1024
     t0 = time.perf_counter()
-    oracle.abft(As, Bs, Cs, 1.5, 0.5, bm=128, bn=128)
+    oracle.gemm(np.asfortranarray(A[:ms, :]), np.asfortranarray(B[:, :ns]),
+                np.asfortranarray(C[:ms, :ns]), 1.5, 0.5)
     dt = time.perf_counter() - t0
     flops = 2.0 * ms * ns * k
-    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle.abft on the leading {ms}x{ns} block of C with k={k} "
-                      f"(bm=bn=128 tiles, same operands): {flops / 1e9:.2f} GFLOP in {dt:.1f} s"}
+    ma = 512
+    t1 = time.perf_counter()
+    oracle.abft(np.asfortranarray(A[:ma, :]), np.asfortranarray(B[:, :ma]),
+                np.asfortranarray(C[:ma, :ma]), 1.5, 0.5, bm=128, bn=128)
+    da = time.perf_counter() - t1
+    fa = 2.0 * ma * ma * k
+    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle.gemm (OpenMP, {threads} threads) on the leading {ms}x{ns} block of C "
+                      f"with k={k}: {flops / 1e9:.1f} GFLOP in {dt:.1f} s",
+            "host": {"cpu_model": model, "logical_cpus": os.cpu_count(), "omp_threads": threads},
+            "abft_one_thread": {"value": fa / da / 1e12, "unit": "TFLOP/s", "cores": 1,
+                                "sample": f"oracle.abft on the leading {ma}x{ma} block with k={k} "
+                                          f"(128x128 tiles): {fa / 1e9:.1f} GFLOP in {da:.1f} s"}}
 
 
 def main():
@@ -279,6 +467,9 @@ def main():
     from paper_2104_00897_amd import ftgemm
 
     h = ftgemm.Handle(capacity=16384)
+    if args.calibrate:
+        print(json.dumps({"calibrate": calibrate_lambda(torch, ftgemm, h, args.calibrate)}), flush=True)
+        return
     n = args.n
     res, host = measure(torch, ftgemm, h, n, n, n, 1.5, 0.5, 0, 0, args.steps, args.warmup, args.tile)
     flops = 2.0 * n ** 3
@@ -309,33 +500,36 @@ def main():
                    "uncorrectable": res["uncorrectable"]},
         "roofline": {"bound": "mfma", "achieved": round(kernel_tf, 3), "peak": PEAK_F64_MFMA,
                      "unit": "TFLOP/s", "frac": round(kernel_tf / PEAK_F64_MFMA, 4),
-                     "traffic": TRAFFIC_F64_N8192 if n == 8192 else None,
-                     "kernel": "protected FP64 product kernel (128x128 tile, 8 waves)",
+                     "traffic": TRAFFIC_F64.get(n),
+                     "kernel": f"protected FP64 product kernel (tile configuration {res['tile']})",
                      "kernel_ms": round(res["kernel_ms_protected"], 4)},
     }
+    print(json.dumps({"headline": res}), file=sys.stderr, flush=True)
     if args.tiles:
         for t in (1, 2, 3, 4, 5):
             r, _ = measure(torch, ftgemm, h, n, n, n, 1.5, 0.5, 0, 0, max(3, args.steps // 2), 1, t)
             print(json.dumps({"tile_sweep": r}), file=sys.stderr, flush=True)
-    if args.sweep:
+    if not args.no_sweep:
         sweep = []
-        for nn in (1024, 2048, 4096, 8192, 16384):
-            r, _ = measure(torch, ftgemm, h, nn, nn, nn, 1.5, 0.5, 0, 0, max(3, args.steps // 2), 1, 0)
-            sweep.append(r)
+        shapes = [(nn, nn, nn, 0) for nn in (1024, 2048, 4096, 8192) if nn != n]
+        shapes += [(16384, 16384, kk, ta) for kk in (128, 256, 512) for ta in (0, 1)]
+        for mm, nn, kk, ta in shapes:
+            r, _ = measure(torch, ftgemm, h, mm, nn, kk, 1.5, 0.5, ta, 0, args.steps, 2, 0)
+            sweep.append({key: (round(v, 4) if isinstance(v, float) else v) for key, v in r.items()})
             print(json.dumps({"sweep": r}), file=sys.stderr, flush=True)
-        for kk in (128, 256, 512):
-            for ta in (0, 1):
-                r, _ = measure(torch, ftgemm, h, 16384, 16384, kk, 1.5, 0.5, ta, 0, args.steps, 1, 0)
-                sweep.append(r)
-                print(json.dumps({"sweep": r}), file=sys.stderr, flush=True)
         line["sweep"] = sweep
     if not args.no_configs:
+        only = set(x for x in args.only.split(",") if x)
         cf = {}
         for name, fn in [("cfg1", lambda: cfg1_latency(torch, ftgemm, h, args.steps)),
-                         ("cfg3_bf16", lambda: cfg3_lowp(torch, ftgemm, h, "bf16", args.steps)),
-                         ("cfg3_fp8", lambda: cfg3_lowp(torch, ftgemm, h, "fp8", args.steps)),
+                         ("cfg3_bf16", lambda: cfg3_lowp(torch, ftgemm, h, "bf16", args.steps,
+                                                         fp_calls=args.fp_calls)),
+                         ("cfg3_fp8", lambda: cfg3_lowp(torch, ftgemm, h, "fp8", args.steps,
+                                                        fp_calls=args.fp_calls)),
                          ("cfg4", lambda: cfg4_ftlinear(torch, ftgemm, h, max(2, args.steps // 2))),
                          ("cfg5", lambda: cfg5_batched(torch, ftgemm, h, args.steps))]:
+            if only and name.split("_")[0] not in only:
+                continue
             cf[name] = fn()
             print(json.dumps({name: cf[name]}), file=sys.stderr, flush=True)
         line["configs"] = cf

@@ -8,8 +8,12 @@
  *   - checksum encoding A^c = [A; e^T A], B^r = [B, B e]            (§2.1)
  *   - the relations e^T C = (e^T A) B and C e = A (B e) maintained
  *     through the rank-k updates of the k loop                       (§2.1)
- *   - encoding fused into the operand loads and the beta scaling of C,
- *     reference sums taken from the computed C in registers          (§5.2)
+ *   - the checksum row/column of the encoded operands summed per output
+ *     tile, by default in one encode pass over A and B ahead of the
+ *     product (optionally inside the k loop from the staged panels, the
+ *     fused packing of §5.2); the maintained checksums, the encoding of
+ *     C_in with the beta scaling and the reference sums of the computed C
+ *     fused into the product kernel                                   (§5.2)
  *   - a mismatch above the round-off threshold locates the faulty row
  *     and column; the element is corrected by subtracting the error
  *     magnitude (§5.1, §6.3), one error per verification interval
@@ -21,9 +25,18 @@
  *   - Matrix pointers are DEVICE pointers owned by the caller.  C is
  *     updated in place; C must not alias A or B.
  *   - `stream` is a hipStream_t (NULL = the default stream).  Launches are
- *     asynchronous on it; no entry point synchronises except
- *     ftg_report_read with sync = 1.  No entry point allocates memory per
- *     call: device buffers belong to the handle.
+ *     asynchronous on it.  Device buffers belong to the handle.  A call
+ *     that needs more workspace than the handle holds (the FP64 encode
+ *     pass, the low-precision checksum pieces and packed operand copies)
+ *     grows it first: that allocates and waits for the device.  Calls that
+ *     fit the workspace allocate nothing and never synchronise; size it
+ *     up front with ftg_workspace_reserve (or one call of the largest
+ *     shape).  Growth is refused (FTG_ERR_UNSUPPORTED) under stream capture;
+ *     a workspace that a captured graph has used is not freed when it is
+ *     outgrown but kept until ftg_destroy (the graph replays with its
+ *     address).  Otherwise only ftg_report_read, ftg_batched_reserve,
+ *     ftg_workspace_reserve, ftg_timing_read and ftg_destroy wait for the
+ *     device.
  *   - Argument errors return FTG_ERR_INVALID_ARG and set
  *     ftg_last_error_arg() to the BLAS xerbla position of the first bad
  *     argument of dgemm: 1 transa, 2 transb, 3 m, 4 n, 5 k, 8 lda,
@@ -107,7 +120,7 @@ typedef struct ftg_config {
                             k loop (one verification per tile); otherwise a
                             multiple of 128                                     */
     double lambda;       /* threshold scale of the FP32-accumulating paths
-                            (0 = default 4); unused for FP64                   */
+                            (0 = ftg_default_lambda()); unused for FP64        */
     int32_t correct_policy;       /* 0: subtract, re-verify, else recompute;
                                      1: always recompute the located element    */
     int32_t uncorrectable_policy; /* 0: report only; 1: recompute the tile      */
@@ -117,9 +130,9 @@ typedef struct ftg_config {
                             of the encoded operands come from one encode pass
                             over A and B before the product (default); 1 =
                             summed from the staged panels inside the k loop
-                            (§5.2's fused encoding).  Batched calls always
-                            encode in the loop; low precision always uses its
-                            encode pass                                         */
+                            (§5.2's fused encoding).  Batched calls take the
+                            same choice; low precision always uses its encode
+                            pass                                                */
     const ftg_inject* inject; /* NULL = no injection (host memory, read at call) */
 } ftg_config;
 
@@ -147,11 +160,21 @@ typedef struct ftg_inject_record {
 
 /* Report accumulated on the handle since the last ftg_report_reset.
  * records/inject_log point to HOST arrays of `capacity` entries owned by
- * the caller; n_records/n_injected may exceed capacity (entries dropped). */
+ * the caller; n_records/n_inject_log may exceed capacity (entries dropped;
+ * the counters still count every slot).  The report capacity only bounds
+ * the records kept: flagged slots are repaired through a separate queue of
+ * max(report_capacity, 16384) entries per call, and a slot that finds that
+ * queue full is counted uncorrectable and in `lost`. */
 typedef struct ftg_fault_report {
     uint64_t injected, detected, corrected_subtract, corrected_recompute;
     uint64_t checksum_only, uncorrectable, tiles_recomputed;
-    uint32_t n_records, n_inject_log, capacity, reserved;
+    uint32_t n_records, n_inject_log, capacity;
+    uint32_t lost;  /* flagged slots the handle's repair queue could not take
+                       (counted in uncorrectable; their elements stay as the
+                       kernel left them) */
+    double max_pass_ratio; /* largest |delta| / tau among the checks that
+                              passed: how close rounding noise came to the
+                              threshold (the noise margin is its inverse) */
     ftg_fault_record* records;
     ftg_inject_record* inject_log;
 } ftg_fault_report;
@@ -219,6 +242,11 @@ ftg_status ftg_dgemm_batched_uneven(ftg_handle h, int64_t count, const ftg_op* t
                                     const uint32_t* faults_per_problem, void* stream,
                                     const ftg_config* cfg);
 
+/* Grows the handle's workspace to at least `bytes` so that later calls up to
+ * that size neither allocate nor synchronise (see the file header).
+ * Allocates and waits for the device; not during stream capture. */
+ftg_status ftg_workspace_reserve(ftg_handle h, size_t bytes);
+
 /* Grows the batched descriptor table to `capacity` problems (at most
  * 2^24).  Allocates and waits for the device: not during stream capture. */
 ftg_status ftg_batched_reserve(ftg_handle h, int64_t capacity);
@@ -234,6 +262,9 @@ ftg_status ftg_report_read(ftg_handle h, void* stream, ftg_fault_report* out, in
 /* Clears the device report with a kernel launched on `stream`
  * (graph-capturable). */
 ftg_status ftg_report_reset(ftg_handle h, void* stream);
+
+/* The threshold scale lambda that ftg_gemm_ex uses when cfg->lambda = 0. */
+double ftg_default_lambda(void);
 
 /* BLAS info of the last FTG_ERR_INVALID_ARG returned on this handle. */
 int ftg_last_error_arg(ftg_handle h);

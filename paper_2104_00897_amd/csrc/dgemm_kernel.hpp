@@ -582,6 +582,7 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
         if (tid == 0) { Vp->nfr = 0; Vp->nfc = 0; }
         __syncthreads();
         const bool cin = final && args.beta != 0.0;
+        double pass_ratio = 0.0;
         for (int line = tid; line < BM + BN; line += NT) {
             const bool isrow = line < BM;
             const int x = isrow ? line : line - BM;
@@ -615,8 +616,11 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
                 } else {
                     if (atomicAdd(&Vp->nfc, 1) == 0) { Vp->fj = x; Vp->dfj = d; Vp->tfj = tau; }
                 }
+            } else if (tau > 0.0) {
+                pass_ratio = fmax(pass_ratio, fabs(d) / tau);
             }
         }
+        note_pass_ratio(args.rep, pass_ratio);
         __syncthreads();
     };
 
@@ -994,14 +998,15 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
         const bool many = nr > 1 || nc > 1;
         if (many && args.uncorrectable_policy == 1 && redo_budget > 0) {
             // more than one error in the final slot: recompute the tile, no injection
-            if (tid == 0) {
+            auto count_recomputed = [&]() {
                 atomicAdd(&args.rep->cnt[kDetected], 1ull);
                 atomicAdd(&args.rep->cnt[kUncorrectable], 1ull);
                 atomicAdd(&args.rep->cnt[kTilesRecomputed], 1ull);
                 push_record(args.rep, args.problem, tm, tn, t, -1, -1, FTG_KIND_TILE_RECOMPUTED,
                             nr ? Vp->dfi : Vp->dfj, nr ? Vp->tfi : Vp->tfj);
-            }
+            };
             if constexpr (IVL) {
+                if (tid == 0) count_recomputed();
                 __syncthreads();
                 --redo_budget;
                 inj_from = n_int;
@@ -1016,8 +1021,11 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
                     q.problem = args.problem; q.tm = tm; q.tn = tn; q.interval = t;
                     q.nr = nr; q.nc = nc; q.fi = q.fj = 0; q.R = R; q.Q = Q;
                     q.whole = 1; q.pad1 = 0; q.m0 = m0; q.n0 = n0;
-                    q.dfi = q.tfi = q.dfj = q.tfj = q.exp_row = q.exp_col = q.cin = 0.0;
-                    push_repair(args.rep, q);
+                    q.dfi = nr ? Vp->dfi : 0.0; q.tfi = nr ? Vp->tfi : 0.0;
+                    q.dfj = nc ? Vp->dfj : 0.0; q.tfj = nc ? Vp->tfj : 0.0;
+                    q.exp_row = q.exp_col = q.cin = 0.0;
+                    // counted as recomputed only once the repair kernel will see it
+                    if (push_repair(args.rep, q)) count_recomputed();
                 }
                 __syncthreads();
                 return;

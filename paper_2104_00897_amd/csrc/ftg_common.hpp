@@ -15,6 +15,9 @@ constexpr int kKGran = 128;
 // Most verification intervals per tile with injection on (LDS fault table).
 constexpr int kMaxIntervals = 128;
 
+// Smallest repair-queue capacity of a handle (flagged slots of one call).
+constexpr unsigned int kMinRepairQueue = 16384;
+
 // A flagged final-slot check handed from a GEMM kernel to the repair kernel.
 // Row/column indices are tile-local; expected checksums already include the
 // alpha/beta scaling; cin is C_in at the located element (0 when beta = 0).
@@ -40,18 +43,6 @@ struct DevReport {
     RepairReq* rq;
 };
 
-// Appends a repair request (one thread); returns false when the queue is full.
-__device__ inline bool push_repair(DevReport* rep, const RepairReq& r)
-{
-    const unsigned int idx = atomicAdd(&rep->rq_count, 1u);
-    if (idx < rep->rq_capacity) {
-        rep->rq[idx] = r;
-        return true;
-    }
-    atomicAdd(&rep->rq_lost, 1u);
-    return false;
-}
-
 enum Cnt {
     kInjected = 0,
     kDetected = 1,
@@ -59,7 +50,8 @@ enum Cnt {
     kCorrRecomp = 3,
     kChecksumOnly = 4,
     kUncorrectable = 5,
-    kTilesRecomputed = 6
+    kTilesRecomputed = 6,
+    kMaxPassRatio = 7  // bit pattern of the largest |delta|/tau of a passing check
 };
 
 // Injector parameters of one problem (see ftg_inject in ftgemm.h).
@@ -150,6 +142,22 @@ __device__ inline double tau_of(int acc32, double lambda, int64_t nterms, double
 }
 
 __device__ inline bool flagged(double d, double tau) { return !(fabs(d) <= tau); }
+
+// Noise margin of the threshold: the largest |delta| / tau among the checks
+// that passed, over every call since the last report reset.  Called by every
+// lane of a wave with its own ratio (0 for none).  Non-negative doubles order
+// like their bit patterns, so an integer maximum keeps the largest; a wave
+// skips the atomic when the stored value is already larger.
+__device__ inline void note_pass_ratio(DevReport* rep, double r)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_xor(r, off));
+    if ((threadIdx.x & 63) == 0 && r > 0.0) {
+        const unsigned long long u = (unsigned long long)__double_as_longlong(r);
+        if (u > __hip_atomic_load(&rep->cnt[kMaxPassRatio], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(&rep->cnt[kMaxPassRatio], u);
+    }
+}
 
 // The faulty value no longer carries the true one (absorption): its rounding
 // unit in the output precision (binary32 when acc32) exceeds tau / (2 q), the
@@ -275,6 +283,25 @@ __device__ inline void push_inject(DevReport* rep, int problem, int tm, int tn, 
         r.new_val = newv;
         rep->inject_log[idx] = r;
     }
+}
+
+// Appends a repair request (one thread).  A full queue must not lose a fault
+// silently: the slot is then counted and recorded as uncorrectable (its tile
+// keeps what the kernel stored, or C_in for an unstored whole-tile request),
+// rq_lost counts it, and the report read returns FTG_ERR_UNCORRECTED.
+__device__ inline bool push_repair(DevReport* rep, const RepairReq& r)
+{
+    const unsigned int idx = atomicAdd(&rep->rq_count, 1u);
+    if (idx < rep->rq_capacity) {
+        rep->rq[idx] = r;
+        return true;
+    }
+    atomicAdd(&rep->rq_lost, 1u);
+    atomicAdd(&rep->cnt[kDetected], 1ull);
+    atomicAdd(&rep->cnt[kUncorrectable], 1ull);
+    push_record(rep, r.problem, r.tm, r.tn, r.interval, -1, -1, FTG_KIND_UNCORRECTABLE,
+                r.nr ? r.dfi : r.dfj, r.nr ? r.tfi : r.tfj);
+    return false;
 }
 
 // Workgroup id -> tile id.  Consecutive workgroup ids are spread round-robin

@@ -22,6 +22,9 @@ namespace {
 
 using ftg::DevReport;
 
+// Default threshold scale of the FP32-accumulating paths (ftg_config.lambda = 0).
+constexpr double kDefaultLambda = 1.0;
+
 constexpr int kTuneBuckets = 12;  // ceil(log2) of a dimension clamped to [4, 15]
 constexpr int kDtypes = 4;
 
@@ -49,6 +52,10 @@ struct ftg_handle_s {
     // products, magnitude bounds); grows to the largest shape seen
     unsigned char* d_work = nullptr;
     size_t work_bytes = 0;
+    bool work_captured = false;  // a captured graph holds the workspace's address
+    static constexpr int kMaxRetired = 64;
+    unsigned char* retired[kMaxRetired] = {};  // outgrown workspaces captured graphs may still use
+    int n_retired = 0;
     // optional timing of the product launches: event pairs on the call's stream
     bool timing = false;
     hipEvent_t tev[2 * 256] = {};
@@ -171,23 +178,43 @@ bool make_inject(const ftg_inject* in, int64_t m, int64_t n, int64_t k, int64_t 
 // ---------------------------------------------------------------- workspace
 namespace {
 
-// Grows the handle's device workspace to `bytes` (allocation is not allowed
-// under stream capture: warm up with the largest shape first).
-ftg_status ensure_work(ftg_handle h, size_t bytes, hipStream_t s)
+// Replaces the workspace by one of `bytes` (waits for the device first: the
+// old buffer may still be in use by queued work).  A buffer that a captured
+// graph has used is not freed but kept until the handle is destroyed, since
+// the graph replays with its address.
+ftg_status grow_work(ftg_handle h, size_t bytes)
 {
-    if (bytes <= h->work_bytes) return FTG_OK;
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
-        return FTG_ERR_UNSUPPORTED;
     if (hipDeviceSynchronize() != hipSuccess) return FTG_ERR_HIP;
-    if (h->d_work) hipFree(h->d_work);
-    for (auto& e : h->tev)
-        if (e) hipEventDestroy(e);
+    if (h->d_work) {
+        if (h->work_captured) {
+            if (h->n_retired == ftg_handle_s::kMaxRetired) return FTG_ERR_UNSUPPORTED;
+            h->retired[h->n_retired++] = h->d_work;
+        } else {
+            hipFree(h->d_work);
+        }
+    }
     h->d_work = nullptr;
     h->work_bytes = 0;
+    h->work_captured = false;
     if (hipMalloc(&h->d_work, bytes) != hipSuccess) return FTG_ERR_HIP;
     h->work_bytes = bytes;
     return FTG_OK;
+}
+
+// Makes the handle's device workspace hold `bytes` for the call about to be
+// queued on `s`.  Growing allocates and synchronises the device, so it is
+// refused under stream capture: reserve the largest shape first.
+ftg_status ensure_work(ftg_handle h, size_t bytes, hipStream_t s)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) return FTG_ERR_HIP;
+    const bool capturing = cs != hipStreamCaptureStatusNone;
+    if (bytes <= h->work_bytes) {
+        if (capturing) h->work_captured = true;
+        return FTG_OK;
+    }
+    if (capturing) return FTG_ERR_UNSUPPORTED;
+    return grow_work(h, bytes);
 }
 
 // Records an event pair around one product launch when timing is on (not
@@ -239,14 +266,17 @@ ftg_status ftg_create(ftg_handle* out, size_t report_capacity)
     bool ok = hipMalloc(&h->rep, sizeof(DevReport)) == hipSuccess;
     ok = ok && hipMalloc(&h->d_records, sizeof(ftg_fault_record) * std::max<size_t>(1, report_capacity)) == hipSuccess;
     ok = ok && hipMalloc(&h->d_inject, sizeof(ftg_inject_record) * std::max<size_t>(1, report_capacity)) == hipSuccess;
-    ok = ok && hipMalloc(&h->d_repair, sizeof(ftg::RepairReq) * std::max<size_t>(1, report_capacity)) == hipSuccess;
+    // the repair queue holds the flagged slots of one call; it is independent of
+    // the record capacity so that a small report still repairs every slot
+    const size_t rq_cap = std::max<size_t>(report_capacity, ftg::kMinRepairQueue);
+    ok = ok && hipMalloc(&h->d_repair, sizeof(ftg::RepairReq) * rq_cap) == hipSuccess;
     if (ok) {
         DevReport r;
         std::memset(&r, 0, sizeof(r));
         r.capacity = (unsigned)report_capacity;
         r.records = h->d_records;
         r.inject_log = h->d_inject;
-        r.rq_capacity = (unsigned)report_capacity;
+        r.rq_capacity = (unsigned)rq_cap;
         r.rq = h->d_repair;
         ok = hipMemcpy(h->rep, &r, sizeof(r), hipMemcpyHostToDevice) == hipSuccess;
     }
@@ -267,6 +297,7 @@ ftg_status ftg_destroy(ftg_handle h)
     if (h->d_blob) hipFree(h->d_blob);
     if (h->d_queue) hipFree(h->d_queue);
     if (h->d_work) hipFree(h->d_work);
+    for (int i = 0; i < h->n_retired; ++i) hipFree(h->retired[i]);
     for (auto& e : h->tev)
         if (e) hipEventDestroy(e);
     for (int i = 0; i < 3; ++i)
@@ -278,6 +309,8 @@ ftg_status ftg_destroy(ftg_handle h)
 }
 
 int ftg_last_error_arg(ftg_handle h) { return h ? h->last_info : 0; }
+
+double ftg_default_lambda(void) { return kDefaultLambda; }
 
 ftg_status ftg_tile_info(ftg_dtype ab_type, int32_t id, int32_t* bm, int32_t* bn, int32_t* bk)
 {
@@ -335,9 +368,28 @@ static ftg_status check_gemm(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int6
     return FTG_OK;
 }
 
-ftg_status ftg_dgemm(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n, int64_t k,
-                     double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
-                     double beta, double* C, int64_t ldc, void* stream, const ftg_config* cfg)
+}  // extern "C"
+
+namespace {
+
+// Where the FP64 encode pass writes the checksum row/column of the operands:
+// the handle's workspace (grown on demand), or a fixed buffer of `cap` bytes
+// that is never grown.
+struct EncodeBuffer {
+    double* fixed = nullptr;
+    size_t cap = 0;
+};
+
+// Encode-pass bytes of one FP64 call with bm x bn tiles.
+size_t dencode_bytes(int64_t m, int64_t n, int64_t k, int bm, int bn)
+{
+    return (size_t)(((m + bm - 1) / bm) + ((n + bn - 1) / bn)) * (size_t)k * 2 * sizeof(double);
+}
+
+ftg_status dgemm_impl(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n, int64_t k,
+                      double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+                      double beta, double* C, int64_t ldc, void* stream, const ftg_config* cfg,
+                      const EncodeBuffer& eb)
 {
     if (!h) return FTG_ERR_INVALID_ARG;
     ftg_status st = check_gemm(h, ta, tb, m, n, k, lda, ldb, ldc, cfg);
@@ -392,9 +444,16 @@ ftg_status ftg_dgemm(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n, i
     }
     if (abft && !(cfg && cfg->encode_in_loop)) {
         // encode pass: checksum row/column of both operands for every tile panel
-        const size_t bytes = (size_t)(a.tiles_m + a.tiles_n) * (size_t)k * 2 * sizeof(double);
-        if ((st = ensure_work(h, bytes, s)) != FTG_OK) return st;
-        double* w = (double*)h->d_work;
+        // (every entry is written, so the buffer needs no clearing)
+        const size_t bytes = dencode_bytes(m, n, k, bm, bn);
+        double* w;
+        if (eb.fixed) {
+            if (bytes > eb.cap) return FTG_ERR_UNSUPPORTED;
+            w = eb.fixed;
+        } else {
+            if ((st = ensure_work(h, bytes, s)) != FTG_OK) return st;
+            w = (double*)h->d_work;
+        }
         ftg::DEncArgs e;
         std::memset(&e, 0, sizeof(e));
         const int chunks = (int)((k + ftg::kDEncChunk - 1) / ftg::kDEncChunk);
@@ -419,6 +478,25 @@ ftg_status ftg_dgemm(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n, i
         e = ftg::launch_repair(h->rep, rp, nullptr, s);
     }
     return e == hipSuccess ? FTG_OK : FTG_ERR_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+ftg_status ftg_dgemm(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n, int64_t k,
+                     double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+                     double beta, double* C, int64_t ldc, void* stream, const ftg_config* cfg)
+{
+    return dgemm_impl(h, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream, cfg,
+                      EncodeBuffer{});
+}
+
+ftg_status ftg_workspace_reserve(ftg_handle h, size_t bytes)
+{
+    if (!h) return FTG_ERR_INVALID_ARG;
+    if (bytes <= h->work_bytes) return FTG_OK;
+    return grow_work(h, bytes);
 }
 
 
@@ -597,7 +675,7 @@ ftg_status ftg_gemm_ex(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n,
     a.er_stride = c1.cslice;
     a.ec_stride = c2.cslice;
     a.RA = ea.XR; a.MA = ea.XM; a.CB = eb_.XR; a.MB = eb_.XM;
-    a.lambda = (cfg && cfg->lambda > 0.0) ? cfg->lambda : 4.0;
+    a.lambda = (cfg && cfg->lambda > 0.0) ? cfg->lambda : kDefaultLambda;
     a.problem = 0;
     if (cfg && cfg->inject) {
         const int64_t slots = (int64_t)a.tiles_m * a.tiles_n;
@@ -893,6 +971,8 @@ ftg_status ftg_report_read(ftg_handle h, void* stream, ftg_fault_report* out, in
     out->checksum_only = r.cnt[ftg::kChecksumOnly];
     out->uncorrectable = r.cnt[ftg::kUncorrectable];
     out->tiles_recomputed = r.cnt[ftg::kTilesRecomputed];
+    out->lost = r.rq_lost;
+    std::memcpy(&out->max_pass_ratio, &r.cnt[ftg::kMaxPassRatio], sizeof(double));
     out->n_records = r.n_records;
     out->n_inject_log = r.n_inject;
     const size_t nr = std::min<size_t>({(size_t)r.n_records, (size_t)out->capacity, h->capacity});
@@ -907,8 +987,9 @@ ftg_status ftg_report_read(ftg_handle h, void* stream, ftg_fault_report* out, in
             return FTG_ERR_HIP;
     if (sync) {
         if (hipStreamSynchronize(s) != hipSuccess) return FTG_ERR_HIP;
-        // uncorrectable slots left as they were (not recomputed)
-        if (out->uncorrectable > out->tiles_recomputed) return FTG_ERR_UNCORRECTED;
+        // uncorrectable slots left as they were (not recomputed), including
+        // slots the full repair queue could not take
+        if (out->uncorrectable > out->tiles_recomputed || out->lost) return FTG_ERR_UNCORRECTED;
     }
     return FTG_OK;
 }

@@ -659,6 +659,7 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
         // expected sums: alpha s (maintained checksum) + beta (C_in sums); threshold
         // from the magnitude bound (sum_p |a_ip|) max_p (sum_j |b_pj|) (and columns alike)
         const double asd = (double)as, bd = (double)args.beta;
+        double pass_ratio = 0.0;
         for (int line = tid; line < BM + BN; line += Cf::NT) {
             const bool isrow = line < BM;
             const int x = isrow ? line : line - BM;
@@ -709,8 +710,11 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
                 } else {
                     if (atomicAdd(&V.nfc, 1) == 0) { V.fj = x; V.dfj = d; V.tfj = tau; V.exj = ex; }
                 }
+            } else if (tau > 0.0) {
+                pass_ratio = fmax(pass_ratio, fabs(d) / tau);
             }
         }
+        note_pass_ratio(args.rep, pass_ratio);
         __syncthreads();
         const int nr = __builtin_amdgcn_readfirstlane(V.nfr);
         const int nc = __builtin_amdgcn_readfirstlane(V.nfc);

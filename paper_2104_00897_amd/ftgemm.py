@@ -61,7 +61,8 @@ class FaultReport(ct.Structure):
                 ("corrected_subtract", ct.c_uint64), ("corrected_recompute", ct.c_uint64),
                 ("checksum_only", ct.c_uint64), ("uncorrectable", ct.c_uint64),
                 ("tiles_recomputed", ct.c_uint64), ("n_records", ct.c_uint32),
-                ("n_inject_log", ct.c_uint32), ("capacity", ct.c_uint32), ("reserved", ct.c_uint32),
+                ("n_inject_log", ct.c_uint32), ("capacity", ct.c_uint32), ("lost", ct.c_uint32),
+                ("max_pass_ratio", ct.c_double),
                 ("records", ct.POINTER(FaultRecord)), ("inject_log", ct.POINTER(InjectRecord))]
 
 
@@ -69,7 +70,7 @@ EXPORTS = [
     "ftg_create", "ftg_destroy", "ftg_dgemm", "ftg_gemm_ex", "ftg_dgemm_batched_uneven",
     "ftg_batched_reserve", "ftg_report_read", "ftg_report_reset", "ftg_last_error_arg",
     "ftg_tile_info", "ftg_tune_set", "ftg_tune_get", "ftg_timing_enable", "ftg_timing_read",
-    "ftg_status_string",
+    "ftg_status_string", "ftg_workspace_reserve", "ftg_default_lambda",
 ]
 
 _lib = None
@@ -89,6 +90,7 @@ def load() -> ct.CDLL:
     lib.ftg_destroy.argtypes = [h]
     lib.ftg_dgemm.argtypes = [h, i32, i32, i64, i64, i64, ct.c_double, vp, i64, vp, i64,
                               ct.c_double, vp, i64, vp, ct.POINTER(Config)]
+    lib.ftg_workspace_reserve.argtypes = [h, ct.c_size_t]
     lib.ftg_gemm_ex.argtypes = [h, i32, i32, i64, i64, i64, i32, i32, vp, vp, ct.c_float, vp, i64,
                                 vp, i64, ct.c_float, vp, i64, vp, ct.POINTER(Config)]
     lib.ftg_dgemm_batched_uneven.argtypes = [h, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
@@ -105,10 +107,17 @@ def load() -> ct.CDLL:
     lib.ftg_status_string.argtypes = [i32]
     lib.ftg_status_string.restype = ct.c_char_p
     for name in EXPORTS:
-        if name != "ftg_status_string":
+        if name not in ("ftg_status_string", "ftg_default_lambda"):
             getattr(lib, name).restype = ct.c_int
+    lib.ftg_default_lambda.argtypes = []
+    lib.ftg_default_lambda.restype = ct.c_double
     _lib = lib
     return lib
+
+
+def default_lambda() -> float:
+    """Threshold scale of the FP32-accumulating paths when the config leaves it 0."""
+    return load().ftg_default_lambda()
 
 
 def tile_info(dtype: int, tile_id: int):
@@ -126,6 +135,8 @@ class Report:
     checksum_only: int = 0
     uncorrectable: int = 0
     tiles_recomputed: int = 0
+    lost: int = 0
+    max_pass_ratio: float = 0.0
     status: int = OK
     records: list = field(default_factory=list)
     inject_log: list = field(default_factory=list)
@@ -176,6 +187,9 @@ class Handle:
                                 C_ptr, ldc, stream, ct.byref(cfg) if cfg is not None else None)
         self._check(st, "ftg_dgemm")
 
+    def workspace_reserve(self, nbytes: int):
+        self._check(self.lib.ftg_workspace_reserve(self.h, nbytes), "ftg_workspace_reserve")
+
     def gemm_ex(self, ta, tb, m, n, k, ab_type, c_type, scale_a, scale_b, alpha, A_ptr, lda,
                 B_ptr, ldb, beta, C_ptr, ldc, stream=None, cfg=None):
         st = self.lib.ftg_gemm_ex(self.h, ta, tb, m, n, k, ab_type, c_type, scale_a, scale_b,
@@ -197,7 +211,8 @@ class Handle:
         if st not in (OK, ERR_UNCORRECTED):
             raise FtgError(st, "ftg_report_read")
         rep = Report(out.injected, out.detected, out.corrected_subtract, out.corrected_recompute,
-                     out.checksum_only, out.uncorrectable, out.tiles_recomputed, st)
+                     out.checksum_only, out.uncorrectable, out.tiles_recomputed, out.lost,
+                     out.max_pass_ratio, st)
         fields = [f for f, _ in FaultRecord._fields_ if f != "reserved"]
         rep.records = [{f: getattr(r, f) for f in fields}
                        for r in recs[:min(out.n_records, self.capacity)]]

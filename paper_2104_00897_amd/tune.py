@@ -15,8 +15,9 @@ import math
 
 from . import ftgemm
 
-FP64_TILES = (1, 2, 3, 4)
-FP64_INTERVAL_TILES = (2, 3)
+FP64_TILES = (1, 2, 3, 4, 5)
+FP64_INTERVAL_TILES = (2, 3, 5)
+FP64_BATCHED_TILES = (2, 3)
 LOWP_TILES = (1,)
 
 
@@ -113,3 +114,38 @@ def autotune(handle, shapes, dtype=ftgemm.F64, steps=5, warmup=2, abft=True, int
         table.set(dtype, m, n, k, best)
         handle.tune_set(dtype, m, n, k, best)
     return table
+
+
+def autotune_batched(handle, sizes, steps=3, warmup=1, reps=8, abft=True,
+                     table: TuneTable | None = None) -> TuneTable:
+    """Tile choice of the batched entry point per shape bucket.  For every bucket
+    present in `sizes` ((m, n, k) triples), a batched call of `reps` problems of
+    that bucket's first shape (separate outputs, enough tiles to occupy the
+    chip as in a mixed batch) is timed with each batched tile configuration,
+    and the fastest is recorded in `table` and the handle (a batched call reads
+    the handle's table for every problem whose config leaves the tile 0)."""
+    import torch
+    table = table or TuneTable()
+    seen = set()
+    stream = ftgemm.current_stream_ptr
+    for m, n, k in sizes:
+        key = TuneTable.key(ftgemm.F64, m, n, k)
+        if key in seen:
+            continue
+        seen.add(key)
+        m, n, k = int(m), int(n), int(k)
+        A = torch.rand((k, m), device="cuda", dtype=torch.float64)
+        B = torch.rand((n, k), device="cuda", dtype=torch.float64)
+        Cs = [torch.empty((n, m), device="cuda", dtype=torch.float64) for _ in range(reps)]
+        plan = ftgemm.BatchPlan([ftgemm.batch_problem(A, B, C, 1.0, 0.0) for C in Cs])
+        best, best_ms = 0, float("inf")
+        for tile in FP64_BATCHED_TILES:
+            cfg = ftgemm.make_config(abft=abft, tile=tile)
+            ms = _time(torch, lambda: handle.dgemm_batched(plan, stream(), cfg), steps, warmup)
+            if ms < best_ms:
+                best, best_ms = tile, ms
+        table.set(ftgemm.F64, m, n, k, best)
+        handle.tune_set(ftgemm.F64, m, n, k, best)
+        del A, B, Cs, plan
+    return table
+

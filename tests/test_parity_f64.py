@@ -12,7 +12,8 @@ import pytest
 
 import oracle
 from paper_2104_00897_amd import inputs
-from tests.gpu_util import assert_close_f64, magnitude
+from tests.gpu_util import (assert_close_f64, check_detectable_corrected, check_flip_values,
+                            fp64_fault_taus, magnitude)
 
 pytestmark = pytest.mark.gpu
 
@@ -138,6 +139,7 @@ def check_log_matches_plan(rep, plan, tile):
     want = sorted((f.tile_m * bm + f.row, -1 if f.target == oracle.TARGET_CHECKSUM else f.tile_n * bn + f.col,
                    f.pflip, f.bit) for f in plan)
     assert got == want
+    check_flip_values(rep.inject_log)
 
 
 def test_cfg1_256_four_faults(env):
@@ -183,26 +185,58 @@ def test_faults_every_tile_exponent_bits(env, tile, ta, tb):
     assert_close_f64(out, ref, magnitude(A, B, C, 1.5, 0.5, ta, tb), k)
 
 
-def test_default_bit_range_detectable_faults_corrected(env):
-    """Bits 40..63 (A10): every fault whose magnitude clears 4 tau is corrected; a
-    fault below tau/4 is masked and its element stays within tau of the oracle."""
+@pytest.mark.parametrize("tile", [2, 3, 5])
+def test_default_bit_range_detectable_faults_corrected(env, tile):
+    """Bits 40..63 (A10): every fault whose error clears 4 tau of its tile row and
+    column is located and corrected; any other fault that stays uncorrected is
+    masked, its element within the flip's own size of the oracle."""
     ftgemm = env[0]
     m, n, k = 512, 512, 512
     A, B, C = inputs.gemm_operands_f64(m, n, k, seed=6)
+    bm, bn = TILES[tile]
     F = 16
-    cfg = ftgemm.make_config(tile=2, seed=77, n_faults=F)
+    cfg = ftgemm.make_config(tile=tile, seed=77, n_faults=F)
     out, rep = run(env, A, B, C, 1.5, 0.5, 0, 0, cfg)
+    check_log_matches_plan(rep, plan_for(77, F, m, n, k, tile), tile)
     ref = oracle.gemm(A, B, C, 1.5, 0.5)
     M = magnitude(A, B, C, 1.5, 0.5, 0, 0)
-    fixed = {(r["row"], r["col"]) for r in rep.records if r["kind"] in (1, 2)}
+    taus = fp64_fault_taus(A, B, C, 1.5, 0.5, 0, 0, rep.inject_log, bm, bn)
+    big, masked_log = check_detectable_corrected(rep, taus, 1.5)
+    assert big >= F // 2
     masked = np.zeros(ref.shape, dtype=bool)
-    for f in rep.inject_log:
-        if (f["row"], f["col"]) not in fixed:
-            d = abs(f["new_val"] - f["old_val"]) * 1.5  # alpha scales the accumulator
-            assert abs(out[f["row"], f["col"]] - ref[f["row"], f["col"]]) <= d * 1.01 + 1e-12 * M[f["row"], f["col"]]
-            masked[f["row"], f["col"]] = True
-    assert rep.injected == F
+    for g in masked_log:
+        d = abs(g["new_val"] - g["old_val"]) * 1.5  # alpha scales the accumulator
+        assert abs(out[g["row"], g["col"]] - ref[g["row"], g["col"]]) <= d * 1.01 + 1e-12 * M[g["row"], g["col"]]
+        masked[g["row"], g["col"]] = True
+    assert rep.injected == F and rep.uncorrectable == 0
     assert_close_f64(out, ref, M, k, skip=masked)
+
+
+@pytest.mark.parametrize("tile", [2, 3, 5])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_direct_staging_all_transposes_ragged(env, tile, ta, tb):
+    """Even leading dimensions and 16-byte aligned operands select the kernels that
+    load full k-blocks straight into LDS; ragged edges in every dimension (the
+    edge tiles and the k tail take the register path inside the same kernel)."""
+    ftgemm = env[0]
+    m, n, k = 302, 286, 198
+    A, B, C = inputs.gemm_operands_f64(m, n, k, seed=14, ta=ta, tb=tb)
+    assert A.shape[0] % 2 == 0 and B.shape[0] % 2 == 0
+    ref = oracle.gemm(A, B, C, 1.5, 0.5, ta, tb)
+    M = magnitude(A, B, C, 1.5, 0.5, ta, tb)
+    out, rep = run(env, A, B, C, 1.5, 0.5, ta, tb, ftgemm.make_config(tile=tile))
+    assert_close_f64(out, ref, M, k)
+    assert rep.detected == 0
+    bm, bn = TILES[tile]
+    F = min(8, -(-m // bm) * -(-n // bn))
+    cfg = ftgemm.make_config(tile=tile, seed=40 + tile, n_faults=F, bit_lo=52, bit_hi=62)
+    out, rep = run(env, A, B, C, 1.5, 0.5, ta, tb, cfg)
+    check_log_matches_plan(rep, plan_for(40 + tile, F, m, n, k, tile, bit_lo=52, bit_hi=62), tile)
+    assert rep.corrected_subtract + rep.corrected_recompute == F
+    assert_close_f64(out, ref, M, k)
+    # the unprotected kernel of the same configuration gives the same product
+    out_u, _ = run(env, A, B, C, 1.5, 0.5, ta, tb, ftgemm.make_config(tile=tile, abft=False))
+    assert_close_f64(out_u, ref, M, k)
 
 
 def test_checksum_fault_is_checksum_only(env):

@@ -16,11 +16,16 @@ import pytest
 
 import oracle
 from paper_2104_00897_amd import inputs
+from tests.gpu_util import check_flip_values
 
 pytestmark = pytest.mark.gpu
 
 U32 = 2.0 ** -24
-LAMBDA = 4.0   # the library default
+
+
+def default_lambda():
+    from paper_2104_00897_amd import ftgemm
+    return ftgemm.default_lambda()
 
 
 @pytest.fixture(scope="module")
@@ -145,20 +150,27 @@ def plan_for(r, seed, F, bit_lo, bit_hi, target=oracle.TARGET_ACC):
 
 
 def fault_taus(r, alpha, beta, log):
-    """Threshold of each injected element's row under the binary32 rule (A10
-    classifies a flip by |delta| against it): 2 lambda sqrt(k + Q + 8) u32 M_i with
-    M_i = |alpha| (sum_p |a_ip|) max_p (sum_{j in J} |b_pj|) + |beta| sum_{j in J} |c_ij|."""
+    """Threshold of each injected element under the binary32 rule, the larger of its
+    tile row's and tile column's (a fault must clear both lines to be located):
+    2 lambda sqrt(k + len + 8) u32 M with the row magnitude bound
+    M_i = |alpha| (sum_p |a_ip|) max_p (sum_{j in J} |b_pj|) + |beta| sum_{j in J} |c_ij|
+    and the column's alike."""
     a = np.abs(r.va.T if r.ta else r.va)
     b = np.abs(r.vb.T if r.tb else r.vb)
+    lam = default_lambda()
     out = []
     for g in log:
         i, j = g["row"], g["col"]
+        I = slice((i // 128) * 128, min(r.m, (i // 128) * 128 + 128))
         J = slice((j // 128) * 128, min(r.n, (j // 128) * 128 + 128))
-        Q = J.stop - J.start
-        mag = abs(r.alpha_eff(alpha)) * a[i, :].sum() * b[:, J].sum(axis=1).max()
+        R, Q = I.stop - I.start, J.stop - J.start
+        mr = abs(r.alpha_eff(alpha)) * a[i, :].sum() * b[:, J].sum(axis=1).max()
+        mc = abs(r.alpha_eff(alpha)) * b[:, j].sum() * a[I, :].sum(axis=0).max()
         if beta != 0:
-            mag += abs(beta) * np.abs(r.C[i, J].astype(np.float64)).sum()
-        out.append(oracle.tau(r.k + Q + 8, mag, acc32=True, lam=LAMBDA))
+            mr += abs(beta) * np.abs(r.C[i, J].astype(np.float64)).sum()
+            mc += abs(beta) * np.abs(r.C[I, j].astype(np.float64)).sum()
+        out.append(max(oracle.tau(r.k + Q + 8, mr, acc32=True, lam=lam),
+                       oracle.tau(r.k + R + 8, mc, acc32=True, lam=lam)))
     return out
 
 
@@ -168,11 +180,12 @@ def check_flips(r, alpha, beta, out, rep, plan):
     masked, its element then within the flip's own size of the oracle."""
     got = sorted((g["row"], g["col"], g["pflip"], g["bit"]) for g in rep.inject_log)
     assert got == sorted((f.tile_m * 128 + f.row, f.tile_n * 128 + f.col, f.pflip, f.bit) for f in plan)
+    check_flip_values(rep.inject_log, acc32=True)
     taus = fault_taus(r, alpha, beta, rep.inject_log)
     fixed = {(g["row"], g["col"]) for g in rep.records if g["kind"] in (1, 2)}
     Cin = r.C.astype(np.float64) if beta else None
     _, orecs, _ = oracle.abft(r.va, r.vb, Cin, r.alpha_eff(alpha), beta, r.ta, r.tb, bm=128, bn=128,
-                              plan=plan, acc32=True, lam=LAMBDA)
+                              plan=plan, acc32=True, lam=default_lambda())
     olocated = {(o.row, o.col) for o in orecs if o.kind in (1, 2)}
     ref = r.oracle(alpha, beta)
     skip = np.zeros(ref.shape, dtype=bool)
@@ -258,6 +271,7 @@ def test_cfg3_full_size_sampled(env, kind):
     torch.cuda.synchronize()
     rep = h.read()
     assert rep.injected == 16 and rep.uncorrectable == 0
+    check_flip_values(rep.inject_log, acc32=True)
     fixed = {(g["row"], g["col"]) for g in rep.records if g["kind"] in (1, 2)}
     rng = np.random.default_rng(1)
     rows = list(rng.integers(0, n, 48)) + [g["row"] for g in rep.inject_log]
