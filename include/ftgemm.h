@@ -31,7 +31,8 @@
  *     grows it first: that allocates and waits for the device.  Calls that
  *     fit the workspace allocate nothing and never synchronise; size it
  *     up front with ftg_workspace_reserve (or one call of the largest
- *     shape).  Growth is refused (FTG_ERR_UNSUPPORTED) under stream capture;
+ *     shape), and use ftg_dgemm_noalloc where no allocation may happen at
+ *     all.  Growth is refused (FTG_ERR_UNSUPPORTED) under stream capture;
  *     a workspace that a captured graph has used is not freed when it is
  *     outgrown but kept until ftg_destroy (the graph replays with its
  *     address).  Otherwise only ftg_report_read, ftg_batched_reserve,
@@ -193,6 +194,25 @@ ftg_status ftg_dgemm(ftg_handle h, ftg_op transa, ftg_op transb, int64_t m, int6
                      int64_t k, double alpha, const double* A, int64_t lda, const double* B,
                      int64_t ldb, double beta, double* C, int64_t ldc, void* stream,
                      const ftg_config* cfg);
+
+/* ftg_dgemm for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments, semantics and fault report as ftg_dgemm, but the encode
+ * pass writes into a fixed scratch buffer of ftg_dgemm_noalloc_max_bytes()
+ * bytes (64 MiB) that the library holds per device until the process ends,
+ * instead of the handle's growable workspace: the call never allocates,
+ * frees or synchronises.  It needs (ceil(m/bm) + ceil(n/bn)) * k * 16 bytes
+ * for the chosen tile (bm x bn; 128 x 128 by default from 2048^2 outputs
+ * on), e.g. 16 MiB at 8192^3 and 64 MiB at 16384^3; a larger shape returns
+ * FTG_ERR_UNSUPPORTED before anything is launched (encode_in_loop = 1 needs
+ * no scratch at all).  Every call on a device shares that device's buffer:
+ * calls that overlap on one device (several streams, or several handles)
+ * race; serialise them. */
+ftg_status ftg_dgemm_noalloc(ftg_handle h, ftg_op transa, ftg_op transb, int64_t m, int64_t n,
+                             int64_t k, double alpha, const double* A, int64_t lda,
+                             const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+                             void* stream, const ftg_config* cfg);
+size_t ftg_dgemm_noalloc_max_bytes(void);
 
 /* Mixed-precision protected GEMM: A, B of type ab_type (FTG_BF16 or
  * FTG_F8_E4M3, OCP e4m3fn), FP32 accumulation on MFMA, FP32 maintained

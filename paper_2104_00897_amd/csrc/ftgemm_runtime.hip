@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "../../include/ftgemm.h"
@@ -56,6 +57,7 @@ struct ftg_handle_s {
     static constexpr int kMaxRetired = 64;
     unsigned char* retired[kMaxRetired] = {};  // outgrown workspaces captured graphs may still use
     int n_retired = 0;
+    void* scratch = nullptr;     // device address of the scratch-free entry point's buffer
     // optional timing of the product launches: event pairs on the call's stream
     bool timing = false;
     hipEvent_t tev[2 * 256] = {};
@@ -217,6 +219,32 @@ ftg_status ensure_work(ftg_handle h, size_t bytes, hipStream_t s)
     return grow_work(h, bytes);
 }
 
+// Scratch of the scratch-free entry point: one copy per device, held until
+// the process ends.  Host code never passes `scratch` itself to a kernel (in
+// host code it names a host-side stand-in); it uses the device address that
+// hipGetSymbolAddress returns for the current device, kept per device.
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (which must be current), looked up
+// once per device.
+ftg_status scratch_address(int device, void** out)
+{
+    if (device < 0 || device >= kMaxDevices) return FTG_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return FTG_ERR_HIP;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return FTG_OK;
+}
+
 // Records an event pair around one product launch when timing is on (not
 // under stream capture, and only while pairs are free).
 struct LaunchTimer {
@@ -281,6 +309,7 @@ ftg_status ftg_create(ftg_handle* out, size_t report_capacity)
         ok = hipMemcpy(h->rep, &r, sizeof(r), hipMemcpyHostToDevice) == hipSuccess;
     }
     if (ok) ok = ftg_batched_reserve(h, 1024) == FTG_OK;
+    if (ok) ok = scratch_address(h->device, &h->scratch) == FTG_OK;
     if (!ok) { ftg_destroy(h); return FTG_ERR_HIP; }
     *out = h;
     return FTG_OK;
@@ -374,7 +403,7 @@ namespace {
 
 // Where the FP64 encode pass writes the checksum row/column of the operands:
 // the handle's workspace (grown on demand), or a fixed buffer of `cap` bytes
-// that is never grown.
+// that is never grown (the scratch-free entry point).
 struct EncodeBuffer {
     double* fixed = nullptr;
     size_t cap = 0;
@@ -491,6 +520,19 @@ ftg_status ftg_dgemm(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n, i
     return dgemm_impl(h, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream, cfg,
                       EncodeBuffer{});
 }
+
+ftg_status ftg_dgemm_noalloc(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n, int64_t k,
+                             double alpha, const double* A, int64_t lda, const double* B,
+                             int64_t ldb, double beta, double* C, int64_t ldc, void* stream,
+                             const ftg_config* cfg)
+{
+    if (!h) return FTG_ERR_INVALID_ARG;
+    if (!h->scratch) return FTG_ERR_HIP;
+    return dgemm_impl(h, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream, cfg,
+                      EncodeBuffer{(double*)h->scratch, kNoallocScratchBytes});
+}
+
+size_t ftg_dgemm_noalloc_max_bytes(void) { return kNoallocScratchBytes; }
 
 ftg_status ftg_workspace_reserve(ftg_handle h, size_t bytes)
 {

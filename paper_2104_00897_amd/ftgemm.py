@@ -70,7 +70,8 @@ EXPORTS = [
     "ftg_create", "ftg_destroy", "ftg_dgemm", "ftg_gemm_ex", "ftg_dgemm_batched_uneven",
     "ftg_batched_reserve", "ftg_report_read", "ftg_report_reset", "ftg_last_error_arg",
     "ftg_tile_info", "ftg_tune_set", "ftg_tune_get", "ftg_timing_enable", "ftg_timing_read",
-    "ftg_status_string", "ftg_workspace_reserve", "ftg_default_lambda",
+    "ftg_status_string", "ftg_dgemm_noalloc", "ftg_dgemm_noalloc_max_bytes",
+    "ftg_workspace_reserve", "ftg_default_lambda",
 ]
 
 _lib = None
@@ -90,6 +91,8 @@ def load() -> ct.CDLL:
     lib.ftg_destroy.argtypes = [h]
     lib.ftg_dgemm.argtypes = [h, i32, i32, i64, i64, i64, ct.c_double, vp, i64, vp, i64,
                               ct.c_double, vp, i64, vp, ct.POINTER(Config)]
+    lib.ftg_dgemm_noalloc.argtypes = lib.ftg_dgemm.argtypes
+    lib.ftg_dgemm_noalloc_max_bytes.argtypes = []
     lib.ftg_workspace_reserve.argtypes = [h, ct.c_size_t]
     lib.ftg_gemm_ex.argtypes = [h, i32, i32, i64, i64, i64, i32, i32, vp, vp, ct.c_float, vp, i64,
                                 vp, i64, ct.c_float, vp, i64, vp, ct.POINTER(Config)]
@@ -107,8 +110,9 @@ def load() -> ct.CDLL:
     lib.ftg_status_string.argtypes = [i32]
     lib.ftg_status_string.restype = ct.c_char_p
     for name in EXPORTS:
-        if name not in ("ftg_status_string", "ftg_default_lambda"):
+        if name not in ("ftg_status_string", "ftg_dgemm_noalloc_max_bytes", "ftg_default_lambda"):
             getattr(lib, name).restype = ct.c_int
+    lib.ftg_dgemm_noalloc_max_bytes.restype = ct.c_size_t
     lib.ftg_default_lambda.argtypes = []
     lib.ftg_default_lambda.restype = ct.c_double
     _lib = lib
@@ -186,6 +190,13 @@ class Handle:
         st = self.lib.ftg_dgemm(self.h, ta, tb, m, n, k, alpha, A_ptr, lda, B_ptr, ldb, beta,
                                 C_ptr, ldc, stream, ct.byref(cfg) if cfg is not None else None)
         self._check(st, "ftg_dgemm")
+
+    def dgemm_noalloc(self, ta, tb, m, n, k, alpha, A_ptr, lda, B_ptr, ldb, beta, C_ptr, ldc,
+                      stream=None, cfg=None):
+        st = self.lib.ftg_dgemm_noalloc(self.h, ta, tb, m, n, k, alpha, A_ptr, lda, B_ptr, ldb,
+                                        beta, C_ptr, ldc, stream,
+                                        ct.byref(cfg) if cfg is not None else None)
+        self._check(st, "ftg_dgemm_noalloc")
 
     def workspace_reserve(self, nbytes: int):
         self._check(self.lib.ftg_workspace_reserve(self.h, nbytes), "ftg_workspace_reserve")
