@@ -35,7 +35,7 @@ PEAK_HBM = 8000.0     # GB/s
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a plain-copy calibration
 # (profiles/dgemm_abft_*_traffic.md); an entry is dropped whenever that kernel
 # changes, and the line then reports null until it is measured again
-TRAFFIC_F64: dict = {}
+TRAFFIC_F64: dict = {16384: 1.5406e11}
 
 
 def parse():
@@ -48,7 +48,9 @@ def parse():
     p.add_argument("--no-sweep", action="store_true", help="skip the FP64 size sweep and rank-k shapes")
     p.add_argument("--fp-calls", type=int, default=1000,
                    help="fault-free calls of the BF16/FP8 false-positive campaign")
-    p.add_argument("--only", default="", help="comma list of legs to run among cfg1,cfg3,cfg4,cfg5")
+    p.add_argument("--only", default="", help="comma list of legs to run among cfg1,cfg3,cfg4,cfg5,unfused")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only copy 1 GiB between device buffers three times (reference for HBM counters)")
     p.add_argument("--tiles", action="store_true", help="time every FP64 tile configuration at --n")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-configs", action="store_true", help="skip the other workloads (cfg 1, 3, 4, 5)")
@@ -328,6 +330,53 @@ def cfg4_ftlinear(torch, ftgemm, h, steps):
                        "uncorrectable": rep.uncorrectable}}
 
 
+def unfused_comparison(torch, ftgemm, h, steps, sizes=(4096, 8192, 16384), kc_online=512):
+    """The fused protected product against the unfused comparator (the online ABFT
+    of section 5.1 built around the unprotected product, whole-matrix checksums):
+    FP64 NN n^3, alpha = 1.5, beta = 0.5, U[-1,1], one flip per rank-K_c slab in
+    both (exponent bits, so each is corrected).  The unfused scheme runs offline
+    (one slab) and online (K_c = 512); its cost is compared with the paper's
+    model (6 + 2K/K_c) P_mm / (n P_mv), P_mm the unprotected product's rate and
+    P_mv = 2 flop per 8 bytes at the 8 TB/s HBM peak."""
+    rows = []
+    for n in sizes:
+        dA, dB, dC, _ = device_operands(torch, ftgemm, n, n, n, seed=n + 3)
+        fl = 2.0 * n ** 3
+        nint = n // kc_online
+        inj = dict(seed=5, bit_lo=52, bit_hi=62)
+        fns = {
+            "unprotected": lambda: ftgemm.gemm_f64(h, dA, dB, dC, 1.5, 0.5, cfg=ftgemm.make_config(abft=False)),
+            "fused": lambda: ftgemm.gemm_f64(h, dA, dB, dC, 1.5, 0.5,
+                                             cfg=ftgemm.make_config(n_faults=nint, **inj)),
+            "unfused_offline": lambda: ftgemm.gemm_f64_unfused(h, dA, dB, dC, 1.5, 0.5,
+                                                               cfg=ftgemm.make_config(n_faults=1, **inj)),
+            "unfused_online": lambda: ftgemm.gemm_f64_unfused(
+                h, dA, dB, dC, 1.5, 0.5, cfg=ftgemm.make_config(interval_k=kc_online, n_faults=nint, **inj)),
+            "unfused_online_no_faults": lambda: ftgemm.gemm_f64_unfused(
+                h, dA, dB, dC, 1.5, 0.5, cfg=ftgemm.make_config(interval_k=kc_online)),
+            "slabs_unprotected": lambda: ftgemm.gemm_f64_unfused(
+                h, dA, dB, dC, 1.5, 0.5, cfg=ftgemm.make_config(abft=False, interval_k=kc_online)),
+        }
+        h.reset()
+        t = timed_ab(torch, fns, max(2, steps // 3), 1)
+        rep = h.read()
+        p_mm = fl / t["unprotected"] / 1e9          # TFLOP/s
+        p_mv = 2.0 / 8.0 * PEAK_HBM / 1e3           # TFLOP/s at the HBM peak
+        model = lambda kk: 100.0 * (6 + 2.0 * kk) * p_mm / (n * p_mv)
+        row = {"n": n, "kc_online": kc_online,
+               **{f"ms_{k}": v for k, v in t.items()},
+               "overhead_pct": {k: 100.0 * (v / t["unprotected"] - 1.0) for k, v in t.items()
+                                if k != "unprotected"},
+               "abft_passes_over_slabs_pct": 100.0 * (t["unfused_online"] / t["slabs_unprotected"] - 1.0),
+               "model_overhead_pct": {"offline": model(1), "online": model(n // kc_online)},
+               "faults": {"injected": rep.injected, "corrected": rep.corrected_subtract + rep.corrected_recompute,
+                          "uncorrectable": rep.uncorrectable}}
+        rows.append(row)
+        print(json.dumps({"unfused_row": row}), file=sys.stderr, flush=True)
+        del dA, dB, dC
+    return rows
+
+
 def batched_problem_seed(seed: int, p: int) -> int:
     """Injector seed of problem p of a batched call (the rule documented with
     ftg_dgemm_batched_uneven): output 2^32 + p of SplitMix64 seeded with `seed`."""
@@ -466,6 +515,14 @@ def main():
     import torch
     from paper_2104_00897_amd import ftgemm
 
+    if args.copy_calibration:
+        a = torch.empty(2 ** 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": 2 ** 30}), flush=True)
+        return
     h = ftgemm.Handle(capacity=16384)
     if args.calibrate:
         print(json.dumps({"calibrate": calibrate_lambda(torch, ftgemm, h, args.calibrate)}), flush=True)
@@ -527,7 +584,8 @@ def main():
                          ("cfg3_fp8", lambda: cfg3_lowp(torch, ftgemm, h, "fp8", args.steps,
                                                         fp_calls=args.fp_calls)),
                          ("cfg4", lambda: cfg4_ftlinear(torch, ftgemm, h, max(2, args.steps // 2))),
-                         ("cfg5", lambda: cfg5_batched(torch, ftgemm, h, args.steps))]:
+                         ("cfg5", lambda: cfg5_batched(torch, ftgemm, h, args.steps)),
+                         ("unfused", lambda: unfused_comparison(torch, ftgemm, h, args.steps))]:
             if only and name.split("_")[0] not in only:
                 continue
             cf[name] = fn()

@@ -214,6 +214,31 @@ ftg_status ftg_dgemm_noalloc(ftg_handle h, ftg_op transa, ftg_op transb, int64_t
                              void* stream, const ftg_config* cfg);
 size_t ftg_dgemm_noalloc_max_bytes(void);
 
+/* The unfused comparator: the online ABFT of §5.1 built around an
+ * unprotected GEMM (the paper's "first trial", FT-MKL), for measuring what
+ * fusing saves.  Same arguments and BLAS semantics as ftg_dgemm.  The
+ * checksums are whole-matrix vectors (e^T op(A), op(B) e, C_in e,
+ * e^T C_in), encoded before the product.  The product runs as rank-K_c
+ * updates C += alpha op(A)[:, slab] op(B)[slab, :] (K_c = cfg->interval_k,
+ * a multiple of 128; 0 = one slab) by the unprotected FP64 kernel.  After
+ * each slab, separate memory-bound passes update C^r and C^c, recompute the
+ * reference row sums of C and check them; the reference column sums are
+ * taken only after a row mismatch.  One flagged row and column locate an
+ * element, which the repair kernel corrects as for ftg_dgemm (subtract the
+ * difference, re-verify, else recompute from a fresh dot product).  So one
+ * error per slab of the whole matrix is correctable (§2.1); more are
+ * reported uncorrectable (uncorrectable_policy must be 0).  Thresholds
+ * follow the FP64 rule with the whole row or column as the line.  The
+ * injector draws from the same slot permutation as ftg_dgemm with one slot
+ * per slab: a fault flips a bit of an element of C (or of the maintained
+ * row checksum) in memory at the end of its slab, logged with pflip = the
+ * slab's last step.  With beta != 0 the call keeps a copy of C_in in the
+ * workspace (m * n doubles) for recomputed elements. */
+ftg_status ftg_dgemm_unfused(ftg_handle h, ftg_op transa, ftg_op transb, int64_t m, int64_t n,
+                             int64_t k, double alpha, const double* A, int64_t lda,
+                             const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+                             void* stream, const ftg_config* cfg);
+
 /* Mixed-precision protected GEMM: A, B of type ab_type (FTG_BF16 or
  * FTG_F8_E4M3, OCP e4m3fn), FP32 accumulation on MFMA, FP32 maintained
  * checksums, FP64 reference sums and locate/correct; C of type c_type

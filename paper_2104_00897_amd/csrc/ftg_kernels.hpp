@@ -115,6 +115,47 @@ inline hipError_t launch_dgemm_batched(const BatchLaunch& L, int tile_id, int ta
 inline bool dgemm_tile_intervals(int id) { return id == 2 || id == 3 || id == 5; }
 hipError_t launch_dscale(double* C, int64_t m, int64_t n, int64_t ldc, double beta, hipStream_t s);
 
+// ---- the unfused comparator (unfused.hip)
+// Verification state of one slab: flagged row/column counts and the first
+// (smallest) flagged row and column.
+struct UfStatus {
+    int nr, nc, fi, fj;
+};
+// The lines of one check direction: reference sums, maintained checksums (with
+// alpha applied), magnitude sums, the C_in sums and their absolute sums (NULL
+// when beta = 0), `n` lines of `len` elements after `pend` steps.
+struct UfLines {
+    const double* ref;
+    const double* maint;
+    const double* mag;
+    const double* cin;
+    const double* cina;
+    double beta;
+    int64_t n, len, pend;
+};
+// y_j (+)= sc sum_i S(i, j) v_i and ya_j (+)= |sc| sum_i |S(i, j)| va_i over the
+// columns of a column-major rows x cols S (v, va NULL: ones; ya NULL: skipped);
+// gate != NULL: nothing unless gate->nr > 0
+hipError_t uf_dot_cols(const double* S, int64_t ld, int64_t rows, int64_t cols, const double* v,
+                       const double* va, double sc, double* y, double* ya, int accumulate,
+                       const UfStatus* gate, hipStream_t s);
+// the same over the rows: y_i (+)= sc sum_j S(i, j) v_j, with a partial-sum
+// buffer of uf_rows_part_doubles(rows, cols) doubles
+hipError_t uf_dot_rows(const double* S, int64_t ld, int64_t rows, int64_t cols, const double* v,
+                       const double* va, double sc, double* y, double* ya, int accumulate, double* part,
+                       hipStream_t s);
+size_t uf_rows_part_doubles(int64_t rows, int64_t cols);
+hipError_t uf_fill(double* x, int64_t n, double v, hipStream_t s);
+hipError_t uf_status_clear(UfStatus* st, int n, hipStream_t s);
+hipError_t uf_copy(const double* C, int64_t ldc, int64_t m, int64_t n, double* out, hipStream_t s);
+// flags the lines of one direction (cols = 1: columns, skipped unless a row was flagged)
+hipError_t uf_verify(const UfLines& L, UfStatus* st, int cols, DevReport* rep, hipStream_t s);
+// queues a flagged slab for the repair kernel
+hipError_t uf_handoff(const UfLines& R, const UfLines& Cl, UfStatus* st, int interval, int final,
+                      const double* cin_copy, int64_t m, DevReport* rep, double* maint_r, hipStream_t s);
+hipError_t uf_inject(const InjectParams& ip, double* C, int64_t ldc, int64_t m, int64_t n, int interval,
+                     int64_t plo, int64_t phi, double* maint_r, DevReport* rep, hipStream_t s);
+
 inline void dgemm_tile_shape(int id, int* bm, int* bn, int* bk)
 {
     *bk = 16;

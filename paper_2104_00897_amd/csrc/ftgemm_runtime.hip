@@ -534,6 +534,137 @@ ftg_status ftg_dgemm_noalloc(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int6
 
 size_t ftg_dgemm_noalloc_max_bytes(void) { return kNoallocScratchBytes; }
 
+ftg_status ftg_dgemm_unfused(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n, int64_t k,
+                             double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+                             double beta, double* C, int64_t ldc, void* stream, const ftg_config* cfg)
+{
+    if (!h) return FTG_ERR_INVALID_ARG;
+    ftg_status st = check_gemm(h, ta, tb, m, n, k, lda, ldb, ldc, cfg);
+    if (st != FTG_OK) return st;
+    if (cfg && cfg->inject && cfg->inject->bit_hi > 63) return set_err(h, 20);
+    if (cfg && cfg->uncorrectable_policy != 0) return FTG_ERR_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    if (m == 0 || n == 0 || ((alpha == 0.0 || k == 0) && beta == 1.0)) return FTG_OK;
+    if (alpha == 0.0 || k == 0)
+        return ftg::launch_dscale(C, m, n, ldc, beta, s) == hipSuccess ? FTG_OK : FTG_ERR_HIP;
+    if (m >= (int64_t(1) << 31) || n >= (int64_t(1) << 31) || k >= (int64_t(1) << 31) ||
+        lda >= (1 << 20) || ldb >= (1 << 20) || ldc >= (1 << 20))
+        return FTG_ERR_UNSUPPORTED;
+    const bool abft = !cfg || cfg->abft;
+    const int64_t kc = (cfg && cfg->interval_k > 0 && cfg->interval_k < k) ? cfg->interval_k : k;
+    const int64_t n_int = (k + kc - 1) / kc;
+    if (n_int >= (int64_t(1) << 20)) return FTG_ERR_UNSUPPORTED;
+    int tile = cfg && cfg->tile ? cfg->tile : 0;
+    if (!tile) {
+        tile = h->tune[FTG_F64][bucket(m)][bucket(n)][bucket(kc)];
+        if (!tile) tile = heuristic_tile_f64(m, n, kc, false);
+    }
+    int bm, bn, bk;
+    ftg::dgemm_tile_shape(tile, &bm, &bn, &bk);
+    if (bm == 0) return set_err(h, 20);
+
+    ftg::DGemmArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.C = C;
+    a.lda = (int)lda; a.ldb = (int)ldb; a.ldc = (int)ldc;
+    a.m = (int)m; a.n = (int)n;
+    a.tiles_m = (int)((m + bm - 1) / bm);
+    a.tiles_n = (int)((n + bn - 1) / bn);
+    a.ta = ta == FTG_OP_T; a.tb = tb == FTG_OP_T;
+    a.alpha = alpha;
+    a.rep = h->rep;
+    a.bm = bm; a.bn = bn;
+    // the product of one slab (rank-kc update) by the unprotected kernel
+    auto slab_gemm = [&](int64_t p0, int64_t len, double b) {
+        a.A = a.ta ? A + p0 : A + p0 * lda;
+        a.B = a.tb ? B + p0 * ldb : B + p0;
+        a.k = (int)len; a.kc = (int)len;
+        a.beta = b;
+        a.lds_direct = ftg::lds_direct_ok(a.A, lda, a.B, ldb);
+        return ftg::launch_dgemm(a, tile, false, s);
+    };
+    if (!abft) {
+        for (int64_t t = 0; t < n_int; ++t) {
+            const int64_t p0 = t * kc, len = std::min(kc, k - p0);
+            if (slab_gemm(p0, len, t == 0 ? beta : 1.0) != hipSuccess) return FTG_ERR_HIP;
+        }
+        return FTG_OK;
+    }
+    ftg::InjectParams ip;
+    std::memset(&ip, 0, sizeof(ip));
+    if (cfg && cfg->inject && !ftg::make_inject(cfg->inject, m, n, k, n_int, 40, 63, &ip, 0, false))
+        return FTG_ERR_UNSUPPORTED;
+
+    // workspace: checksum vectors, reference sums, partial sums, C_in copy, slab states
+    const bool cin = beta != 0.0;
+    const int64_t mx = std::max(m, n);
+    size_t part = ftg::uf_rows_part_doubles(k, mx);
+    part = std::max(part, ftg::uf_rows_part_doubles(mx, std::max(n, kc)));
+    size_t off = 0;
+    auto take = [&](size_t doubles) { const size_t at = off; off += (doubles + 31) / 32 * 32; return at; };
+    const size_t o_ea = take(k), o_eaa = take(k), o_be = take(k), o_bea = take(k);
+    const size_t o_er = take(m), o_mr = take(m), o_ec = take(n), o_mc = take(n);
+    const size_t o_rs = take(m), o_cs = take(n);
+    const size_t o_cr = take(cin ? m : 0), o_cra = take(cin ? m : 0);
+    const size_t o_cc = take(cin ? n : 0), o_cca = take(cin ? n : 0);
+    const size_t o_part = take(part);
+    const size_t o_copy = take(cin ? (size_t)m * n : 0);
+    const size_t o_st = take((size_t)n_int * 2);
+    if ((st = ensure_work(h, off * sizeof(double), s)) != FTG_OK) return st;
+    double* w = (double*)h->d_work;
+    double *ea = w + o_ea, *eaa = w + o_eaa, *be = w + o_be, *bea = w + o_bea;
+    double *er = w + o_er, *mr = w + o_mr, *ec = w + o_ec, *mc = w + o_mc, *rs = w + o_rs, *cs = w + o_cs;
+    double *pw = w + o_part, *copy = cin ? w + o_copy : nullptr;
+    auto* sts = (ftg::UfStatus*)(w + o_st);
+    const int ita = a.ta, itb = a.tb;
+    hipError_t e = ftg::uf_status_clear(sts, (int)n_int, s);
+    // T_enc: e^T op(A) and op(B) e (k-vectors with their absolute sums) ...
+    if (e == hipSuccess)
+        e = ita ? ftg::uf_dot_rows(A, lda, k, m, nullptr, nullptr, 1.0, ea, eaa, 0, pw, s)
+                : ftg::uf_dot_cols(A, lda, m, k, nullptr, nullptr, 1.0, ea, eaa, 0, nullptr, s);
+    if (e == hipSuccess)
+        e = itb ? ftg::uf_dot_cols(B, ldb, n, k, nullptr, nullptr, 1.0, be, bea, 0, nullptr, s)
+                : ftg::uf_dot_rows(B, ldb, k, n, nullptr, nullptr, 1.0, be, bea, 0, pw, s);
+    // ... and C_in e, e^T C_in (kept with a copy of C_in for recomputed elements)
+    if (e == hipSuccess && cin) e = ftg::uf_dot_rows(C, ldc, m, n, nullptr, nullptr, 1.0, w + o_cr, w + o_cra, 0, pw, s);
+    if (e == hipSuccess && cin)
+        e = ftg::uf_dot_cols(C, ldc, m, n, nullptr, nullptr, 1.0, w + o_cc, w + o_cca, 0, nullptr, s);
+    if (e == hipSuccess && cin) e = ftg::uf_copy(C, ldc, m, n, copy, s);
+    if (e == hipSuccess) e = ftg::uf_fill(er, (int64_t)(o_mc + n - o_er), 0.0, s);  // er, mr, ec, mc
+    ftg::UfLines Lr{rs, er, mr, cin ? w + o_cr : nullptr, cin ? w + o_cra : nullptr, beta, m, n, 0};
+    ftg::UfLines Lc{cs, ec, mc, cin ? w + o_cc : nullptr, cin ? w + o_cca : nullptr, beta, n, m, 0};
+    ftg::RepairProblem rp;
+    std::memset(&rp, 0, sizeof(rp));
+    rp.A = A; rp.B = B; rp.C = C;
+    rp.lda = lda; rp.ldb = ldb; rp.ldc = ldc;
+    rp.ta = ita; rp.tb = itb; rp.correct_policy = cfg ? cfg->correct_policy : 0;
+    rp.ab_type = FTG_F64; rp.c_type = FTG_F64;
+    rp.alpha = alpha; rp.beta = beta;
+    for (int64_t t = 0; t < n_int && e == hipSuccess; ++t) {
+        const int64_t p0 = t * kc, p1 = std::min(k, p0 + kc), len = p1 - p0;
+        // the rank-kc update of C by the unprotected product
+        if (slab_gemm(p0, len, t == 0 ? beta : 1.0) != hipSuccess) return FTG_ERR_HIP;
+        // T_update: C^r += alpha op(A)[:, slab] (op(B) e)[slab], C^c += alpha (e^T op(A))[slab] op(B)[slab, :]
+        e = ita ? ftg::uf_dot_cols(A + p0, lda, len, m, be + p0, bea + p0, alpha, er, mr, 1, nullptr, s)
+                : ftg::uf_dot_rows(A + p0 * lda, lda, m, len, be + p0, bea + p0, alpha, er, mr, 1, pw, s);
+        if (e == hipSuccess)
+            e = itb ? ftg::uf_dot_rows(B + p0 * ldb, ldb, n, len, ea + p0, eaa + p0, alpha, ec, mc, 1, pw, s)
+                    : ftg::uf_dot_cols(B + p0, ldb, len, n, ea + p0, eaa + p0, alpha, ec, mc, 1, nullptr, s);
+        if (e == hipSuccess && ip.on) e = ftg::uf_inject(ip, C, ldc, m, n, (int)t, p0, p1, er, h->rep, s);
+        // T_ref: reference row sums, checked; column sums only after a row mismatch
+        Lr.pend = Lc.pend = p1;
+        if (e == hipSuccess) e = ftg::uf_dot_rows(C, ldc, m, n, nullptr, nullptr, 1.0, rs, nullptr, 0, pw, s);
+        if (e == hipSuccess) e = ftg::uf_verify(Lr, sts + t, 0, h->rep, s);
+        if (e == hipSuccess) e = ftg::uf_dot_cols(C, ldc, m, n, nullptr, nullptr, 1.0, cs, nullptr, 0, sts + t, s);
+        if (e == hipSuccess) e = ftg::uf_verify(Lc, sts + t, 1, h->rep, s);
+        if (e == hipSuccess)
+            e = ftg::uf_handoff(Lr, Lc, sts + t, (int)t, t == n_int - 1, copy, m, h->rep, er, s);
+        rp.k = p1;
+        if (e == hipSuccess) e = ftg::launch_repair(h->rep, rp, nullptr, s);
+    }
+    return e == hipSuccess ? FTG_OK : FTG_ERR_HIP;
+}
+
 ftg_status ftg_workspace_reserve(ftg_handle h, size_t bytes)
 {
     if (!h) return FTG_ERR_INVALID_ARG;

@@ -71,7 +71,7 @@ EXPORTS = [
     "ftg_batched_reserve", "ftg_report_read", "ftg_report_reset", "ftg_last_error_arg",
     "ftg_tile_info", "ftg_tune_set", "ftg_tune_get", "ftg_timing_enable", "ftg_timing_read",
     "ftg_status_string", "ftg_dgemm_noalloc", "ftg_dgemm_noalloc_max_bytes",
-    "ftg_workspace_reserve", "ftg_default_lambda",
+    "ftg_workspace_reserve", "ftg_default_lambda", "ftg_dgemm_unfused",
 ]
 
 _lib = None
@@ -92,6 +92,7 @@ def load() -> ct.CDLL:
     lib.ftg_dgemm.argtypes = [h, i32, i32, i64, i64, i64, ct.c_double, vp, i64, vp, i64,
                               ct.c_double, vp, i64, vp, ct.POINTER(Config)]
     lib.ftg_dgemm_noalloc.argtypes = lib.ftg_dgemm.argtypes
+    lib.ftg_dgemm_unfused.argtypes = lib.ftg_dgemm.argtypes
     lib.ftg_dgemm_noalloc_max_bytes.argtypes = []
     lib.ftg_workspace_reserve.argtypes = [h, ct.c_size_t]
     lib.ftg_gemm_ex.argtypes = [h, i32, i32, i64, i64, i64, i32, i32, vp, vp, ct.c_float, vp, i64,
@@ -197,6 +198,13 @@ class Handle:
                                         beta, C_ptr, ldc, stream,
                                         ct.byref(cfg) if cfg is not None else None)
         self._check(st, "ftg_dgemm_noalloc")
+
+    def dgemm_unfused(self, ta, tb, m, n, k, alpha, A_ptr, lda, B_ptr, ldb, beta, C_ptr, ldc,
+                      stream=None, cfg=None):
+        st = self.lib.ftg_dgemm_unfused(self.h, ta, tb, m, n, k, alpha, A_ptr, lda, B_ptr, ldb,
+                                        beta, C_ptr, ldc, stream,
+                                        ct.byref(cfg) if cfg is not None else None)
+        self._check(st, "ftg_dgemm_unfused")
 
     def workspace_reserve(self, nbytes: int):
         self._check(self.lib.ftg_workspace_reserve(self.h, nbytes), "ftg_workspace_reserve")
@@ -325,6 +333,18 @@ def gemm_f64(handle: Handle, A, B, C, alpha=1.0, beta=0.0, ta=OP_N, tb=OP_N, cfg
     n = n if n is not None else (rows_b if tb else cols_b)
     handle.dgemm(ta, tb, m, n, k, alpha, ptr(A), max(1, rows_a), ptr(B), max(1, rows_b), beta,
                  ptr(C), max(1, C.shape[1]), current_stream_ptr(), cfg)
+    return C
+
+
+def gemm_f64_unfused(handle: Handle, A, B, C, alpha=1.0, beta=0.0, ta=OP_N, tb=OP_N, cfg=None):
+    """The unfused comparator (ftg_dgemm_unfused) on column-major float64 device tensors."""
+    rows_a, cols_a = A.shape[1], A.shape[0]
+    rows_b, cols_b = B.shape[1], B.shape[0]
+    m = cols_a if ta else rows_a
+    k = rows_a if ta else cols_a
+    n = rows_b if tb else cols_b
+    handle.dgemm_unfused(ta, tb, m, n, k, alpha, ptr(A), max(1, rows_a), ptr(B), max(1, rows_b),
+                         beta, ptr(C), max(1, C.shape[1]), current_stream_ptr(), cfg)
     return C
 
 
