@@ -48,7 +48,7 @@ def parse():
     p.add_argument("--no-sweep", action="store_true", help="skip the FP64 size sweep and rank-k shapes")
     p.add_argument("--fp-calls", type=int, default=1000,
                    help="fault-free calls of the BF16/FP8 false-positive campaign")
-    p.add_argument("--only", default="", help="comma list of legs to run among cfg1,cfg3,cfg4,cfg5,unfused")
+    p.add_argument("--only", default="", help="comma list of legs to run among cfg1,cfg3,cfg4,cfg5,unfused,level3")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only copy 1 GiB between device buffers three times (reference for HBM counters)")
     p.add_argument("--tiles", action="store_true", help="time every FP64 tile configuration at --n")
@@ -248,14 +248,30 @@ def cfg3_lowp(torch, ftgemm, h, kind, steps, n=8192, fp_calls=1000):
     rep = h.read()
     fl = 2.0 * n ** 3
     peak = 2500.0 if kind == "bf16" else 5000.0
-    scale = float(sa.item() * sb.item()) if sa is not None else 1.0
+    # the kernels fold the scales into alpha in binary32: alpha s_A s_B
+    scale = float(np.float32(np.float32(sa.item()) * np.float32(sb.item()))) if sa is not None else 1.0
     a = np.abs(lowp_values(torch, dA, sa, kind))
     b = np.abs(lowp_values(torch, dB, sb, kind))
     lam = ftgemm.default_lambda()
     classes = fault_classes(rep, a, b, lam, scale)
+    # error of the FP32 result against the binary64 product of the same values (the
+    # FP64 path, itself held to the oracle at 1e-12): normwise and componentwise
+    f0 = fns["p0"]
+    f0()
+    A64 = (dA.view(torch.bfloat16) if kind == "bf16" else dA.view(torch.float8_e4m3fn)).double()
+    B64 = (dB.view(torch.bfloat16) if kind == "bf16" else dB.view(torch.float8_e4m3fn)).double()
+    C64 = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    M64 = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    ftgemm.gemm_f64(h, A64, B64, C64, scale, 0.0)
+    ftgemm.gemm_f64(h, A64.abs(), B64.abs(), M64, scale, 0.0)
+    torch.cuda.synchronize()
+    diff = dC.double() - C64
+    err = {"normwise_rel": float(torch.linalg.norm(diff) / torch.linalg.norm(C64)),
+           "max_componentwise": float((diff.abs() / M64).max()),
+           "bound_componentwise": 2.0 * (n + 2) * 2.0 ** -24}
+    del A64, B64, C64, M64, diff
     # false-positive campaign: fault-free calls at the default threshold
     h.reset()
-    f0 = fns["p0"]
     for _ in range(fp_calls):
         f0()
     torch.cuda.synchronize()
@@ -267,7 +283,7 @@ def cfg3_lowp(torch, ftgemm, h, kind, steps, n=8192, fp_calls=1000):
             "faults": {"injected": rep.injected, "corrected": rep.corrected_subtract + rep.corrected_recompute,
                        "detected": rep.detected, "uncorrectable": rep.uncorrectable,
                        "per_distinct_flip": classes},
-            "lambda": lam,
+            "lambda": lam, "error_vs_fp64": err,
             "false_positives": {"calls": fp_calls, "flagged_slots": fp.detected,
                                 "checks_per_call": 2 * n * (n // 128),
                                 "max_pass_ratio": fp.max_pass_ratio}}
@@ -375,6 +391,36 @@ def unfused_comparison(torch, ftgemm, h, steps, sizes=(4096, 8192, 16384), kc_on
         print(json.dumps({"unfused_row": row}), file=sys.stderr, flush=True)
         del dA, dB, dC
     return rows
+
+
+def level3_routines(torch, ftgemm, h, steps, n=8192):
+    """FT-DSYMM (C := 1.5 A B + 0.5 C, A symmetric lower) and FT-DTRMM
+    (B := 1.5 op(A) B, A lower, left, NN) at m = n = 8192, U[-1,1], protected
+    with one flip per 2^32 MACs against the same routine with ABFT off.  TFLOP/s
+    count the routine's own multiply-adds: 2 m^2 n for DSYMM, m^2 n for DTRMM."""
+    g = torch.Generator(device="cuda").manual_seed(11)
+    rnd = lambda: torch.rand((n, n), generator=g, device="cuda", dtype=torch.float64) * 2 - 1
+    A, B, C = rnd(), rnd(), rnd()
+    B0 = B.clone()
+    rate = 2.0 ** -32
+    cp = ftgemm.make_config(seed=3, per_mac_rate=rate)
+    cu = ftgemm.make_config(abft=False)
+    out = {}
+    for name, fl, fn in [
+        ("dsymm", 2.0 * n ** 3, lambda c: ftgemm.dsymm_f64(h, A, B0, C, 1.5, 0.5, 0, 0, c)),
+        ("dtrmm", 1.0 * n ** 3, lambda c: (B.copy_(B0), ftgemm.dtrmm_f64(h, A, B, 1.5, 0, 0, 0, 0, c))),
+    ]:
+        h.reset()
+        t = timed_ab(torch, {"p": lambda: fn(cp), "u": lambda: fn(cu)}, max(2, steps // 2), 1)
+        rep = h.read()
+        out[name] = {"m": n, "n": n, "ms_protected": t["p"], "ms_unprotected": t["u"],
+                     "tflops_protected": fl / t["p"] / 1e9, "tflops_unprotected": fl / t["u"] / 1e9,
+                     "overhead_pct": 100.0 * (t["p"] / t["u"] - 1.0),
+                     "faults": {"injected": rep.injected,
+                                "corrected": rep.corrected_subtract + rep.corrected_recompute,
+                                "uncorrectable": rep.uncorrectable}}
+        print(json.dumps({name: out[name]}), file=sys.stderr, flush=True)
+    return out
 
 
 def batched_problem_seed(seed: int, p: int) -> int:
@@ -585,7 +631,8 @@ def main():
                                                         fp_calls=args.fp_calls)),
                          ("cfg4", lambda: cfg4_ftlinear(torch, ftgemm, h, max(2, args.steps // 2))),
                          ("cfg5", lambda: cfg5_batched(torch, ftgemm, h, args.steps)),
-                         ("unfused", lambda: unfused_comparison(torch, ftgemm, h, args.steps))]:
+                         ("unfused", lambda: unfused_comparison(torch, ftgemm, h, args.steps)),
+                         ("level3", lambda: level3_routines(torch, ftgemm, h, args.steps))]:
             if only and name.split("_")[0] not in only:
                 continue
             cf[name] = fn()

@@ -60,6 +60,9 @@ extern "C" {
 #endif
 
 typedef enum { FTG_OP_N = 0, FTG_OP_T = 1 } ftg_op;
+typedef enum { FTG_LEFT = 0, FTG_RIGHT = 1 } ftg_side;
+typedef enum { FTG_LOWER = 0, FTG_UPPER = 1 } ftg_uplo;
+typedef enum { FTG_NON_UNIT = 0, FTG_UNIT = 1 } ftg_diag;
 
 /* operand element types (A and B share one type; C is FTG_F64 or FTG_F32) */
 typedef enum { FTG_F64 = 0, FTG_F32 = 1, FTG_BF16 = 2, FTG_F8_E4M3 = 3 } ftg_dtype;
@@ -238,6 +241,31 @@ ftg_status ftg_dgemm_unfused(ftg_handle h, ftg_op transa, ftg_op transb, int64_t
                              int64_t k, double alpha, const double* A, int64_t lda,
                              const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                              void* stream, const ftg_config* cfg);
+
+/* FT-DSYMM (BLAS dsymm semantics, column-major; §6.2.3: DGEMM's protection
+ * with modified packing): C := alpha A B + beta C (side = FTG_LEFT, A m x m)
+ * or alpha B A + beta C (FTG_RIGHT, A n x n), A symmetric with only the
+ * `uplo` triangle read.  A is first expanded into a dense copy in the
+ * handle's workspace; the product then runs as one ftg_dgemm on it, with its
+ * checksums, verification, correction, injection (cfg->inject) and report.
+ * xerbla positions: 1 side, 2 uplo, 3 m, 4 n, 7 lda, 9 ldb, 12 ldc. */
+ftg_status ftg_dsymm(ftg_handle h, ftg_side side, ftg_uplo uplo, int64_t m, int64_t n, double alpha,
+                     const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                     int64_t ldc, void* stream, const ftg_config* cfg);
+
+/* FT-DTRMM (BLAS dtrmm semantics; §6.2.3): B := alpha op(A) B (FTG_LEFT,
+ * A m x m) or alpha B op(A) (FTG_RIGHT, A n x n), A triangular (`uplo`
+ * triangle read; FTG_UNIT: the diagonal is taken as 1 and not read).  A is
+ * expanded with zeros into a dense copy and B copied into the workspace; B
+ * is then overwritten by protected products over blocks of 1024 output rows
+ * (left) or columns (right), each with k cut to the nonzero part of op(A),
+ * so about half the multiply-adds of a dense product run.  Every block is
+ * one ftg_dgemm with `cfg` (an injector config applies to each block).
+ * alpha = 0 sets B to 0 without reading A.  xerbla positions: 1 side,
+ * 2 uplo, 3 transa, 4 diag, 5 m, 6 n, 9 lda, 11 ldb. */
+ftg_status ftg_dtrmm(ftg_handle h, ftg_side side, ftg_uplo uplo, ftg_op transa, ftg_diag diag, int64_t m,
+                     int64_t n, double alpha, const double* A, int64_t lda, double* B, int64_t ldb, void* stream,
+                     const ftg_config* cfg);
 
 /* Mixed-precision protected GEMM: A, B of type ab_type (FTG_BF16 or
  * FTG_F8_E4M3, OCP e4m3fn), FP32 accumulation on MFMA, FP32 maintained

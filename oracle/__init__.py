@@ -17,6 +17,8 @@ Functions and the passages of the paper (Zhai et al., FT-BLAS, ICS'21) they foll
   flip64/flip32 single-bit flips of a value                (fault model, §1)
   splitmix64    counter-based generator (Steele et al. 2014)
   tau / gamma   round-off threshold (reading of §2.1's "round-off threshold")
+  dsymm / dtrmm the Level-3 routines of §6.2.3 that run on the protected
+                product, by their plain definitions
 """
 from __future__ import annotations
 
@@ -116,6 +118,12 @@ def _load():
     lib.ftgo_abft.argtypes = [ct.POINTER(_Params), dp, dp, dp, ct.POINTER(_Fault), i64,
                               ct.POINTER(_Record), i64, ct.POINTER(_Counts)]
     lib.ftgo_abft.restype = ct.c_int
+    lib.ftgo_dsymm.argtypes = [ct.c_int, ct.c_int, i64, i64, ct.c_double, dp, i64, dp, i64, ct.c_double,
+                               dp, i64]
+    lib.ftgo_dsymm.restype = ct.c_int
+    lib.ftgo_dtrmm.argtypes = [ct.c_int, ct.c_int, ct.c_int, ct.c_int, i64, i64, ct.c_double, dp, i64,
+                               dp, i64]
+    lib.ftgo_dtrmm.restype = ct.c_int
     _lib = lib
     return lib
 
@@ -255,3 +263,29 @@ def abft(A, B, C=None, alpha=1.0, beta=0.0, ta=0, tb=0, bm=128, bn=128, kc=0, pl
                for r in recs[:min(cap, cnt.n_records)]]
     counts = {f: getattr(cnt, f) for f, _ in _Counts._fields_}
     return C, records, counts
+
+
+def dsymm(A, B, C=None, alpha=1.0, beta=0.0, side=0, uplo=0):
+    """C := alpha A B + beta C (side 0) or alpha B A + beta C (side 1), A symmetric
+    with only its lower (uplo 0) or upper (uplo 1) triangle read."""
+    A = _f64(A); B = _f64(B)
+    m, n = B.shape
+    C = np.zeros((m, n), order="F") if C is None else _f64(C).copy(order="F")
+    info = _load().ftgo_dsymm(side, uplo, m, n, alpha, _dptr(A), _ld(A), _dptr(B), _ld(B), beta,
+                              _dptr(C), _ld(C))
+    if info:
+        raise ValueError(f"ftgo_dsymm: invalid argument {info}")
+    return C
+
+
+def dtrmm(A, B, alpha=1.0, side=0, uplo=0, ta=0, diag=0):
+    """B := alpha op(A) B (side 0) or alpha B op(A) (side 1), A triangular (uplo 0
+    lower, 1 upper; diag 1 = unit, diagonal not read); returns the new B."""
+    A = _f64(A)
+    B = _f64(B).copy(order="F")
+    m, n = B.shape
+    info = _load().ftgo_dtrmm(side, uplo, ta, diag, m, n, alpha, _dptr(A), _ld(A), _dptr(B), _ld(B))
+    if info:
+        raise ValueError(f"ftgo_dtrmm: invalid argument {info}")
+    return B
+

@@ -613,3 +613,94 @@ int ftgo_abft(const ftgo_params* P, const double* A, const double* B, double* C,
     free(sub);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* 6. Level-3 routines that run on the protected product (§6.2.3): their    */
+/*    plain definitions, reading only the referenced triangle of A.        */
+/*    side 0 = left, 1 = right; uplo 0 = lower, 1 = upper; diag 1 = unit.   */
+/* ------------------------------------------------------------------------ */
+
+/* element (i, j) of a symmetric matrix stored in one triangle */
+static double sym_at(int uplo, const double* A, int64_t lda, int64_t i, int64_t j)
+{
+    int stored = uplo == 0 ? i >= j : i <= j;
+    return stored ? A[i + j * lda] : A[j + i * lda];
+}
+
+/* C := alpha A B + beta C (left, A m x m) or alpha B A + beta C (right, A n x n) */
+int ftgo_dsymm(int side, int uplo, int64_t m, int64_t n, double alpha, const double* A, int64_t lda,
+               const double* B, int64_t ldb, double beta, double* C, int64_t ldc)
+{
+    if (side != 0 && side != 1) return 1;
+    if (uplo != 0 && uplo != 1) return 2;
+    if (m < 0) return 3;
+    if (n < 0) return 4;
+    if (lda < max64(1, side == 0 ? m : n)) return 7;
+    if (ldb < max64(1, m)) return 9;
+    if (ldc < max64(1, m)) return 12;
+    if (m == 0 || n == 0 || (alpha == 0.0 && beta == 1.0)) return 0;
+    int64_t k = side == 0 ? m : n;
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n; ++j) {
+        for (int64_t i = 0; i < m; ++i) {
+            double s = 0.0;
+            if (alpha != 0.0)
+                for (int64_t p = 0; p < k; ++p)
+                    s = s + (side == 0 ? sym_at(uplo, A, lda, i, p) * B[p + j * ldb]
+                                       : B[i + p * ldb] * sym_at(uplo, A, lda, p, j));
+            double* c = &C[i + j * ldc];
+            *c = (beta == 0.0) ? alpha * s : alpha * s + beta * (*c);
+        }
+    }
+    return 0;
+}
+
+/* element (i, j) of op(A) for a triangular A: 0 outside the stored triangle,
+ * 1 on a unit diagonal; *nz = 0 where the element is an implicit zero */
+static double tri_op_at(int uplo, int ta, int diag, const double* A, int64_t lda, int64_t i, int64_t j, int* nz)
+{
+    int64_t r = ta ? j : i, c = ta ? i : j; /* position in the stored matrix */
+    *nz = 1;
+    if (r == c) return diag ? 1.0 : A[r + c * lda];
+    if (uplo == 0 ? r > c : r < c) return A[r + c * lda];
+    *nz = 0;
+    return 0.0;
+}
+
+/* B := alpha op(A) B (left, A m x m) or alpha B op(A) (right, A n x n); only
+ * the nonzero terms of op(A) enter the sums (ascending p) */
+int ftgo_dtrmm(int side, int uplo, int ta, int diag, int64_t m, int64_t n, double alpha, const double* A,
+               int64_t lda, double* B, int64_t ldb)
+{
+    if (side != 0 && side != 1) return 1;
+    if (uplo != 0 && uplo != 1) return 2;
+    if (ta != 0 && ta != 1) return 3;
+    if (diag != 0 && diag != 1) return 4;
+    if (m < 0) return 5;
+    if (n < 0) return 6;
+    if (lda < max64(1, side == 0 ? m : n)) return 9;
+    if (ldb < max64(1, m)) return 11;
+    if (m == 0 || n == 0) return 0;
+    double* T = (double*)malloc(sizeof(double) * (size_t)(m * n));
+    if (!T) return -2;
+    int64_t k = side == 0 ? m : n;
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n; ++j) {
+        for (int64_t i = 0; i < m; ++i) {
+            double s = 0.0;
+            if (alpha != 0.0)
+                for (int64_t p = 0; p < k; ++p) {
+                    int nz;
+                    double a = side == 0 ? tri_op_at(uplo, ta, diag, A, lda, i, p, &nz)
+                                         : tri_op_at(uplo, ta, diag, A, lda, p, j, &nz);
+                    if (!nz) continue;
+                    s = s + (side == 0 ? a * B[p + j * ldb] : B[i + p * ldb] * a);
+                }
+            T[i + j * m] = alpha * s;
+        }
+    }
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < m; ++i) B[i + j * ldb] = T[i + j * m];
+    free(T);
+    return 0;
+}

@@ -156,6 +156,15 @@ hipError_t uf_handoff(const UfLines& R, const UfLines& Cl, UfStatus* st, int int
 hipError_t uf_inject(const InjectParams& ip, double* C, int64_t ldc, int64_t m, int64_t n, int interval,
                      int64_t plo, int64_t phi, double* maint_r, DevReport* rep, hipStream_t s);
 
+// Dense column-major copy out (ld ldo) of an m x n block of C.
+hipError_t uf_copy2d(const double* C, int64_t ldc, int64_t m, int64_t n, double* out, int64_t ldo, hipStream_t s);
+
+// ---- packing of symmetric / triangular operands (level3.hip)
+hipError_t launch_pack_sym(const double* A, int64_t lda, int64_t n, int lower, double* out, int64_t ldo,
+                           hipStream_t s);
+hipError_t launch_pack_tri(const double* A, int64_t lda, int64_t n, int lower, int unit, double* out, int64_t ldo,
+                           hipStream_t s);
+
 inline void dgemm_tile_shape(int id, int* bm, int* bn, int* bk)
 {
     *bk = 16;

@@ -665,6 +665,109 @@ ftg_status ftg_dgemm_unfused(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int6
     return e == hipSuccess ? FTG_OK : FTG_ERR_HIP;
 }
 
+// ---------------------------------------------------------------- FT-DSYMM, FT-DTRMM
+// Both pack the symmetric or triangular operand into a dense copy at the front
+// of the workspace and run the protected GEMM on it (§6.2.3: DGEMM's scheme
+// with modified packing); the encode passes of those products use the rest of
+// the workspace, sized up front so that nothing is reallocated in between.
+static int64_t even_ld(int64_t x) { return std::max<int64_t>(2, (x + 1) / 2 * 2); }
+
+// Upper bound of one protected product's encode-pass bytes (the smallest tile).
+static size_t encode_bound(int64_t m, int64_t n, int64_t k)
+{
+    return dencode_bytes(m, n, k, 64, 64);
+}
+
+ftg_status ftg_dsymm(ftg_handle h, ftg_side side, ftg_uplo uplo, int64_t m, int64_t n, double alpha,
+                     const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                     int64_t ldc, void* stream, const ftg_config* cfg)
+{
+    if (!h) return FTG_ERR_INVALID_ARG;
+    if (side != FTG_LEFT && side != FTG_RIGHT) return set_err(h, 1);
+    if (uplo != FTG_LOWER && uplo != FTG_UPPER) return set_err(h, 2);
+    if (m < 0) return set_err(h, 3);
+    if (n < 0) return set_err(h, 4);
+    const int64_t ka = side == FTG_LEFT ? m : n;
+    if (lda < std::max<int64_t>(1, ka)) return set_err(h, 7);
+    if (ldb < std::max<int64_t>(1, m)) return set_err(h, 9);
+    if (ldc < std::max<int64_t>(1, m)) return set_err(h, 12);
+    if (m == 0 || n == 0 || (alpha == 0.0 && beta == 1.0)) return FTG_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (alpha == 0.0) return ftg::launch_dscale(C, m, n, ldc, beta, s) == hipSuccess ? FTG_OK : FTG_ERR_HIP;
+    if (ka >= (1 << 20)) return FTG_ERR_UNSUPPORTED;
+    const int64_t ldp = even_ld(ka);
+    const size_t pack = align256((size_t)ldp * ka * sizeof(double));
+    const size_t enc = encode_bound(m, n, ka);
+    ftg_status st = ensure_work(h, pack + enc, s);
+    if (st != FTG_OK) return st;
+    double* Af = (double*)h->d_work;
+    if (ftg::launch_pack_sym(A, lda, ka, uplo == FTG_LOWER, Af, ldp, s) != hipSuccess) return FTG_ERR_HIP;
+    const EncodeBuffer eb{(double*)(h->d_work + pack), enc};
+    if (side == FTG_LEFT)
+        return dgemm_impl(h, FTG_OP_N, FTG_OP_N, m, n, m, alpha, Af, ldp, B, ldb, beta, C, ldc, stream, cfg, eb);
+    return dgemm_impl(h, FTG_OP_N, FTG_OP_N, m, n, n, alpha, B, ldb, Af, ldp, beta, C, ldc, stream, cfg, eb);
+}
+
+ftg_status ftg_dtrmm(ftg_handle h, ftg_side side, ftg_uplo uplo, ftg_op transa, ftg_diag diag, int64_t m,
+                     int64_t n, double alpha, const double* A, int64_t lda, double* B, int64_t ldb, void* stream,
+                     const ftg_config* cfg)
+{
+    if (!h) return FTG_ERR_INVALID_ARG;
+    if (side != FTG_LEFT && side != FTG_RIGHT) return set_err(h, 1);
+    if (uplo != FTG_LOWER && uplo != FTG_UPPER) return set_err(h, 2);
+    if (transa != FTG_OP_N && transa != FTG_OP_T) return set_err(h, 3);
+    if (diag != FTG_NON_UNIT && diag != FTG_UNIT) return set_err(h, 4);
+    if (m < 0) return set_err(h, 5);
+    if (n < 0) return set_err(h, 6);
+    const int64_t ka = side == FTG_LEFT ? m : n;
+    if (lda < std::max<int64_t>(1, ka)) return set_err(h, 9);
+    if (ldb < std::max<int64_t>(1, m)) return set_err(h, 11);
+    if (m == 0 || n == 0) return FTG_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (alpha == 0.0) return ftg::launch_dscale(B, m, n, ldb, 0.0, s) == hipSuccess ? FTG_OK : FTG_ERR_HIP;
+    if (ka >= (1 << 20) || m >= (1 << 20)) return FTG_ERR_UNSUPPORTED;
+    const int64_t ldp = even_ld(ka), ldq = even_ld(m);
+    const size_t pack = align256((size_t)ldp * ka * sizeof(double));
+    const size_t copy = align256((size_t)ldq * n * sizeof(double));
+    const size_t enc = encode_bound(m, n, ka);
+    ftg_status st = ensure_work(h, pack + copy + enc, s);
+    if (st != FTG_OK) return st;
+    double* Af = (double*)h->d_work;
+    double* Bc = (double*)(h->d_work + pack);
+    if (ftg::launch_pack_tri(A, lda, ka, uplo == FTG_LOWER, diag == FTG_UNIT, Af, ldp, s) != hipSuccess)
+        return FTG_ERR_HIP;
+    if (ftg::uf_copy2d(B, ldb, m, n, Bc, ldq, s) != hipSuccess) return FTG_ERR_HIP;
+    const EncodeBuffer eb{(double*)(h->d_work + pack + copy), enc};
+    // op(A) is lower triangular when (lower, N) or (upper, T): row i of op(A) is
+    // nonzero for columns p <= i only; otherwise for p >= i.  The product runs in
+    // blocks of output rows (left) or columns (right) with k cut to the nonzero
+    // range, which halves the multiply-adds of a dense product.
+    const bool lower_eff = (uplo == FTG_LOWER) == (transa == FTG_OP_N);
+    const int64_t nb = 1024;
+    const int ta = transa == FTG_OP_T;
+    // element (r, c) of op(Af) and its address
+    auto opa = [&](int64_t r, int64_t c) { return ta ? Af + c + r * ldp : Af + r + c * ldp; };
+    if (side == FTG_LEFT) {
+        for (int64_t i0 = 0; i0 < m; i0 += nb) {
+            const int64_t rows = std::min(nb, m - i0);
+            const int64_t k0 = lower_eff ? 0 : i0, k1 = lower_eff ? i0 + rows : m;
+            st = dgemm_impl(h, transa, FTG_OP_N, rows, n, k1 - k0, alpha, opa(i0, k0), ldp, Bc + k0, ldq, 0.0,
+                            B + i0, ldb, stream, cfg, eb);
+            if (st != FTG_OK) return st;
+        }
+    } else {
+        for (int64_t j0 = 0; j0 < n; j0 += nb) {
+            const int64_t cols = std::min(nb, n - j0);
+            // column j of op(A) is nonzero for rows p >= j (lower) or p <= j (upper)
+            const int64_t k0 = lower_eff ? j0 : 0, k1 = lower_eff ? n : j0 + cols;
+            st = dgemm_impl(h, FTG_OP_N, transa, m, cols, k1 - k0, alpha, Bc + k0 * ldq, ldq, opa(k0, j0), ldp, 0.0,
+                            B + j0 * ldb, ldb, stream, cfg, eb);
+            if (st != FTG_OK) return st;
+        }
+    }
+    return FTG_OK;
+}
+
 ftg_status ftg_workspace_reserve(ftg_handle h, size_t bytes)
 {
     if (!h) return FTG_ERR_INVALID_ARG;

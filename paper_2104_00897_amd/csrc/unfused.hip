@@ -142,15 +142,15 @@ __global__ void uf_status_clear_kernel(UfStatus* st, int n)
     }
 }
 
-// Copies C_in (column-major m x n) into a dense m x n buffer.
+// Copies a column-major m x n block of C into out (leading dimension ldo).
 __global__ __launch_bounds__(256) void uf_copy_kernel(const double* __restrict__ C, int64_t ldc, int64_t m,
-                                                      int64_t n, double* __restrict__ out)
+                                                      int64_t n, double* __restrict__ out, int64_t ldo)
 {
     const int64_t total = m * n;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = e % m, j = e / m;
-        out[e] = C[i + j * ldc];
+        out[i + j * ldo] = C[i + j * ldc];
     }
 }
 
@@ -297,14 +297,19 @@ hipError_t uf_status_clear(UfStatus* st, int n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t uf_copy(const double* C, int64_t ldc, int64_t m, int64_t n, double* out, hipStream_t s)
+hipError_t uf_copy2d(const double* C, int64_t ldc, int64_t m, int64_t n, double* out, int64_t ldo, hipStream_t s)
 {
     const int64_t total = m * n;
     if (total <= 0) return hipSuccess;
     unsigned g = grid_of(total, 256);
     if (g > 8192) g = 8192;
-    hipLaunchKernelGGL(uf_copy_kernel, dim3(g), dim3(256), 0, s, C, ldc, m, n, out);
+    hipLaunchKernelGGL(uf_copy_kernel, dim3(g), dim3(256), 0, s, C, ldc, m, n, out, ldo);
     return hipGetLastError();
+}
+
+hipError_t uf_copy(const double* C, int64_t ldc, int64_t m, int64_t n, double* out, hipStream_t s)
+{
+    return uf_copy2d(C, ldc, m, n, out, m, s);
 }
 
 hipError_t uf_verify(const UfLines& L, UfStatus* st, int cols, DevReport* rep, hipStream_t s)

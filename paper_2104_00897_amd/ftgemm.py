@@ -17,6 +17,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libftgemm.so")
 
 OP_N, OP_T = 0, 1
+LEFT, RIGHT = 0, 1
+LOWER, UPPER = 0, 1
+NON_UNIT, UNIT = 0, 1
 F64, F32, BF16, F8_E4M3 = 0, 1, 2, 3
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_UNCORRECTED = 0, 1, 2, 3, 4
 KIND_SUBTRACT, KIND_RECOMPUTE, KIND_CHECKSUM_ONLY, KIND_UNCORRECTABLE, KIND_TILE_RECOMPUTED = 1, 2, 3, 4, 5
@@ -71,7 +74,7 @@ EXPORTS = [
     "ftg_batched_reserve", "ftg_report_read", "ftg_report_reset", "ftg_last_error_arg",
     "ftg_tile_info", "ftg_tune_set", "ftg_tune_get", "ftg_timing_enable", "ftg_timing_read",
     "ftg_status_string", "ftg_dgemm_noalloc", "ftg_dgemm_noalloc_max_bytes",
-    "ftg_workspace_reserve", "ftg_default_lambda", "ftg_dgemm_unfused",
+    "ftg_workspace_reserve", "ftg_default_lambda", "ftg_dgemm_unfused", "ftg_dsymm", "ftg_dtrmm",
 ]
 
 _lib = None
@@ -93,6 +96,10 @@ def load() -> ct.CDLL:
                               ct.c_double, vp, i64, vp, ct.POINTER(Config)]
     lib.ftg_dgemm_noalloc.argtypes = lib.ftg_dgemm.argtypes
     lib.ftg_dgemm_unfused.argtypes = lib.ftg_dgemm.argtypes
+    lib.ftg_dsymm.argtypes = [h, i32, i32, i64, i64, ct.c_double, vp, i64, vp, i64, ct.c_double, vp,
+                              i64, vp, ct.POINTER(Config)]
+    lib.ftg_dtrmm.argtypes = [h, i32, i32, i32, i32, i64, i64, ct.c_double, vp, i64, vp, i64, vp,
+                              ct.POINTER(Config)]
     lib.ftg_dgemm_noalloc_max_bytes.argtypes = []
     lib.ftg_workspace_reserve.argtypes = [h, ct.c_size_t]
     lib.ftg_gemm_ex.argtypes = [h, i32, i32, i64, i64, i64, i32, i32, vp, vp, ct.c_float, vp, i64,
@@ -205,6 +212,17 @@ class Handle:
                                         beta, C_ptr, ldc, stream,
                                         ct.byref(cfg) if cfg is not None else None)
         self._check(st, "ftg_dgemm_unfused")
+
+    def dsymm(self, side, uplo, m, n, alpha, A_ptr, lda, B_ptr, ldb, beta, C_ptr, ldc, stream=None,
+              cfg=None):
+        st = self.lib.ftg_dsymm(self.h, side, uplo, m, n, alpha, A_ptr, lda, B_ptr, ldb, beta, C_ptr,
+                                ldc, stream, ct.byref(cfg) if cfg is not None else None)
+        self._check(st, "ftg_dsymm")
+
+    def dtrmm(self, side, uplo, ta, diag, m, n, alpha, A_ptr, lda, B_ptr, ldb, stream=None, cfg=None):
+        st = self.lib.ftg_dtrmm(self.h, side, uplo, ta, diag, m, n, alpha, A_ptr, lda, B_ptr, ldb,
+                                stream, ct.byref(cfg) if cfg is not None else None)
+        self._check(st, "ftg_dtrmm")
 
     def workspace_reserve(self, nbytes: int):
         self._check(self.lib.ftg_workspace_reserve(self.h, nbytes), "ftg_workspace_reserve")
@@ -346,6 +364,24 @@ def gemm_f64_unfused(handle: Handle, A, B, C, alpha=1.0, beta=0.0, ta=OP_N, tb=O
     handle.dgemm_unfused(ta, tb, m, n, k, alpha, ptr(A), max(1, rows_a), ptr(B), max(1, rows_b),
                          beta, ptr(C), max(1, C.shape[1]), current_stream_ptr(), cfg)
     return C
+
+
+def dsymm_f64(handle: Handle, A, B, C, alpha=1.0, beta=0.0, side=LEFT, uplo=LOWER, cfg=None):
+    """C := alpha A B + beta C (LEFT) or alpha B A + beta C (RIGHT) on column-major
+    float64 device tensors; A symmetric, only its `uplo` triangle read."""
+    m, n = C.shape[1], C.shape[0]
+    handle.dsymm(side, uplo, m, n, alpha, ptr(A), max(1, A.shape[1]), ptr(B), max(1, B.shape[1]), beta,
+                 ptr(C), max(1, C.shape[1]), current_stream_ptr(), cfg)
+    return C
+
+
+def dtrmm_f64(handle: Handle, A, B, alpha=1.0, side=LEFT, uplo=LOWER, ta=OP_N, diag=NON_UNIT, cfg=None):
+    """B := alpha op(A) B (LEFT) or alpha B op(A) (RIGHT) on column-major float64
+    device tensors; A triangular (`uplo` triangle read)."""
+    m, n = B.shape[1], B.shape[0]
+    handle.dtrmm(side, uplo, ta, diag, m, n, alpha, ptr(A), max(1, A.shape[1]), ptr(B), max(1, B.shape[1]),
+                 current_stream_ptr(), cfg)
+    return B
 
 
 def batch_problem(A, B, C, alpha=1.0, beta=0.0, ta=OP_N, tb=OP_N):

@@ -517,3 +517,53 @@ def test_flip32_bit_patterns(x, bit, want):
 def test_flip64_bit_patterns(x, bit, want):
     assert oracle.flip64(x, bit) == want
     assert oracle.flip64(oracle.flip64(x, bit), bit) == x
+
+
+# ----------------------------------------------------------------------------- DSYMM / DTRMM
+def _sym_full(A, uplo):
+    L = np.tril(A) if uplo == 0 else np.triu(A)
+    return L + (L.T - np.diag(np.diag(L)))
+
+
+@pytest.mark.parametrize("side,uplo", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_dsymm_integer_exact(side, uplo):
+    """Only the referenced triangle is read: the other one holds NaN; the result
+    equals the exact integer product with the symmetric matrix built by hand."""
+    rng = np.random.default_rng(50 + side * 2 + uplo)
+    m, n = 23, 17
+    k = m if side == 0 else n
+    A = rng.integers(-8, 9, size=(k, k)).astype(np.float64)
+    full = _sym_full(A, uplo)
+    Anan = A.copy()
+    Anan[np.triu_indices(k, 1) if uplo == 0 else np.tril_indices(k, -1)] = np.nan
+    B = rng.integers(-8, 9, size=(m, n)).astype(np.float64)
+    C = rng.integers(-8, 9, size=(m, n)).astype(np.float64)
+    out = oracle.dsymm(np.asfortranarray(Anan), B, C, 1.5, -2.0, side, uplo)
+    fi, bi = full.astype(np.int64), B.astype(np.int64)
+    prod = (fi @ bi if side == 0 else bi @ fi).astype(np.float64)
+    np.testing.assert_array_equal(out, 1.5 * prod - 2.0 * C)
+
+
+@pytest.mark.parametrize("side", [0, 1])
+@pytest.mark.parametrize("uplo", [0, 1])
+@pytest.mark.parametrize("ta", [0, 1])
+@pytest.mark.parametrize("diag", [0, 1])
+def test_dtrmm_integer_exact(side, uplo, ta, diag):
+    """The other triangle holds NaN and a unit diagonal holds NaN too (neither may
+    be read); the result equals the exact integer product with the triangle."""
+    rng = np.random.default_rng(60 + 8 * side + 4 * uplo + 2 * ta + diag)
+    m, n = 19, 13
+    k = m if side == 0 else n
+    A = rng.integers(-8, 9, size=(k, k)).astype(np.float64)
+    T = np.tril(A) if uplo == 0 else np.triu(A)
+    if diag:
+        np.fill_diagonal(T, 1.0)
+    Anan = A.copy()
+    Anan[np.triu_indices(k, 1) if uplo == 0 else np.tril_indices(k, -1)] = np.nan
+    if diag:
+        np.fill_diagonal(Anan, np.nan)
+    B = rng.integers(-8, 9, size=(m, n)).astype(np.float64)
+    out = oracle.dtrmm(np.asfortranarray(Anan), B, 2.0, side, uplo, ta, diag)
+    op = (T.T if ta else T).astype(np.int64)
+    prod = (op @ B.astype(np.int64) if side == 0 else B.astype(np.int64) @ op).astype(np.float64)
+    np.testing.assert_array_equal(out, 2.0 * prod)
