@@ -394,14 +394,19 @@ def unfused_comparison(torch, ftgemm, h, steps, sizes=(4096, 8192, 16384), kc_on
 
 
 def level3_routines(torch, ftgemm, h, steps, n=8192):
-    """FT-DSYMM (C := 1.5 A B + 0.5 C, A symmetric lower) and FT-DTRMM
-    (B := 1.5 op(A) B, A lower, left, NN) at m = n = 8192, U[-1,1], protected
-    with one flip per 2^32 MACs against the same routine with ABFT off.  TFLOP/s
-    count the routine's own multiply-adds: 2 m^2 n for DSYMM, m^2 n for DTRMM."""
+    """FT-DSYMM (C := 1.5 A B + 0.5 C, A symmetric lower), FT-DTRMM
+    (B := 1.5 op(A) B) and FT-DTRSM (B := 1.5 op(A)^-1 B), A lower, left, no
+    transpose, at m = n = 8192, U[-1,1] operands (for DTRSM a well-conditioned
+    triangle: diagonal in [1, 2], off-diagonal U[-1,1] * 0.5/n), protected with
+    one flip per 2^32 MACs against the same routine with ABFT off.  TFLOP/s
+    count the routine's own multiply-adds: 2 m^2 n for DSYMM, m^2 n for DTRMM
+    and DTRSM."""
     g = torch.Generator(device="cuda").manual_seed(11)
     rnd = lambda: torch.rand((n, n), generator=g, device="cuda", dtype=torch.float64) * 2 - 1
     A, B, C = rnd(), rnd(), rnd()
     B0 = B.clone()
+    At = A * (0.5 / n)
+    At.diagonal().copy_(torch.rand(n, generator=g, device="cuda", dtype=torch.float64) + 1.0)
     rate = 2.0 ** -32
     cp = ftgemm.make_config(seed=3, per_mac_rate=rate)
     cu = ftgemm.make_config(abft=False)
@@ -409,6 +414,7 @@ def level3_routines(torch, ftgemm, h, steps, n=8192):
     for name, fl, fn in [
         ("dsymm", 2.0 * n ** 3, lambda c: ftgemm.dsymm_f64(h, A, B0, C, 1.5, 0.5, 0, 0, c)),
         ("dtrmm", 1.0 * n ** 3, lambda c: (B.copy_(B0), ftgemm.dtrmm_f64(h, A, B, 1.5, 0, 0, 0, 0, c))),
+        ("dtrsm", 1.0 * n ** 3, lambda c: (B.copy_(B0), ftgemm.dtrsm_f64(h, At, B, 1.5, 0, 0, 0, 0, c))),
     ]:
         h.reset()
         t = timed_ab(torch, {"p": lambda: fn(cp), "u": lambda: fn(cu)}, max(2, steps // 2), 1)

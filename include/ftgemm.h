@@ -267,6 +267,29 @@ ftg_status ftg_dtrmm(ftg_handle h, ftg_side side, ftg_uplo uplo, ftg_op transa, 
                      int64_t n, double alpha, const double* A, int64_t lda, double* B, int64_t ldb, void* stream,
                      const ftg_config* cfg);
 
+/* FT-DTRSM (BLAS dtrsm semantics; §3.3.3, §6.2.3): B := alpha op(A)^-1 B
+ * (FTG_LEFT, A m x m) or alpha B op(A)^-1 (FTG_RIGHT, A n x n), A
+ * triangular (`uplo` triangle read; FTG_UNIT: unit diagonal, not read).
+ * The solve is blocked along op(A): every block off the diagonal is an
+ * update B_K := -op(A)[K, D] X_D + beta B_K by the protected GEMM (outer
+ * blocks of 1024, inner blocks of 256), and every 256 x 256 block on the
+ * diagonal is solved by a kernel that checks each right-hand side against
+ * the column checksum relation e^T M Y = e^T R with a rigorous rounding
+ * threshold and solves a mismatching one again (reported as
+ * FTG_KIND_RECOMPUTE with row = -1 and col = the right-hand side; tile_m =
+ * the diagonal block).  The result is only as accurate as op(A) is well
+ * conditioned, as for any triangular solve.  cfg->abft = 0 runs the same
+ * blocking unprotected.  With cfg->inject (target FTG_TARGET_ACC only),
+ * every protected step -- each update and each diagonal solve, numbered s
+ * in execution order -- draws its own plan from seed SplitMix64(seed,
+ * 2^33 + s); a diagonal solve's slots are its right-hand sides, and a flip
+ * hits an unknown right after it is formed.  alpha = 0 sets B to 0.
+ * xerbla positions: 1 side, 2 uplo, 3 transa, 4 diag, 5 m, 6 n, 9 lda,
+ * 11 ldb; 20 for an invalid injector. */
+ftg_status ftg_dtrsm(ftg_handle h, ftg_side side, ftg_uplo uplo, ftg_op transa, ftg_diag diag, int64_t m,
+                     int64_t n, double alpha, const double* A, int64_t lda, double* B, int64_t ldb, void* stream,
+                     const ftg_config* cfg);
+
 /* Mixed-precision protected GEMM: A, B of type ab_type (FTG_BF16 or
  * FTG_F8_E4M3, OCP e4m3fn), FP32 accumulation on MFMA, FP32 maintained
  * checksums, FP64 reference sums and locate/correct; C of type c_type

@@ -18,7 +18,7 @@ Functions and the passages of the paper (Zhai et al., FT-BLAS, ICS'21) they foll
   splitmix64    counter-based generator (Steele et al. 2014)
   tau / gamma   round-off threshold (reading of §2.1's "round-off threshold")
   dsymm / dtrmm the Level-3 routines of §6.2.3 that run on the protected
-                product, by their plain definitions
+  / dtrsm       product, by their plain definitions (dtrsm: substitution)
 """
 from __future__ import annotations
 
@@ -124,6 +124,8 @@ def _load():
     lib.ftgo_dtrmm.argtypes = [ct.c_int, ct.c_int, ct.c_int, ct.c_int, i64, i64, ct.c_double, dp, i64,
                                dp, i64]
     lib.ftgo_dtrmm.restype = ct.c_int
+    lib.ftgo_dtrsm.argtypes = lib.ftgo_dtrmm.argtypes
+    lib.ftgo_dtrsm.restype = ct.c_int
     _lib = lib
     return lib
 
@@ -287,5 +289,17 @@ def dtrmm(A, B, alpha=1.0, side=0, uplo=0, ta=0, diag=0):
     info = _load().ftgo_dtrmm(side, uplo, ta, diag, m, n, alpha, _dptr(A), _ld(A), _dptr(B), _ld(B))
     if info:
         raise ValueError(f"ftgo_dtrmm: invalid argument {info}")
+    return B
+
+
+def dtrsm(A, B, alpha=1.0, side=0, uplo=0, ta=0, diag=0):
+    """B := alpha op(A)^-1 B (side 0) or alpha B op(A)^-1 (side 1) by substitution,
+    A triangular (uplo 0 lower, 1 upper; diag 1 = unit); returns the new B."""
+    A = _f64(A)
+    B = _f64(B).copy(order="F")
+    m, n = B.shape
+    info = _load().ftgo_dtrsm(side, uplo, ta, diag, m, n, alpha, _dptr(A), _ld(A), _dptr(B), _ld(B))
+    if info:
+        raise ValueError(f"ftgo_dtrsm: invalid argument {info}")
     return B
 

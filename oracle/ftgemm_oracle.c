@@ -704,3 +704,58 @@ int ftgo_dtrmm(int side, int uplo, int ta, int diag, int64_t m, int64_t n, doubl
     free(T);
     return 0;
 }
+
+/* B := alpha op(A)^-1 B (left, A m x m) or alpha B op(A)^-1 (right, A n x n),
+ * A triangular: substitution in the order op(A) dictates, one right-hand
+ * side at a time, subtracting the solved terms in ascending index order. */
+int ftgo_dtrsm(int side, int uplo, int ta, int diag, int64_t m, int64_t n, double alpha, const double* A,
+               int64_t lda, double* B, int64_t ldb)
+{
+    if (side != 0 && side != 1) return 1;
+    if (uplo != 0 && uplo != 1) return 2;
+    if (ta != 0 && ta != 1) return 3;
+    if (diag != 0 && diag != 1) return 4;
+    if (m < 0) return 5;
+    if (n < 0) return 6;
+    if (lda < max64(1, side == 0 ? m : n)) return 9;
+    if (ldb < max64(1, m)) return 11;
+    if (m == 0 || n == 0) return 0;
+    /* op(A) is lower triangular when (lower, no transpose) or (upper, transpose) */
+    int lower_op = (uplo == 0) == (ta == 0);
+    if (side == 0) {
+#pragma omp parallel for schedule(static)
+        for (int64_t j = 0; j < n; ++j) {
+            for (int64_t q = 0; q < m; ++q) {
+                int64_t i = lower_op ? q : m - 1 - q;
+                double s = alpha * B[i + j * ldb];
+                int64_t p0 = lower_op ? 0 : i + 1, p1 = lower_op ? i : m;
+                for (int64_t p = p0; p < p1; ++p) {
+                    int nz;
+                    double a = tri_op_at(uplo, ta, diag, A, lda, i, p, &nz);
+                    s = s - a * B[p + j * ldb];
+                }
+                if (!diag) { int nz; s = s / tri_op_at(uplo, ta, diag, A, lda, i, i, &nz); }
+                B[i + j * ldb] = s;
+            }
+        }
+    } else {
+        /* X op(A) = alpha B: column j of X needs the columns p with op(A)(p, j)
+         * nonzero: p > j when op(A) is lower (solve backward), p < j when upper */
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < m; ++i) {
+            for (int64_t q = 0; q < n; ++q) {
+                int64_t j = lower_op ? n - 1 - q : q;
+                double s = alpha * B[i + j * ldb];
+                int64_t p0 = lower_op ? j + 1 : 0, p1 = lower_op ? n : j;
+                for (int64_t p = p0; p < p1; ++p) {
+                    int nz;
+                    double a = tri_op_at(uplo, ta, diag, A, lda, p, j, &nz);
+                    s = s - B[i + p * ldb] * a;
+                }
+                if (!diag) { int nz; s = s / tri_op_at(uplo, ta, diag, A, lda, j, j, &nz); }
+                B[i + j * ldb] = s;
+            }
+        }
+    }
+    return 0;
+}

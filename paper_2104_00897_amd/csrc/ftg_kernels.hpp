@@ -165,6 +165,28 @@ hipError_t launch_pack_sym(const double* A, int64_t lda, int64_t n, int lower, d
 hipError_t launch_pack_tri(const double* A, int64_t lda, int64_t n, int lower, int unit, double* out, int64_t ldo,
                            hipStream_t s);
 
+// ---- FT-DTRSM diagonal-block solve (trsm.hip)
+// Solves M Y = scale * R in place for `count` right-hand sides: M is the
+// nb x nb triangular block with element (r, c) at M[r + c ldm] (trans = 0) or
+// M[c + r ldm] (trans = 1), lower or upper, unit diagonal optional; element
+// (i, c) of R is R[i rs + c cs].  Faults: slots are right-hand sides; records
+// and injection-log entries carry `block` as tile_m and global rows row0 + i.
+struct TrsmDiag {
+    const double* M;
+    int64_t ldm;
+    int nb, trans, lower, unit;
+    double* R;
+    int64_t rs, cs, count;
+    double scale;
+    InjectParams inj;
+    DevReport* rep;
+    int block;
+    int verify;  // 0: no checksum verification (the unprotected solve)
+    int64_t row0;
+};
+int trsm_diag_max_nb();
+hipError_t launch_trsm_diag(const TrsmDiag& d, hipStream_t s);
+
 inline void dgemm_tile_shape(int id, int* bm, int* bn, int* bk)
 {
     *bk = 16;

@@ -768,6 +768,130 @@ ftg_status ftg_dtrmm(ftg_handle h, ftg_side side, ftg_uplo uplo, ftg_op transa, 
     return FTG_OK;
 }
 
+// ---------------------------------------------------------------- FT-DTRSM
+// B := alpha op(A)^-1 B (left) or alpha B op(A)^-1 (right), blocked as in
+// §3.3.3: blocks on the diagonal are solved by the checksum-verified
+// diagonal kernel, every other block of the solve is an update
+// B_K := -op(A)[K, D] X_D + beta B_K on the protected GEMM.  Outer blocks of
+// 1024 make those updates large products; inside an outer block, inner
+// blocks of 256 are solved in turn with smaller updates.  The first update
+// that touches a block applies alpha (as beta); a block that no update
+// touches (the very first one) gets alpha in the diagonal solve.
+ftg_status ftg_dtrsm(ftg_handle h, ftg_side side, ftg_uplo uplo, ftg_op transa, ftg_diag diag, int64_t m,
+                     int64_t n, double alpha, const double* A, int64_t lda, double* B, int64_t ldb, void* stream,
+                     const ftg_config* cfg)
+{
+    if (!h) return FTG_ERR_INVALID_ARG;
+    if (side != FTG_LEFT && side != FTG_RIGHT) return set_err(h, 1);
+    if (uplo != FTG_LOWER && uplo != FTG_UPPER) return set_err(h, 2);
+    if (transa != FTG_OP_N && transa != FTG_OP_T) return set_err(h, 3);
+    if (diag != FTG_NON_UNIT && diag != FTG_UNIT) return set_err(h, 4);
+    if (m < 0) return set_err(h, 5);
+    if (n < 0) return set_err(h, 6);
+    const int64_t ka = side == FTG_LEFT ? m : n;
+    if (lda < std::max<int64_t>(1, ka)) return set_err(h, 9);
+    if (ldb < std::max<int64_t>(1, m)) return set_err(h, 11);
+    if (cfg) {
+        if (cfg->inject && (cfg->inject->target != FTG_TARGET_ACC || cfg->inject->bit_hi > 63 ||
+                            cfg->inject->bit_lo < 0 || cfg->inject->bit_hi < cfg->inject->bit_lo))
+            return set_err(h, 20);
+    }
+    if (m == 0 || n == 0) return FTG_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (alpha == 0.0) return ftg::launch_dscale(B, m, n, ldb, 0.0, s) == hipSuccess ? FTG_OK : FTG_ERR_HIP;
+    if (ka >= (int64_t(1) << 31) || lda >= (1 << 20) || ldb >= (1 << 20)) return FTG_ERR_UNSUPPORTED;
+    const bool abft = !cfg || cfg->abft;
+    const int64_t rhs = side == FTG_LEFT ? n : m;   // right-hand sides
+    const size_t enc = encode_bound(side == FTG_LEFT ? 1024 : m, side == FTG_LEFT ? n : 1024, ka);
+    ftg_status st = ensure_work(h, enc, s);
+    if (st != FTG_OK) return st;
+    const EncodeBuffer eb{(double*)h->d_work, enc};
+    const int ta = transa == FTG_OP_T;
+    // op(A) lower triangular: the solve runs forward (left) / backward (right)
+    const bool lower_eff = (uplo == FTG_LOWER) == (transa == FTG_OP_N);
+    const bool forward = side == FTG_LEFT ? lower_eff : !lower_eff;
+    auto opa = [&](int64_t r, int64_t c) { return ta ? A + c + r * lda : A + r + c * lda; };
+    const int64_t NB = 1024, nbd = ftg::trsm_diag_max_nb();
+    int step = 0;  // protected steps so far: each draws its own injection plan
+    auto step_cfg = [&](ftg_config* c, ftg_inject* in) -> const ftg_config* {
+        if (!cfg) return nullptr;
+        *c = *cfg;
+        if (cfg->inject) {
+            *in = *cfg->inject;
+            in->seed = ftg::splitmix64(cfg->inject->seed, (uint64_t(1) << 33) + (uint64_t)step);
+            c->inject = in;
+        }
+        ++step;
+        return c;
+    };
+    // update of the blocks in [k0, k1) by the solved range [d0, d1)
+    auto update = [&](int64_t k0, int64_t k1, int64_t d0, int64_t d1, double beta) -> ftg_status {
+        if (d1 <= d0) return FTG_OK;
+        ftg_config c;
+        ftg_inject in;
+        const ftg_config* pc = step_cfg(&c, &in);
+        if (side == FTG_LEFT)
+            return dgemm_impl(h, transa, FTG_OP_N, k1 - k0, n, d1 - d0, -1.0, opa(k0, d0), lda, B + d0, ldb, beta,
+                              B + k0, ldb, stream, pc, eb);
+        return dgemm_impl(h, FTG_OP_N, transa, m, k1 - k0, d1 - d0, -1.0, B + d0 * ldb, ldb, opa(d0, k0), lda, beta,
+                          B + k0 * ldb, ldb, stream, pc, eb);
+    };
+    auto solve = [&](int64_t k0, int64_t k1, double scale, int block) -> ftg_status {
+        ftg::TrsmDiag d;
+        std::memset(&d, 0, sizeof(d));
+        // left: M = op(A)[K, K]; right: M = op(A)[K, K]^T (rows of B solved from the right)
+        d.M = A + k0 + k0 * lda;
+        d.ldm = lda;
+        d.nb = (int)(k1 - k0);
+        d.trans = side == FTG_LEFT ? ta : !ta;
+        d.lower = forward;
+        d.unit = diag == FTG_UNIT;
+        d.R = side == FTG_LEFT ? B + k0 : B + k0 * ldb;
+        d.rs = side == FTG_LEFT ? 1 : ldb;
+        d.cs = side == FTG_LEFT ? ldb : 1;
+        d.count = rhs;
+        d.scale = scale;
+        d.rep = h->rep;
+        d.block = block;
+        d.verify = abft;
+        d.row0 = k0;
+        ftg_config c;
+        ftg_inject in;
+        const ftg_config* pc = step_cfg(&c, &in);
+        if (abft && pc && pc->inject &&
+            !ftg::make_inject(pc->inject, d.nb, rhs, d.nb, rhs, 40, 63, &d.inj, 0, false))
+            return FTG_ERR_UNSUPPORTED;
+        return ftg::launch_trsm_diag(d, s) == hipSuccess ? FTG_OK : FTG_ERR_HIP;
+    };
+    // blocks in solve order
+    const int64_t nouter = (ka + NB - 1) / NB;
+    for (int64_t oi = 0; oi < nouter; ++oi) {
+        const int64_t ob = forward ? oi : nouter - 1 - oi;
+        const int64_t K0 = ob * NB, K1 = std::min(ka, K0 + NB);
+        // outer update by everything solved before this block
+        const bool first_outer = oi == 0;
+        if (!first_outer) {
+            st = forward ? update(K0, K1, 0, K0, alpha) : update(K0, K1, K1, ka, alpha);
+            if (st != FTG_OK) return st;
+        }
+        const int64_t ninner = (K1 - K0 + nbd - 1) / nbd;
+        for (int64_t ii = 0; ii < ninner; ++ii) {
+            const int64_t ib = forward ? ii : ninner - 1 - ii;
+            const int64_t k0 = K0 + ib * nbd, k1 = std::min(K1, k0 + nbd);
+            if (ii > 0) {
+                // inner update by the blocks of this outer block solved so far
+                const double beta = first_outer ? alpha : 1.0;
+                st = forward ? update(k0, k1, K0, k0, beta) : update(k0, k1, k1, K1, beta);
+                if (st != FTG_OK) return st;
+            }
+            const double scale = (first_outer && ii == 0) ? alpha : 1.0;
+            st = solve(k0, k1, scale, (int)(k0 / nbd));
+            if (st != FTG_OK) return st;
+        }
+    }
+    return FTG_OK;
+}
+
 ftg_status ftg_workspace_reserve(ftg_handle h, size_t bytes)
 {
     if (!h) return FTG_ERR_INVALID_ARG;

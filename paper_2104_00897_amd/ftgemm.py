@@ -75,6 +75,7 @@ EXPORTS = [
     "ftg_tile_info", "ftg_tune_set", "ftg_tune_get", "ftg_timing_enable", "ftg_timing_read",
     "ftg_status_string", "ftg_dgemm_noalloc", "ftg_dgemm_noalloc_max_bytes",
     "ftg_workspace_reserve", "ftg_default_lambda", "ftg_dgemm_unfused", "ftg_dsymm", "ftg_dtrmm",
+    "ftg_dtrsm",
 ]
 
 _lib = None
@@ -100,6 +101,7 @@ def load() -> ct.CDLL:
                               i64, vp, ct.POINTER(Config)]
     lib.ftg_dtrmm.argtypes = [h, i32, i32, i32, i32, i64, i64, ct.c_double, vp, i64, vp, i64, vp,
                               ct.POINTER(Config)]
+    lib.ftg_dtrsm.argtypes = lib.ftg_dtrmm.argtypes
     lib.ftg_dgemm_noalloc_max_bytes.argtypes = []
     lib.ftg_workspace_reserve.argtypes = [h, ct.c_size_t]
     lib.ftg_gemm_ex.argtypes = [h, i32, i32, i64, i64, i64, i32, i32, vp, vp, ct.c_float, vp, i64,
@@ -223,6 +225,11 @@ class Handle:
         st = self.lib.ftg_dtrmm(self.h, side, uplo, ta, diag, m, n, alpha, A_ptr, lda, B_ptr, ldb,
                                 stream, ct.byref(cfg) if cfg is not None else None)
         self._check(st, "ftg_dtrmm")
+
+    def dtrsm(self, side, uplo, ta, diag, m, n, alpha, A_ptr, lda, B_ptr, ldb, stream=None, cfg=None):
+        st = self.lib.ftg_dtrsm(self.h, side, uplo, ta, diag, m, n, alpha, A_ptr, lda, B_ptr, ldb,
+                                stream, ct.byref(cfg) if cfg is not None else None)
+        self._check(st, "ftg_dtrsm")
 
     def workspace_reserve(self, nbytes: int):
         self._check(self.lib.ftg_workspace_reserve(self.h, nbytes), "ftg_workspace_reserve")
@@ -380,6 +387,15 @@ def dtrmm_f64(handle: Handle, A, B, alpha=1.0, side=LEFT, uplo=LOWER, ta=OP_N, d
     device tensors; A triangular (`uplo` triangle read)."""
     m, n = B.shape[1], B.shape[0]
     handle.dtrmm(side, uplo, ta, diag, m, n, alpha, ptr(A), max(1, A.shape[1]), ptr(B), max(1, B.shape[1]),
+                 current_stream_ptr(), cfg)
+    return B
+
+
+def dtrsm_f64(handle: Handle, A, B, alpha=1.0, side=LEFT, uplo=LOWER, ta=OP_N, diag=NON_UNIT, cfg=None):
+    """B := alpha op(A)^-1 B (LEFT) or alpha B op(A)^-1 (RIGHT) on column-major
+    float64 device tensors; A triangular (`uplo` triangle read)."""
+    m, n = B.shape[1], B.shape[0]
+    handle.dtrsm(side, uplo, ta, diag, m, n, alpha, ptr(A), max(1, A.shape[1]), ptr(B), max(1, B.shape[1]),
                  current_stream_ptr(), cfg)
     return B
 

@@ -567,3 +567,31 @@ def test_dtrmm_integer_exact(side, uplo, ta, diag):
     op = (T.T if ta else T).astype(np.int64)
     prod = (op @ B.astype(np.int64) if side == 0 else B.astype(np.int64) @ op).astype(np.float64)
     np.testing.assert_array_equal(out, 2.0 * prod)
+
+
+@pytest.mark.parametrize("side", [0, 1])
+@pytest.mark.parametrize("uplo", [0, 1])
+@pytest.mark.parametrize("ta", [0, 1])
+@pytest.mark.parametrize("diag", [0, 1])
+def test_dtrsm_recovers_integer_solution(side, uplo, ta, diag):
+    """B = op(T) X (or X op(T)) for an integer X and a triangular T with small
+    integers off the diagonal and a power-of-two (or unit) diagonal: every
+    partial sum of the substitution is an exact integer multiple of a power of
+    two, so the solve must return X bitwise.  The unread triangle holds NaN."""
+    rng = np.random.default_rng(100 + 8 * side + 4 * uplo + 2 * ta + diag)
+    m, n = 17, 11
+    k = m if side == 0 else n
+    A = rng.integers(-3, 4, size=(k, k)).astype(np.float64)
+    np.fill_diagonal(A, rng.choice([-4.0, -2.0, -1.0, 1.0, 2.0, 4.0], size=k))
+    T = np.tril(A) if uplo == 0 else np.triu(A)
+    if diag:
+        np.fill_diagonal(T, 1.0)
+    op = T.T if ta else T
+    X = rng.integers(-5, 6, size=(m, n)).astype(np.float64)
+    B = op @ X if side == 0 else X @ op
+    Anan = A.copy()
+    Anan[np.triu_indices(k, 1) if uplo == 0 else np.tril_indices(k, -1)] = np.nan
+    if diag:
+        np.fill_diagonal(Anan, np.nan)
+    out = oracle.dtrsm(np.asfortranarray(Anan), np.asfortranarray(2.0 * B), 0.5, side, uplo, ta, diag)
+    np.testing.assert_array_equal(out, X)
