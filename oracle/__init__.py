@@ -19,6 +19,9 @@ Functions and the passages of the paper (Zhai et al., FT-BLAS, ICS'21) they foll
   tau / gamma   round-off threshold (reading of §2.1's "round-off threshold")
   dsymm / dtrmm the Level-3 routines of §6.2.3 that run on the protected
   / dtrsm       product, by their plain definitions (dtrsm: substitution)
+  dscal / dnrm2 the Level-1/2 routines protected by duplicated computation
+  / dgemv       (§3.1, §3.2, §4), by their plain BLAS definitions (dnrm2:
+  / dtrsv       exact power-of-two scaling; dtrsv: substitution)
 """
 from __future__ import annotations
 
@@ -126,6 +129,14 @@ def _load():
     lib.ftgo_dtrmm.restype = ct.c_int
     lib.ftgo_dtrsm.argtypes = lib.ftgo_dtrmm.argtypes
     lib.ftgo_dtrsm.restype = ct.c_int
+    lib.ftgo_dscal.argtypes = [i64, ct.c_double, dp, i64]
+    lib.ftgo_dscal.restype = None
+    lib.ftgo_dnrm2.argtypes = [i64, dp, i64]
+    lib.ftgo_dnrm2.restype = ct.c_double
+    lib.ftgo_dgemv.argtypes = [ct.c_int, i64, i64, ct.c_double, dp, i64, dp, i64, ct.c_double, dp, i64]
+    lib.ftgo_dgemv.restype = ct.c_int
+    lib.ftgo_dtrsv.argtypes = [ct.c_int, ct.c_int, ct.c_int, i64, dp, i64, dp, i64]
+    lib.ftgo_dtrsv.restype = ct.c_int
     _lib = lib
     return lib
 
@@ -303,3 +314,56 @@ def dtrsm(A, B, alpha=1.0, side=0, uplo=0, ta=0, diag=0):
         raise ValueError(f"ftgo_dtrsm: invalid argument {info}")
     return B
 
+
+
+def _vec(buf):
+    """1-D float64 copy of a strided-vector buffer."""
+    return np.ascontiguousarray(np.asarray(buf, dtype=np.float64).ravel()).copy()
+
+
+def dscal(buf, n, alpha, incx=1):
+    """x := alpha x over n elements of buf at stride incx (BLAS dscal); returns
+    the new buffer."""
+    x = _vec(buf)
+    if n > 0 and incx > 0 and (n - 1) * incx >= x.size:
+        raise ValueError("dscal: buffer too short")
+    _load().ftgo_dscal(n, alpha, _dptr(x), incx)
+    return x
+
+
+def dnrm2(buf, n, incx=1):
+    """Euclidean norm of n elements of buf at stride incx (BLAS dnrm2)."""
+    x = _vec(buf)
+    if n > 0 and incx > 0 and (n - 1) * incx >= x.size:
+        raise ValueError("dnrm2: buffer too short")
+    return float(_load().ftgo_dnrm2(n, _dptr(x), incx))
+
+
+def dgemv(A, xbuf, ybuf, alpha=1.0, beta=0.0, ta=0, incx=1, incy=1):
+    """y := alpha op(A) x + beta y (BLAS dgemv) on the vectors held in xbuf/ybuf
+    at strides incx/incy (negative: element 0 at the far end); returns the new
+    y buffer."""
+    A = _f64(A)
+    m, n = A.shape
+    x, y = _vec(xbuf), _vec(ybuf)
+    lenx, leny = (m, n) if ta else (n, m)
+    if (lenx - 1) * abs(incx) >= max(x.size, 1) or (leny - 1) * abs(incy) >= max(y.size, 1):
+        raise ValueError("dgemv: vector buffer too short")
+    info = _load().ftgo_dgemv(ta, m, n, alpha, _dptr(A), _ld(A), _dptr(x), incx, beta, _dptr(y), incy)
+    if info:
+        raise ValueError(f"ftgo_dgemv: invalid argument {info}")
+    return y
+
+
+def dtrsv(A, xbuf, uplo=0, ta=0, diag=0, incx=1):
+    """x := op(A)^-1 x (BLAS dtrsv) on the vector held in xbuf at stride incx;
+    returns the new buffer."""
+    A = _f64(A)
+    n = A.shape[0]
+    x = _vec(xbuf)
+    if n and (n - 1) * abs(incx) >= x.size:
+        raise ValueError("dtrsv: vector buffer too short")
+    info = _load().ftgo_dtrsv(uplo, ta, diag, n, _dptr(A), _ld(A), _dptr(x), incx)
+    if info:
+        raise ValueError(f"ftgo_dtrsv: invalid argument {info}")
+    return x

@@ -759,3 +759,108 @@ int ftgo_dtrsm(int side, int uplo, int ta, int diag, int64_t m, int64_t n, doubl
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Level-1 and Level-2 routines that FT-BLAS protects by duplicated
+ * computation (§4), by their plain BLAS definitions.  Vectors are n
+ * elements at stride inc; for a negative stride element 0 sits at the far
+ * end (x + (1 - n) inc), as BLAS defines. */
+
+static const double* vec0c(const double* x, int64_t n, int64_t inc) { return inc > 0 ? x : x + (1 - n) * inc; }
+static double* vec0(double* x, int64_t n, int64_t inc) { return inc > 0 ? x : x + (1 - n) * inc; }
+
+/* x := alpha x (nothing for n <= 0 or incx <= 0): one product per element. */
+void ftgo_dscal(int64_t n, double alpha, double* x, int64_t incx)
+{
+    if (n <= 0 || incx <= 0) return;
+    for (int64_t i = 0; i < n; ++i) x[i * incx] = alpha * x[i * incx];
+}
+
+/* Euclidean norm of n elements at stride incx (0 for n <= 0 or incx <= 0).
+ * NaN if an element is NaN, else +Inf if one is infinite, else
+ * 2^e sqrt(sum_i (x_i 2^-e)^2) with 2^e the power of two of the largest
+ * magnitude.  Scaling by a power of two is exact, so no square overflows
+ * (every scaled element is below 2 in magnitude) and the roundings are
+ * those of the squares, the ascending sum and the square root. */
+double ftgo_dnrm2(int64_t n, const double* x, int64_t incx)
+{
+    if (n <= 0 || incx <= 0) return 0.0;
+    int has_nan = 0, has_inf = 0;
+    double amax = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double v = x[i * incx];
+        if (isnan(v)) has_nan = 1;
+        else if (isinf(v)) has_inf = 1;
+        else if (fabs(v) > amax) amax = fabs(v);
+    }
+    if (has_nan) return NAN;
+    if (has_inf) return INFINITY;
+    if (amax == 0.0) return 0.0;
+    int e = ilogb(amax);
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double t = ldexp(x[i * incx], -e);
+        s = s + t * t;
+    }
+    return ldexp(sqrt(s), e);
+}
+
+/* y := alpha op(A) x + beta y (BLAS dgemv; A m x n column-major; x has n
+ * elements without transpose, m with; y the other count).  Each element is
+ * alpha times the ascending dot product plus beta y_i (y is not read when
+ * beta = 0; A and x are not read when alpha = 0).  Returns the xerbla
+ * position of an invalid argument, 0 otherwise. */
+int ftgo_dgemv(int ta, int64_t m, int64_t n, double alpha, const double* A, int64_t lda, const double* x,
+               int64_t incx, double beta, double* y, int64_t incy)
+{
+    if (ta != 0 && ta != 1) return 1;
+    if (m < 0) return 2;
+    if (n < 0) return 3;
+    if (lda < max64(1, m)) return 6;
+    if (incx == 0) return 8;
+    if (incy == 0) return 11;
+    if (m == 0 || n == 0 || (alpha == 0.0 && beta == 1.0)) return 0;
+    int64_t lenx = ta ? m : n, leny = ta ? n : m;
+    const double* x0 = vec0c(x, lenx, incx);
+    double* y0 = vec0(y, leny, incy);
+    for (int64_t i = 0; i < leny; ++i) {
+        double s = 0.0;
+        if (alpha != 0.0)
+            for (int64_t p = 0; p < lenx; ++p) s = s + (ta ? A[p + i * lda] : A[i + p * lda]) * x0[p * incx];
+        double by = beta == 0.0 ? 0.0 : beta * y0[i * incy];
+        y0[i * incy] = alpha * s + by;
+    }
+    return 0;
+}
+
+/* x := op(A)^-1 x (BLAS dtrsv; A n x n triangular, the `uplo` triangle
+ * read; diag = 1: unit diagonal, not read): substitution in the order op(A)
+ * dictates, subtracting the solved terms in ascending index order, then
+ * dividing by the diagonal. */
+int ftgo_dtrsv(int uplo, int ta, int diag, int64_t n, const double* A, int64_t lda, double* x, int64_t incx)
+{
+    if (uplo != 0 && uplo != 1) return 1;
+    if (ta != 0 && ta != 1) return 2;
+    if (diag != 0 && diag != 1) return 3;
+    if (n < 0) return 4;
+    if (lda < max64(1, n)) return 6;
+    if (incx == 0) return 8;
+    if (n == 0) return 0;
+    double* x0 = vec0(x, n, incx);
+    int lower_op = (uplo == 0) == (ta == 0);
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t i = lower_op ? q : n - 1 - q;
+        double s = x0[i * incx];
+        int64_t p0 = lower_op ? 0 : i + 1, p1 = lower_op ? i : n;
+        for (int64_t p = p0; p < p1; ++p) {
+            int nz;
+            s = s - tri_op_at(uplo, ta, diag, A, lda, i, p, &nz) * x0[p * incx];
+        }
+        if (!diag) {
+            int nz;
+            s = s / tri_op_at(uplo, ta, diag, A, lda, i, i, &nz);
+        }
+        x0[i * incx] = s;
+    }
+    return 0;
+}

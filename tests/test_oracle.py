@@ -595,3 +595,134 @@ def test_dtrsm_recovers_integer_solution(side, uplo, ta, diag):
         np.fill_diagonal(Anan, np.nan)
     out = oracle.dtrsm(np.asfortranarray(Anan), np.asfortranarray(2.0 * B), 0.5, side, uplo, ta, diag)
     np.testing.assert_array_equal(out, X)
+
+
+# ---------------------------------------------------------------- Level-1/2
+# The routines FT-BLAS protects by duplicated computation (§4): DSCAL, DNRM2,
+# DGEMV, DTRSV.  Pinned by exact arithmetic, closed forms and library routines.
+
+def test_dscal_exact_products_and_stride():
+    """alpha = 3 times small integers and powers of two is exact; stride 2
+    scales only the even positions; n <= 0 or incx <= 0 leave x unchanged;
+    alpha = 0 multiplies (NaN stays NaN, as the BLAS definition has no
+    special case)."""
+    x = np.array([1.0, -2.0, 0.5, 2.0 ** -1000, 7.0, np.nan])
+    np.testing.assert_array_equal(oracle.dscal(x, 6, 3.0), [3.0, -6.0, 1.5, 3 * 2.0 ** -1000, 21.0, np.nan])
+    np.testing.assert_array_equal(oracle.dscal(x[:5], 3, -2.0, incx=2), [-2.0, -2.0, -1.0, 2.0 ** -1000, -14.0])
+    np.testing.assert_array_equal(oracle.dscal(x, 0, 5.0), x)
+    np.testing.assert_array_equal(oracle.dscal(x, 6, 5.0, incx=0), x)
+    out = oracle.dscal(x, 6, 0.0)
+    assert np.isnan(out[5]) and np.all(out[:5] == 0.0)
+
+
+@pytest.mark.parametrize("v,expect", [
+    ([3.0, 4.0], 5.0),
+    ([1.0, 2.0, 2.0], 3.0),
+    ([2.0, 3.0, 6.0], 7.0),
+    ([0.0, 0.0], 0.0),
+    ([-5.0], 5.0),
+    ([1.0, 1.0, 1.0, 1.0], 2.0),
+])
+def test_dnrm2_closed_forms(v, expect):
+    """Pythagorean triples and quadruples give exact norms; four equal entries
+    give twice their magnitude."""
+    assert oracle.dnrm2(np.array(v), len(v)) == expect
+
+
+@pytest.mark.parametrize("e", [600, -600, -1070, 1000])
+def test_dnrm2_no_overflow_or_underflow(e):
+    """(3, 4, 12) 2^e has norm 13 2^e exactly, far outside the range where the
+    plain sum of squares over- or underflows (2^-1070 is subnormal)."""
+    s = 2.0 ** e
+    assert oracle.dnrm2(np.array([3.0 * s, 4.0 * s, 12.0 * s]), 3) == 13.0 * s
+
+
+def test_dnrm2_special_values_and_stride():
+    assert math.isnan(oracle.dnrm2(np.array([1.0, np.nan, np.inf]), 3))
+    assert oracle.dnrm2(np.array([1.0, -np.inf, 2.0]), 3) == math.inf
+    assert oracle.dnrm2(np.array([3.0, 99.0, 4.0, 99.0]), 2, incx=2) == 5.0
+    assert oracle.dnrm2(np.array([3.0, 4.0]), 0) == 0.0
+    assert oracle.dnrm2(np.array([3.0, 4.0]), 2, incx=0) == 0.0
+
+
+def test_dnrm2_matches_numpy_on_random_data():
+    """Against numpy's norm (a library routine): both are within a few
+    rounding units of the exact value for data this well scaled."""
+    rng = np.random.default_rng(7)
+    for n in (1, 17, 1000, 100003):
+        x = rng.standard_normal(n)
+        ref = float(np.linalg.norm(x))
+        assert abs(oracle.dnrm2(x, n) - ref) <= 1e-14 * ref
+
+
+def test_dgemv_integer_example_both_operations():
+    """A = [[1, 2, 3], [4, 5, 6]]: A (1, 0, -1) = (-2, -2) and A^T (1, 1) =
+    (5, 7, 9); alpha and beta apply as alpha op(A) x + beta y."""
+    A = np.asfortranarray([[1.0, 2.0, 3.0], [4.0, 5.0, 6.0]])
+    np.testing.assert_array_equal(oracle.dgemv(A, [1.0, 0.0, -1.0], [0.0, 0.0]), [-2.0, -2.0])
+    np.testing.assert_array_equal(oracle.dgemv(A, [1.0, 1.0], [0.0, 0.0, 0.0], ta=1), [5.0, 7.0, 9.0])
+    np.testing.assert_array_equal(oracle.dgemv(A, [1.0, 0.0, -1.0], [10.0, 20.0], alpha=2.0, beta=0.5),
+                                  [1.0, 6.0])
+    # the transposed product is not the plain one: a swapped operand fails here
+    np.testing.assert_array_equal(oracle.dgemv(A, [1.0, 2.0], [0.0, 0.0, 0.0], ta=1), [9.0, 12.0, 15.0])
+
+
+def test_dgemv_negative_strides_and_beta_zero():
+    """A negative increment walks the vector from the far end; beta = 0 does
+    not read y (NaN there is ignored); alpha = 0 reads neither A nor x."""
+    A = np.asfortranarray([[1.0, 2.0, 3.0], [4.0, 5.0, 6.0]])
+    xb = [-1.0, 0.0, 1.0]  # with incx = -1 element 0 is the last entry: x = (1, 0, -1)
+    np.testing.assert_array_equal(oracle.dgemv(A, xb, [np.nan, np.nan], incx=-1), [-2.0, -2.0])
+    yb = [7.0, 99.0, 5.0]  # incy = -2: y = (5, 7), written back at the same places
+    np.testing.assert_array_equal(oracle.dgemv(A, [1.0, 0.0, -1.0], yb, beta=1.0, incy=-2), [5.0, 99.0, 3.0])
+    Anan = np.full((2, 3), np.nan, order="F")
+    np.testing.assert_array_equal(oracle.dgemv(Anan, [np.nan] * 3, [2.0, 4.0], alpha=0.0, beta=3.0), [6.0, 12.0])
+
+
+def test_dgemv_matches_numpy_within_bound():
+    """Against numpy's matmul: |diff| <= 2 gamma_n (|A| |x|) elementwise (both
+    sides are within gamma_n |A||x| of the exact product)."""
+    rng = np.random.default_rng(3)
+    for ta in (0, 1):
+        A = np.asfortranarray(rng.standard_normal((37, 53)))
+        lenx = 37 if ta else 53
+        x = rng.standard_normal(lenx)
+        out = oracle.dgemv(A, x, np.zeros(53 if ta else 37), ta=ta)
+        op = A.T if ta else A
+        g = lenx * 2.0 ** -53 / (1 - lenx * 2.0 ** -53)
+        assert np.all(np.abs(out - op @ x) <= 2 * g * (np.abs(op) @ np.abs(x)))
+
+
+@pytest.mark.parametrize("uplo", [0, 1])
+@pytest.mark.parametrize("ta", [0, 1])
+@pytest.mark.parametrize("diag", [0, 1])
+@pytest.mark.parametrize("incx", [1, -2])
+def test_dtrsv_recovers_integer_solution(uplo, ta, diag, incx):
+    """b = op(T) x for an integer x and a triangular T with small integers off
+    the diagonal and a power-of-two (or unit) diagonal: every partial sum is
+    exact, so the solve returns x bitwise; the unread triangle (and a unit
+    diagonal) hold NaN."""
+    rng = np.random.default_rng(200 + 8 * uplo + 4 * ta + 2 * diag + (incx < 0))
+    n = 23
+    A = rng.integers(-3, 4, size=(n, n)).astype(np.float64)
+    np.fill_diagonal(A, rng.choice([-4.0, -2.0, -1.0, 1.0, 2.0, 4.0], size=n))
+    T = np.tril(A) if uplo == 0 else np.triu(A)
+    if diag:
+        np.fill_diagonal(T, 1.0)
+    op = T.T if ta else T
+    x = rng.integers(-5, 6, size=n).astype(np.float64)
+    b = op @ x
+    Anan = A.copy()
+    Anan[np.triu_indices(n, 1) if uplo == 0 else np.tril_indices(n, -1)] = np.nan
+    if diag:
+        np.fill_diagonal(Anan, np.nan)
+    buf = np.full(1 + (n - 1) * abs(incx), 123.0)
+    pos = np.arange(n) * abs(incx)
+    if incx < 0:
+        pos = pos[::-1]
+    buf[pos] = b
+    out = oracle.dtrsv(np.asfortranarray(Anan), buf, uplo, ta, diag, incx)
+    np.testing.assert_array_equal(out[pos], x)
+    mask = np.ones(buf.size, bool)
+    mask[pos] = False
+    assert np.all(out[mask] == 123.0)
