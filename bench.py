@@ -48,7 +48,7 @@ def parse():
     p.add_argument("--no-sweep", action="store_true", help="skip the FP64 size sweep and rank-k shapes")
     p.add_argument("--fp-calls", type=int, default=1000,
                    help="fault-free calls of the BF16/FP8 false-positive campaign")
-    p.add_argument("--only", default="", help="comma list of legs to run among cfg1,cfg3,cfg4,cfg5,unfused,level3")
+    p.add_argument("--only", default="", help="comma list of legs to run among cfg1,cfg3,cfg4,cfg5,unfused,level3,dmr")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only copy 1 GiB between device buffers three times (reference for HBM counters)")
     p.add_argument("--tiles", action="store_true", help="time every FP64 tile configuration at --n")
@@ -393,6 +393,58 @@ def unfused_comparison(torch, ftgemm, h, steps, sizes=(4096, 8192, 16384), kc_on
     return rows
 
 
+def dmr_routines(torch, ftgemm, h, steps):
+    """The duplicated-computation routines of §4 at HBM-filling sizes: DSCAL
+    (x := -x) and DNRM2 over 2^28 doubles, DGEMV without transpose and
+    transposed at 16384^2 (alpha = 1, beta = 0.5), DTRSV lower at n = 16384
+    (diagonal in [1, 2], off-diagonal U[-1,1] * 0.5/n; x reset before each
+    solve); all U[-1,1].  Each is timed protected, protected with 20 injected
+    faults per call (the paper's error-injection experiment, §6.3), and with
+    protection off; GB/s count the routine's algorithmic bytes (DSCAL 16 n,
+    DNRM2 8 n, DGEMV 8 (mn + n + 2m), DTRSV 8 (n(n+1)/2 + 2n)) against the
+    8 TB/s HBM peak."""
+    g = torch.Generator(device="cuda").manual_seed(17)
+    rnd = lambda *shape: torch.rand(shape, generator=g, device="cuda", dtype=torch.float64) * 2 - 1
+    out = {}
+
+    def leg(name, nbytes, fn, calls):
+        cp, cu = ftgemm.make_config(), ftgemm.make_config(abft=False)
+        cf = ftgemm.make_config(seed=23, n_faults=20)
+        h.reset()
+        t = timed_ab(torch, {"p": lambda: fn(cp), "f": lambda: fn(cf), "u": lambda: fn(cu)}, calls, 2)
+        rep = h.read()
+        r = {"ms_protected": t["p"], "ms_with_20_faults": t["f"], "ms_unprotected": t["u"],
+             "gbs_protected": nbytes / t["p"] / 1e6, "gbs_unprotected": nbytes / t["u"] / 1e6,
+             "hbm_frac_protected": nbytes / t["p"] / 1e6 / PEAK_HBM,
+             "overhead_pct": 100.0 * (t["p"] / t["u"] - 1.0),
+             "overhead_with_faults_pct": 100.0 * (t["f"] / t["u"] - 1.0),
+             "faults": {"injected": rep.injected, "corrected": rep.corrected_recompute,
+                        "uncorrectable": rep.uncorrectable}}
+        out[name] = r
+        print(json.dumps({name: r}), file=sys.stderr, flush=True)
+
+    n1 = 1 << 28
+    x = rnd(n1)
+    leg("dscal_2^28", 16.0 * n1, lambda c: ftgemm.dscal_f64(h, x, -1.0, cfg=c), steps)
+    res = torch.empty(1, dtype=torch.float64, device="cuda")
+    leg("dnrm2_2^28", 8.0 * n1, lambda c: ftgemm.dnrm2_f64(h, x, res, cfg=c), steps)
+    del x
+    n2 = 16384
+    A = rnd(n2, n2)
+    xv, yv = rnd(n2), rnd(n2)
+    for ta in (0, 1):
+        leg(f"dgemv_{'t' if ta else 'n'}_{n2}", 8.0 * (n2 * n2 + 3 * n2),
+            lambda c, ta=ta: ftgemm.dgemv_f64(h, A, xv, yv, 1.0, 0.5, ta, cfg=c), steps)
+    A.mul_(0.5 / n2)
+    A.diagonal().copy_(torch.rand(n2, generator=g, device="cuda", dtype=torch.float64) + 1.0)
+    x0 = rnd(n2)
+    xs = x0.clone()
+    leg(f"dtrsv_{n2}", 8.0 * (n2 * (n2 + 1) / 2 + 2 * n2),
+        lambda c: (xs.copy_(x0), ftgemm.dtrsv_f64(h, A, xs, ftgemm.LOWER, ftgemm.OP_N, cfg=c)), max(2, steps // 2))
+    del A
+    return out
+
+
 def level3_routines(torch, ftgemm, h, steps, n=8192):
     """FT-DSYMM (C := 1.5 A B + 0.5 C, A symmetric lower), FT-DTRMM
     (B := 1.5 op(A) B) and FT-DTRSM (B := 1.5 op(A)^-1 B), A lower, left, no
@@ -638,7 +690,8 @@ def main():
                          ("cfg4", lambda: cfg4_ftlinear(torch, ftgemm, h, max(2, args.steps // 2))),
                          ("cfg5", lambda: cfg5_batched(torch, ftgemm, h, args.steps)),
                          ("unfused", lambda: unfused_comparison(torch, ftgemm, h, args.steps)),
-                         ("level3", lambda: level3_routines(torch, ftgemm, h, args.steps))]:
+                         ("level3", lambda: level3_routines(torch, ftgemm, h, args.steps)),
+                         ("dmr", lambda: dmr_routines(torch, ftgemm, h, args.steps))]:
             if only and name.split("_")[0] not in only:
                 continue
             cf[name] = fn()

@@ -290,6 +290,70 @@ ftg_status ftg_dtrsm(ftg_handle h, ftg_side side, ftg_uplo uplo, ftg_op transa, 
                      int64_t n, double alpha, const double* A, int64_t lda, double* B, int64_t ldb, void* stream,
                      const ftg_config* cfg);
 
+/* ---- Level-1 and Level-2 routines protected by duplicated computation
+ * (DMR; §4): every floating-point operation runs twice, the two results
+ * are compared bit for bit after each group of 8 operations of a lane (and
+ * after every step of a reduction), and a mismatching group is recomputed
+ * from the operands still in registers and compared again: agreement is
+ * counted in corrected_recompute (record kind FTG_KIND_RECOMPUTE), a
+ * second mismatch in uncorrectable.  Loads and stores are not duplicated.
+ * cfg->abft = 0 runs the same kernels with one copy (the unprotected
+ * baseline).  Vectors follow BLAS: n elements at stride inc, a negative
+ * stride starting from the far end; the pointer is the lowest address of
+ * the vector.  All pointers are device memory; the calls queue on `stream`
+ * and return at once.
+ *
+ * Injector (cfg->inject): F = n_faults, or ceil(per_mac_rate x operation
+ * count), distinct verification units (the routine's slots, drawn by the
+ * same keyed bijection as the GEMM slots; F <= 64, else
+ * FTG_ERR_UNSUPPORTED).  A fault flips bit b in [bit_lo, bit_hi] (default
+ * 40..63) of the unit's first result (FTG_TARGET_ACC), of its duplicate
+ * (FTG_TARGET_CHECKSUM), or of the first result in the computation and
+ * again in the recomputation (FTG_TARGET_TWO_IN_SLOT: the unit then ends
+ * uncorrectable).  Log entries carry the element in row/col and the
+ * verification step in interval and pflip.  Invalid injector fields: xerbla
+ * position 20. */
+
+/* FT-DSCAL: x := alpha x.  Nothing for n <= 0 or incx <= 0 (BLAS).  Units:
+ * the n elements (one product each); row = the element. */
+ftg_status ftg_dscal(ftg_handle h, int64_t n, double alpha, double* x, int64_t incx, void* stream,
+                     const ftg_config* cfg);
+
+/* FT-DNRM2: *result (device) := the Euclidean norm of x, by Blue's scaled
+ * sums of squares (no overflow or harmful underflow for any finite input);
+ * NaN if an element is NaN, else +Inf if one is infinite; 0 for n <= 0 or
+ * incx <= 0.  Workgroup sums go to the handle's workspace.  Units: the n
+ * elements (a fault hits the sum that took the element). */
+ftg_status ftg_dnrm2(ftg_handle h, int64_t n, const double* x, int64_t incx, double* result, void* stream,
+                     const ftg_config* cfg);
+
+/* FT-DGEMV: y := alpha op(A) x + beta y, A m x n column-major (BLAS dgemv;
+ * y is not read when beta = 0; A and x are not read when alpha = 0).
+ * Without transpose one lane owns a row and adds 8 columns per step;
+ * transposed one wave owns an output element and each lane adds 8 rows 64
+ * apart per step.  Long reductions are cut into chunks whose sums meet in a
+ * second pass (workspace).  Units: without transpose (row i, columns
+ * 8g..8g+7) as u = i + m g; transposed (output j, the rows 512 t + l + 64 v,
+ * v < 8, of lane l in step t) as u = j + n (64 t + l) over the (t, l) with
+ * 512 t + l < m.  xerbla positions: 1 trans, 2 m, 3 n, 6 lda, 8 incx,
+ * 11 incy. */
+ftg_status ftg_dgemv(ftg_handle h, ftg_op trans, int64_t m, int64_t n, double alpha, const double* A,
+                     int64_t lda, const double* x, int64_t incx, double beta, double* y, int64_t incy,
+                     void* stream, const ftg_config* cfg);
+
+/* FT-DTRSV: x := op(A)^-1 x, A n x n triangular (the `uplo` triangle read;
+ * FTG_UNIT: unit diagonal, not read).  Blocked as in §3.2: for each block
+ * of 128 rows in solve order, the update by the solved part runs as a
+ * duplicated DGEMV pass, then one workgroup solves the diagonal block by
+ * substitution, multiplying by reciprocals of the diagonal (formed as the
+ * block is staged).  Units: the n unknowns; a fault hits the unknown's
+ * right-hand side after the update (phase 0) or the unknown as it is formed
+ * (phase 1), chosen by the plan.  A corrected unknown is bitwise the
+ * fault-free one.  xerbla positions: 1 uplo, 2 trans, 3 diag, 4 n, 6 lda,
+ * 8 incx. */
+ftg_status ftg_dtrsv(ftg_handle h, ftg_uplo uplo, ftg_op trans, ftg_diag diag, int64_t n, const double* A,
+                     int64_t lda, double* x, int64_t incx, void* stream, const ftg_config* cfg);
+
 /* Mixed-precision protected GEMM: A, B of type ab_type (FTG_BF16 or
  * FTG_F8_E4M3, OCP e4m3fn), FP32 accumulation on MFMA, FP32 maintained
  * checksums, FP64 reference sums and locate/correct; C of type c_type

@@ -1,0 +1,1136 @@
+// Level-1 and Level-2 routines protected by duplicated computation (DMR),
+// the scheme FT-BLAS applies to its memory-bound routines (§4): DSCAL,
+// DNRM2, DGEMV and DTRSV.
+//
+// Every floating-point operation runs twice.  The second run works on copies
+// of its operands that the compiler cannot prove equal to the originals, so
+// it emits its own instructions.  The two results are compared bit for bit
+// at every verification step: a group of 8 operations per lane (the paper
+// compares once per unrolled iteration, §4.3).  A mismatch recomputes the
+// step, twice, from the operands still held in registers (the paper's
+// in-register checkpoint, §4.4) and compares again.  Agreement corrects the
+// step (FTG_KIND_RECOMPUTE); a second mismatch is reported uncorrectable.
+// Loads and stores are not duplicated: memory lies outside the sphere of
+// replication (§4.1).  Reductions across lanes, waves and workgroups are
+// duplicated and compared the same way.
+//
+// On MI355X these routines are bound by HBM bandwidth: a few flops per
+// 8-byte element, against about 10 binary64 flops per byte that the vector
+// units deliver at 8 TB/s.  So the duplicate fills issue slots that would
+// otherwise idle (the argument of §4.2 for the CPU).
+#include <hip/hip_runtime.h>
+#include <limits.h>
+#include <stdint.h>
+
+#include "ftg_common.hpp"
+#include "ftg_kernels.hpp"
+
+namespace ftg {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kU = 8;                  // operations per lane between two comparisons
+constexpr int kVecStep = 64 * kU;      // DSCAL/DNRM2: elements per wave step
+constexpr int kVecMaxBlocks = 2048;
+constexpr int kGnRows = 64;            // DGEMV without transpose: rows per workgroup (one per lane)
+constexpr int kGtCols = 4;             // DGEMV transposed: output elements per workgroup (one per wave)
+constexpr int kGtStep = 64 * kU;       // DGEMV transposed: rows per wave step
+constexpr int kGvTarget = 2048;        // DGEMV: workgroups aimed at per launch
+constexpr int kTrsvB = 128;            // DTRSV: order of the diagonal blocks
+constexpr int kTrsvLd = kTrsvB + 1;    // LDS leading dimension of a staged block
+constexpr int kTrsvMaxParts = 128;     // DTRSV: partial sums per row of a block update
+
+// Blue's scaling for binary64 (Blue, ACM TOMS 1978; thresholds as derived by
+// Anderson, ACM TOMS 2017): the squares of magnitudes in [tsml, tbig]
+// neither overflow nor lose accuracy to underflow.  Larger magnitudes are
+// summed scaled by sbig, smaller ones by ssml (all powers of two, so the
+// scaling is exact).
+constexpr double kTsml = 0x1p-511, kTbig = 0x1p486, kSsml = 0x1p537, kSbig = 0x1p-538;
+
+// A copy of x that the compiler cannot prove equal to x: an operation on it
+// is issued again rather than shared with the same operation on x.
+__device__ __forceinline__ double dup(double x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+__device__ __forceinline__ bool differ(double a, double b)
+{
+    return __double_as_longlong(a) != __double_as_longlong(b);
+}
+
+template <typename T>
+__host__ __device__ __forceinline__ T imin(T a, T b) { return a < b ? a : b; }
+
+// First planned step after `after` whose fault belongs to thread `owner`.
+__device__ __forceinline__ int next_fault(const DmrPlan& p, int64_t owner, int after)
+{
+    int best = INT_MAX;
+    for (int q = 0; q < p.n; ++q)
+        if (p.f[q].owner == owner && p.f[q].step > after && p.f[q].step < best) best = p.f[q].step;
+    return best;
+}
+
+// Flips the planned bit of the step's first result (FTG_TARGET_ACC and
+// FTG_TARGET_TWO_IN_SLOT) or of its duplicate (FTG_TARGET_CHECKSUM) and logs
+// it when `log`.  Returns the bit to flip again in the recomputation (the
+// fault persists under FTG_TARGET_TWO_IN_SLOT), else -1.
+__device__ __forceinline__ int apply_fault(const DmrPlan& p, const DmrFault& f, double& v1, double& v2, DevReport* rep, bool log,
+                           int tm, int64_t row, int64_t col, int step)
+{
+    double old, now;
+    if (p.target == FTG_TARGET_CHECKSUM) {
+        old = v2;
+        v2 = flip_f64(v2, f.bit);
+        now = v2;
+    } else {
+        old = v1;
+        v1 = flip_f64(v1, f.bit);
+        now = v1;
+    }
+    if (log) push_inject(rep, 0, tm, -1, step, row, col, step, f.bit, p.target, old, now);
+    return p.target == FTG_TARGET_TWO_IN_SLOT ? f.bit : -1;
+}
+
+// Counts and records a detected mismatch: corrected by the recomputation
+// (`fixed`) or not.  delta: the difference of the two mismatching copies.
+__device__ void note_repair(DevReport* rep, bool fixed, int tm, int64_t row, int64_t col, int step, double a,
+                            double b)
+{
+    atomicAdd(&rep->cnt[kDetected], 1ull);
+    atomicAdd(&rep->cnt[fixed ? kCorrRecomp : kUncorrectable], 1ull);
+    push_record(rep, 0, tm, -1, step, row, col, fixed ? FTG_KIND_RECOMPUTE : FTG_KIND_UNCORRECTABLE, a - b, 0.0);
+}
+
+// ------------------------------------------------------------------ DSCAL
+// Wave w takes the runs of 512 elements w, w + nwaves, ...; lane l of a run
+// starting at c0 holds elements c0 + l + 64 u (u < 8), so every load and
+// store of a wave is one coalesced 512-byte access (contiguous x).
+
+// Planned faults of one step of one lane, packed 7 bits per element u (bit
+// 6: a fault; bits 0..5: the bit to flip).
+__device__ __forceinline__ uint64_t step_faults(const DmrPlan& p, int64_t me, int step)
+{
+    uint64_t pk = 0;
+    for (int q = 0; q < p.n; ++q)
+        if (p.f[q].owner == me && p.f[q].step == step) pk |= (uint64_t)(64 | p.f[q].bit) << (7 * p.f[q].sub);
+    return pk;
+}
+
+// A DSCAL step that leaves the common path -- planned faults, or a
+// mismatch there -- done again from memory (x is not yet overwritten):
+// product and duplicate of each element, the planned flips, comparison,
+// recomputation of a mismatching element, records, stores.  Out of line, so
+// that the common path keeps few registers.  Returns the mismatches found.
+template <bool UNIT>
+__device__ __noinline__ int scal_slow_step(double* __restrict__ x, int64_t n, int64_t inc, double alpha, int64_t c0,
+                                           int lane, int step, uint64_t pk, int target, DevReport* rep)
+{
+    int found = 0;
+#pragma unroll 1
+    for (int u = 0; u < kU; ++u) {
+        const int64_t i = c0 + lane + 64 * u;
+        if (i >= n) break;
+        const double v = x[UNIT ? i : i * inc];
+        double r = alpha * v, d = alpha * dup(v);
+        int again = -1;
+        const int fb = (int)((pk >> (7 * u)) & 127);
+        if (fb & 64) {
+            DmrPlan one;
+            one.target = target;
+            DmrFault f;
+            f.bit = fb & 63;
+            again = apply_fault(one, f, r, d, rep, true, -1, i, -1, step);
+        }
+        if (differ(r, d)) {
+            double r1 = alpha * dup(v);
+            const double r2 = alpha * dup(v);
+            if (again >= 0) r1 = flip_f64(r1, again);
+            note_repair(rep, !differ(r1, r2), -1, i, -1, step, r, d);
+            r = r1;
+            ++found;
+        }
+        x[UNIT ? i : i * inc] = r;
+    }
+    return found;
+}
+
+template <bool DMR, bool UNIT>
+__global__ __launch_bounds__(kThreads) void scal_kernel(double* __restrict__ x, int64_t n, int64_t inc,
+                                                        double alpha, int64_t nwaves, DmrPlan plan,
+                                                        DevReport* rep)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t w = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    const int64_t me = w * 64 + lane;
+    int next = INT_MAX;
+    if (DMR && plan.n) next = next_fault(plan, me, -1);
+    int step = 0;
+    for (int64_t c0 = w * kVecStep; c0 < n; c0 += nwaves * kVecStep, ++step) {
+        if (DMR && step == next) {
+            const uint64_t pk = step_faults(plan, me, step);
+            next = next_fault(plan, me, step);
+            scal_slow_step<UNIT>(x, n, inc, alpha, c0, lane, step, pk, plan.target, rep);
+            continue;
+        }
+        double v[kU], r[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int64_t i = c0 + lane + 64 * u;
+            v[u] = i < n ? x[UNIT ? i : i * inc] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) r[u] = alpha * v[u];
+        if constexpr (DMR) {
+            // each product against its duplicate, as it is formed
+            bool bad = false;
+#pragma unroll
+            for (int u = 0; u < kU; ++u) bad |= differ(r[u], alpha * dup(v[u]));
+            if (bad) {
+                // a mismatch that the step's recomputation does not show again was
+                // transient: the recomputed (stored) values are the corrected ones
+                if (scal_slow_step<UNIT>(x, n, inc, alpha, c0, lane, step, 0, 0, rep) == 0)
+                    note_repair(rep, true, -1, c0 + lane, -1, step, 0.0, 0.0);
+                continue;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int64_t i = c0 + lane + 64 * u;
+            if (i < n) x[UNIT ? i : i * inc] = r[u];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ DNRM2
+// Sums of squares of the small, medium and big elements (Blue's scaling).
+struct Sq3 {
+    double s, m, b;
+};
+
+__device__ __forceinline__ int sq_class(double v)
+{
+    const double ax = fabs(v);
+    return ax > kTbig ? 2 : (ax < kTsml ? 0 : 1);  // NaN: medium
+}
+
+__device__ __forceinline__ void sq_add(double v, Sq3& a)
+{
+    const double ax = fabs(v);
+    const bool big = ax > kTbig, sml = ax < kTsml;
+    const double y = v * (big ? kSbig : (sml ? kSsml : 1.0));
+    const double t = fma(y, y, big ? a.b : (sml ? a.s : a.m));
+    a.b = big ? t : a.b;
+    a.s = sml ? t : a.s;
+    a.m = (big || sml) ? a.m : t;
+}
+
+__device__ __forceinline__ bool differ3(const Sq3& a, const Sq3& b)
+{
+    return differ(a.s, b.s) | differ(a.m, b.m) | differ(a.b, b.b);
+}
+
+__device__ __forceinline__ Sq3 dup3(const Sq3& a) { return Sq3{dup(a.s), dup(a.m), dup(a.b)}; }
+
+__device__ __forceinline__ Sq3 wave_sum3(const Sq3& a)
+{
+    return Sq3{group_sum<64>(a.s), group_sum<64>(a.m), group_sum<64>(a.b)};
+}
+
+__device__ __forceinline__ Sq3 add3(const Sq3& a, const Sq3& b) { return Sq3{a.s + b.s, a.m + b.m, a.b + b.b}; }
+
+// Flips bit `bit` of the accumulator of class `cls`.
+__device__ __forceinline__ void flip3(Sq3& a, int cls, int bit)
+{
+    if (cls == 0) a.s = flip_f64(a.s, bit);
+    else if (cls == 1) a.m = flip_f64(a.m, bit);
+    else a.b = flip_f64(a.b, bit);
+}
+
+// The norm from the three sums (the combination step of Blue's algorithm).
+__device__ double sq_norm(const Sq3& a)
+{
+    if (a.b > 0.0) {
+        double b = a.b;
+        if (a.m > 0.0 || a.m != a.m) b = b + (a.m * kSbig) * kSbig;
+        return sqrt(b) * 0x1p538;  // 1 / sbig
+    }
+    if (a.s > 0.0) {
+        if (a.m > 0.0 || a.m != a.m) {
+            const double ym = sqrt(a.m), ys = sqrt(a.s) * 0x1p-537;  // 1 / ssml
+            const double lo = ys > ym ? ym : ys, hi = ys > ym ? ys : ym;
+            const double q = lo / hi;
+            return sqrt(hi * hi * (1.0 + q * q));
+        }
+        return sqrt(a.s) * 0x1p-537;
+    }
+    return sqrt(a.m);
+}
+
+// Workgroup sums of the three accumulators (duplicated across lanes, then
+// across the four waves); thread 0 gets the result.
+template <bool DMR>
+__device__ Sq3 block_sum3(Sq3 a1, Sq3 a2, DevReport* rep, int step)
+{
+    __shared__ double red[kThreads / 64][3];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    Sq3 t1 = wave_sum3(a1);
+    if constexpr (DMR) {
+        const Sq3 t2 = wave_sum3(dup3(a2));
+        if (differ3(t1, t2)) {
+            const Sq3 r1 = wave_sum3(dup3(a1)), r2 = wave_sum3(dup3(a1));
+            if (lane == 0) note_repair(rep, !differ3(r1, r2), -1, -1, -1, step, t1.m, t2.m);
+            t1 = r1;
+        }
+    }
+    if (lane == 0) {
+        red[wv][0] = t1.s;
+        red[wv][1] = t1.m;
+        red[wv][2] = t1.b;
+    }
+    __syncthreads();
+    Sq3 b1{0.0, 0.0, 0.0};
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < kThreads / 64; ++q) b1 = add3(b1, Sq3{red[q][0], red[q][1], red[q][2]});
+        if constexpr (DMR) {
+            Sq3 b2{0.0, 0.0, 0.0};
+            for (int q = 0; q < kThreads / 64; ++q) b2 = add3(b2, dup3(Sq3{red[q][0], red[q][1], red[q][2]}));
+            if (differ3(b1, b2)) {
+                Sq3 r1{0.0, 0.0, 0.0}, r2{0.0, 0.0, 0.0};
+                for (int q = 0; q < kThreads / 64; ++q) {
+                    r1 = add3(r1, dup3(Sq3{red[q][0], red[q][1], red[q][2]}));
+                    r2 = add3(r2, dup3(Sq3{red[q][0], red[q][1], red[q][2]}));
+                }
+                note_repair(rep, !differ3(r1, r2), -1, -1, -1, step, b1.m, b2.m);
+                b1 = r1;
+            }
+        }
+    }
+    return b1;
+}
+
+struct Sq3N {
+    Sq3 a;
+    int found;
+};
+
+// A DNRM2 step that leaves the common path (planned faults, or a mismatch
+// there), done again from memory starting from the verified sums `chk`:
+// both copies, the planned flips (of the sum that took the element),
+// comparison, recomputation of both copies from chk on a mismatch, record.
+// Returns the step's sums and the mismatches found.  Out of line, so that
+// the common path keeps few registers.
+template <bool UNIT>
+__device__ __noinline__ Sq3N nrm2_slow_step(const double* __restrict__ x, int64_t n, int64_t inc, int64_t c0,
+                                            int lane, int step, Sq3 chk, uint64_t pk, int target, DevReport* rep)
+{
+    // one element at a time, reloaded where needed: few registers
+    auto at = [&](int u) {
+        const int64_t i = c0 + lane + 64 * u;
+        return i < n ? x[UNIT ? i : i * inc] : 0.0;
+    };
+    Sq3 a1 = chk, a2 = chk;
+#pragma unroll 1
+    for (int u = 0; u < kU; ++u) {
+        const double v = at(u);
+        sq_add(v, a1);
+        sq_add(dup(v), a2);
+    }
+    int again = -1, again_cls = 0;
+#pragma unroll 1
+    for (int u = 0; u < kU; ++u) {
+        const int fb = (int)((pk >> (7 * u)) & 127);
+        if (!(fb & 64)) continue;
+        const int cls = sq_class(at(u));  // the sum that took the element
+        double t1 = cls == 0 ? a1.s : (cls == 1 ? a1.m : a1.b);
+        double t2 = cls == 0 ? a2.s : (cls == 1 ? a2.m : a2.b);
+        DmrPlan one;
+        one.target = target;
+        DmrFault f;
+        f.bit = fb & 63;
+        const int g = apply_fault(one, f, t1, t2, rep, true, -1, c0 + lane + 64 * u, -1, step);
+        if (cls == 0) {
+            a1.s = t1;
+            a2.s = t2;
+        } else if (cls == 1) {
+            a1.m = t1;
+            a2.m = t2;
+        } else {
+            a1.b = t1;
+            a2.b = t2;
+        }
+        if (g >= 0) {
+            again = g;
+            again_cls = cls;
+        }
+    }
+    Sq3N out{a1, 0};
+    if (differ3(a1, a2)) {
+        Sq3 r1 = chk, r2 = chk;
+#pragma unroll 1
+        for (int u = 0; u < kU; ++u) {
+            const double v = at(u);
+            sq_add(dup(v), r1);
+            sq_add(dup(v), r2);
+        }
+        if (again >= 0) flip3(r1, again_cls, again);
+        note_repair(rep, !differ3(r1, r2), -1, c0 + lane, -1, step, a1.s + a1.m + a1.b, a2.s + a2.m + a2.b);
+        out.a = r1;
+        out.found = 1;
+    }
+    return out;
+}
+
+// Per-workgroup sums of squares of the elements (same element order as
+// DSCAL), three doubles per workgroup into part.
+template <bool DMR, bool UNIT>
+__global__ __launch_bounds__(kThreads) void nrm2_part_kernel(const double* __restrict__ x, int64_t n, int64_t inc,
+                                                             int64_t nwaves, double* __restrict__ part,
+                                                             DmrPlan plan, DevReport* rep)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t w = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    const int64_t me = w * 64 + lane;
+    int next = INT_MAX;
+    if (DMR && plan.n) next = next_fault(plan, me, -1);
+    Sq3 a1{0.0, 0.0, 0.0}, a2{0.0, 0.0, 0.0};
+    int step = 0;
+    for (int64_t c0 = w * kVecStep; c0 < n; c0 += nwaves * kVecStep, ++step) {
+        if (DMR && step == next) {
+            const uint64_t pk = step_faults(plan, me, step);
+            next = next_fault(plan, me, step);
+            a1 = nrm2_slow_step<UNIT>(x, n, inc, c0, lane, step, a1, pk, plan.target, rep).a;
+            a2 = a1;
+            continue;
+        }
+        double v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int64_t i = c0 + lane + 64 * u;
+            v[u] = i < n ? x[UNIT ? i : i * inc] : 0.0;
+        }
+        const Sq3 chk = a1;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) sq_add(v[u], a1);
+        if constexpr (DMR) {
+#pragma unroll
+            for (int u = 0; u < kU; ++u) sq_add(dup(v[u]), a2);
+            if (differ3(a1, a2)) {
+                const Sq3N r = nrm2_slow_step<UNIT>(x, n, inc, c0, lane, step, chk, 0, 0, rep);
+                // not seen again by the recomputation: a transient mismatch, corrected by it
+                if (r.found == 0) note_repair(rep, true, -1, c0 + lane, -1, step, 0.0, 0.0);
+                a1 = r.a;
+                a2 = r.a;
+            }
+        }
+    }
+    const Sq3 b = block_sum3<DMR>(a1, a2, rep, -1);
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x + 0] = b.s;
+        part[3 * blockIdx.x + 1] = b.m;
+        part[3 * blockIdx.x + 2] = b.b;
+    }
+}
+
+// Sums the workgroups' partial sums and forms the norm (one workgroup).
+template <bool DMR>
+__global__ __launch_bounds__(kThreads) void nrm2_final_kernel(const double* __restrict__ part, int nparts,
+                                                              double* __restrict__ out, DevReport* rep)
+{
+    Sq3 a1{0.0, 0.0, 0.0}, a2{0.0, 0.0, 0.0};
+    for (int p = threadIdx.x; p < nparts; p += kThreads) {
+        const Sq3 v{part[3 * p], part[3 * p + 1], part[3 * p + 2]};
+        a1 = add3(a1, v);
+        if constexpr (DMR) a2 = add3(a2, dup3(v));
+    }
+    if constexpr (DMR) {
+        if (differ3(a1, a2)) {
+            Sq3 r1{0.0, 0.0, 0.0}, r2{0.0, 0.0, 0.0};
+            for (int p = threadIdx.x; p < nparts; p += kThreads) {
+                const Sq3 v{part[3 * p], part[3 * p + 1], part[3 * p + 2]};
+                r1 = add3(r1, dup3(v));
+                r2 = add3(r2, dup3(v));
+            }
+            note_repair(rep, !differ3(r1, r2), -1, -1, -1, -1, a1.m, a2.m);
+            a1 = r1;
+            a2 = r1;
+        }
+    }
+    const Sq3 b = block_sum3<DMR>(a1, a2, rep, -1);
+    if (threadIdx.x == 0) {
+        double r = sq_norm(b);
+        if constexpr (DMR) {
+            const double r2 = sq_norm(dup3(b));
+            if (differ(r, r2)) {
+                const double q1 = sq_norm(dup3(b)), q2 = sq_norm(dup3(b));
+                note_repair(rep, !differ(q1, q2), -1, -1, -1, -1, r, r2);
+                r = q1;
+            }
+        }
+        *out = r;
+    }
+}
+
+// ------------------------------------------------------------------ DGEMV
+// One launch over a stored panel of A.  Without transpose (gemv_n_kernel)
+// the panel is rows x cols with rows the output elements; transposed
+// (gemv_t_kernel) it is rows x cols with cols the outputs.  The reduction
+// dimension is cut into chunks of `width`; with one chunk the launch writes
+// y := alpha s + beta y, otherwise every chunk's sums go to part[c ldp + i]
+// and gemv_reduce_kernel finishes.
+struct Gv {
+    const double* A;
+    int64_t lda;
+    int64_t rows, cols;
+    const double* x;  // element 0 of the reduction vector
+    int64_t incx;
+    double* y;        // element 0 of the output vector
+    int64_t incy;
+    double alpha, beta;
+    double* part;
+    int64_t ldp;
+    int64_t width;    // chunk width along the reduction
+    int64_t bout;     // workgroups along the outputs
+    int direct;       // 1: write y; 0: write partial sums
+    DevReport* rep;
+};
+
+__device__ __forceinline__ double axpby(double alpha, double t, double beta, double yv)
+{
+    return beta == 0.0 ? alpha * t : fma(alpha, t, beta * yv);
+}
+
+template <bool DMR>
+__device__ double out_value(const Gv& g, double t, double yv, int64_t row)
+{
+    double o1 = axpby(g.alpha, t, g.beta, yv);
+    if constexpr (DMR) {
+        const double o2 = axpby(g.alpha, dup(t), g.beta, dup(yv));
+        if (differ(o1, o2)) {
+            const double r1 = axpby(g.alpha, dup(t), g.beta, dup(yv));
+            const double r2 = axpby(g.alpha, dup(t), g.beta, dup(yv));
+            note_repair(g.rep, !differ(r1, r2), -1, row, -1, -1, o1, o2);
+            o1 = r1;
+        }
+    }
+    return o1;
+}
+
+// y_i := alpha sum_j A(i, j) x_j + beta y_i.  Workgroup (rb, c): rows
+// rb*64 + lane, one per lane; wave wv takes a quarter of chunk c's columns,
+// 8 columns per step (8 coalesced 512-byte column segments in flight per
+// wave); the four waves' sums meet in LDS.
+template <bool DMR, bool XUNIT>
+__global__ __launch_bounds__(kThreads) void gemv_n_kernel(Gv g, DmrPlan plan)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t rb = blockIdx.x % g.bout, c = blockIdx.x / g.bout;
+    const int64_t i = rb * kGnRows + lane;
+    const bool valid = i < g.rows;
+    const int64_t wcols = g.width / 4;
+    const int64_t j0w = c * g.width + wv * wcols;
+    const int64_t j1w = imin(g.cols, j0w + wcols);
+    const double* Ai = g.A + (valid ? i : 0);  // lanes past the last row read row 0 and store nothing
+    const int64_t me = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    int next = INT_MAX;
+    if (DMR && plan.n) next = next_fault(plan, me, -1);
+    double acc1 = 0.0, acc2 = 0.0;
+    int step = 0;
+    for (int64_t j0 = j0w; j0 < j1w; j0 += kU, ++step) {
+        const int64_t cnt = j1w - j0;
+        double a[kU], xv[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const bool in = u < cnt;
+            const int64_t j = in ? j0 + u : j0;
+            const double av = Ai[j * g.lda];
+            const double xx = XUNIT ? g.x[j] : g.x[j * g.incx];
+            a[u] = in ? av : 0.0;
+            xv[u] = in ? xx : 0.0;
+        }
+        const double chk = acc1;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) acc1 = fma(a[u], xv[u], acc1);
+        if constexpr (DMR) {
+#pragma unroll
+            for (int u = 0; u < kU; ++u) acc2 = fma(dup(a[u]), xv[u], acc2);
+            int again = -1;
+            if (step == next) {
+                for (int q = 0; q < plan.n; ++q) {
+                    const DmrFault f = plan.f[q];
+                    if (f.owner == me && f.step == step)
+                        again = apply_fault(plan, f, acc1, acc2, g.rep, true, -1, i, j0, step);
+                }
+                next = next_fault(plan, me, step);
+            }
+            if (differ(acc1, acc2)) {
+                double r1 = chk, r2 = chk;
+#pragma unroll
+                for (int u = 0; u < kU; ++u) r1 = fma(dup(a[u]), xv[u], r1);
+#pragma unroll
+                for (int u = 0; u < kU; ++u) r2 = fma(dup(a[u]), xv[u], r2);
+                if (again >= 0) r1 = flip_f64(r1, again);
+                note_repair(g.rep, !differ(r1, r2), -1, i, j0, step, acc1, acc2);
+                acc1 = r1;
+                acc2 = r1;
+            }
+        }
+    }
+    __shared__ double red[kThreads];
+    red[threadIdx.x] = acc1;
+    __syncthreads();
+    if (wv != 0) return;
+    double t1 = ((red[lane] + red[64 + lane]) + red[128 + lane]) + red[192 + lane];
+    if constexpr (DMR) {
+        const double t2 = ((dup(red[lane]) + dup(red[64 + lane])) + dup(red[128 + lane])) + dup(red[192 + lane]);
+        if (differ(t1, t2)) {
+            const double r1 = ((dup(red[lane]) + dup(red[64 + lane])) + dup(red[128 + lane])) + dup(red[192 + lane]);
+            const double r2 = ((dup(red[lane]) + dup(red[64 + lane])) + dup(red[128 + lane])) + dup(red[192 + lane]);
+            note_repair(g.rep, !differ(r1, r2), -1, i, -1, -1, t1, t2);
+            t1 = r1;
+        }
+    }
+    if (!valid) return;
+    if (!g.direct) {
+        g.part[c * g.ldp + i] = t1;
+        return;
+    }
+    const double yv = g.beta != 0.0 ? g.y[i * g.incy] : 0.0;
+    g.y[i * g.incy] = out_value<DMR>(g, t1, yv, i);
+}
+
+// y_j := alpha sum_i A(i, j) x_i + beta y_j.  Workgroup (jb, c): wave wv
+// computes output jb*4 + wv over chunk c's rows; lane l of a step starting
+// at r0 adds rows r0 + l + 64 u (u < 8), then the wave's lanes are summed.
+template <bool DMR, bool XUNIT>
+__global__ __launch_bounds__(kThreads) void gemv_t_kernel(Gv g, DmrPlan plan)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t jb = blockIdx.x % g.bout, c = blockIdx.x / g.bout;
+    const int64_t j = jb * kGtCols + wv;
+    if (j >= g.cols) return;  // whole waves; no barrier follows
+    const int64_t r0w = c * g.width, r1w = imin(g.rows, r0w + g.width);
+    const double* Aj = g.A + j * g.lda;
+    const int64_t me = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    int next = INT_MAX;
+    if (DMR && plan.n) next = next_fault(plan, me, -1);
+    double acc1 = 0.0, acc2 = 0.0;
+    int step = 0;
+    for (int64_t r0 = r0w; r0 < r1w; r0 += kGtStep, ++step) {
+        double a[kU], xv[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int64_t ii = r0 + lane + 64 * u;
+            const bool in = ii < r1w;
+            const int64_t ic = in ? ii : r0w;
+            const double av = Aj[ic];
+            const double xx = XUNIT ? g.x[ic] : g.x[ic * g.incx];
+            a[u] = in ? av : 0.0;
+            xv[u] = in ? xx : 0.0;
+        }
+        const double chk = acc1;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) acc1 = fma(a[u], xv[u], acc1);
+        if constexpr (DMR) {
+#pragma unroll
+            for (int u = 0; u < kU; ++u) acc2 = fma(dup(a[u]), xv[u], acc2);
+            int again = -1;
+            if (step == next) {
+                for (int q = 0; q < plan.n; ++q) {
+                    const DmrFault f = plan.f[q];
+                    if (f.owner == me && f.step == step)
+                        again = apply_fault(plan, f, acc1, acc2, g.rep, true, -1, r0 + lane, j, step);
+                }
+                next = next_fault(plan, me, step);
+            }
+            if (differ(acc1, acc2)) {
+                double r1 = chk, r2 = chk;
+#pragma unroll
+                for (int u = 0; u < kU; ++u) r1 = fma(dup(a[u]), xv[u], r1);
+#pragma unroll
+                for (int u = 0; u < kU; ++u) r2 = fma(dup(a[u]), xv[u], r2);
+                if (again >= 0) r1 = flip_f64(r1, again);
+                note_repair(g.rep, !differ(r1, r2), -1, r0 + lane, j, step, acc1, acc2);
+                acc1 = r1;
+                acc2 = r1;
+            }
+        }
+    }
+    double t1 = group_sum<64>(acc1);
+    if constexpr (DMR) {
+        const double t2 = group_sum<64>(dup(acc2));
+        if (differ(t1, t2)) {
+            const double r1 = group_sum<64>(dup(acc1));
+            const double r2 = group_sum<64>(dup(acc1));
+            if (lane == 0) note_repair(g.rep, !differ(r1, r2), -1, -1, j, -1, t1, t2);
+            t1 = r1;
+        }
+    }
+    if (lane != 0) return;
+    if (!g.direct) {
+        g.part[c * g.ldp + j] = t1;
+        return;
+    }
+    const double yv = g.beta != 0.0 ? g.y[j * g.incy] : 0.0;
+    g.y[j * g.incy] = out_value<DMR>(g, t1, yv, j);
+}
+
+// y_i := alpha sum_c part[c ldp + i] + beta y_i over the chunks.
+template <bool DMR>
+__global__ __launch_bounds__(kThreads) void gemv_reduce_kernel(Gv g, int64_t len, int64_t nparts)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= len) return;
+    double t1 = 0.0, t2 = 0.0;
+    for (int64_t c = 0; c < nparts; ++c) {
+        const double p = g.part[c * g.ldp + i];
+        t1 += p;
+        if constexpr (DMR) t2 += dup(p);
+    }
+    if constexpr (DMR) {
+        if (differ(t1, t2)) {
+            double r1 = 0.0, r2 = 0.0;
+            for (int64_t c = 0; c < nparts; ++c) {
+                const double p = g.part[c * g.ldp + i];
+                r1 += dup(p);
+                r2 += dup(p);
+            }
+            note_repair(g.rep, !differ(r1, r2), -1, i, -1, -1, t1, t2);
+            t1 = r1;
+        }
+    }
+    const double yv = g.beta != 0.0 ? g.y[i * g.incy] : 0.0;
+    g.y[i * g.incy] = out_value<DMR>(g, t1, yv, i);
+}
+
+// ------------------------------------------------------------------ DTRSV
+// Diagonal-block solve of the blocked DTRSV (§3.2: the update by the
+// solved part runs as a DGEMV, the small diagonal part by substitution).
+// One workgroup stages the block's triangle of op(A) in LDS, forms the
+// right-hand side r_i = x_i - sum_c part[c ldp + i], then wave 0 substitutes
+// with two rows per lane: x_k = r_k / a_kk (a multiplication by the
+// reciprocal formed while staging, as the paper's packing stores them),
+// then every row takes the term a_ik x_k.  Both copies of the substitution
+// run side by side; x_k is compared as it is formed.  A mismatch recomputes
+// r_k from the staged right-hand side and the unknowns solved so far, in the
+// order of the original updates, so a corrected x_k is bitwise the one a
+// fault-free run forms.
+struct Tv {
+    const double* A;
+    int64_t lda;
+    double* x;       // element 0
+    int64_t incx;
+    int64_t r0;      // first row of the block
+    int nb;          // rows in the block
+    int lower, trans, unit;
+    const double* part;
+    int nparts;
+    int64_t ldp;
+    int block;
+    DevReport* rep;
+};
+
+__device__ __forceinline__ double readlane_f64(double v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+template <bool DMR>
+__global__ __launch_bounds__(kThreads) void trsv_diag_kernel(Tv t, DmrPlan plan)
+{
+    // M[k kTrsvLd + i] = op(A)(r0 + i, r0 + k) inside the triangle, 0 outside
+    __shared__ double M[kTrsvB * kTrsvLd];
+    __shared__ double rhs[kTrsvB], xs[kTrsvB], dr[kTrsvB];
+    const int tid = threadIdx.x, nb = t.nb;
+    // 16 loads in flight per thread, then their LDS stores
+    constexpr int kBatch = 16;
+    for (int e0 = 0; e0 < kTrsvB * kTrsvB; e0 += kThreads * kBatch) {
+        double v[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            // consecutive threads read consecutive elements of a column of A
+            const int e = e0 + b * kThreads + tid;
+            const int i = t.trans ? e / kTrsvB : e % kTrsvB;
+            const int k = t.trans ? e % kTrsvB : e / kTrsvB;
+            const bool tri = i < nb && k < nb && (t.lower ? i >= k : i <= k);
+            const bool one = tri && i == k && t.unit;
+            v[b] = one ? 1.0 : 0.0;
+            if (tri && !one)
+                v[b] = t.trans ? t.A[(t.r0 + k) + (t.r0 + i) * t.lda] : t.A[(t.r0 + i) + (t.r0 + k) * t.lda];
+        }
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            const int e = e0 + b * kThreads + tid;
+            const int i = t.trans ? e / kTrsvB : e % kTrsvB;
+            const int k = t.trans ? e % kTrsvB : e / kTrsvB;
+            M[k * kTrsvLd + i] = v[b];
+        }
+    }
+    __syncthreads();
+    if (tid < kTrsvB) {
+        double q1 = 0.0, s1 = 0.0;
+        if (tid < nb) {
+            const double dg = M[tid * kTrsvLd + tid];
+            q1 = 1.0 / dg;
+            const int64_t gi = t.r0 + tid;
+            const double xi = t.x[gi * t.incx];
+            s1 = xi;
+            double s2 = xi;
+            int c = 0;
+            for (; c + 8 <= t.nparts; c += 8) {
+                double p[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) p[u] = t.part[(c + u) * t.ldp + tid];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    s1 = s1 - p[u];
+                    if constexpr (DMR) s2 = s2 - dup(p[u]);
+                }
+            }
+            for (; c < t.nparts; ++c) {
+                const double p = t.part[c * t.ldp + tid];
+                s1 = s1 - p;
+                if constexpr (DMR) s2 = s2 - dup(p);
+            }
+            if constexpr (DMR) {
+                const double q2 = 1.0 / dup(dg);
+                if (differ(q1, q2)) {
+                    const double a1 = 1.0 / dup(dg), a2 = 1.0 / dup(dg);
+                    note_repair(t.rep, !differ(a1, a2), t.block, gi, -1, 0, q1, q2);
+                    q1 = a1;
+                }
+                int again = -1;
+                for (int q = 0; q < plan.n; ++q) {
+                    const DmrFault f = plan.f[q];
+                    if (f.owner == t.block && f.step == tid && f.sub == 0)
+                        again = apply_fault(plan, f, s1, s2, t.rep, true, t.block, gi, -1, 0);
+                }
+                if (differ(s1, s2)) {
+                    double r1 = xi, r2 = xi;
+                    for (int c = 0; c < t.nparts; ++c) {
+                        const double p = t.part[c * t.ldp + tid];
+                        r1 = r1 - dup(p);
+                        r2 = r2 - dup(p);
+                    }
+                    if (again >= 0) r1 = flip_f64(r1, again);
+                    note_repair(t.rep, !differ(r1, r2), t.block, gi, -1, 0, s1, s2);
+                    s1 = r1;
+                }
+            }
+        }
+        dr[tid] = q1;
+        rhs[tid] = s1;
+    }
+    __syncthreads();
+    if (tid >= 64) return;
+    const int lane = tid;
+    double ra1 = rhs[lane], rb1 = rhs[lane + 64];
+    double ra2 = ra1, rb2 = rb1;
+    const double da = dr[lane], db = dr[lane + 64];
+    // steps of this block with a planned substitution fault (bit k of fm[k / 64])
+    uint64_t fm[2] = {0, 0};
+    if constexpr (DMR) {
+        for (int p = 0; p < plan.n; ++p)
+            if (plan.f[p].owner == t.block && plan.f[p].sub == 1) fm[plan.f[p].step >> 6] |= 1ull << (plan.f[p].step & 63);
+    }
+    for (int q = 0; q < nb; ++q) {
+        const int k = t.lower ? q : nb - 1 - q;
+        const bool upper_half = k >= 64;
+        double x1 = readlane_f64(upper_half ? rb1 * db : ra1 * da, k & 63);
+        if constexpr (DMR) {
+            double x2 = readlane_f64(upper_half ? rb2 * dup(db) : ra2 * dup(da), k & 63);
+            int again = -1;
+            if ((fm[k >> 6] >> (k & 63)) & 1) {
+                for (int p = 0; p < plan.n; ++p) {
+                    const DmrFault f = plan.f[p];
+                    if (f.owner == t.block && f.step == k && f.sub == 1)
+                        again = apply_fault(plan, f, x1, x2, t.rep, lane == 0, t.block, t.r0 + k, -1, 1);
+                }
+            }
+            if (differ(x1, x2)) {
+                // r_k again from the staged right-hand side and the solved unknowns, in solve order
+                double y1 = rhs[k], y2 = rhs[k];
+                for (int s = 0; s < q; ++s) {
+                    const int pcol = t.lower ? s : nb - 1 - s;
+                    const double mv = M[pcol * kTrsvLd + k], xv = xs[pcol];
+                    y1 = fma(-dup(mv), xv, y1);
+                    y2 = fma(-dup(mv), xv, y2);
+                }
+                y1 = y1 * dup(dr[k]);
+                y2 = y2 * dup(dr[k]);
+                if (again >= 0) y1 = flip_f64(y1, again);
+                if (lane == 0) note_repair(t.rep, !differ(y1, y2), t.block, t.r0 + k, -1, 1, x1, x2);
+                x1 = y1;
+                x2 = y1;
+            }
+            if (lane == 0) xs[k] = x1;
+            const double ma = M[k * kTrsvLd + lane], mb = M[k * kTrsvLd + lane + 64];
+            ra1 = fma(-ma, x1, ra1);
+            rb1 = fma(-mb, x1, rb1);
+            ra2 = fma(-dup(ma), x2, ra2);
+            rb2 = fma(-dup(mb), x2, rb2);
+        } else {
+            if (lane == 0) xs[k] = x1;
+            const double ma = M[k * kTrsvLd + lane], mb = M[k * kTrsvLd + lane + 64];
+            ra1 = fma(-ma, x1, ra1);
+            rb1 = fma(-mb, x1, rb1);
+        }
+    }
+    // xs was written by lane 0 of this wave; LDS accesses of a wave complete in order
+    for (int h = 0; h < 2; ++h) {
+        const int i = lane + 64 * h;
+        if (i < nb) t.x[(t.r0 + i) * t.incx] = xs[i];
+    }
+}
+
+int64_t vec_blocks(int64_t n)
+{
+    int64_t b = (n + kVecStep * (kThreads / 64) - 1) / (kVecStep * (kThreads / 64));
+    return b < 1 ? 1 : (b > kVecMaxBlocks ? kVecMaxBlocks : b);
+}
+
+// Thread and step of element i of a DSCAL/DNRM2 launch with `nwaves` waves.
+void map_vec(DmrPlan& plan, int64_t nwaves)
+{
+    for (int q = 0; q < plan.n; ++q) {
+        DmrFault& f = plan.f[q];
+        const int64_t c = f.unit / kVecStep, r = f.unit % kVecStep;
+        f.owner = (c % nwaves) * 64 + r % 64;
+        f.step = (int)(c / nwaves);
+        f.sub = (int)(r / 64);
+    }
+}
+
+// Shape of a DGEMV launch: workgroups along the outputs, chunk width and
+// count along the reduction (aiming at kGvTarget workgroups, at most
+// max_chunks chunks).
+struct GvShape {
+    int64_t bout, width, chunks;
+};
+
+GvShape gv_shape(int trans, int64_t rows, int64_t cols, int64_t target, int64_t max_chunks)
+{
+    GvShape s;
+    const int64_t red = trans ? rows : cols;          // reduction length
+    const int64_t gran = trans ? kGtStep : 4 * kU;    // chunk width granularity
+    s.bout = trans ? (cols + kGtCols - 1) / kGtCols : (rows + kGnRows - 1) / kGnRows;
+    int64_t want = (target + s.bout - 1) / s.bout;
+    const int64_t most = (red + gran - 1) / gran;
+    if (want > most) want = most;
+    if (want > max_chunks) want = max_chunks;
+    if (want < 1) want = 1;
+    s.width = ((red + want - 1) / want + gran - 1) / gran * gran;
+    s.chunks = (red + s.width - 1) / s.width;
+    return s;
+}
+
+// Thread and step of DGEMV unit u (see dmr_units_gemv).
+void map_gemv(DmrPlan& plan, int trans, int64_t rows, int64_t cols, const GvShape& sh)
+{
+    for (int q = 0; q < plan.n; ++q) {
+        DmrFault& f = plan.f[q];
+        if (!trans) {
+            const int64_t i = f.unit % rows, j0 = (f.unit / rows) * kU;
+            const int64_t c = j0 / sh.width, wcols = sh.width / 4;
+            const int64_t wv = (j0 - c * sh.width) / wcols;
+            const int64_t step = (j0 - c * sh.width - wv * wcols) / kU;
+            const int64_t bid = c * sh.bout + i / kGnRows;
+            f.owner = bid * kThreads + wv * 64 + i % kGnRows;
+            f.step = (int)step;
+        } else {
+            const int64_t j = f.unit % cols, rest = f.unit / cols;
+            const int64_t lane = rest % 64, r0 = (rest / 64) * kGtStep;  // the lane's first row is r0 + lane
+            const int64_t c = r0 / sh.width;
+            const int64_t bid = c * sh.bout + j / kGtCols;
+            f.owner = bid * kThreads + (j % kGtCols) * 64 + lane;
+            f.step = (int)((r0 - c * sh.width) / kGtStep);
+        }
+        f.sub = 0;
+    }
+}
+
+template <bool DMR>
+hipError_t gemv_launch(int trans, const Gv& g, int64_t grid, const DmrPlan& plan, bool xunit, hipStream_t s)
+{
+    if (!trans) {
+        if (xunit) hipLaunchKernelGGL((gemv_n_kernel<DMR, true>), dim3((unsigned)grid), dim3(kThreads), 0, s, g, plan);
+        else hipLaunchKernelGGL((gemv_n_kernel<DMR, false>), dim3((unsigned)grid), dim3(kThreads), 0, s, g, plan);
+    } else {
+        if (xunit) hipLaunchKernelGGL((gemv_t_kernel<DMR, true>), dim3((unsigned)grid), dim3(kThreads), 0, s, g, plan);
+        else hipLaunchKernelGGL((gemv_t_kernel<DMR, false>), dim3((unsigned)grid), dim3(kThreads), 0, s, g, plan);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int64_t dmr_units_vec(int64_t n) { return n; }
+
+// Without transpose: (output row i, group of 8 consecutive columns g) as
+// u = i + m g.  Transposed: (output column j, lane group: the rows
+// 512 t + l + 64 u, u < 8, that one lane adds between two comparisons, for
+// every (t, l) with 512 t + l < m) as u = j + n (64 t + l).
+int64_t dmr_units_gemv(int trans, int64_t m, int64_t n)
+{
+    if (!trans) return m * ((n + kU - 1) / kU);
+    const int64_t groups = (m / kGtStep) * 64 + imin<int64_t>(64, m % kGtStep);
+    return n * groups;
+}
+
+int64_t dmr_units_trsv(int64_t n) { return n; }
+
+size_t dmr_nrm2_work_bytes(int64_t n) { return (size_t)vec_blocks(n) * 3 * sizeof(double); }
+
+size_t dmr_gemv_work_bytes(int trans, int64_t m, int64_t n)
+{
+    const GvShape sh = gv_shape(trans, m, n, kGvTarget, INT64_MAX);
+    return sh.chunks > 1 ? (size_t)sh.chunks * (size_t)(trans ? n : m) * sizeof(double) : 0;
+}
+
+size_t dmr_trsv_work_bytes(int64_t n) { return n > 0 ? (size_t)kTrsvB * kTrsvMaxParts * sizeof(double) : 0; }
+
+hipError_t launch_dmr_scal(double* x, int64_t n, int64_t inc, double alpha, bool dmr, DmrPlan plan, DevReport* rep,
+                           hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = vec_blocks(n), nwaves = blocks * (kThreads / 64);
+    map_vec(plan, nwaves);
+    const dim3 grid((unsigned)blocks), blk(kThreads);
+    if (dmr) {
+        if (inc == 1) hipLaunchKernelGGL((scal_kernel<true, true>), grid, blk, 0, s, x, n, inc, alpha, nwaves, plan, rep);
+        else hipLaunchKernelGGL((scal_kernel<true, false>), grid, blk, 0, s, x, n, inc, alpha, nwaves, plan, rep);
+    } else {
+        if (inc == 1) hipLaunchKernelGGL((scal_kernel<false, true>), grid, blk, 0, s, x, n, inc, alpha, nwaves, plan, rep);
+        else hipLaunchKernelGGL((scal_kernel<false, false>), grid, blk, 0, s, x, n, inc, alpha, nwaves, plan, rep);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_dmr_nrm2(const double* x, int64_t n, int64_t inc, double* out, double* work, bool dmr,
+                           DmrPlan plan, DevReport* rep, hipStream_t s)
+{
+    const int64_t blocks = vec_blocks(n), nwaves = blocks * (kThreads / 64);
+    map_vec(plan, nwaves);
+    const dim3 grid((unsigned)blocks), blk(kThreads);
+    if (dmr) {
+        if (inc == 1) hipLaunchKernelGGL((nrm2_part_kernel<true, true>), grid, blk, 0, s, x, n, inc, nwaves, work, plan, rep);
+        else hipLaunchKernelGGL((nrm2_part_kernel<true, false>), grid, blk, 0, s, x, n, inc, nwaves, work, plan, rep);
+        hipLaunchKernelGGL((nrm2_final_kernel<true>), dim3(1), blk, 0, s, work, (int)blocks, out, rep);
+    } else {
+        if (inc == 1) hipLaunchKernelGGL((nrm2_part_kernel<false, true>), grid, blk, 0, s, x, n, inc, nwaves, work, plan, rep);
+        else hipLaunchKernelGGL((nrm2_part_kernel<false, false>), grid, blk, 0, s, x, n, inc, nwaves, work, plan, rep);
+        hipLaunchKernelGGL((nrm2_final_kernel<false>), dim3(1), blk, 0, s, work, (int)blocks, out, rep);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_dmr_gemv(int trans, int64_t m, int64_t n, double alpha, const double* A, int64_t lda,
+                           const double* x, int64_t incx, double beta, double* y, int64_t incy, double* work,
+                           bool dmr, DmrPlan plan, DevReport* rep, hipStream_t s)
+{
+    const GvShape sh = gv_shape(trans, m, n, kGvTarget, INT64_MAX);
+    map_gemv(plan, trans, m, n, sh);
+    Gv g;
+    g.A = A;
+    g.lda = lda;
+    g.rows = m;
+    g.cols = n;
+    g.x = x;
+    g.incx = incx;
+    g.y = y;
+    g.incy = incy;
+    g.alpha = alpha;
+    g.beta = beta;
+    g.part = work;
+    g.ldp = trans ? n : m;
+    g.width = sh.width;
+    g.bout = sh.bout;
+    g.direct = sh.chunks == 1;
+    g.rep = rep;
+    const int64_t grid = sh.bout * sh.chunks;
+    hipError_t e = dmr ? gemv_launch<true>(trans, g, grid, plan, incx == 1, s)
+                       : gemv_launch<false>(trans, g, grid, plan, incx == 1, s);
+    if (e != hipSuccess || g.direct) return e;
+    const int64_t len = trans ? n : m;
+    const unsigned rgrid = (unsigned)((len + kThreads - 1) / kThreads);
+    if (dmr) hipLaunchKernelGGL((gemv_reduce_kernel<true>), dim3(rgrid), dim3(kThreads), 0, s, g, len, sh.chunks);
+    else hipLaunchKernelGGL((gemv_reduce_kernel<false>), dim3(rgrid), dim3(kThreads), 0, s, g, len, sh.chunks);
+    return hipGetLastError();
+}
+
+hipError_t launch_dmr_trsv(int lower, int trans, int unit, int64_t n, const double* A, int64_t lda, double* x,
+                           int64_t incx, double* work, bool dmr, DmrPlan plan, DevReport* rep, hipStream_t s)
+{
+    for (int q = 0; q < plan.n; ++q) {
+        plan.f[q].owner = plan.f[q].unit / kTrsvB;
+        plan.f[q].step = (int)(plan.f[q].unit % kTrsvB);
+    }
+    DmrPlan none;
+    none.n = 0;
+    none.target = 0;
+    const int64_t nblk = (n + kTrsvB - 1) / kTrsvB;
+    for (int64_t q = 0; q < nblk; ++q) {
+        const int64_t b = lower ? q : nblk - 1 - q;
+        const int64_t r0 = b * kTrsvB;
+        const int nbk = (int)imin<int64_t>(kTrsvB, n - r0);
+        const int64_t d0 = lower ? 0 : r0 + nbk, d1 = lower ? r0 : n;  // the solved part
+        int64_t nparts = 0;
+        if (d1 > d0) {
+            // partial sums of op(A)[block rows, solved columns] x[solved]
+            Gv g;
+            g.lda = lda;
+            g.x = x + d0 * incx;
+            g.incx = incx;
+            g.y = nullptr;
+            g.incy = 0;
+            g.alpha = 1.0;
+            g.beta = 0.0;
+            g.part = work;
+            g.ldp = kTrsvB;
+            g.direct = 0;
+            g.rep = rep;
+            if (!trans) {  // op(A)(i, j) = A(i, j)
+                g.A = A + r0 + d0 * lda;
+                g.rows = nbk;
+                g.cols = d1 - d0;
+            } else {       // op(A)(i, j) = A(j, i)
+                g.A = A + d0 + r0 * lda;
+                g.rows = d1 - d0;
+                g.cols = nbk;
+            }
+            const GvShape sh = gv_shape(trans, g.rows, g.cols, 256, kTrsvMaxParts);
+            g.width = sh.width;
+            g.bout = sh.bout;
+            nparts = sh.chunks;
+            const hipError_t e = dmr ? gemv_launch<true>(trans, g, sh.bout * sh.chunks, none, incx == 1, s)
+                                     : gemv_launch<false>(trans, g, sh.bout * sh.chunks, none, incx == 1, s);
+            if (e != hipSuccess) return e;
+        }
+        Tv t;
+        t.A = A;
+        t.lda = lda;
+        t.x = x;
+        t.incx = incx;
+        t.r0 = r0;
+        t.nb = nbk;
+        t.lower = lower;
+        t.trans = trans;
+        t.unit = unit;
+        t.part = work;
+        t.nparts = (int)nparts;
+        t.ldp = kTrsvB;
+        t.block = (int)b;
+        t.rep = rep;
+        if (dmr) hipLaunchKernelGGL((trsv_diag_kernel<true>), dim3(1), dim3(kThreads), 0, s, t, plan);
+        else hipLaunchKernelGGL((trsv_diag_kernel<false>), dim3(1), dim3(kThreads), 0, s, t, plan);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace ftg

@@ -187,6 +187,41 @@ struct TrsmDiag {
 int trsm_diag_max_nb();
 hipError_t launch_trsm_diag(const TrsmDiag& d, hipStream_t s);
 
+// ---- duplicated-computation (DMR) Level-1/2 routines (dmr.hip)
+// Injection plan of one call: up to kDmrMaxFaults verification units, each
+// with the bit to flip.  The caller fills unit, bit and sub (DTRSV: the phase,
+// 0 = residual, 1 = substitution); the launcher maps every unit to the thread
+// (owner) and verification step of its kernel.
+constexpr int kDmrMaxFaults = 64;
+struct DmrFault {
+    int64_t owner, unit;
+    int step, sub, bit, pad;
+};
+struct DmrPlan {
+    int n, target;
+    DmrFault f[kDmrMaxFaults];
+};
+// Verification units of each routine (the injector's slot count).
+int64_t dmr_units_vec(int64_t n);                                // DSCAL, DNRM2: elements
+int64_t dmr_units_gemv(int trans, int64_t m, int64_t n);          // see ftg_dgemv
+int64_t dmr_units_trsv(int64_t n);                               // elements of x
+// Workspace bytes of a call (0 when none is needed).
+size_t dmr_nrm2_work_bytes(int64_t n);
+size_t dmr_gemv_work_bytes(int trans, int64_t m, int64_t n);
+size_t dmr_trsv_work_bytes(int64_t n);
+// x: element 0 of the vector, inc its stride (positive for DSCAL/DNRM2).
+hipError_t launch_dmr_scal(double* x, int64_t n, int64_t inc, double alpha, bool dmr, DmrPlan plan,
+                           DevReport* rep, hipStream_t s);
+hipError_t launch_dmr_nrm2(const double* x, int64_t n, int64_t inc, double* out, double* work, bool dmr,
+                           DmrPlan plan, DevReport* rep, hipStream_t s);
+// y := alpha op(A) x + beta y with A m x n (lda), x/y element 0 and strides.
+hipError_t launch_dmr_gemv(int trans, int64_t m, int64_t n, double alpha, const double* A, int64_t lda,
+                           const double* x, int64_t incx, double beta, double* y, int64_t incy, double* work,
+                           bool dmr, DmrPlan plan, DevReport* rep, hipStream_t s);
+// x := op(A)^-1 x; lower = op(A) is lower triangular, trans = A read transposed.
+hipError_t launch_dmr_trsv(int lower, int trans, int unit, int64_t n, const double* A, int64_t lda, double* x,
+                           int64_t incx, double* work, bool dmr, DmrPlan plan, DevReport* rep, hipStream_t s);
+
 inline void dgemm_tile_shape(int id, int* bm, int* bn, int* bk)
 {
     *bk = 16;

@@ -129,6 +129,23 @@ uint64_t inv_mod(uint64_t a, uint64_t S)
     return (uint64_t)t;
 }
 
+// The keyed bijection of the injector's slots: slot(r) = a r + b mod S with
+// a coprime to S (drawn from the seed; a = 1 if no draw of 64 is coprime).
+void slot_affine(uint64_t seed, uint64_t S, uint64_t* a, uint64_t* b)
+{
+    *a = 1;
+    *b = 0;
+    if (S <= 1) return;
+    *b = ftg::splitmix64(seed, 0) % S;
+    for (uint64_t t = 1; t <= 64; ++t) {
+        const uint64_t cand = 1 + ftg::splitmix64(seed, t) % (S - 1);
+        if (gcd_u64(cand, S) == 1) {
+            *a = cand;
+            return;
+        }
+    }
+}
+
 }  // namespace
 
 namespace ftg {
@@ -148,17 +165,8 @@ bool make_inject(const ftg_inject* in, int64_t m, int64_t n, int64_t k, int64_t 
     if (F == 0 || slots <= 0) return true;
     if (slots >= (int64_t(1) << 32)) return false;
     const uint64_t S = (uint64_t)slots;
-    uint64_t a = 1, b = 0;
-    if (S > 1) {
-        b = splitmix64(in->seed, 0) % S;
-        for (uint64_t t = 1; t <= 64; ++t) {
-            const uint64_t cand = 1 + splitmix64(in->seed, t) % (S - 1);
-            if (gcd_u64(cand, S) == 1) {
-                a = cand;
-                break;
-            }
-        }
-    }
+    uint64_t a, b;
+    slot_affine(in->seed, S, &a, &b);
     ip->on = 1;
     ip->target = (int)in->target;
     ip->bit_lo = in->bit_lo;
@@ -890,6 +898,167 @@ ftg_status ftg_dtrsm(ftg_handle h, ftg_side side, ftg_uplo uplo, ftg_op transa, 
         }
     }
     return FTG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Injector of a duplicated-computation routine: F distinct verification
+// units out of S (F = n_faults, or ceil(ops * per_mac_rate)), unit r of the
+// plan = a r + b mod S by the slot bijection, each with a bit in
+// [bit_lo, bit_hi] (default 40..63) and a phase bit.  Empty when the routine
+// runs unprotected or without injector; false when F exceeds the plan's room.
+bool make_dmr_plan(const ftg_config* cfg, bool dmr, uint64_t S, double ops, ftg::DmrPlan* p)
+{
+    std::memset(p, 0, sizeof(*p));
+    if (!dmr || !cfg || !cfg->inject || S == 0) return true;
+    const ftg_inject* in = cfg->inject;
+    uint64_t F = in->n_faults;
+    if (F == 0 && in->per_mac_rate > 0.0) F = (uint64_t)std::ceil(ops * in->per_mac_rate);
+    if (F == 0) return true;
+    if (F > S) F = S;
+    if (F > (uint64_t)ftg::kDmrMaxFaults) return false;
+    uint64_t a, b;
+    slot_affine(in->seed, S, &a, &b);
+    int lo = in->bit_lo, hi = in->bit_hi;
+    if (lo == 0 && hi == 0) {
+        lo = 40;
+        hi = 63;
+    }
+    for (uint64_t r = 0; r < F; ++r) {
+        ftg::DmrFault& f = p->f[r];
+        f.unit = (int64_t)(((unsigned __int128)a * r + b) % S);
+        f.bit = lo + (int)(ftg::splitmix64(in->seed, 1024 + 8 * r + 3) % (uint64_t)(hi - lo + 1));
+        f.sub = (int)(ftg::splitmix64(in->seed, 1024 + 8 * r + 4) & 1);
+    }
+    p->n = (int)F;
+    p->target = (int)in->target;
+    return true;
+}
+
+// Injector checks shared by the duplicated-computation routines.
+bool dmr_inject_ok(const ftg_config* cfg)
+{
+    if (!cfg || !cfg->inject) return true;
+    const ftg_inject* in = cfg->inject;
+    return in->target <= FTG_TARGET_TWO_IN_SLOT && in->bit_lo >= 0 && in->bit_hi <= 63 &&
+           in->bit_lo <= in->bit_hi && in->per_mac_rate >= 0.0;
+}
+
+// Element 0 of a BLAS vector of n elements at stride inc (for a negative
+// stride, the last element in memory).
+template <typename T>
+T* vec_first(T* x, int64_t n, int64_t inc)
+{
+    return inc > 0 ? x : x + (1 - n) * inc;
+}
+
+}  // namespace
+
+extern "C" {
+
+ftg_status ftg_dscal(ftg_handle h, int64_t n, double alpha, double* x, int64_t incx, void* stream,
+                     const ftg_config* cfg)
+{
+    if (!h) return FTG_ERR_INVALID_ARG;
+    if (!dmr_inject_ok(cfg)) return set_err(h, 20);
+    if (n <= 0 || incx <= 0) return FTG_OK;
+    if (n >= (int64_t(1) << 40) || incx >= (int64_t(1) << 20)) return FTG_ERR_UNSUPPORTED;
+    const bool dmr = !cfg || cfg->abft;
+    ftg::DmrPlan plan;
+    if (!make_dmr_plan(cfg, dmr, (uint64_t)ftg::dmr_units_vec(n), (double)n, &plan)) return FTG_ERR_UNSUPPORTED;
+    return ftg::launch_dmr_scal(x, n, incx, alpha, dmr, plan, h->rep, (hipStream_t)stream) == hipSuccess
+               ? FTG_OK
+               : FTG_ERR_HIP;
+}
+
+ftg_status ftg_dnrm2(ftg_handle h, int64_t n, const double* x, int64_t incx, double* result, void* stream,
+                     const ftg_config* cfg)
+{
+    if (!h || !result) return FTG_ERR_INVALID_ARG;
+    if (!dmr_inject_ok(cfg)) return set_err(h, 20);
+    hipStream_t s = (hipStream_t)stream;
+    if (n <= 0 || incx <= 0) return ftg::launch_dscale(result, 1, 1, 1, 0.0, s) == hipSuccess ? FTG_OK : FTG_ERR_HIP;
+    if (n >= (int64_t(1) << 40) || incx >= (int64_t(1) << 20)) return FTG_ERR_UNSUPPORTED;
+    const bool dmr = !cfg || cfg->abft;
+    ftg::DmrPlan plan;
+    if (!make_dmr_plan(cfg, dmr, (uint64_t)ftg::dmr_units_vec(n), (double)n, &plan)) return FTG_ERR_UNSUPPORTED;
+    const ftg_status st = ensure_work(h, ftg::dmr_nrm2_work_bytes(n), s);
+    if (st != FTG_OK) return st;
+    return ftg::launch_dmr_nrm2(x, n, incx, result, (double*)h->d_work, dmr, plan, h->rep, s) == hipSuccess
+               ? FTG_OK
+               : FTG_ERR_HIP;
+}
+
+ftg_status ftg_dgemv(ftg_handle h, ftg_op trans, int64_t m, int64_t n, double alpha, const double* A,
+                     int64_t lda, const double* x, int64_t incx, double beta, double* y, int64_t incy,
+                     void* stream, const ftg_config* cfg)
+{
+    if (!h) return FTG_ERR_INVALID_ARG;
+    if (trans != FTG_OP_N && trans != FTG_OP_T) return set_err(h, 1);
+    if (m < 0) return set_err(h, 2);
+    if (n < 0) return set_err(h, 3);
+    if (lda < std::max<int64_t>(1, m)) return set_err(h, 6);
+    if (incx == 0) return set_err(h, 8);
+    if (incy == 0) return set_err(h, 11);
+    if (!dmr_inject_ok(cfg)) return set_err(h, 20);
+    if (m == 0 || n == 0 || (alpha == 0.0 && beta == 1.0)) return FTG_OK;
+    if (m >= (int64_t(1) << 36) || n >= (int64_t(1) << 36) || std::abs(incx) >= (int64_t(1) << 20) ||
+        std::abs(incy) >= (int64_t(1) << 20))
+        return FTG_ERR_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    const bool dmr = !cfg || cfg->abft;
+    const int ta = trans == FTG_OP_T;
+    const int64_t lenx = ta ? m : n, leny = ta ? n : m;
+    if (alpha == 0.0) {
+        // y := beta y without reading A or x: the same elements in memory order
+        // (y is the lowest address of the vector for either sign of incy)
+        double* ylo = y;
+        const int64_t ainc = incy > 0 ? incy : -incy;
+        if (beta == 0.0) return ftg::launch_dscale(ylo, 1, leny, ainc, 0.0, s) == hipSuccess ? FTG_OK : FTG_ERR_HIP;
+        ftg::DmrPlan none;
+        std::memset(&none, 0, sizeof(none));
+        return ftg::launch_dmr_scal(ylo, leny, ainc, beta, dmr, none, h->rep, s) == hipSuccess ? FTG_OK
+                                                                                             : FTG_ERR_HIP;
+    }
+    ftg::DmrPlan plan;
+    if (!make_dmr_plan(cfg, dmr, (uint64_t)ftg::dmr_units_gemv(ta, m, n), (double)m * (double)n, &plan))
+        return FTG_ERR_UNSUPPORTED;
+    const ftg_status st = ensure_work(h, ftg::dmr_gemv_work_bytes(ta, m, n), s);
+    if (st != FTG_OK) return st;
+    return ftg::launch_dmr_gemv(ta, m, n, alpha, A, lda, vec_first(x, lenx, incx), incx, beta,
+                                vec_first(y, leny, incy), incy, (double*)h->d_work, dmr, plan, h->rep,
+                                s) == hipSuccess
+               ? FTG_OK
+               : FTG_ERR_HIP;
+}
+
+ftg_status ftg_dtrsv(ftg_handle h, ftg_uplo uplo, ftg_op trans, ftg_diag diag, int64_t n, const double* A,
+                     int64_t lda, double* x, int64_t incx, void* stream, const ftg_config* cfg)
+{
+    if (!h) return FTG_ERR_INVALID_ARG;
+    if (uplo != FTG_LOWER && uplo != FTG_UPPER) return set_err(h, 1);
+    if (trans != FTG_OP_N && trans != FTG_OP_T) return set_err(h, 2);
+    if (diag != FTG_NON_UNIT && diag != FTG_UNIT) return set_err(h, 3);
+    if (n < 0) return set_err(h, 4);
+    if (lda < std::max<int64_t>(1, n)) return set_err(h, 6);
+    if (incx == 0) return set_err(h, 8);
+    if (!dmr_inject_ok(cfg)) return set_err(h, 20);
+    if (n == 0) return FTG_OK;
+    if (n >= (int64_t(1) << 31) || std::abs(incx) >= (int64_t(1) << 20)) return FTG_ERR_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    const bool dmr = !cfg || cfg->abft;
+    ftg::DmrPlan plan;
+    if (!make_dmr_plan(cfg, dmr, (uint64_t)ftg::dmr_units_trsv(n), 0.5 * (double)n * (double)n, &plan))
+        return FTG_ERR_UNSUPPORTED;
+    const ftg_status st = ensure_work(h, ftg::dmr_trsv_work_bytes(n), s);
+    if (st != FTG_OK) return st;
+    const int lower_eff = (uplo == FTG_LOWER) == (trans == FTG_OP_N);
+    return ftg::launch_dmr_trsv(lower_eff, trans == FTG_OP_T, diag == FTG_UNIT, n, A, lda, vec_first(x, n, incx),
+                                incx, (double*)h->d_work, dmr, plan, h->rep, s) == hipSuccess
+               ? FTG_OK
+               : FTG_ERR_HIP;
 }
 
 ftg_status ftg_workspace_reserve(ftg_handle h, size_t bytes)

@@ -75,7 +75,7 @@ EXPORTS = [
     "ftg_tile_info", "ftg_tune_set", "ftg_tune_get", "ftg_timing_enable", "ftg_timing_read",
     "ftg_status_string", "ftg_dgemm_noalloc", "ftg_dgemm_noalloc_max_bytes",
     "ftg_workspace_reserve", "ftg_default_lambda", "ftg_dgemm_unfused", "ftg_dsymm", "ftg_dtrmm",
-    "ftg_dtrsm",
+    "ftg_dtrsm", "ftg_dscal", "ftg_dnrm2", "ftg_dgemv", "ftg_dtrsv",
 ]
 
 _lib = None
@@ -102,6 +102,11 @@ def load() -> ct.CDLL:
     lib.ftg_dtrmm.argtypes = [h, i32, i32, i32, i32, i64, i64, ct.c_double, vp, i64, vp, i64, vp,
                               ct.POINTER(Config)]
     lib.ftg_dtrsm.argtypes = lib.ftg_dtrmm.argtypes
+    lib.ftg_dscal.argtypes = [h, i64, ct.c_double, vp, i64, vp, ct.POINTER(Config)]
+    lib.ftg_dnrm2.argtypes = [h, i64, vp, i64, vp, vp, ct.POINTER(Config)]
+    lib.ftg_dgemv.argtypes = [h, i32, i64, i64, ct.c_double, vp, i64, vp, i64, ct.c_double, vp, i64, vp,
+                              ct.POINTER(Config)]
+    lib.ftg_dtrsv.argtypes = [h, i32, i32, i32, i64, vp, i64, vp, i64, vp, ct.POINTER(Config)]
     lib.ftg_dgemm_noalloc_max_bytes.argtypes = []
     lib.ftg_workspace_reserve.argtypes = [h, ct.c_size_t]
     lib.ftg_gemm_ex.argtypes = [h, i32, i32, i64, i64, i64, i32, i32, vp, vp, ct.c_float, vp, i64,
@@ -230,6 +235,26 @@ class Handle:
         st = self.lib.ftg_dtrsm(self.h, side, uplo, ta, diag, m, n, alpha, A_ptr, lda, B_ptr, ldb,
                                 stream, ct.byref(cfg) if cfg is not None else None)
         self._check(st, "ftg_dtrsm")
+
+    def dscal(self, n, alpha, x_ptr, incx, stream=None, cfg=None):
+        st = self.lib.ftg_dscal(self.h, n, alpha, x_ptr, incx, stream,
+                                ct.byref(cfg) if cfg is not None else None)
+        self._check(st, "ftg_dscal")
+
+    def dnrm2(self, n, x_ptr, incx, out_ptr, stream=None, cfg=None):
+        st = self.lib.ftg_dnrm2(self.h, n, x_ptr, incx, out_ptr, stream,
+                                ct.byref(cfg) if cfg is not None else None)
+        self._check(st, "ftg_dnrm2")
+
+    def dgemv(self, ta, m, n, alpha, A_ptr, lda, x_ptr, incx, beta, y_ptr, incy, stream=None, cfg=None):
+        st = self.lib.ftg_dgemv(self.h, ta, m, n, alpha, A_ptr, lda, x_ptr, incx, beta, y_ptr, incy,
+                                stream, ct.byref(cfg) if cfg is not None else None)
+        self._check(st, "ftg_dgemv")
+
+    def dtrsv(self, uplo, ta, diag, n, A_ptr, lda, x_ptr, incx, stream=None, cfg=None):
+        st = self.lib.ftg_dtrsv(self.h, uplo, ta, diag, n, A_ptr, lda, x_ptr, incx, stream,
+                                ct.byref(cfg) if cfg is not None else None)
+        self._check(st, "ftg_dtrsv")
 
     def workspace_reserve(self, nbytes: int):
         self._check(self.lib.ftg_workspace_reserve(self.h, nbytes), "ftg_workspace_reserve")
@@ -398,6 +423,49 @@ def dtrsm_f64(handle: Handle, A, B, alpha=1.0, side=LEFT, uplo=LOWER, ta=OP_N, d
     handle.dtrsm(side, uplo, ta, diag, m, n, alpha, ptr(A), max(1, A.shape[1]), ptr(B), max(1, B.shape[1]),
                  current_stream_ptr(), cfg)
     return B
+
+
+def _vec_len(buf, n, inc):
+    if n > 0 and inc != 0 and (n - 1) * abs(inc) >= buf.numel():
+        raise FtgError(ERR_INVALID_ARG, "vector buffer shorter than n elements at the stride")
+
+
+def dscal_f64(handle: Handle, x, alpha, n=None, incx=1, cfg=None):
+    """x := alpha x over n elements at stride incx of the float64 device tensor x."""
+    n = x.numel() if n is None else n
+    _vec_len(x, n, incx)
+    handle.dscal(n, alpha, ptr(x), incx, current_stream_ptr(), cfg)
+    return x
+
+
+def dnrm2_f64(handle: Handle, x, out, n=None, incx=1, cfg=None):
+    """out[0] := the Euclidean norm of n elements of x at stride incx (out: a
+    one-element float64 device tensor)."""
+    n = x.numel() if n is None else n
+    _vec_len(x, n, incx)
+    handle.dnrm2(n, ptr(x), incx, ptr(out), current_stream_ptr(), cfg)
+    return out
+
+
+def dgemv_f64(handle: Handle, A, x, y, alpha=1.0, beta=0.0, ta=OP_N, incx=1, incy=1, cfg=None):
+    """y := alpha op(A) x + beta y with A a column-major float64 device tensor
+    (see to_device) and x, y 1-D float64 device tensors read at their strides."""
+    m, n = A.shape[1], A.shape[0]
+    lenx, leny = (m, n) if ta else (n, m)
+    _vec_len(x, lenx, incx)
+    _vec_len(y, leny, incy)
+    handle.dgemv(ta, m, n, alpha, ptr(A), max(1, m), ptr(x), incx, beta, ptr(y), incy,
+                 current_stream_ptr(), cfg)
+    return y
+
+
+def dtrsv_f64(handle: Handle, A, x, uplo=LOWER, ta=OP_N, diag=NON_UNIT, incx=1, cfg=None):
+    """x := op(A)^-1 x with A a column-major float64 device tensor (the `uplo`
+    triangle read) and x a 1-D float64 device tensor read at stride incx."""
+    n = A.shape[1]
+    _vec_len(x, n, incx)
+    handle.dtrsv(uplo, ta, diag, n, ptr(A), max(1, n), ptr(x), incx, current_stream_ptr(), cfg)
+    return x
 
 
 def batch_problem(A, B, C, alpha=1.0, beta=0.0, ta=OP_N, tb=OP_N):
