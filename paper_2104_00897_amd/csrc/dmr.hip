@@ -22,6 +22,8 @@
 #include <limits.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "ftg_common.hpp"
 #include "ftg_kernels.hpp"
 
@@ -39,7 +41,6 @@ constexpr int kGtStep = 64 * kU;       // DGEMV transposed: rows per wave step
 constexpr int kGvTarget = 2048;        // DGEMV: workgroups aimed at per launch
 constexpr int kTrsvB = 128;            // DTRSV: order of the diagonal blocks
 constexpr int kTrsvLd = kTrsvB + 1;    // LDS leading dimension of a staged block
-constexpr int kTrsvMaxParts = 128;     // DTRSV: partial sums per row of a block update
 
 // Blue's scaling for binary64 (Blue, ACM TOMS 1978; thresholds as derived by
 // Anderson, ACM TOMS 2017): the squares of magnitudes in [tsml, tbig]
@@ -706,29 +707,39 @@ __global__ __launch_bounds__(kThreads) void gemv_reduce_kernel(Gv g, int64_t len
 }
 
 // ------------------------------------------------------------------ DTRSV
-// Diagonal-block solve of the blocked DTRSV (§3.2: the update by the
-// solved part runs as a DGEMV, the small diagonal part by substitution).
-// One workgroup stages the block's triangle of op(A) in LDS, forms the
-// right-hand side r_i = x_i - sum_c part[c ldp + i], then wave 0 substitutes
-// with two rows per lane: x_k = r_k / a_kk (a multiplication by the
-// reciprocal formed while staging, as the paper's packing stores them),
-// then every row takes the term a_ik x_k.  Both copies of the substitution
-// run side by side; x_k is compared as it is formed.  A mismatch recomputes
-// r_k from the staged right-hand side and the unknowns solved so far, in the
-// order of the original updates, so a corrected x_k is bitwise the one a
-// fault-free run forms.
-struct Tv {
+// Blocked DTRSV (§3.2: the update by the solved part is a DGEMV, the small
+// diagonal part a substitution) in one launch: one workgroup per block of
+// 128 rows, taken in solve order from a ticket counter.  Workgroup q
+//   - stages its block's triangle of op(A) in LDS;
+//   - for every block j solved before it, in solve order, loads its part of
+//     the block row of op(A) against block j (the loads leave before the
+//     wait), waits until block j is published, reads x_j and adds the
+//     products (duplicated, compared every 8 multiply-adds);
+//   - forms the right-hand side x_i - sum and substitutes (below);
+//   - writes its unknowns, then publishes them (release fence, flag store).
+// Tickets follow the order in which workgroups start, so every block a
+// workgroup waits for belongs to a workgroup already running, and no wait
+// can keep its producer from running.  Waits are bounded all the same: one
+// that runs out records an uncorrectable fault and goes on, so every
+// workgroup ends.
+//
+// Substitution (wave 0, two rows per lane): x_k = r_k / a_kk -- a
+// multiplication by the reciprocal formed while staging, as the paper's
+// packing stores them (§3.3.3) -- then every row takes the term a_ik x_k.
+// Both copies run side by side and x_k is compared as it is formed.  A
+// mismatch recomputes r_k from the staged right-hand side and the unknowns
+// solved so far, in the order of the original updates, so a corrected x_k
+// is bitwise the one a fault-free run forms.
+struct Tc {
     const double* A;
     int64_t lda;
-    double* x;       // element 0
+    double* x;             // element 0
     int64_t incx;
-    int64_t r0;      // first row of the block
-    int nb;          // rows in the block
+    int64_t n;
+    int nblk;
     int lower, trans, unit;
-    const double* part;
-    int nparts;
-    int64_t ldp;
-    int block;
+    unsigned int* sync;    // [0] ticket counter, [1 + b] block b published (zeroed before the launch)
+    int spin_limit;
     DevReport* rep;
 };
 
@@ -739,85 +750,261 @@ __device__ __forceinline__ double readlane_f64(double v, int l)
     return __hiloint2double(hi, lo);
 }
 
-template <bool DMR>
-__global__ __launch_bounds__(kThreads) void trsv_diag_kernel(Tv t, DmrPlan plan)
+// The block's triangle of op(A) into M[k kTrsvLd + i] = op(A)(r0 + i, r0 + k)
+// (0 outside the triangle and past nb; 1 on a unit diagonal, not read), 16
+// loads in flight per thread, consecutive threads reading consecutive
+// elements of a column of A.
+__device__ __forceinline__ void stage_tri(double* M, const Tc& t, int64_t r0, int nb)
 {
-    // M[k kTrsvLd + i] = op(A)(r0 + i, r0 + k) inside the triangle, 0 outside
-    __shared__ double M[kTrsvB * kTrsvLd];
-    __shared__ double rhs[kTrsvB], xs[kTrsvB], dr[kTrsvB];
-    const int tid = threadIdx.x, nb = t.nb;
-    // 16 loads in flight per thread, then their LDS stores
     constexpr int kBatch = 16;
     for (int e0 = 0; e0 < kTrsvB * kTrsvB; e0 += kThreads * kBatch) {
         double v[kBatch];
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
-            // consecutive threads read consecutive elements of a column of A
-            const int e = e0 + b * kThreads + tid;
+            const int e = e0 + b * kThreads + (int)threadIdx.x;
             const int i = t.trans ? e / kTrsvB : e % kTrsvB;
             const int k = t.trans ? e % kTrsvB : e / kTrsvB;
             const bool tri = i < nb && k < nb && (t.lower ? i >= k : i <= k);
             const bool one = tri && i == k && t.unit;
             v[b] = one ? 1.0 : 0.0;
-            if (tri && !one)
-                v[b] = t.trans ? t.A[(t.r0 + k) + (t.r0 + i) * t.lda] : t.A[(t.r0 + i) + (t.r0 + k) * t.lda];
+            if (tri && !one) v[b] = t.trans ? t.A[(r0 + k) + (r0 + i) * t.lda] : t.A[(r0 + i) + (r0 + k) * t.lda];
         }
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
-            const int e = e0 + b * kThreads + tid;
+            const int e = e0 + b * kThreads + (int)threadIdx.x;
             const int i = t.trans ? e / kTrsvB : e % kTrsvB;
             const int k = t.trans ? e % kTrsvB : e / kTrsvB;
             M[k * kTrsvLd + i] = v[b];
         }
     }
+}
+
+// Wave 0: solves the staged block for the right-hand side rhs (reciprocal
+// diagonal dr) and writes the unknowns to x.  Lane l holds rows l and l + 64
+// (halves 0 and 1).  The solve runs as two phases, one per half in solve
+// order (a lower block solves half 0 first, an upper one half 1); in the
+// first phase the other half's rows take every term too, in the second they
+// are done.  A step is a multiply, a broadcast (readlane) and one or two
+// multiply-adds per lane.  Steps go in unrolled chunks of 16 whose columns of
+// M sit in registers (the next chunk's are read while a chunk runs); a
+// chunk's unknowns reach LDS together at its end.  The chunk loop itself is
+// not unrolled: it runs once per block, on a cold instruction cache.
+template <bool DMR>
+__device__ __forceinline__ void substitute(const double* M, const double* rhs, const double* dr, double* xs,
+                                           const Tc& t, int64_t r0, int nb, int block, const DmrPlan& plan)
+{
+    const int lane = threadIdx.x;
+    double r1[2] = {rhs[lane], rhs[lane + 64]};
+    double r2[2] = {r1[0], r1[1]};
+    const double d[2] = {dr[lane], dr[lane + 64]};
+    // rows of this block with a planned substitution fault (bit k of fm[k / 64])
+    uint64_t fm[2] = {0, 0};
+    if constexpr (DMR) {
+        for (int f = 0; f < plan.n; ++f)
+            if (plan.f[f].owner == block && plan.f[f].sub == 1) fm[plan.f[f].step >> 6] |= 1ull << (plan.f[f].step & 63);
+    }
+    auto col = [&](int q) { return t.lower ? q : nb - 1 - q; };  // row solved at step q
+    constexpr int kStep = 16;
+    int done = 0;  // steps before the phase
+    auto phase = [&](auto hc, auto oc) __attribute__((always_inline)) {
+        constexpr int H = decltype(hc)::value;    // the half solved in this phase
+        constexpr bool UO = decltype(oc)::value;  // the other half still takes terms
+        const int nh = nb - 64 * H < 0 ? 0 : (nb - 64 * H > 64 ? 64 : nb - 64 * H);
+        auto krow = [&](int i) { return t.lower ? 64 * H + i : 64 * H + nh - 1 - i; };  // row of the phase's step i
+        double mh[kStep], mo[kStep];
+        auto load_chunk = [&](int i0, double* a, double* b) __attribute__((always_inline)) {
+#pragma unroll
+            for (int j = 0; j < kStep; ++j) {
+                const int kj = krow(i0 + j < nh ? i0 + j : nh - 1);
+                a[j] = M[kj * kTrsvLd + lane + 64 * H];
+                if (UO) b[j] = M[kj * kTrsvLd + lane + 64 * (1 - H)];
+            }
+        };
+        if (nh > 0) load_chunk(0, mh, mo);
+        for (int i0 = 0; i0 < nh; i0 += kStep) {
+            double nmh[kStep], nmo[kStep];
+            load_chunk(i0 + kStep < nh ? i0 + kStep : i0, nmh, nmo);
+            double xv[kStep];
+#pragma unroll
+            for (int j = 0; j < kStep; ++j) {
+                xv[j] = 0.0;
+                if (i0 + j >= nh) continue;  // uniform
+                const int k = krow(i0 + j);
+                double x1 = readlane_f64(r1[H] * d[H], k & 63);
+                if constexpr (DMR) {
+                    double x2 = readlane_f64(r2[H] * dup(d[H]), k & 63);
+                    int again = -1;
+                    if ((fm[H] >> (k & 63)) & 1) {
+                        for (int f = 0; f < plan.n; ++f) {
+                            const DmrFault ff = plan.f[f];
+                            if (ff.owner == block && ff.step == k && ff.sub == 1)
+                                again = apply_fault(plan, ff, x1, x2, t.rep, lane == 0, block, r0 + k, -1, 1);
+                        }
+                    }
+                    if (differ(x1, x2)) {
+                        // r_k again from the staged right-hand side and the solved
+                        // unknowns (this chunk's first), in solve order
+                        if (lane == 0) {
+#pragma unroll
+                            for (int jj = 0; jj < j; ++jj) xs[krow(i0 + jj)] = xv[jj];
+                        }
+                        const int pos = done + i0 + j;
+                        double y1 = rhs[k], y2 = rhs[k];
+                        for (int s2 = 0; s2 < pos; ++s2) {
+                            const int ks = col(s2);
+                            const double mv = M[ks * kTrsvLd + k], xq = xs[ks];
+                            y1 = fma(-dup(mv), xq, y1);
+                            y2 = fma(-dup(mv), xq, y2);
+                        }
+                        y1 = y1 * dup(dr[k]);
+                        y2 = y2 * dup(dr[k]);
+                        if (again >= 0) y1 = flip_f64(y1, again);
+                        if (lane == 0) note_repair(t.rep, !differ(y1, y2), block, r0 + k, -1, 1, x1, x2);
+                        x1 = y1;
+                        x2 = y1;
+                    }
+                    r2[H] = fma(-dup(mh[j]), x2, r2[H]);
+                    if (UO) r2[1 - H] = fma(-dup(mo[j]), x2, r2[1 - H]);
+                }
+                xv[j] = x1;
+                r1[H] = fma(-mh[j], x1, r1[H]);
+                if (UO) r1[1 - H] = fma(-mo[j], x1, r1[1 - H]);
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int j = 0; j < kStep; ++j)
+                    if (i0 + j < nh) xs[krow(i0 + j)] = xv[j];
+            }
+#pragma unroll
+            for (int j = 0; j < kStep; ++j) {
+                mh[j] = nmh[j];
+                if (UO) mo[j] = nmo[j];
+            }
+        }
+        done += nh;
+    };
+    if (t.lower) {
+        phase(std::integral_constant<int, 0>{}, std::true_type{});
+        phase(std::integral_constant<int, 1>{}, std::false_type{});
+    } else {
+        phase(std::integral_constant<int, 1>{}, std::true_type{});
+        phase(std::integral_constant<int, 0>{}, std::false_type{});
+    }
+    // xs was written by lane 0 of this wave; LDS accesses of a wave complete in order
+    if (lane < nb) t.x[(r0 + lane) * t.incx] = xs[lane];
+    if (lane + 64 < nb) t.x[(r0 + lane + 64) * t.incx] = xs[lane + 64];
+}
+
+template <bool DMR>
+__global__ __launch_bounds__(kThreads, 1) void trsv_chain_kernel(Tc t, DmrPlan plan)
+{
+    __shared__ double M[kTrsvB * kTrsvLd];
+    __shared__ double rhs[kTrsvB], xs[kTrsvB], dr[kTrsvB], xj[kTrsvB];
+    __shared__ double red[kThreads];
+    __shared__ int s_ticket, s_late;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        s_ticket = (int)atomicAdd(&t.sync[0], 1u);
+        s_late = 0;
+    }
     __syncthreads();
+    const int q = s_ticket;  // position in solve order
+    const int block = t.lower ? q : t.nblk - 1 - q;
+    const int64_t r0 = (int64_t)block * kTrsvB;
+    const int nb = (int)imin<int64_t>(kTrsvB, t.n - r0);
+    // this block's own entries of x: no other workgroup writes them
+    const double xi = tid < nb ? t.x[(r0 + tid) * t.incx] : 0.0;
+    stage_tri(M, t, r0, nb);
+
+    // products of the block row with the solved blocks: thread (i, h) takes
+    // row i and columns 16 c + 8 h + u (u < 8) of each chunk c of 16 columns
+    const int i = t.trans ? tid >> 1 : tid & (kTrsvB - 1);
+    const int h = t.trans ? tid & 1 : tid >> 7;
+    const bool rowok = i < nb;
+    const int64_t gi = r0 + (rowok ? i : 0);
+    double acc1 = 0.0, acc2 = 0.0;
+    for (int p = 0; p < q; ++p) {
+        const int j = t.lower ? p : t.nblk - 1 - p;
+        const int64_t c0 = (int64_t)j * kTrsvB;
+        const int nbj = (int)imin<int64_t>(kTrsvB, t.n - c0);
+        double a[8][kU];
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc)
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int c = cc * 16 + h * kU + u;
+                const bool ok = rowok && c < nbj;
+                const int64_t gc = c0 + (c < nbj ? c : 0);
+                const double v = t.trans ? t.A[gc + gi * t.lda] : t.A[gi + gc * t.lda];
+                a[cc][u] = ok ? v : 0.0;
+            }
+        if (tid == 0) {
+            int spins = 0;
+            while (__hip_atomic_load(&t.sync[1 + j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins >= t.spin_limit) {
+                    s_late = 1;
+                    break;
+                }
+            }
+        }
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (tid < kTrsvB) xj[tid] = tid < nbj ? t.x[(c0 + tid) * t.incx] : 0.0;
+        __syncthreads();
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) {
+            const double chk = acc1;
+#pragma unroll
+            for (int u = 0; u < kU; ++u) acc1 = fma(a[cc][u], xj[cc * 16 + h * kU + u], acc1);
+            if constexpr (DMR) {
+#pragma unroll
+                for (int u = 0; u < kU; ++u) acc2 = fma(dup(a[cc][u]), xj[cc * 16 + h * kU + u], acc2);
+                if (differ(acc1, acc2)) {
+                    double r1 = chk, r2 = chk;
+#pragma unroll
+                    for (int u = 0; u < kU; ++u) r1 = fma(dup(a[cc][u]), xj[cc * 16 + h * kU + u], r1);
+#pragma unroll
+                    for (int u = 0; u < kU; ++u) r2 = fma(dup(a[cc][u]), xj[cc * 16 + h * kU + u], r2);
+                    note_repair(t.rep, !differ(r1, r2), block, gi, c0 + cc * 16 + h * kU, p, acc1, acc2);
+                    acc1 = r1;
+                    acc2 = r1;
+                }
+            }
+        }
+        __syncthreads();  // xj is rewritten for the next block
+    }
+    red[tid] = acc1;
+    __syncthreads();
+    // right-hand side r_i = x_i - (both halves of the products), reciprocal diagonal
     if (tid < kTrsvB) {
         double q1 = 0.0, s1 = 0.0;
         if (tid < nb) {
+            const double pa = t.trans ? red[2 * tid] : red[tid];
+            const double pb = t.trans ? red[2 * tid + 1] : red[tid + kTrsvB];
             const double dg = M[tid * kTrsvLd + tid];
             q1 = 1.0 / dg;
-            const int64_t gi = t.r0 + tid;
-            const double xi = t.x[gi * t.incx];
-            s1 = xi;
-            double s2 = xi;
-            int c = 0;
-            for (; c + 8 <= t.nparts; c += 8) {
-                double p[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) p[u] = t.part[(c + u) * t.ldp + tid];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    s1 = s1 - p[u];
-                    if constexpr (DMR) s2 = s2 - dup(p[u]);
-                }
-            }
-            for (; c < t.nparts; ++c) {
-                const double p = t.part[c * t.ldp + tid];
-                s1 = s1 - p;
-                if constexpr (DMR) s2 = s2 - dup(p);
-            }
+            const int64_t g = r0 + tid;
+            s1 = xi - (pa + pb);
             if constexpr (DMR) {
+                double s2 = xi - (dup(pa) + dup(pb));
                 const double q2 = 1.0 / dup(dg);
                 if (differ(q1, q2)) {
                     const double a1 = 1.0 / dup(dg), a2 = 1.0 / dup(dg);
-                    note_repair(t.rep, !differ(a1, a2), t.block, gi, -1, 0, q1, q2);
+                    note_repair(t.rep, !differ(a1, a2), block, g, -1, 0, q1, q2);
                     q1 = a1;
                 }
                 int again = -1;
-                for (int q = 0; q < plan.n; ++q) {
-                    const DmrFault f = plan.f[q];
-                    if (f.owner == t.block && f.step == tid && f.sub == 0)
-                        again = apply_fault(plan, f, s1, s2, t.rep, true, t.block, gi, -1, 0);
+                for (int f = 0; f < plan.n; ++f) {
+                    const DmrFault ff = plan.f[f];
+                    if (ff.owner == block && ff.step == tid && ff.sub == 0)
+                        again = apply_fault(plan, ff, s1, s2, t.rep, true, block, g, -1, 0);
                 }
                 if (differ(s1, s2)) {
-                    double r1 = xi, r2 = xi;
-                    for (int c = 0; c < t.nparts; ++c) {
-                        const double p = t.part[c * t.ldp + tid];
-                        r1 = r1 - dup(p);
-                        r2 = r2 - dup(p);
-                    }
+                    double r1 = xi - (dup(pa) + dup(pb));
+                    const double r2 = xi - (dup(pa) + dup(pb));
                     if (again >= 0) r1 = flip_f64(r1, again);
-                    note_repair(t.rep, !differ(r1, r2), t.block, gi, -1, 0, s1, s2);
+                    note_repair(t.rep, !differ(r1, r2), block, g, -1, 0, s1, s2);
                     s1 = r1;
                 }
             }
@@ -827,64 +1014,24 @@ __global__ __launch_bounds__(kThreads) void trsv_diag_kernel(Tv t, DmrPlan plan)
     }
     __syncthreads();
     if (tid >= 64) return;
-    const int lane = tid;
-    double ra1 = rhs[lane], rb1 = rhs[lane + 64];
-    double ra2 = ra1, rb2 = rb1;
-    const double da = dr[lane], db = dr[lane + 64];
-    // steps of this block with a planned substitution fault (bit k of fm[k / 64])
-    uint64_t fm[2] = {0, 0};
-    if constexpr (DMR) {
-        for (int p = 0; p < plan.n; ++p)
-            if (plan.f[p].owner == t.block && plan.f[p].sub == 1) fm[plan.f[p].step >> 6] |= 1ull << (plan.f[p].step & 63);
-    }
-    for (int q = 0; q < nb; ++q) {
-        const int k = t.lower ? q : nb - 1 - q;
-        const bool upper_half = k >= 64;
-        double x1 = readlane_f64(upper_half ? rb1 * db : ra1 * da, k & 63);
-        if constexpr (DMR) {
-            double x2 = readlane_f64(upper_half ? rb2 * dup(db) : ra2 * dup(da), k & 63);
-            int again = -1;
-            if ((fm[k >> 6] >> (k & 63)) & 1) {
-                for (int p = 0; p < plan.n; ++p) {
-                    const DmrFault f = plan.f[p];
-                    if (f.owner == t.block && f.step == k && f.sub == 1)
-                        again = apply_fault(plan, f, x1, x2, t.rep, lane == 0, t.block, t.r0 + k, -1, 1);
-                }
-            }
-            if (differ(x1, x2)) {
-                // r_k again from the staged right-hand side and the solved unknowns, in solve order
-                double y1 = rhs[k], y2 = rhs[k];
-                for (int s = 0; s < q; ++s) {
-                    const int pcol = t.lower ? s : nb - 1 - s;
-                    const double mv = M[pcol * kTrsvLd + k], xv = xs[pcol];
-                    y1 = fma(-dup(mv), xv, y1);
-                    y2 = fma(-dup(mv), xv, y2);
-                }
-                y1 = y1 * dup(dr[k]);
-                y2 = y2 * dup(dr[k]);
-                if (again >= 0) y1 = flip_f64(y1, again);
-                if (lane == 0) note_repair(t.rep, !differ(y1, y2), t.block, t.r0 + k, -1, 1, x1, x2);
-                x1 = y1;
-                x2 = y1;
-            }
-            if (lane == 0) xs[k] = x1;
-            const double ma = M[k * kTrsvLd + lane], mb = M[k * kTrsvLd + lane + 64];
-            ra1 = fma(-ma, x1, ra1);
-            rb1 = fma(-mb, x1, rb1);
-            ra2 = fma(-dup(ma), x2, ra2);
-            rb2 = fma(-dup(mb), x2, rb2);
-        } else {
-            if (lane == 0) xs[k] = x1;
-            const double ma = M[k * kTrsvLd + lane], mb = M[k * kTrsvLd + lane + 64];
-            ra1 = fma(-ma, x1, ra1);
-            rb1 = fma(-mb, x1, rb1);
+    substitute<DMR>(M, rhs, dr, xs, t, r0, nb, block, plan);
+    // publish: the unknowns' stores complete and become visible device-wide before the flag
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (tid == 0) {
+        __hip_atomic_store(&t.sync[1 + block], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (s_late) {
+            // a wait ran out: the products used whatever x held then
+            atomicAdd(&t.rep->cnt[kDetected], 1ull);
+            atomicAdd(&t.rep->cnt[kUncorrectable], 1ull);
+            push_record(t.rep, 0, block, -1, 0, r0, -1, FTG_KIND_UNCORRECTABLE, 0.0, 0.0);
         }
     }
-    // xs was written by lane 0 of this wave; LDS accesses of a wave complete in order
-    for (int h = 0; h < 2; ++h) {
-        const int i = lane + 64 * h;
-        if (i < nb) t.x[(t.r0 + i) * t.incx] = xs[i];
-    }
+}
+
+__global__ void zero_u32_kernel(unsigned int* p, int64_t count)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = 0u;
 }
 
 int64_t vec_blocks(int64_t n)
@@ -991,7 +1138,7 @@ size_t dmr_gemv_work_bytes(int trans, int64_t m, int64_t n)
     return sh.chunks > 1 ? (size_t)sh.chunks * (size_t)(trans ? n : m) * sizeof(double) : 0;
 }
 
-size_t dmr_trsv_work_bytes(int64_t n) { return n > 0 ? (size_t)kTrsvB * kTrsvMaxParts * sizeof(double) : 0; }
+size_t dmr_trsv_work_bytes(int64_t n) { return n > 0 ? (size_t)((n + kTrsvB - 1) / kTrsvB + 1) * sizeof(unsigned int) : 0; }
 
 hipError_t launch_dmr_scal(double* x, int64_t n, int64_t inc, double alpha, bool dmr, DmrPlan plan, DevReport* rep,
                            hipStream_t s)
@@ -1069,68 +1216,27 @@ hipError_t launch_dmr_trsv(int lower, int trans, int unit, int64_t n, const doub
         plan.f[q].owner = plan.f[q].unit / kTrsvB;
         plan.f[q].step = (int)(plan.f[q].unit % kTrsvB);
     }
-    DmrPlan none;
-    none.n = 0;
-    none.target = 0;
     const int64_t nblk = (n + kTrsvB - 1) / kTrsvB;
-    for (int64_t q = 0; q < nblk; ++q) {
-        const int64_t b = lower ? q : nblk - 1 - q;
-        const int64_t r0 = b * kTrsvB;
-        const int nbk = (int)imin<int64_t>(kTrsvB, n - r0);
-        const int64_t d0 = lower ? 0 : r0 + nbk, d1 = lower ? r0 : n;  // the solved part
-        int64_t nparts = 0;
-        if (d1 > d0) {
-            // partial sums of op(A)[block rows, solved columns] x[solved]
-            Gv g;
-            g.lda = lda;
-            g.x = x + d0 * incx;
-            g.incx = incx;
-            g.y = nullptr;
-            g.incy = 0;
-            g.alpha = 1.0;
-            g.beta = 0.0;
-            g.part = work;
-            g.ldp = kTrsvB;
-            g.direct = 0;
-            g.rep = rep;
-            if (!trans) {  // op(A)(i, j) = A(i, j)
-                g.A = A + r0 + d0 * lda;
-                g.rows = nbk;
-                g.cols = d1 - d0;
-            } else {       // op(A)(i, j) = A(j, i)
-                g.A = A + d0 + r0 * lda;
-                g.rows = d1 - d0;
-                g.cols = nbk;
-            }
-            const GvShape sh = gv_shape(trans, g.rows, g.cols, 256, kTrsvMaxParts);
-            g.width = sh.width;
-            g.bout = sh.bout;
-            nparts = sh.chunks;
-            const hipError_t e = dmr ? gemv_launch<true>(trans, g, sh.bout * sh.chunks, none, incx == 1, s)
-                                     : gemv_launch<false>(trans, g, sh.bout * sh.chunks, none, incx == 1, s);
-            if (e != hipSuccess) return e;
-        }
-        Tv t;
-        t.A = A;
-        t.lda = lda;
-        t.x = x;
-        t.incx = incx;
-        t.r0 = r0;
-        t.nb = nbk;
-        t.lower = lower;
-        t.trans = trans;
-        t.unit = unit;
-        t.part = work;
-        t.nparts = (int)nparts;
-        t.ldp = kTrsvB;
-        t.block = (int)b;
-        t.rep = rep;
-        if (dmr) hipLaunchKernelGGL((trsv_diag_kernel<true>), dim3(1), dim3(kThreads), 0, s, t, plan);
-        else hipLaunchKernelGGL((trsv_diag_kernel<false>), dim3(1), dim3(kThreads), 0, s, t, plan);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    unsigned int* sync = reinterpret_cast<unsigned int*>(work);
+    // a fill kernel, not a memset, so that the call can be captured in a graph
+    const int64_t zb = imin<int64_t>((nblk + 1 + 255) / 256, 1024);
+    hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)zb), dim3(256), 0, s, sync, nblk + 1);
+    Tc t;
+    t.A = A;
+    t.lda = lda;
+    t.x = x;
+    t.incx = incx;
+    t.n = n;
+    t.nblk = (int)nblk;
+    t.lower = lower;
+    t.trans = trans;
+    t.unit = unit;
+    t.sync = sync;
+    t.spin_limit = 1 << 22;
+    t.rep = rep;
+    if (dmr) hipLaunchKernelGGL((trsv_chain_kernel<true>), dim3((unsigned)nblk), dim3(kThreads), 0, s, t, plan);
+    else hipLaunchKernelGGL((trsv_chain_kernel<false>), dim3((unsigned)nblk), dim3(kThreads), 0, s, t, plan);
+    return hipGetLastError();
 }
 
 }  // namespace ftg
