@@ -425,6 +425,14 @@ def dmr_routines(torch, ftgemm, h, steps):
 
     n1 = 1 << 28
     x = rnd(n1)
+    # context: what torch's own streaming kernels reach on the same 2 GiB vector
+    y = torch.empty_like(x)
+    t = timed_ab(torch, {"copy": lambda: y.copy_(x), "scale": lambda: x.mul_(-1.0),
+                         "norm": lambda: torch.linalg.vector_norm(x)}, steps, 2)
+    out["torch_reference"] = {"copy_gbs": 16.0 * n1 / t["copy"] / 1e6, "mul_inplace_gbs": 16.0 * n1 / t["scale"] / 1e6,
+                              "vector_norm_gbs": 8.0 * n1 / t["norm"] / 1e6}
+    print(json.dumps({"torch_reference": out["torch_reference"]}), file=sys.stderr, flush=True)
+    del y
     leg("dscal_2^28", 16.0 * n1, lambda c: ftgemm.dscal_f64(h, x, -1.0, cfg=c), steps)
     res = torch.empty(1, dtype=torch.float64, device="cuda")
     leg("dnrm2_2^28", 8.0 * n1, lambda c: ftgemm.dnrm2_f64(h, x, res, cfg=c), steps)
@@ -450,7 +458,8 @@ def level3_routines(torch, ftgemm, h, steps, n=8192):
     (B := 1.5 op(A) B) and FT-DTRSM (B := 1.5 op(A)^-1 B), A lower, left, no
     transpose, at m = n = 8192, U[-1,1] operands (for DTRSM a well-conditioned
     triangle: diagonal in [1, 2], off-diagonal U[-1,1] * 0.5/n), protected with
-    one flip per 2^32 MACs against the same routine with ABFT off.  TFLOP/s
+    one flip per 2^32 MACs (and without injection) against the same routine
+    with ABFT off.  TFLOP/s
     count the routine's own multiply-adds: 2 m^2 n for DSYMM, m^2 n for DTRMM
     and DTRSM."""
     g = torch.Generator(device="cuda").manual_seed(11)
@@ -461,6 +470,7 @@ def level3_routines(torch, ftgemm, h, steps, n=8192):
     At.diagonal().copy_(torch.rand(n, generator=g, device="cuda", dtype=torch.float64) + 1.0)
     rate = 2.0 ** -32
     cp = ftgemm.make_config(seed=3, per_mac_rate=rate)
+    cn = ftgemm.make_config()
     cu = ftgemm.make_config(abft=False)
     out = {}
     for name, fl, fn in [
@@ -469,11 +479,14 @@ def level3_routines(torch, ftgemm, h, steps, n=8192):
         ("dtrsm", 1.0 * n ** 3, lambda c: (B.copy_(B0), ftgemm.dtrsm_f64(h, At, B, 1.5, 0, 0, 0, 0, c))),
     ]:
         h.reset()
-        t = timed_ab(torch, {"p": lambda: fn(cp), "u": lambda: fn(cu)}, max(2, steps // 2), 1)
+        t = timed_ab(torch, {"p": lambda: fn(cp), "n": lambda: fn(cn), "u": lambda: fn(cu)},
+                     max(2, steps // 2), 1)
         rep = h.read()
-        out[name] = {"m": n, "n": n, "ms_protected": t["p"], "ms_unprotected": t["u"],
+        out[name] = {"m": n, "n": n, "ms_protected": t["p"], "ms_protected_no_faults": t["n"],
+                     "ms_unprotected": t["u"],
                      "tflops_protected": fl / t["p"] / 1e9, "tflops_unprotected": fl / t["u"] / 1e9,
                      "overhead_pct": 100.0 * (t["p"] / t["u"] - 1.0),
+                     "overhead_no_faults_pct": 100.0 * (t["n"] / t["u"] - 1.0),
                      "faults": {"injected": rep.injected,
                                 "corrected": rep.corrected_subtract + rep.corrected_recompute,
                                 "uncorrectable": rep.uncorrectable}}

@@ -342,11 +342,12 @@ ftg_status ftg_dgemv(ftg_handle h, ftg_op trans, int64_t m, int64_t n, double al
                      void* stream, const ftg_config* cfg);
 
 /* FT-DTRSV: x := op(A)^-1 x, A n x n triangular (the `uplo` triangle read;
- * FTG_UNIT: unit diagonal, not read).  Blocked as in §3.2: for each block
- * of 128 rows in solve order, the update by the solved part runs as a
- * duplicated DGEMV pass, then one workgroup solves the diagonal block by
- * substitution, multiplying by reciprocals of the diagonal (formed as the
- * block is staged).  Units: the n unknowns; a fault hits the unknown's
+ * FTG_UNIT: unit diagonal, not read).  Blocked as in §3.2, in one launch:
+ * one workgroup per block of 128 rows, in solve order, adds the duplicated
+ * products of its block row with every block solved before it (waiting for
+ * each to be published), then solves its diagonal block by substitution,
+ * multiplying by reciprocals of the diagonal (formed as the block is
+ * staged).  The handle's workspace holds the blocks' flags.  Units: the n unknowns; a fault hits the unknown's
  * right-hand side after the update (phase 0) or the unknown as it is formed
  * (phase 1), chosen by the plan.  A corrected unknown is bitwise the
  * fault-free one.  xerbla positions: 1 uplo, 2 trans, 3 diag, 4 n, 6 lda,

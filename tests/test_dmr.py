@@ -75,6 +75,24 @@ def test_dscal_bitwise(env, n, incx, abft):
     assert h.read().detected == 0
 
 
+def test_dscal_unaligned_and_odd_lengths(env):
+    """A vector starting 8 bytes past a 16-byte boundary (the one-element path)
+    and lengths that end inside a run, against the 16-byte path's results."""
+    ftgemm, h, torch = env
+    rng = np.random.default_rng(77)
+    for n in (1, 2, 511, 513, 1025, 100001):
+        buf = rng.standard_normal(n + 1)
+        d = dev(torch, buf)
+        h.reset()
+        ftgemm.dscal_f64(h, d[1:], 0.375, n=n)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(host(d), np.concatenate([buf[:1], oracle.dscal(buf[1:], n, 0.375)]))
+        ftgemm.dscal_f64(h, d[1:], 2.0, n=n, cfg=ftgemm.make_config(seed=n, n_faults=min(n, 5)))
+        torch.cuda.synchronize()
+        rep = h.read()
+        assert rep.injected == min(n, 5) and rep.corrected_recompute == min(n, 5)
+
+
 def test_dscal_quick_returns_and_specials(env):
     ftgemm, h, torch = env
     buf = np.array([1.0, np.nan, np.inf, -0.0, 5.0])
@@ -171,6 +189,20 @@ def test_dnrm2_matches_oracle(env, n, incx, abft):
     got = nrm2(ftgemm, h, torch, buf, n, incx, ftgemm.make_config(abft=abft))
     ref = oracle.dnrm2(buf, n, incx)
     assert abs(got - ref) <= nrm2_bound(n) * ref
+
+
+def test_dnrm2_unaligned(env):
+    """The one-element path (a vector 8 bytes past a 16-byte boundary)."""
+    ftgemm, h, torch = env
+    rng = np.random.default_rng(78)
+    for n in (3, 777, 100001):
+        buf = rng.standard_normal(n + 1)
+        d = dev(torch, buf)
+        out = torch.full((1,), -1.0, dtype=torch.float64, device="cuda")
+        ftgemm.dnrm2_f64(h, d[1:], out, n=n)
+        torch.cuda.synchronize()
+        ref = oracle.dnrm2(buf[1:], n)
+        assert abs(float(out.item()) - ref) <= nrm2_bound(n) * ref
 
 
 @pytest.mark.parametrize("e", [0, 600, -600, -1070, 1000])
