@@ -283,7 +283,10 @@ ftg_status ftg_dtrmm(ftg_handle h, ftg_side side, ftg_uplo uplo, ftg_op transa, 
  * every protected step -- each update and each diagonal solve, numbered s
  * in execution order -- draws its own plan from seed SplitMix64(seed,
  * 2^33 + s); a diagonal solve's slots are its right-hand sides, and a flip
- * hits an unknown right after it is formed.  alpha = 0 sets B to 0.
+ * hits an unknown right after it is formed.  n_faults applies to each step;
+ * a per_mac_rate to the whole call: step s takes floor(d_s), d_s = its
+ * multiply-adds (nb (nb + 1) / 2 per right-hand side for a diagonal solve)
+ * times the rate plus d_{s-1} - floor(d_{s-1}).  alpha = 0 sets B to 0.
  * xerbla positions: 1 side, 2 uplo, 3 transa, 4 diag, 5 m, 6 n, 9 lda,
  * 11 ldb; 20 for an invalid injector. */
 ftg_status ftg_dtrsm(ftg_handle h, ftg_side side, ftg_uplo uplo, ftg_op transa, ftg_diag diag, int64_t m,

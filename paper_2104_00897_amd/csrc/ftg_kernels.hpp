@@ -183,9 +183,13 @@ struct TrsmDiag {
     int block;
     int verify;  // 0: no checksum verification (the unprotected solve)
     int64_t row0;
+    const double* wsum;  // verify: e^T M at wsum[c], e^T |M| at wsum[trsm_diag_max_nb() + c]
 };
 int trsm_diag_max_nb();
 hipError_t launch_trsm_diag(const TrsmDiag& d, hipStream_t s);
+// The column sums a verified solve of block d reads through d.wsum, into w
+// (2 * trsm_diag_max_nb() doubles).
+hipError_t launch_trsm_colsum(const TrsmDiag& d, double* w, hipStream_t s);
 
 // ---- duplicated-computation (DMR) Level-1/2 routines (dmr.hip)
 // Injection plan of one call: up to kDmrMaxFaults verification units, each

@@ -811,9 +811,12 @@ ftg_status ftg_dtrsm(ftg_handle h, ftg_side side, ftg_uplo uplo, ftg_op transa, 
     const bool abft = !cfg || cfg->abft;
     const int64_t rhs = side == FTG_LEFT ? n : m;   // right-hand sides
     const size_t enc = encode_bound(side == FTG_LEFT ? 1024 : m, side == FTG_LEFT ? n : 1024, ka);
-    ftg_status st = ensure_work(h, enc, s);
+    // after the encode region: the column sums of the diagonal block being solved
+    const size_t colsum_bytes = 2 * (size_t)ftg::trsm_diag_max_nb() * sizeof(double);
+    ftg_status st = ensure_work(h, enc + colsum_bytes, s);
     if (st != FTG_OK) return st;
     const EncodeBuffer eb{(double*)h->d_work, enc};
+    double* colsum = (double*)((char*)h->d_work + enc);
     const int ta = transa == FTG_OP_T;
     // op(A) lower triangular: the solve runs forward (left) / backward (right)
     const bool lower_eff = (uplo == FTG_LOWER) == (transa == FTG_OP_N);
@@ -821,13 +824,24 @@ ftg_status ftg_dtrsm(ftg_handle h, ftg_side side, ftg_uplo uplo, ftg_op transa, 
     auto opa = [&](int64_t r, int64_t c) { return ta ? A + c + r * lda : A + r + c * lda; };
     const int64_t NB = 1024, nbd = ftg::trsm_diag_max_nb();
     int step = 0;  // protected steps so far: each draws its own injection plan
-    auto step_cfg = [&](ftg_config* c, ftg_inject* in) -> const ftg_config* {
+    // a per-MAC rate applies to the whole call: each step takes the whole
+    // faults its multiply-adds are due, the fraction carried to the next step
+    // (rounding each step up would multiply the rate of the many small steps)
+    double carry = 0.0;
+    auto step_cfg = [&](ftg_config* c, ftg_inject* in, double macs) -> const ftg_config* {
         if (!cfg) return nullptr;
         *c = *cfg;
         if (cfg->inject) {
             *in = *cfg->inject;
             in->seed = ftg::splitmix64(cfg->inject->seed, (uint64_t(1) << 33) + (uint64_t)step);
-            c->inject = in;
+            if (in->n_faults == 0 && in->per_mac_rate > 0.0) {
+                const double due = macs * in->per_mac_rate + carry;
+                const double f = std::floor(due);
+                carry = due - f;
+                in->n_faults = (uint32_t)f;
+                in->per_mac_rate = 0.0;
+            }
+            c->inject = in->n_faults ? in : nullptr;
         }
         ++step;
         return c;
@@ -837,7 +851,7 @@ ftg_status ftg_dtrsm(ftg_handle h, ftg_side side, ftg_uplo uplo, ftg_op transa, 
         if (d1 <= d0) return FTG_OK;
         ftg_config c;
         ftg_inject in;
-        const ftg_config* pc = step_cfg(&c, &in);
+        const ftg_config* pc = step_cfg(&c, &in, (double)(k1 - k0) * (double)(d1 - d0) * (double)rhs);
         if (side == FTG_LEFT)
             return dgemm_impl(h, transa, FTG_OP_N, k1 - k0, n, d1 - d0, -1.0, opa(k0, d0), lda, B + d0, ldb, beta,
                               B + k0, ldb, stream, pc, eb);
@@ -863,12 +877,14 @@ ftg_status ftg_dtrsm(ftg_handle h, ftg_side side, ftg_uplo uplo, ftg_op transa, 
         d.block = block;
         d.verify = abft;
         d.row0 = k0;
+        d.wsum = colsum;
         ftg_config c;
         ftg_inject in;
-        const ftg_config* pc = step_cfg(&c, &in);
+        const ftg_config* pc = step_cfg(&c, &in, 0.5 * (double)d.nb * (double)(d.nb + 1) * (double)rhs);
         if (abft && pc && pc->inject &&
             !ftg::make_inject(pc->inject, d.nb, rhs, d.nb, rhs, 40, 63, &d.inj, 0, false))
             return FTG_ERR_UNSUPPORTED;
+        if (abft && ftg::launch_trsm_colsum(d, colsum, s) != hipSuccess) return FTG_ERR_HIP;
         return ftg::launch_trsm_diag(d, s) == hipSuccess ? FTG_OK : FTG_ERR_HIP;
     };
     // blocks in solve order

@@ -63,50 +63,12 @@ __global__ __launch_bounds__(256) void trsm_diag_kernel(TrsmDiag d)
     auto at = [&](int i, int c) -> double* { return d.R + (int64_t)i * d.rs + (c0 + c) * d.cs; };
     auto in_tri = [&](int r, int c) { return lower ? r >= c : r <= c; };
 
-    // column sums of M (the checksum row e^T M) and of |M|, read along the
-    // direction that is contiguous in memory
-    if (!d.verify) {
-    } else if (d.trans) {
-        // column c of M is row c of the stored block: a thread per column,
-        // kBatch rows loaded before they are added
+    // column sums of M (the checksum row e^T M) and of |M|, formed once per
+    // block by trsm_colsum_kernel
+    if (d.verify) {
         for (int c = tid; c < nb; c += 256) {
-            double s = 0.0, sa = 0.0;
-            for (int r0 = 0; r0 < nb; r0 += kBatch) {
-                double v[kBatch];
-#pragma unroll
-                for (int u = 0; u < kBatch; ++u)
-                    v[u] = (r0 + u < nb && in_tri(r0 + u, c)) ? m_at(d, r0 + u, c) : 0.0;
-#pragma unroll
-                for (int u = 0; u < kBatch; ++u) {
-                    s += v[u];
-                    sa += fabs(v[u]);
-                }
-            }
-            w[c] = s;
-            wa[c] = sa;
-        }
-    } else {
-        // column c is contiguous: a wave per column, lanes over its rows
-        const int lane = tid & 63;
-        for (int c = tid >> 6; c < nb; c += 4) {
-            double v[kMaxNb / 64];
-#pragma unroll
-            for (int u = 0; u < kMaxNb / 64; ++u) {
-                const int r = lane + 64 * u;
-                v[u] = (r < nb && in_tri(r, c)) ? m_at(d, r, c) : 0.0;
-            }
-            double s = 0.0, sa = 0.0;
-#pragma unroll
-            for (int u = 0; u < kMaxNb / 64; ++u) {
-                s += v[u];
-                sa += fabs(v[u]);
-            }
-            s = group_sum<64>(s);
-            sa = group_sum<64>(sa);
-            if (lane == 0) {
-                w[c] = s;
-                wa[c] = sa;
-            }
+            w[c] = d.wsum[c];
+            wa[c] = d.wsum[kMaxNb + c];
         }
     }
 
@@ -132,15 +94,33 @@ __global__ __launch_bounds__(256) void trsm_diag_kernel(TrsmDiag d)
         __syncthreads();
     };
     stage();
-    if (d.verify && tid < kRhs) {
-        double s = 0.0, sa = 0.0;
-        for (int i = 0; i < nb; ++i) {
-            s += Y[i][tid];
-            sa += fabs(Y[i][tid]);
+    // sums over the rows of each right-hand side, 8 threads per right-hand
+    // side (rows p, p + 8, ...), their partial sums added in a fixed order
+    __shared__ double part[2][8][kRhs];
+    auto col_sums = [&](auto term_a, auto term_b, double* out_a, double* out_b) __attribute__((always_inline)) {
+        const int c = tid % kRhs, p = tid / kRhs;
+        double a = 0.0, b = 0.0;
+        for (int i = p; i < nb; i += 8) {
+            a += term_a(i, c);
+            b += term_b(i, c);
         }
-        esum[tid] = s;
-        easum[tid] = sa;
-    }
+        part[0][p][c] = a;
+        part[1][p][c] = b;
+        __syncthreads();
+        if (tid < kRhs) {
+            double sa = 0.0, sb = 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                sa += part[0][q][tid];
+                sb += part[1][q][tid];
+            }
+            out_a[tid] = sa;
+            out_b[tid] = sb;
+        }
+        __syncthreads();
+    };
+    if (d.verify)
+        col_sums([&](int i, int c) { return Y[i][c]; }, [&](int i, int c) { return fabs(Y[i][c]); }, esum, easum);
     // planned faults of this workgroup's right-hand sides (slot = right-hand side)
     int f_step = -1, f_bit = 0, f_c = -1;
     if (d.inj.on && tid < nc) {
@@ -321,21 +301,25 @@ __global__ __launch_bounds__(256) void trsm_diag_kernel(TrsmDiag d)
     // threshold grows with the computed unknowns, so a fault that drives them
     // to overflow makes it infinite: such a check counts as failed too.
     auto bad = [](double dl, double tau) { return flagged(dl, tau) || !isfinite(tau); };
-    auto check = [&](int c, double* dl, double* tau) {
-        double ref = 0.0, mag = 0.0;
-        for (int i = 0; i < nb; ++i) {
-            ref = fma(w[i], Y[i][c], ref);
-            mag = fma(wa[i], fabs(Y[i][c]), mag);
+    __shared__ double cref[kRhs], cmag[kRhs];
+    // (every thread takes part; the difference and threshold of right-hand
+    // side c come out in thread c)
+    auto check = [&](int c, double* dl, double* tau) __attribute__((always_inline)) {
+        col_sums([&](int i, int cc) { return w[i] * Y[i][cc]; }, [&](int i, int cc) { return wa[i] * fabs(Y[i][cc]); },
+                 cref, cmag);
+        if (c < kRhs) {
+            *dl = cref[c] - esum[c];
+            *tau = tau_of(0, 0.0, 2 * (int64_t)nb + 8, cmag[c] + easum[c]);
         }
-        *dl = ref - esum[c];
-        *tau = tau_of(0, 0.0, 2 * (int64_t)nb + 8, mag + easum[c]);
     };
     double ratio = 0.0, dl0 = 0.0, tau0 = 0.0;
     int flag = 0;
-    if (d.verify && tid < nc) {
+    if (d.verify) {
         check(tid, &dl0, &tau0);
-        flag = bad(dl0, tau0);
-        if (!flag && tau0 > 0.0) ratio = fabs(dl0) / tau0;
+        if (tid < nc) {
+            flag = bad(dl0, tau0);
+            if (!flag && tau0 > 0.0) ratio = fabs(dl0) / tau0;
+        }
     }
     if (tid < kRhs) redo[tid] = flag;
     note_pass_ratio(d.rep, ratio);
@@ -344,9 +328,9 @@ __global__ __launch_bounds__(256) void trsm_diag_kernel(TrsmDiag d)
     if (__syncthreads_or(flag)) {
         stage();
         solve(false);
+        double dl = 0.0, tau = 0.0;
+        check(tid, &dl, &tau);
         if (tid < nc && redo[tid]) {
-            double dl, tau;
-            check(tid, &dl, &tau);
             const int kind = bad(dl, tau) ? FTG_KIND_UNCORRECTABLE : FTG_KIND_RECOMPUTE;
             atomicAdd(&d.rep->cnt[kDetected], 1ull);
             atomicAdd(&d.rep->cnt[kind == FTG_KIND_RECOMPUTE ? kCorrRecomp : kUncorrectable], 1ull);
@@ -368,9 +352,61 @@ __global__ __launch_bounds__(256) void trsm_diag_kernel(TrsmDiag d)
     }
 }
 
+// Column sums e^T M and e^T |M| of one diagonal block into w[c] and
+// w[kMaxNb + c]: without transpose a wave per column (contiguous in memory),
+// transposed a lane per column with the rows split over the four waves.
+__global__ __launch_bounds__(256) void trsm_colsum_kernel(TrsmDiag d, double* __restrict__ w)
+{
+    __shared__ double ps[4][64], pa[4][64];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nb = d.nb;
+    auto in_tri = [&](int r, int c) { return d.lower ? r >= c : r <= c; };
+    if (!d.trans) {
+        const int c = blockIdx.x * 4 + wv;
+        if (c >= nb) return;  // a whole wave; this branch has no barrier
+        double s = 0.0, sa = 0.0;
+        for (int r = lane; r < nb; r += 64) {
+            const double v = in_tri(r, c) ? m_at(d, r, c) : 0.0;
+            s += v;
+            sa += fabs(v);
+        }
+        s = group_sum<64>(s);
+        sa = group_sum<64>(sa);
+        if (lane == 0) {
+            w[c] = s;
+            w[kMaxNb + c] = sa;
+        }
+    } else {
+        const int c = blockIdx.x * 64 + lane;
+        double s = 0.0, sa = 0.0;
+        if (c < nb) {
+            for (int r = wv; r < nb; r += 4) {
+                const double v = in_tri(r, c) ? m_at(d, r, c) : 0.0;
+                s += v;
+                sa += fabs(v);
+            }
+        }
+        ps[wv][lane] = s;
+        pa[wv][lane] = sa;
+        __syncthreads();
+        if (wv == 0 && c < nb) {
+            w[c] = ((ps[0][lane] + ps[1][lane]) + ps[2][lane]) + ps[3][lane];
+            w[kMaxNb + c] = ((pa[0][lane] + pa[1][lane]) + pa[2][lane]) + pa[3][lane];
+        }
+    }
+}
+
 }  // namespace
 
 int trsm_diag_max_nb() { return kMaxNb; }
+
+hipError_t launch_trsm_colsum(const TrsmDiag& d, double* w, hipStream_t s)
+{
+    if (d.nb <= 0) return hipSuccess;
+    if (d.nb > kMaxNb) return hipErrorInvalidValue;
+    const unsigned g = d.trans ? (unsigned)((d.nb + 63) / 64) : (unsigned)((d.nb + 3) / 4);
+    hipLaunchKernelGGL(trsm_colsum_kernel, dim3(g), dim3(256), 0, s, d, w);
+    return hipGetLastError();
+}
 
 hipError_t launch_trsm_diag(const TrsmDiag& d, hipStream_t s)
 {
