@@ -890,6 +890,13 @@ __device__ __forceinline__ void substitute(const double* M, const double* rhs, c
             double nmh[kStep], nmo[kStep];
             load_chunk(i0 + kStep < nh ? i0 + kStep : i0, nmh, nmo);
             double xv[kStep];
+            // the chunk's steps compare the two copies of each unknown into one
+            // flag, checked at the chunk's end (a branch per step would
+            // serialise the two copies); a flagged chunk is done again from the
+            // rows as they were at its start
+            const double ck0 = r1[0], ck1 = r1[1];
+            bool bad = false;
+            uint32_t planned = 0;  // steps of the chunk with a planned fault (bit j)
 #pragma unroll
             for (int j = 0; j < kStep; ++j) {
                 xv[j] = 0.0;
@@ -898,21 +905,51 @@ __device__ __forceinline__ void substitute(const double* M, const double* rhs, c
                 double x1 = readlane_f64(r1[H] * d[H], k & 63);
                 if constexpr (DMR) {
                     double x2 = readlane_f64(r2[H] * dup(d[H]), k & 63);
-                    int again = -1;
                     if ((fm[H] >> (k & 63)) & 1) {
+                        planned |= 1u << j;
                         for (int f = 0; f < plan.n; ++f) {
                             const DmrFault ff = plan.f[f];
                             if (ff.owner == block && ff.step == k && ff.sub == 1)
-                                again = apply_fault(plan, ff, x1, x2, t.rep, lane == 0, block, r0 + k, -1, 1);
+                                apply_fault(plan, ff, x1, x2, t.rep, lane == 0, block, r0 + k, -1, 1);
                         }
+                    }
+                    bad |= differ(x1, x2);
+                    r2[H] = fma(-dup(mh[j]), x2, r2[H]);
+                    if (UO) r2[1 - H] = fma(-dup(mo[j]), x2, r2[1 - H]);
+                }
+                xv[j] = x1;
+                r1[H] = fma(-mh[j], x1, r1[H]);
+                if (UO) r1[1 - H] = fma(-mo[j], x1, r1[1 - H]);
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int j = 0; j < kStep; ++j)
+                    if (i0 + j < nh) xs[krow(i0 + j)] = xv[j];
+            }
+            if (DMR && bad) {
+                // the chunk again from its start, one step at a time, reading the
+                // columns from LDS and writing each unknown there as it is formed
+                r1[0] = r2[0] = ck0;
+                r1[1] = r2[1] = ck1;
+                int found = 0;
+#pragma unroll 1
+                for (int j = 0; j < kStep && i0 + j < nh; ++j) {
+                    const int k = krow(i0 + j);
+                    const double mhj = M[k * kTrsvLd + lane + 64 * H];
+                    const double moj = UO ? M[k * kTrsvLd + lane + 64 * (1 - H)] : 0.0;
+                    double x1 = readlane_f64(r1[H] * d[H], k & 63);
+                    double x2 = readlane_f64(r2[H] * dup(d[H]), k & 63);
+                    int again = -1;
+                    if (((planned >> j) & 1) && plan.target == FTG_TARGET_TWO_IN_SLOT) {
+                        // a fault that persists strikes the recomputation too
+                        for (int f = 0; f < plan.n; ++f)
+                            if (plan.f[f].owner == block && plan.f[f].step == k && plan.f[f].sub == 1) again = plan.f[f].bit;
+                        if (again >= 0) x1 = flip_f64(x1, again);
                     }
                     if (differ(x1, x2)) {
                         // r_k again from the staged right-hand side and the solved
-                        // unknowns (this chunk's first), in solve order
-                        if (lane == 0) {
-#pragma unroll
-                            for (int jj = 0; jj < j; ++jj) xs[krow(i0 + jj)] = xv[jj];
-                        }
+                        // unknowns, in solve order
+                        ++found;
                         const int pos = done + i0 + j;
                         double y1 = rhs[k], y2 = rhs[k];
                         for (int s2 = 0; s2 < pos; ++s2) {
@@ -927,18 +964,21 @@ __device__ __forceinline__ void substitute(const double* M, const double* rhs, c
                         if (lane == 0) note_repair(t.rep, !differ(y1, y2), block, r0 + k, -1, 1, x1, x2);
                         x1 = y1;
                         x2 = y1;
+                    } else if ((planned >> j) & 1) {
+                        // a planned fault the chunk check caught and the
+                        // recomputation no longer shows
+                        ++found;
+                        if (lane == 0) note_repair(t.rep, true, block, r0 + k, -1, 1, 0.0, 0.0);
                     }
-                    r2[H] = fma(-dup(mh[j]), x2, r2[H]);
-                    if (UO) r2[1 - H] = fma(-dup(mo[j]), x2, r2[1 - H]);
+                    if (lane == 0) xs[k] = x1;
+                    r2[H] = fma(-dup(mhj), x2, r2[H]);
+                    if (UO) r2[1 - H] = fma(-dup(moj), x2, r2[1 - H]);
+                    r1[H] = fma(-mhj, x1, r1[H]);
+                    if (UO) r1[1 - H] = fma(-moj, x1, r1[1 - H]);
                 }
-                xv[j] = x1;
-                r1[H] = fma(-mh[j], x1, r1[H]);
-                if (UO) r1[1 - H] = fma(-mo[j], x1, r1[1 - H]);
-            }
-            if (lane == 0) {
-#pragma unroll
-                for (int j = 0; j < kStep; ++j)
-                    if (i0 + j < nh) xs[krow(i0 + j)] = xv[j];
+                // a mismatch that the recomputation does not show again was
+                // transient: the recomputed unknowns are the corrected ones
+                if (found == 0 && lane == 0) note_repair(t.rep, true, block, r0 + krow(i0), -1, 1, 0.0, 0.0);
             }
 #pragma unroll
             for (int j = 0; j < kStep; ++j) {
