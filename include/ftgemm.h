@@ -435,7 +435,12 @@ int ftg_last_error_arg(ftg_handle h);
 
 /* Tile configurations: id >= 1.  Writes the tile shape (rows, columns,
  * k-block) of configuration `id` for operand type `ab_type`; returns
- * FTG_ERR_INVALID_ARG for an unknown id. */
+ * FTG_ERR_INVALID_ARG for an unknown id.  For FTG_BF16 and FTG_F8_E4M3 the
+ * shape is that of the checksum tile (the unit of verification, correction
+ * and fault-injection slots), 128 x 128 for both configurations: id 1 runs
+ * one such tile per workgroup, id 2 a 2 x 2 block of them (256 x 256
+ * outputs, eight waves) when K is a multiple of its k-block (32 steps for
+ * bf16) and the operands allow 16-byte loads, otherwise id 1's kernel. */
 ftg_status ftg_tile_info(ftg_dtype ab_type, int32_t id, int32_t* bm, int32_t* bn, int32_t* bk);
 
 /* Tuning table: the tile configuration used when cfg->tile == 0.  Entries

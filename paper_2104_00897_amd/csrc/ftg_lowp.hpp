@@ -49,7 +49,8 @@ struct LowpArgs {
     // plain mode: the k range split in `ksplit` slices (one workgroup per tile
     // and slice), slice s writing C + s cslice; protected mode: ER and EC hold
     // `slices` / `slices_c` such partial products, er_stride / ec_stride apart
-    int ksplit, slices, slices_c, pad2;
+    int ksplit, slices, slices_c;
+    int vec_c;  // C base 16-byte aligned and ldc a multiple of 4
     int64_t cslice, er_stride, ec_stride;
 };
 
@@ -91,6 +92,11 @@ template <typename STA, typename STB, bool F8MMA, int MODE>
 hipError_t launch_lowp_t(const LowpArgs& a, int ta, int tb, hipStream_t s);
 
 void lowp_tile_shape(ftg_dtype t, int id, int* bm, int* bn, int* bk);
+// tile configuration 2: workgroups of 2 x 2 checksum tiles (256 x 256 outputs),
+// k-contiguous operands with 16-byte rows and K a multiple of the k-block
+constexpr int kLowpWideTile = 2;
+bool lowp_wide_ok(const LowpArgs& a, ftg_dtype t);
+hipError_t launch_lowp_wide(const LowpArgs& a, ftg_dtype t, int mode, hipStream_t s);
 int lowp_heuristic_tile(ftg_dtype t, int64_t m, int64_t n, int64_t k);
 
 }  // namespace ftg

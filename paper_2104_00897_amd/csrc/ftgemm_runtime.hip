@@ -1170,6 +1170,7 @@ ftg_status ftg_gemm_ex(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n,
     a.tiles_n = (int)((n + bn - 1) / bn);
     a.vec_a = vec_ok(A, lda, eb);
     a.vec_b = vec_ok(B, ldb, eb);
+    a.vec_c = vec_ok(C, ldc, 4);
     a.alpha = alpha; a.beta = beta;
     a.scale_a = ab_type == FTG_F8_E4M3 ? scale_a : nullptr;
     a.scale_b = ab_type == FTG_F8_E4M3 ? scale_b : nullptr;
@@ -1205,9 +1206,11 @@ ftg_status ftg_gemm_ex(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n,
         a.B = P; a.ldb = (int)ldp; a.vec_b = vec_ok(P, ldp, eb);
     }
     const int ita = 1, itb = 0;  // op(A) rows and op(B) columns are k-contiguous from here on
+    const bool wide = tile == ftg::kLowpWideTile && ftg::lowp_wide_ok(a, ab_type);
     if (!abft) {
         LaunchTimer timer(h, s);
-        const hipError_t e = ftg::launch_lowp_gemm(a, ab_type, ab_type, ita, itb, 0, s);
+        const hipError_t e = wide ? ftg::launch_lowp_wide(a, ab_type, 0, s)
+                                  : ftg::launch_lowp_gemm(a, ab_type, ab_type, ita, itb, 0, s);
         timer.end();
         return e == hipSuccess ? FTG_OK : FTG_ERR_HIP;
     }

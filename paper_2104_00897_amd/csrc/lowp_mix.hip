@@ -373,16 +373,21 @@ hipError_t launch_sscale(float* C, int64_t m, int64_t n, int64_t ldc, float beta
 void lowp_tile_shape(ftg_dtype t, int id, int* bm, int* bn, int* bk)
 {
     *bm = *bn = *bk = 0;
-    if ((t == FTG_BF16 || t == FTG_F8_E4M3) && id == 1) {
+    // id 2 keeps the 128 x 128 checksum tile; its workgroups compute 2 x 2 of them
+    if ((t == FTG_BF16 || t == FTG_F8_E4M3) && (id == 1 || id == kLowpWideTile)) {
         *bm = kLowpTile;
         *bn = kLowpTile;
         *bk = kLowpBK;
     }
 }
 
-int lowp_heuristic_tile(ftg_dtype t, int64_t, int64_t, int64_t)
+int lowp_heuristic_tile(ftg_dtype t, int64_t m, int64_t n, int64_t)
 {
-    return (t == FTG_BF16 || t == FTG_F8_E4M3) ? 1 : 0;
+    if (t != FTG_BF16 && t != FTG_F8_E4M3) return 0;
+    // the wide tile once its workgroups fill the chip (256 CUs, one workgroup
+    // each); the 128 x 128 tile gives smaller problems four times as many
+    const int64_t wide_tiles = ((m + 255) / 256) * ((n + 255) / 256);
+    return wide_tiles >= 192 ? kLowpWideTile : 1;
 }
 
 }  // namespace ftg

@@ -1,0 +1,19 @@
+// Wide (256 x 256 workgroup tile) low-precision GEMM launches.
+#include "lowp_wide.hpp"
+
+namespace ftg {
+
+bool lowp_wide_ok(const LowpArgs& a, ftg_dtype t)
+{
+    const int bk = t == FTG_F8_E4M3 ? WCfg<true>::BK : WCfg<false>::BK;
+    return t == FTG_BF16 && a.vec_a && a.vec_b && a.k >= bk && a.k % bk == 0;
+}
+
+hipError_t launch_lowp_wide(const LowpArgs& a, ftg_dtype t, int mode, hipStream_t s)
+{
+    if (a.tiles_m <= 0 || a.tiles_n <= 0) return hipSuccess;
+    if (!lowp_wide_ok(a, t) || mode != 0) return hipErrorInvalidValue;
+    return launch_lowp_wide_t<false, 0>(a, s);
+}
+
+}  // namespace ftg

@@ -18,7 +18,7 @@ from . import ftgemm
 FP64_TILES = (1, 2, 3, 4, 5)
 FP64_INTERVAL_TILES = (2, 3, 5)
 FP64_BATCHED_TILES = (2, 3)
-LOWP_TILES = (1,)
+LOWP_TILES = (1, 2)
 
 
 def bucket(x: int) -> int:

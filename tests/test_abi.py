@@ -51,3 +51,8 @@ def test_status_strings_and_tile_table():
     assert ftgemm.tile_info(ftgemm.F64, 4) == (256, 128, 16)
     assert ftgemm.tile_info(ftgemm.F64, 5) == (128, 128, 16)
     assert ftgemm.tile_info(ftgemm.F64, 9) is None
+    # low precision: 128 x 128 checksum tiles; configuration 2 computes 2 x 2 per workgroup
+    assert ftgemm.tile_info(ftgemm.BF16, 1) == (128, 128, 64)
+    assert ftgemm.tile_info(ftgemm.BF16, 2) == (128, 128, 64)
+    assert ftgemm.tile_info(ftgemm.F8_E4M3, 2) == (128, 128, 64)
+    assert ftgemm.tile_info(ftgemm.BF16, 3) is None

@@ -42,5 +42,6 @@ def test_autotune_sets_handle():
         assert t.get(ftgemm.F64, m, n, k) in tune.FP64_TILES
         assert h.tune_get(ftgemm.F64, m, n, k) == t.get(ftgemm.F64, m, n, k)
     t2 = tune.autotune(h, [(512, 512, 256)], dtype=ftgemm.BF16, steps=2, warmup=1)
-    assert h.tune_get(ftgemm.BF16, 512, 512, 256) == t2.get(ftgemm.BF16, 512, 512, 256) == 1
+    assert t2.get(ftgemm.BF16, 512, 512, 256) in tune.LOWP_TILES
+    assert h.tune_get(ftgemm.BF16, 512, 512, 256) == t2.get(ftgemm.BF16, 512, 512, 256)
     h.close()
