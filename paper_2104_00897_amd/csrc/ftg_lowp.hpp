@@ -51,6 +51,11 @@ struct LowpArgs {
     // `slices` / `slices_c` such partial products, er_stride / ec_stride apart
     int ksplit, slices, slices_c;
     int vec_c;  // C base 16-byte aligned and ldc a multiple of 4
+    // wide tile, protected: the encode pass's bf16 checksum pieces of A and B
+    // (k-major rows of K elements; XSB after XSA, less than 2^31 bytes apart),
+    // multiplied inside the product instead of by separate GEMMs
+    const uint16_t* XSA;
+    const uint16_t* XSB;
     int64_t cslice, er_stride, ec_stride;
 };
 

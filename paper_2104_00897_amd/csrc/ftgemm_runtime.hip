@@ -1233,35 +1233,40 @@ ftg_status ftg_gemm_ex(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n,
     const int fx = (int)((std::max(m, n) + 255) / 256);
     if (ftg::launch_lowp_encode(e, ab_type, gx, fx, s) != hipSuccess) return FTG_ERR_HIP;
 
-    // checksum products: ER = op(A) [B_J e pieces], EC = [e^T A_I pieces]^T op(B)
-    ftg::LowpArgs c1;
-    std::memset(&c1, 0, sizeof(c1));
-    c1.A = a.A; c1.lda = a.lda; c1.B = eb_.XS; c1.ldb = (int)k;
-    c1.C = (float*)(w + L.er); c1.ldc = (int)m;
-    c1.m = (int)m; c1.n = 3 * a.tiles_n; c1.k = (int)k;
-    c1.tiles_m = a.tiles_m; c1.tiles_n = (c1.n + bn - 1) / bn;
-    c1.vec_a = a.vec_a; c1.vec_b = vec_ok(c1.B, k, 2);
-    c1.alpha = 1.0f; c1.beta = 0.0f;
-    c1.ksplit = ks_r; c1.cslice = (int64_t)m * 3 * a.tiles_n;
-    if (ftg::launch_lowp_gemm(c1, ab_type, FTG_BF16, ita, 0, 0, s) != hipSuccess) return FTG_ERR_HIP;
-    ftg::LowpArgs c2;
-    std::memset(&c2, 0, sizeof(c2));
-    c2.A = ea.XS; c2.lda = (int)k; c2.B = a.B; c2.ldb = a.ldb;
-    c2.C = (float*)(w + L.ec); c2.ldc = 3 * a.tiles_m;
-    c2.m = 3 * a.tiles_m; c2.n = (int)n; c2.k = (int)k;
-    c2.tiles_m = (c2.m + bm - 1) / bm; c2.tiles_n = a.tiles_n;
-    c2.vec_a = vec_ok(c2.A, k, 2); c2.vec_b = a.vec_b;
-    c2.alpha = 1.0f; c2.beta = 0.0f;
-    c2.ksplit = ks_c; c2.cslice = (int64_t)3 * a.tiles_m * n;
-    if (ftg::launch_lowp_gemm(c2, FTG_BF16, ab_type, 1, itb, 0, s) != hipSuccess) return FTG_ERR_HIP;
+    // the wide tile multiplies the checksum pieces inside the product
+    if (wide) {
+        a.XSA = ea.XS; a.XSB = eb_.XS;
+    } else {
+        // checksum products: ER = op(A) [B_J e pieces], EC = [e^T A_I pieces]^T op(B)
+        ftg::LowpArgs c1;
+        std::memset(&c1, 0, sizeof(c1));
+        c1.A = a.A; c1.lda = a.lda; c1.B = eb_.XS; c1.ldb = (int)k;
+        c1.C = (float*)(w + L.er); c1.ldc = (int)m;
+        c1.m = (int)m; c1.n = 3 * a.tiles_n; c1.k = (int)k;
+        c1.tiles_m = a.tiles_m; c1.tiles_n = (c1.n + bn - 1) / bn;
+        c1.vec_a = a.vec_a; c1.vec_b = vec_ok(c1.B, k, 2);
+        c1.alpha = 1.0f; c1.beta = 0.0f;
+        c1.ksplit = ks_r; c1.cslice = (int64_t)m * 3 * a.tiles_n;
+        if (ftg::launch_lowp_gemm(c1, ab_type, FTG_BF16, ita, 0, 0, s) != hipSuccess) return FTG_ERR_HIP;
+        ftg::LowpArgs c2;
+        std::memset(&c2, 0, sizeof(c2));
+        c2.A = ea.XS; c2.lda = (int)k; c2.B = a.B; c2.ldb = a.ldb;
+        c2.C = (float*)(w + L.ec); c2.ldc = 3 * a.tiles_m;
+        c2.m = 3 * a.tiles_m; c2.n = (int)n; c2.k = (int)k;
+        c2.tiles_m = (c2.m + bm - 1) / bm; c2.tiles_n = a.tiles_n;
+        c2.vec_a = vec_ok(c2.A, k, 2); c2.vec_b = a.vec_b;
+        c2.alpha = 1.0f; c2.beta = 0.0f;
+        c2.ksplit = ks_c; c2.cslice = (int64_t)3 * a.tiles_m * n;
+        if (ftg::launch_lowp_gemm(c2, FTG_BF16, ab_type, 1, itb, 0, s) != hipSuccess) return FTG_ERR_HIP;
+        a.ER = c1.C; a.lder = (int)m;
+        a.EC = c2.C; a.ldec = 3 * a.tiles_m;
+        a.slices = ks_r;
+        a.slices_c = ks_c;
+        a.er_stride = c1.cslice;
+        a.ec_stride = c2.cslice;
+    }
 
     // protected product
-    a.ER = c1.C; a.lder = (int)m;
-    a.EC = c2.C; a.ldec = 3 * a.tiles_m;
-    a.slices = ks_r;
-    a.slices_c = ks_c;
-    a.er_stride = c1.cslice;
-    a.ec_stride = c2.cslice;
     a.RA = ea.XR; a.MA = ea.XM; a.CB = eb_.XR; a.MB = eb_.XM;
     a.lambda = (cfg && cfg->lambda > 0.0) ? cfg->lambda : kDefaultLambda;
     a.problem = 0;
@@ -1271,7 +1276,8 @@ ftg_status ftg_gemm_ex(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n,
     }
     {
         LaunchTimer timer(h, s);
-        const hipError_t e = ftg::launch_lowp_gemm(a, ab_type, ab_type, ita, itb, 1, s);
+        const hipError_t e = wide ? ftg::launch_lowp_wide(a, ab_type, 1, s)
+                                  : ftg::launch_lowp_gemm(a, ab_type, ab_type, ita, itb, 1, s);
         timer.end();
         if (e != hipSuccess) return FTG_ERR_HIP;
     }

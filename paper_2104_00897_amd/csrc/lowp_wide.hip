@@ -12,8 +12,11 @@ bool lowp_wide_ok(const LowpArgs& a, ftg_dtype t)
 hipError_t launch_lowp_wide(const LowpArgs& a, ftg_dtype t, int mode, hipStream_t s)
 {
     if (a.tiles_m <= 0 || a.tiles_n <= 0) return hipSuccess;
-    if (!lowp_wide_ok(a, t) || mode != 0) return hipErrorInvalidValue;
-    return launch_lowp_wide_t<false, 0>(a, s);
+    if (!lowp_wide_ok(a, t)) return hipErrorInvalidValue;
+    if (mode == 1 && (!a.XSA || !a.XSB || a.XSB <= a.XSA ||
+                      (const char*)a.XSB - (const char*)a.XSA >= (int64_t(1) << 31)))
+        return hipErrorInvalidValue;
+    return mode ? launch_lowp_wide_t<false, 1>(a, s) : launch_lowp_wide_t<false, 0>(a, s);
 }
 
 }  // namespace ftg

@@ -11,15 +11,18 @@
 // Protected mode keeps the 128 x 128 checksum tiles of the other kernel (the
 // same slots, thresholds and repair requests; a workgroup checks its 2 x 2
 // tiles) but folds the maintained checksums into the product (§5.2: the
-// checksum updates reuse operand panels already staged for the product):
-//   row checksums A_I (B_J e):  the bf16 pieces of B_J e for the two tile
-//       columns of the workgroup ride along as six extra rows of the B stage,
-//       multiplied by the staged A fragments;
-//   column checksums (e^T A_I) B_J: the pieces of e^T A_I as six extra rows of
-//       the A stage, multiplied by the staged B fragments.
-// A wave adds two such MFMAs of each kind per k-step (32 + 4 in all), in FP32
-// accumulation like the data path.
+// checksum updates reuse the operand panels already staged for the product):
+//   row checksums A_I (B_J e): the three bf16 pieces of B_J e of the
+//       workgroup's two tile columns ride along as six extra B rows of every
+//       stage, multiplied by the A fragments already in registers;
+//   column checksums (e^T A_I) B_J: the pieces of e^T A_I likewise as six
+//       extra A rows, multiplied by the B fragments.
+// A wave adds two MFMAs of each kind per k-step (36 instead of 32), FP32
+// accumulation like the data path; the two thin checksum GEMMs of the
+// 128 x 128 path and their re-reads of A and B are gone.
 #pragma once
+#include <type_traits>
+
 #include "lowp_kernel.hpp"
 
 namespace ftg {
@@ -33,7 +36,7 @@ struct WCfg {
     static constexpr int ROWB = 64;
     static constexpr int A_BYTES = BM * ROWB, B_BYTES = BN * ROWB;  // 16 KB each
     static constexpr int X_BYTES = 1024;                             // checksum-piece rows
-    static constexpr int NSTAGE = 4;
+    static constexpr int NSTAGE = 4;  // a power of two
     static constexpr int LPW = (A_BYTES + B_BYTES) / 1024 / 8;       // wave loads per stage
 };
 
@@ -42,12 +45,66 @@ struct WCfg {
 // per pair of rows.
 __device__ __attribute__((always_inline)) inline int wide_swz(int r) { return (r >> 1) & 3; }
 
+// Waits until at most `later` blocks of this wave's loads (PER each) are in
+// flight, and for its LDS reads; then a barrier publishes the block.
+template <int PER>
+__device__ __attribute__((always_inline)) inline void wide_wait_blocks(int later)
+{
+    static_assert(3 * PER <= 15, "vmcnt field");
+    asm volatile("" ::: "memory");
+    // s_waitcnt: vmcnt = later * PER, expcnt unconstrained, lgkmcnt = 0
+    if (later >= 3) __builtin_amdgcn_s_waitcnt(0x70 | (3 * PER));
+    else if (later == 2) __builtin_amdgcn_s_waitcnt(0x70 | (2 * PER));
+    else if (later == 1) __builtin_amdgcn_s_waitcnt(0x70 | PER);
+    else __builtin_amdgcn_s_waitcnt(0x70);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// The kernel arguments (the only explicit argument, at the start of the
+// kernarg segment) through an opaque constant-space pointer: the epilogue's
+// scalar loads of them then stay after the k loop instead of holding scalar
+// registers through it.  (Taking the address of the argument itself would
+// copy it to private memory.)
+typedef const LowpArgs __attribute__((address_space(4)))* KArgsPtr;
+__device__ __attribute__((always_inline)) inline KArgsPtr launder_args()
+{
+    KArgsPtr p = (KArgsPtr)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(p));
+    return p;
+}
+__device__ __attribute__((always_inline)) inline InjectParams inject_of(KArgsPtr p)
+{
+    InjectParams ip;
+    ip.on = p->inj.on; ip.target = p->inj.target; ip.bit_lo = p->inj.bit_lo; ip.bit_hi = p->inj.bit_hi;
+    ip.seed = p->inj.seed; ip.S = p->inj.S; ip.F = p->inj.F; ip.a_inv = p->inj.a_inv; ip.b = p->inj.b;
+    return ip;
+}
+
+// Epilogue staging: 16 columns of 128 rows per wave, 132 floats per column
+// (the 4-float pad keeps the transposing writes and reads conflict-free).
+constexpr int kWideCP = 132;
+constexpr int kWideStgBytes = 8 * 16 * kWideCP * 4;
+
+// Verification bookkeeping of the protected kernel (after the staging area).
+struct WVerify {
+    float er[256][6];                  // row checksum pieces: [row][3 J + piece]
+    float ec[256][6];                  // column checksum pieces: [column][3 I + piece]
+    double rs[4][256];                 // row sums over each wave column's 64 columns
+    double cs[2][256];                 // column sums over each wave row's 128 rows
+    double cir[4][256], cira[4][256];  // the same of C_in and abs(C_in)
+    double cic[2][256], cica[2][256];
+    double dfi[4], tfi[4], dfj[4], tfj[4], exi[4], exj[4];
+    int nfr[4], nfc[4], fi[4], fj[4];
+};
+
 template <bool FP8, int MODE>
 __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
 {
     using Cf = WCfg<FP8>;
     constexpr int BM = Cf::BM, BN = Cf::BN, BK = Cf::BK, NS = Cf::NSTAGE;
     constexpr int STAGE = Cf::A_BYTES + Cf::B_BYTES + (MODE == 1 ? Cf::X_BYTES : 0);
+    static_assert(kWideStgBytes + (MODE == 1 ? sizeof(WVerify) : 0) <= NS * STAGE, "epilogue area");
     __shared__ __attribute__((aligned(16))) unsigned char smem[NS * STAGE];
 
     const int tid = threadIdx.x;
@@ -56,6 +113,13 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
     const int wr = wave >> 2, wc = wave & 3;
     const int wm0 = wr * Cf::WM, wn0 = wc * Cf::WN;
     const int l16 = lane & 15, lq = lane >> 4;
+    // Fragment order: A fragment g holds the wave's row block (g + rot_a) mod 8,
+    // B fragment h its column block (h + rot_b) mod 4.  Protected mode rotates
+    // them so that the row blocks whose checksums a wave updates (2 wc, 2 wc + 1)
+    // and the column blocks (2 wr, 2 wr + 1) are fragments 0 and 1 of every
+    // wave: the checksum MFMAs then take fixed registers (a uniform choice among
+    // fragments would cost branches or selects in the loop).
+    const int rot_a = MODE == 1 ? 2 * wc : 0, rot_b = MODE == 1 ? 2 * wr : 0;
 
     // wide tiles: (tiles_m + 1) / 2 x (tiles_n + 1) / 2 of the 128 x 128 tiles
     const int wtm = (args.tiles_m + 1) >> 1, wtn = (args.tiles_n + 1) >> 1;
@@ -64,7 +128,8 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
     const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
     const int R = (int)min((int64_t)BM, (int64_t)args.m - m0);
     const int Q = (int)min((int64_t)BN, (int64_t)args.n - n0);
-    const int nkb = args.k / BK;
+    const int K = args.k;
+    const int nkb = K / BK;
     const int64_t lda = args.lda, ldb = args.ldb;
     const unsigned char* A = (const unsigned char*)args.A;
     const unsigned char* B = (const unsigned char*)args.B;
@@ -85,11 +150,40 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
     }
     const bool a_wave = wave < 4;  // waves 0-3 load A, 4-7 load B
     const unsigned char* src0 = a_wave ? A + m0 * lda * Cf::EB : B + n0 * ldb * Cf::EB;
+    // protected: wave 0 adds one load per stage of the checksum pieces (k-major
+    // rows of K bf16), lanes 0-23 the six rows of e^T A_I of the workgroup's two
+    // tile rows, lanes 32-55 the six of B_J e; a missing second tile reads the
+    // last row (its checks are skipped)
+    const bool xw = MODE == 1 && wave == 0;
+    const unsigned char* XS = (const unsigned char*)args.XSA;
+    int xoff = 0;
+    bool xlane = false;
+    if constexpr (MODE == 1) {
+        const int64_t xsb = (const unsigned char*)args.XSB - XS;
+        if (lane < 24) {
+            const int r = min(6 * tm + lane / 4, 3 * args.tiles_m - 1);
+            xoff = (int)((int64_t)r * K * 2 + 16 * (lane % 4));
+            xlane = true;
+        } else if (lane >= 32 && lane < 56) {
+            const int j = lane - 32, r = min(6 * tn + j / 4, 3 * args.tiles_n - 1);
+            xoff = (int)(xsb + (int64_t)r * K * 2 + 16 * (j % 4));
+            xlane = true;
+        }
+    }
     auto issue = [&](int kb, int st) __attribute__((always_inline)) {
         unsigned char* base = smem + st * STAGE + (a_wave ? 0 : Cf::A_BYTES);
+        if (MODE == 1 && xw) {
+            if (xlane) lds_dma16(make_rsrc(XS + (int64_t)kb * 64), smem + st * STAGE + Cf::A_BYTES + Cf::B_BYTES, xoff);
+        }
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(src0 + (int64_t)kb * 64);
 #pragma unroll
         for (int u = 0; u < Cf::LPW; ++u) lds_dma16(rs, base + 1024 * ((wave * Cf::LPW + u) & 15), voff[u]);
+    };
+    // wait for a block whose successors (this wave's loads of them) may stay
+    // in flight, then publish it to every wave
+    auto wait_blocks = [&](int later) __attribute__((always_inline)) {
+        if (MODE == 1 && xw) wide_wait_blocks<Cf::LPW + 1>(later);
+        else wide_wait_blocks<Cf::LPW>(later);
     };
 
     f32x4_t acc[8][4];
@@ -97,30 +191,118 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
     for (int g = 0; g < 8; ++g)
 #pragma unroll
         for (int h = 0; h < 4; ++h) acc[g][h] = (f32x4_t){0.0f, 0.0f, 0.0f, 0.0f};
+    // protected: row checksums of rows 16 (2 wc + i) + .. against the pieces of
+    // B_J e (columns 3 J + piece), column checksums of columns 16 (2 wr + i) + ..
+    // against the pieces of e^T A_I (rows 3 I + piece)
+    f32x4_t accr[2], accc[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) accr[i] = accc[i] = (f32x4_t){0.0f, 0.0f, 0.0f, 0.0f};
+
+    // ---- injection plan of this wave's checksum tile (I, J) = (wr, wc / 2):
+    // up to two faults, applied to the accumulator after their k-block by the
+    // wave whose 64 columns hold them (the checksum target is applied to the
+    // expected sum in the epilogue).  Only the blocks stay live through the k
+    // loop; the rest of the plan is drawn again when a fault is applied.
+    const bool inj = MODE == 1 && args.inj.on;
+    const int tmw = 2 * tm + wr, tnw = 2 * tn + (wc >> 1);  // this wave's checksum tile
+    auto wave_faults = [&](const InjectParams& ip, int tiles_m, int tiles_n, int m, int n, int k, Fault* f2)
+        __attribute__((always_inline)) {
+        int nf = 0;
+        if (ip.on && ip.target != FTG_TARGET_CHECKSUM && tmw < tiles_m && tnw < tiles_n)
+            nf = slot_faults(ip, (uint64_t)tnw * tiles_m + tmw, min(128, m - 128 * tmw), min(128, n - 128 * tnw), 0,
+                             k, f2);
+        return nf;
+    };
+    // (the same plan in every lane; read from the first so that the k loop's
+    // control flow stays uniform)
+    int fkb[2] = {-1, -1};
+    if (inj) {
+        Fault f2[2];
+        const int nf = wave_faults(args.inj, args.tiles_m, args.tiles_n, args.m, args.n, K, f2);
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            fkb[q] = __builtin_amdgcn_readfirstlane(q < nf && f2[q].col / 64 == (wc & 1) ? (int)(f2[q].pflip / BK) : -1);
+    }
+    auto apply_fault = [&](int q) __attribute__((always_inline)) {
+        const KArgsPtr ar = launder_args();
+        const InjectParams ip = inject_of(ar);
+        Fault f2[2];
+        wave_faults(ip, ar->tiles_m, ar->tiles_n, ar->m, ar->n, ar->k, f2);
+        const int rr = __builtin_amdgcn_readfirstlane(f2[q].row), col = __builtin_amdgcn_readfirstlane(f2[q].col);
+        const int cc = col % 64, bit = __builtin_amdgcn_readfirstlane(f2[q].bit);
+        const bool own = lane == ((rr % 16) / 4) * 16 + cc % 16;
+        // fragment (g, h) = (rr / 16, cc / 16) by a uniform branch, then the
+        // element rr % 4 of the lane's four
+        const int gh = ((rr / 16 - rot_a) & 7) * 4 + ((cc / 16 - rot_b) & 3), re = rr % 4;
+        float oldv = 0.0f, newv = 0.0f;
+#pragma unroll
+        for (int g = 0; g < 8; ++g)
+#pragma unroll
+            for (int h = 0; h < 4; ++h)
+                if (g * 4 + h == gh) {
+                    f32x4_t v = acc[g][h];
+                    oldv = re == 0 ? v[0] : re == 1 ? v[1] : re == 2 ? v[2] : v[3];
+                    newv = flip_f32(oldv, bit);
+                    const float w = own ? newv : oldv;
+                    v[0] = re == 0 ? w : v[0];
+                    v[1] = re == 1 ? w : v[1];
+                    v[2] = re == 2 ? w : v[2];
+                    v[3] = re == 3 ? w : v[3];
+                    acc[g][h] = v;
+                }
+        if (own)
+            push_inject(ar->rep, ar->problem, tmw, tnw, 0, m0 + 128 * wr + rr, n0 + 128 * (wc >> 1) + col,
+                        f2[q].pflip, bit, FTG_TARGET_ACC, (double)oldv, (double)newv);
+    };
+    auto faults_after = [&](int kb) __attribute__((always_inline)) {
+        if (MODE == 1) {
+            if (kb == fkb[0]) apply_fault(0);
+            if (kb == fkb[1]) apply_fault(1);
+        }
+    };
 
     // fragment read offset inside a row: chunk lq, swizzled by the row (l16)
     const int fo = 16 * (lq ^ wide_swz(l16));
     // A fragments: one set, each refilled with the next block's as soon as
-    // its four MFMAs are issued; B fragments: two sets (every MFMA of a block
-    // reads all four)
-    bf16x8_t fa[8], fb[2][4];
+    // its four MFMAs are issued; B fragments: two sets; checksum-piece
+    // fragments (x[0]: e^T A_I rows, x[1]: B_J e rows; rows 6 and 7 of each
+    // only feed accumulator lanes that are never read): one set, refilled
+    // after the block's last MFMA
+    bf16x8_t fa[8], fb[2][4], fx[2];
     auto a_frag = [&](int st, int g) __attribute__((always_inline)) {
-        return *(const bf16x8_t*)(smem + st * STAGE + (wm0 + 16 * g + l16) * 64 + fo);
+        return *(const bf16x8_t*)(smem + st * STAGE + (wm0 + 16 * ((g + rot_a) & 7) + l16) * 64 + fo);
     };
     auto read_b = [&](int st, bf16x8_t* b) __attribute__((always_inline)) {
         const unsigned char* tb = smem + st * STAGE + Cf::A_BYTES;
 #pragma unroll
-        for (int h = 0; h < 4; ++h) b[h] = *(const bf16x8_t*)(tb + (wn0 + 16 * h + l16) * 64 + fo);
+        for (int h = 0; h < 4; ++h) b[h] = *(const bf16x8_t*)(tb + (wn0 + 16 * ((h + rot_b) & 3) + l16) * 64 + fo);
     };
-    // MFMAs of the current block; with st >= 0 each A fragment is then
-    // replaced by that of the block in stage st
-    auto mfmas = [&](const bf16x8_t* b, int st) __attribute__((always_inline)) {
+    auto read_x = [&](int st) __attribute__((always_inline)) {
+        if constexpr (MODE == 1) {
+            const unsigned char* tx = smem + st * STAGE + Cf::A_BYTES + Cf::B_BYTES + (l16 & 7) * 64 + 16 * lq;
+            fx[0] = *(const bf16x8_t*)tx;
+            fx[1] = *(const bf16x8_t*)(tx + 512);
+        }
+    };
+    // MFMAs of the current block; with `refill` each A fragment is then
+    // replaced by that of the block in stage st.  Protected: row checksums of
+    // A fragments 0 and 1 against x[1] (row blocks 2 wc and 2 wc + 1 after the
+    // rotation), column checksums of x[0] against B fragments 0 and 1 (column
+    // blocks 2 wr and 2 wr + 1).
+    auto mfmas = [&](const bf16x8_t* b, int st, auto refill) __attribute__((always_inline)) {
 #pragma unroll
         for (int g = 0; g < 8; ++g) {
 #pragma unroll
             for (int h = 0; h < 4; ++h)
                 acc[g][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[g], b[h], acc[g][h], 0, 0, 0);
-            if (st >= 0) fa[g] = a_frag(st, g);
+            if constexpr (MODE == 1) {
+                if (g < 2) accr[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[g], fx[1], accr[g], 0, 0, 0);
+                if (g == 7) {
+                    accc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fx[0], b[0], accc[0], 0, 0, 0);
+                    accc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fx[0], b[1], accc[1], 0, 0, 0);
+                }
+            }
+            if constexpr (decltype(refill)::value) fa[g] = a_frag(st, g);
             // keep the written order: the scheduler would otherwise sink the
             // reads below the last MFMAs and expose their latency
             __builtin_amdgcn_sched_barrier(0);
@@ -131,108 +313,271 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
     // are read while block kb's MFMAs run.  The wait for block kb + 1 (its
     // loads by every wave, then a barrier) also retires every wave's reads of
     // block kb, whose stage then takes the load of block kb + NS: NS - 1
-    // blocks stay in flight.
-    auto sync_for = [&](int kb) __attribute__((always_inline)) {
-        const int later = min(nkb - 1, kb + NS - 2) - kb;
-        asm volatile("" ::: "memory");
-        static_assert(2 * Cf::LPW <= 15, "vmcnt field");
-        if (later >= 2) __builtin_amdgcn_s_waitcnt(0x70 | (2 * Cf::LPW));
-        else if (later == 1) __builtin_amdgcn_s_waitcnt(0x70 | Cf::LPW);
-        else __builtin_amdgcn_s_waitcnt(0x70);
-        __builtin_amdgcn_s_barrier();
-        asm volatile("" ::: "memory");
-    };
-    // one k-block with a successor.  (The loop below keeps this body free of
-    // branches around LDS reads: the compiler's wait insertion merges states
-    // at such joins and would then wait for the fragments just requested.)
-    auto step = [&](int kb, bf16x8_t* cb, bf16x8_t* nb) __attribute__((always_inline)) {
-        sync_for(kb + 1);
+    // blocks stay in flight.  (The inner loop keeps its body free of branches
+    // around LDS reads: the compiler's wait insertion merges states at such
+    // joins and would then wait for the fragments just requested; injected
+    // faults are applied between segments of that loop.)
+    auto step = [&](int kb) __attribute__((always_inline)) {
+        wait_blocks(min(nkb - 1, kb + NS - 1) - (kb + 1));
         // the wait above retired the reads of this block's fragments; pass
         // them through an empty asm so that no wait for them is placed after
         // the next block's reads
 #pragma unroll
         for (int g = 0; g < 8; ++g) asm volatile("" : "+v"(fa[g]));
 #pragma unroll
-        for (int h = 0; h < 4; ++h) asm volatile("" : "+v"(cb[h]));
-        if (kb + NS < nkb) issue(kb + NS, kb % NS);
-        read_b((kb + 1) % NS, nb);
+        for (int h = 0; h < 4; ++h) asm volatile("" : "+v"(fb[0][h]));
+        if constexpr (MODE == 1) {
+            asm volatile("" : "+v"(fx[0]));
+            asm volatile("" : "+v"(fx[1]));
+        }
+        if (kb + NS < nkb) issue(kb + NS, kb & (NS - 1));
+        read_b((kb + 1) & (NS - 1), fb[1]);
         __builtin_amdgcn_sched_barrier(0);
-        mfmas(cb, (kb + 1) % NS);
+        mfmas(fb[0], (kb + 1) & (NS - 1), std::true_type{});
+#pragma unroll
+        for (int h = 0; h < 4; ++h) fb[0][h] = fb[1][h];
+        read_x((kb + 1) & (NS - 1));
     };
 #pragma unroll 1
     for (int b = 0; b < NS && b < nkb; ++b) issue(b, b);
     // block 0: this wave's loads of blocks 1 .. NS - 1 may stay in flight
-    {
-        const int later = min(nkb - 1, NS - 1);
-        asm volatile("" ::: "memory");
-        static_assert(3 * Cf::LPW <= 15, "vmcnt field");
-        if (later >= 3) __builtin_amdgcn_s_waitcnt(0x70 | (3 * Cf::LPW));
-        else if (later == 2) __builtin_amdgcn_s_waitcnt(0x70 | (2 * Cf::LPW));
-        else if (later == 1) __builtin_amdgcn_s_waitcnt(0x70 | Cf::LPW);
-        else __builtin_amdgcn_s_waitcnt(0x70);
-        __builtin_amdgcn_s_barrier();
-        asm volatile("" ::: "memory");
-    }
+    wait_blocks(min(nkb - 1, NS - 1));
 #pragma unroll
     for (int g = 0; g < 8; ++g) fa[g] = a_frag(0, g);
     read_b(0, fb[0]);
+    read_x(0);
+    for (int kb = 0; kb < nkb; ++kb) {
+        // the next block after which a fault is applied, else the last block
+        int stop = nkb - 1;
+        if (MODE == 1) {
+            if (fkb[0] >= kb) stop = min(stop, fkb[0]);
+            if (fkb[1] >= kb) stop = min(stop, fkb[1]);
+        }
 #pragma unroll 1
-    for (int kb = 0; kb + 1 < nkb; ++kb) {
-        step(kb, fb[0], fb[1]);
-#pragma unroll
-        for (int h = 0; h < 4; ++h) fb[0][h] = fb[1][h];
+        for (; kb < stop; ++kb) step(kb);
+        if (kb + 1 < nkb) step(kb);
+        else mfmas(fb[0], 0, std::false_type{});
+        faults_after(kb);
     }
-    mfmas(fb[0], -1);
 
     // ---- epilogue.  Lane (lq, l16) of fragment (g, h) holds rows
     // wm0 + 16 g + 4 lq + (0 .. 3) of column wn0 + 16 h + l16.  Column-major C
     // takes the tile through LDS, 16 columns of a wave at a time: each store
     // then writes two whole 512-byte column runs (the fragment layout would
     // scatter every store over 16 columns, one ldc apart).
-    const int64_t ldc = args.ldc;
-    const float as = args.alpha * (args.scale_a ? *args.scale_a : 1.0f) * (args.scale_b ? *args.scale_b : 1.0f);
-    const bool cin = args.beta != 0.0f;
-    const __amdgpu_buffer_rsrc_t rc = make_rsrc(args.C + m0 + n0 * ldc);
-    const bool vec_c = args.vec_c;
-    constexpr int CP = 132;  // LDS floats per staged column (128 rows + 4: conflict-free)
-    float* stg = (float*)smem + wave * (16 * CP);
+    const KArgsPtr ea = launder_args();
+    const int64_t ldc = ea->ldc;
+    const float as = ea->alpha * (ea->scale_a ? *ea->scale_a : 1.0f) * (ea->scale_b ? *ea->scale_b : 1.0f);
+    const bool cin = ea->beta != 0.0f;
+    const __amdgpu_buffer_rsrc_t rc = make_rsrc(ea->C + m0 + n0 * ldc);
+    const bool vec_c = ea->vec_c;
+    float* stg = (float*)smem + wave * (16 * kWideCP);
     // the lane's rows and column pair in the staged layout
     const int rl = 4 * (lane & 31), cl = lane >> 5;
     const int row = wm0 + rl;
+    WVerify& V = *(WVerify*)(smem + kWideStgBytes);
     __syncthreads();  // every wave is done with the ring
+    if constexpr (MODE == 1) {
+        // expected pieces from the checksum accumulators
 #pragma unroll
-    for (int h = 0; h < 4; ++h) {
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int g = 0; g < 8; ++g) *(f32x4_t*)(stg + l16 * CP + 16 * g + 4 * lq) = acc[g][h];
-        __builtin_amdgcn_wave_barrier();
+            for (int r = 0; r < 4; ++r) {
+                if (l16 < 6) V.er[wm0 + 16 * (2 * wc + i) + 4 * lq + r][l16] = accr[i][r];
+                if (4 * lq + r < 6) V.ec[wn0 + 16 * (2 * wr + i) + l16][4 * lq + r] = accc[i][r];
+            }
+        if (tid < 4) { V.nfr[tid] = 0; V.nfc[tid] = 0; }
+    }
+    // One pass over the tile: the final values alpha s acc + beta C_in; with
+    // `sums` their reference sums (binary64, §5.2; rows and columns outside the
+    // matrix excluded) and those of C_in; with `store` the stores.
+    auto pass = [&](bool store, bool sums) __attribute__((always_inline)) {
+        double rsl[4] = {0.0, 0.0, 0.0, 0.0}, cirl[4] = {0.0, 0.0, 0.0, 0.0}, cial[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int p = 0; p < 8; ++p) {
-            const int c = 2 * p + cl;
-            const int col = wn0 + 16 * h + c;
-            f32x4_t v = *(const f32x4_t*)(stg + c * CP + rl);
-            const bool colok = col < Q;
-            const int vo = (int)(((int64_t)col * ldc + row) * 4);
-            if (vec_c && colok && row + 4 <= R) {
+        for (int h = 0; h < 4; ++h) {
+#pragma unroll
+            for (int g = 0; g < 8; ++g) *(f32x4_t*)(stg + l16 * kWideCP + 16 * ((g + rot_a) & 7) + 4 * lq) = acc[g][h];
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll 1
+            for (int p = 0; p < 8; ++p) {
+                const int c = 2 * p + cl;
+                const int col = wn0 + 16 * ((h + rot_b) & 3) + c;
+                const f32x4_t v = *(const f32x4_t*)(stg + c * kWideCP + rl);
+                const bool colok = col < Q;
+                const bool full = colok && row + 4 <= R;
+                const int vo = (int)(((int64_t)col * ldc + row) * 4);
+                f32x4_t ci = (f32x4_t){0.0f, 0.0f, 0.0f, 0.0f};
                 if (cin) {
-                    const u32x4_t ci = __builtin_amdgcn_raw_buffer_load_b128(rc, vo, 0, 0);
+                    if (vec_c && full) {
+                        ci = __builtin_bit_cast(f32x4_t, __builtin_amdgcn_raw_buffer_load_b128(rc, vo, 0, 0));
+                    } else {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) v[r] = fmaf(as, v[r], args.beta * __uint_as_float(ci[r]));
-                } else {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) v[r] = as * v[r];
+                        for (int r = 0; r < 4; ++r)
+                            ci[r] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+                                rc, colok && row + r < R ? vo + 4 * r : kOOB, 0, 0));
+                    }
                 }
-                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, v), rc, vo, 0, 0);
-            } else {
+                f32x4_t x;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int o = colok && row + r < R ? vo + 4 * r : kOOB;
-                    float x = as * v[r];
-                    if (cin) x = fmaf(as, v[r], args.beta * __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rc, o, 0, 0)));
-                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), rc, o, 0, 0);
+                for (int r = 0; r < 4; ++r) x[r] = cin ? fmaf(as, v[r], ea->beta * ci[r]) : as * v[r];
+                if (MODE == 1 && sums) {
+                    // row sums here; column sums here only with C_in (without,
+                    // they were taken from the accumulators before staging)
+                    double s = 0.0, sc = 0.0, sca = 0.0;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const bool ok = colok && row + r < R;
+                        const double xv = ok ? (double)x[r] : 0.0;
+                        s += xv;
+                        rsl[r] += xv;
+                        if (cin) {
+                            const double cv = ok ? (double)ci[r] : 0.0;
+                            sc += cv;
+                            sca += fabs(cv);
+                            cirl[r] += cv;
+                            cial[r] += fabs(cv);
+                        }
+                    }
+                    if (cin) {
+                        s = group_sum<32>(s);
+                        sc = group_sum<32>(sc);
+                        sca = group_sum<32>(sca);
+                        if ((lane & 31) == 0) { V.cs[wr][col] = s; V.cic[wr][col] = sc; V.cica[wr][col] = sca; }
+                    }
+                }
+                if (store) {
+                    if (vec_c && full) {
+                        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, x), rc, vo, 0, 0);
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x[r]), rc,
+                                                                  colok && row + r < R ? vo + 4 * r : kOOB, 0, 0);
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (MODE == 1 && sums) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                rsl[r] += __shfl_xor(rsl[r], 32);
+                if (cin) {
+                    cirl[r] += __shfl_xor(cirl[r], 32);
+                    cial[r] += __shfl_xor(cial[r], 32);
+                }
+                if (lane < 32) {
+                    V.rs[wc][row + r] = rsl[r];
+                    if (cin) { V.cir[wc][row + r] = cirl[r]; V.cira[wc][row + r] = cial[r]; }
                 }
             }
         }
-        __builtin_amdgcn_wave_barrier();
+    };
+    if constexpr (MODE == 0) {
+        pass(true, false);
+    } else {
+        if (!cin) {
+            // column sums of the final values alpha s acc over the wave's 128
+            // rows, straight from the accumulators: the products are the ones
+            // the pass below stores (the same binary32 multiply)
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const int col = wn0 + 16 * ((h + rot_b) & 3) + l16;
+                double sh = 0.0;
+#pragma unroll
+                for (int g = 0; g < 8; ++g)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int rw = wm0 + 16 * ((g + rot_a) & 7) + 4 * lq + r;
+                        sh += (rw < R && col < Q) ? (double)(as * acc[g][h][r]) : 0.0;
+                    }
+                sh = quarter_sum(sh);
+                if (lq == 0) V.cs[wr][col] = sh;
+            }
+        }
+        // with beta != 0 the tile is stored by a second pass after the checks,
+        // which read C_in at a located element
+        const int npass = cin ? 2 : 1;
+#pragma unroll 1
+        for (int ps = 0; ps < npass; ++ps) {
+        pass(ps == npass - 1, ps == 0);
+        if (ps > 0) break;
+        __syncthreads();
+        const double asd = (double)as, bd = (double)ea->beta;
+        double pass_ratio = 0.0;
+        for (int line = tid; line < 1024; line += Cf::NT) {
+            const int t = line >> 8, I = t >> 1, J = t & 1;
+            const int tmc = 2 * tm + I, tnc = 2 * tn + J;
+            if (tmc >= ea->tiles_m || tnc >= ea->tiles_n) continue;
+            const int Rt = min(128, ea->m - 128 * tmc), Qt = min(128, ea->n - 128 * tnc);
+            const bool isrow = (line & 255) < 128;
+            const int xi = line & 127;
+            if (xi >= (isrow ? Rt : Qt)) continue;
+            double ref, ex, mag;
+            if (isrow) {
+                const int rw = 128 * I + xi;
+                ref = V.rs[2 * J][rw] + V.rs[2 * J + 1][rw];
+                double e = (double)V.er[rw][3 * J] + (double)V.er[rw][3 * J + 1] + (double)V.er[rw][3 * J + 2];
+                if (inj && ea->inj.target == FTG_TARGET_CHECKSUM) {
+                    const InjectParams ipe = inject_of(ea);
+                    Fault f2[2];
+                    const int nf = slot_faults(ipe, (uint64_t)tnc * ea->tiles_m + tmc, Rt, Qt, 0, K, f2);
+                    for (int q = 0; q < nf; ++q)
+                        if (f2[q].row == xi) {
+                            const float o = V.er[rw][3 * J];
+                            const float nv = flip_f32(o, f2[q].bit);
+                            e += (double)nv - (double)o;
+                            push_inject(ea->rep, ea->problem, tmc, tnc, 0, m0 + rw, -1, f2[q].pflip, f2[q].bit,
+                                        FTG_TARGET_CHECKSUM, (double)o, (double)nv);
+                        }
+                }
+                ex = asd * e;
+                mag = fabs(asd) * (double)ea->RA[m0 + rw] * (double)ea->MB[tnc];
+                if (cin) {
+                    ex += bd * (V.cir[2 * J][rw] + V.cir[2 * J + 1][rw]);
+                    mag += fabs(bd) * (V.cira[2 * J][rw] + V.cira[2 * J + 1][rw]);
+                }
+            } else {
+                const int cw = 128 * J + xi;
+                ref = V.cs[I][cw];
+                const double e = (double)V.ec[cw][3 * I] + (double)V.ec[cw][3 * I + 1] + (double)V.ec[cw][3 * I + 2];
+                ex = asd * e;
+                mag = fabs(asd) * (double)ea->CB[n0 + cw] * (double)ea->MA[tmc];
+                if (cin) { ex += bd * V.cic[I][cw]; mag += fabs(bd) * V.cica[I][cw]; }
+            }
+            const double d = ref - ex;
+            const double tau = tau_of(1, ea->lambda, (int64_t)(K + (isrow ? Qt : Rt) + 8), mag);
+            if (flagged(d, tau)) {
+                if (isrow) {
+                    if (atomicAdd(&V.nfr[t], 1) == 0) { V.fi[t] = xi; V.dfi[t] = d; V.tfi[t] = tau; V.exi[t] = ex; }
+                } else {
+                    if (atomicAdd(&V.nfc[t], 1) == 0) { V.fj[t] = xi; V.dfj[t] = d; V.tfj[t] = tau; V.exj[t] = ex; }
+                }
+            } else if (tau > 0.0) {
+                pass_ratio = fmax(pass_ratio, fabs(d) / tau);
+            }
+        }
+        note_pass_ratio(ea->rep, pass_ratio);
+        __syncthreads();
+        if (tid < 4) {
+            const int t = tid, I = t >> 1, J = t & 1;
+            const int tmc = 2 * tm + I, tnc = 2 * tn + J;
+            const int nr = V.nfr[t], nc = V.nfc[t];
+            if (tmc < ea->tiles_m && tnc < ea->tiles_n && (nr != 0 || nc != 0)) {
+                RepairReq q;
+                q.problem = ea->problem; q.tm = tmc; q.tn = tnc; q.interval = 0;
+                q.nr = nr; q.nc = nc; q.fi = V.fi[t]; q.fj = V.fj[t];
+                q.R = min(128, ea->m - 128 * tmc); q.Q = min(128, ea->n - 128 * tnc);
+                q.whole = q.pad1 = 0; q.m0 = 128 * (int64_t)tmc; q.n0 = 128 * (int64_t)tnc;
+                q.dfi = V.dfi[t]; q.tfi = V.tfi[t]; q.dfj = V.dfj[t]; q.tfj = V.tfj[t];
+                q.exp_row = nr ? V.exi[t] : 0.0;
+                q.exp_col = nc ? V.exj[t] : 0.0;
+                q.cin = (cin && nr == 1 && nc == 1) ? (double)ea->C[(q.m0 + q.fi) + (q.n0 + q.fj) * ldc] : 0.0;
+                push_repair(ea->rep, q);
+            }
+        }
+        __syncthreads();  // C_in at the located elements is read before the stores
+        }
     }
 }
 

@@ -10,7 +10,7 @@ a k that is not a multiple of the k-block (the 128 x 128 kernel then runs)."""
 import numpy as np
 import pytest
 
-from tests.test_parity_lowp import Run, assert_close32, env  # noqa: F401
+from tests.test_parity_lowp import Run, assert_close32, check_flips, env, plan_for  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
@@ -45,3 +45,53 @@ def test_wide_k_tail_falls_back(env):
     r = Run(env, "bf16", 300, 280, 197, 1, 0, seed=33, integer=True)
     out, _ = r.gpu(1.0, 1.0, ftgemm.make_config(abft=False, tile=WIDE))
     np.testing.assert_array_equal(out, r.oracle(1.0, 1.0))
+
+
+# ---- protected: the checksums folded into the wide product (2 x 2 checksum
+# tiles of 128 x 128 per workgroup, the same slots and thresholds as tile 1)
+
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_wide_protected_integer_exact(env, ta, tb):
+    ftgemm = env[0]
+    r = Run(env, "bf16", 520, 300, 192, ta, tb, seed=34, integer=True)
+    for alpha, beta in [(1.0, 0.0), (1.0, 1.0), (-2.0, 0.5)]:
+        out, rep = r.gpu(alpha, beta, ftgemm.make_config(tile=WIDE), nan_c=(beta == 0.0))
+        np.testing.assert_array_equal(out, r.oracle(alpha, beta))
+        assert rep.detected == 0, rep.records[:3]
+
+
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0)])
+def test_wide_protected_random_no_false_flags(env, ta, tb):
+    ftgemm = env[0]
+    r = Run(env, "bf16", 600, 650, 1024, ta, tb, seed=35)
+    for alpha, beta in [(1.0, 0.0), (1.5, 0.5)]:
+        out, rep = r.gpu(alpha, beta, ftgemm.make_config(tile=WIDE))
+        assert_close32(out, r.oracle(alpha, beta), r.magnitude(alpha, beta), r.k)
+        assert rep.detected == 0, rep.records[:3]
+
+
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0)])
+def test_wide_flips_located_and_corrected(env, ta, tb):
+    ftgemm = env[0]
+    r = Run(env, "bf16", 530, 400, 704, ta, tb, seed=36)
+    F = 12
+    for alpha, beta in [(1.0, 0.0), (1.5, 0.5)]:
+        cfg = ftgemm.make_config(seed=31, n_faults=F, bit_lo=24, bit_hi=30, tile=WIDE)
+        out, rep = r.gpu(alpha, beta, cfg)
+        plan = plan_for(r, 31, F, 24, 30)
+        assert rep.injected == F and rep.uncorrectable == 0
+        assert check_flips(r, alpha, beta, out, rep, plan) >= F // 2
+
+
+def test_wide_checksum_target_and_two_in_slot(env):
+    ftgemm = env[0]
+    r = Run(env, "bf16", 256, 384, 320, 0, 0, seed=37)
+    cfg = ftgemm.make_config(seed=3, n_faults=4, bit_lo=25, bit_hi=30, target=ftgemm.TARGET_CHECKSUM, tile=WIDE)
+    out, rep = r.gpu(1.0, 1.0, cfg)
+    assert rep.injected == 4 and rep.checksum_only == 4
+    assert all(g["kind"] == ftgemm.KIND_CHECKSUM_ONLY and g["col"] == -1 for g in rep.records)
+    assert_close32(out, r.oracle(1.0, 1.0), r.magnitude(1.0, 1.0), r.k)
+    cfg = ftgemm.make_config(seed=5, n_faults=2, bit_lo=26, bit_hi=30, target=ftgemm.TARGET_TWO_IN_SLOT,
+                             tile=WIDE)
+    out, rep = r.gpu(1.0, 0.0, cfg)
+    assert rep.injected == 4 and rep.uncorrectable == 2 and rep.status == ftgemm.ERR_UNCORRECTED
