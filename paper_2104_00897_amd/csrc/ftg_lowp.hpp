@@ -99,8 +99,9 @@ hipError_t launch_lowp_t(const LowpArgs& a, int ta, int tb, hipStream_t s);
 void lowp_tile_shape(ftg_dtype t, int id, int* bm, int* bn, int* bk);
 // tile configuration 2: workgroups of 2 x 2 checksum tiles (256 x 256 outputs),
 // k-contiguous operands with 16-byte rows and K a multiple of the k-block
+// (bf16 plain and protected, fp8 plain)
 constexpr int kLowpWideTile = 2;
-bool lowp_wide_ok(const LowpArgs& a, ftg_dtype t);
+bool lowp_wide_ok(const LowpArgs& a, ftg_dtype t, int mode);
 hipError_t launch_lowp_wide(const LowpArgs& a, ftg_dtype t, int mode, hipStream_t s);
 int lowp_heuristic_tile(ftg_dtype t, int64_t m, int64_t n, int64_t k);
 

@@ -1206,7 +1206,7 @@ ftg_status ftg_gemm_ex(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n,
         a.B = P; a.ldb = (int)ldp; a.vec_b = vec_ok(P, ldp, eb);
     }
     const int ita = 1, itb = 0;  // op(A) rows and op(B) columns are k-contiguous from here on
-    const bool wide = tile == ftg::kLowpWideTile && ftg::lowp_wide_ok(a, ab_type);
+    const bool wide = tile == ftg::kLowpWideTile && ftg::lowp_wide_ok(a, ab_type, abft ? 1 : 0);
     if (!abft) {
         LaunchTimer timer(h, s);
         const hipError_t e = wide ? ftg::launch_lowp_wide(a, ab_type, 0, s)

@@ -3,19 +3,21 @@
 
 namespace ftg {
 
-bool lowp_wide_ok(const LowpArgs& a, ftg_dtype t)
+bool lowp_wide_ok(const LowpArgs& a, ftg_dtype t, int mode)
 {
     const int bk = t == FTG_F8_E4M3 ? WCfg<true>::BK : WCfg<false>::BK;
-    return t == FTG_BF16 && a.vec_a && a.vec_b && a.k >= bk && a.k % bk == 0;
+    const bool type_ok = t == FTG_BF16 || (t == FTG_F8_E4M3 && mode == 0);
+    return type_ok && a.vec_a && a.vec_b && a.k >= bk && a.k % bk == 0;
 }
 
 hipError_t launch_lowp_wide(const LowpArgs& a, ftg_dtype t, int mode, hipStream_t s)
 {
     if (a.tiles_m <= 0 || a.tiles_n <= 0) return hipSuccess;
-    if (!lowp_wide_ok(a, t)) return hipErrorInvalidValue;
+    if (!lowp_wide_ok(a, t, mode)) return hipErrorInvalidValue;
     if (mode == 1 && (!a.XSA || !a.XSB || a.XSB <= a.XSA ||
                       (const char*)a.XSB - (const char*)a.XSA >= (int64_t(1) << 31)))
         return hipErrorInvalidValue;
+    if (t == FTG_F8_E4M3) return launch_lowp_wide_t<true, 0>(a, s);
     return mode ? launch_lowp_wide_t<false, 1>(a, s) : launch_lowp_wide_t<false, 0>(a, s);
 }
 

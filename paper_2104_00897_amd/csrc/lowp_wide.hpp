@@ -27,6 +27,15 @@
 
 namespace ftg {
 
+typedef int i32x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+// bf16: v_mfma_f32_16x16x32_bf16, 8 x 4 fragments of 16 x 16 per wave.
+// fp8: the gfx950 full-rate v_mfma_scale_f32_32x32x64_f8f6f4 (e4m3 operands,
+// unit block scales), 4 x 2 fragments of 32 x 32.  A lane holds row (column)
+// lane % 32 of an operand fragment with steps 32 (lane / 32) .. + 31, and
+// accumulator element q of rows 8 (q / 4) + 4 (lane / 32) + q % 4, column
+// lane % 32 (checked on the device against a decoding product).
 template <bool FP8>
 struct WCfg {
     static constexpr int EB = FP8 ? 1 : 2;                   // bytes per element
@@ -38,6 +47,10 @@ struct WCfg {
     static constexpr int X_BYTES = 1024;                             // checksum-piece rows
     static constexpr int NSTAGE = 4;  // a power of two
     static constexpr int LPW = (A_BYTES + B_BYTES) / 1024 / 8;       // wave loads per stage
+    static constexpr int FD = FP8 ? 32 : 16;                         // fragment edge
+    static constexpr int FM = WM / FD, FN = WN / FD;
+    using Frag = std::conditional_t<FP8, i32x8_t, bf16x8_t>;
+    using Acc = std::conditional_t<FP8, f32x16_t, f32x4_t>;
 };
 
 // 16-byte chunk c of LDS row r is stored at chunk c ^ wide_swz(r): a 16-lane
@@ -105,6 +118,10 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
     constexpr int BM = Cf::BM, BN = Cf::BN, BK = Cf::BK, NS = Cf::NSTAGE;
     constexpr int STAGE = Cf::A_BYTES + Cf::B_BYTES + (MODE == 1 ? Cf::X_BYTES : 0);
     static_assert(kWideStgBytes + (MODE == 1 ? sizeof(WVerify) : 0) <= NS * STAGE, "epilogue area");
+    static_assert(!(FP8 && MODE == 1), "protected fp8 runs the 128 x 128 kernel");
+    constexpr int FM = Cf::FM, FN = Cf::FN;
+    using Frag = typename Cf::Frag;
+    using Acc = typename Cf::Acc;
     __shared__ __attribute__((aligned(16))) unsigned char smem[NS * STAGE];
 
     const int tid = threadIdx.x;
@@ -186,11 +203,11 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
         else wide_wait_blocks<Cf::LPW>(later);
     };
 
-    f32x4_t acc[8][4];
+    Acc acc[FM][FN];
 #pragma unroll
-    for (int g = 0; g < 8; ++g)
+    for (int g = 0; g < FM; ++g)
 #pragma unroll
-        for (int h = 0; h < 4; ++h) acc[g][h] = (f32x4_t){0.0f, 0.0f, 0.0f, 0.0f};
+        for (int h = 0; h < FN; ++h) acc[g][h] = Acc{};
     // protected: row checksums of rows 16 (2 wc + i) + .. against the pieces of
     // B_J e (columns 3 J + piece), column checksums of columns 16 (2 wr + i) + ..
     // against the pieces of e^T A_I (rows 3 I + piece)
@@ -236,10 +253,10 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
         const int gh = ((rr / 16 - rot_a) & 7) * 4 + ((cc / 16 - rot_b) & 3), re = rr % 4;
         float oldv = 0.0f, newv = 0.0f;
 #pragma unroll
-        for (int g = 0; g < 8; ++g)
+        for (int g = 0; g < FM; ++g)
 #pragma unroll
-            for (int h = 0; h < 4; ++h)
-                if (g * 4 + h == gh) {
+            for (int h = 0; h < FN; ++h)
+                if constexpr (!FP8) if (g * 4 + h == gh) {
                     f32x4_t v = acc[g][h];
                     oldv = re == 0 ? v[0] : re == 1 ? v[1] : re == 2 ? v[2] : v[3];
                     newv = flip_f32(oldv, bit);
@@ -268,14 +285,30 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
     // fragments (x[0]: e^T A_I rows, x[1]: B_J e rows; rows 6 and 7 of each
     // only feed accumulator lanes that are never read): one set, refilled
     // after the block's last MFMA
-    bf16x8_t fa[8], fb[2][4], fx[2];
-    auto a_frag = [&](int st, int g) __attribute__((always_inline)) {
-        return *(const bf16x8_t*)(smem + st * STAGE + (wm0 + 16 * ((g + rot_a) & 7) + l16) * 64 + fo);
+    Frag fa[FM], fb[2][FN];
+    bf16x8_t fx[2];
+    // fp8: the lane's 32 steps are chunks 2 (lane / 32) and + 1 of its row
+    const int l32 = lane & 31, lh = lane >> 5;
+    const int fo8a = 16 * ((2 * lh) ^ wide_swz(l32)), fo8b = 16 * ((2 * lh + 1) ^ wide_swz(l32));
+    auto frag_at = [&](const unsigned char* rowp) __attribute__((always_inline)) {
+        if constexpr (FP8) {
+            const u32x4_t lo = *(const u32x4_t*)(rowp + fo8a), hi = *(const u32x4_t*)(rowp + fo8b);
+            return (Frag){(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+        } else {
+            return *(const Frag*)(rowp + fo);
+        }
     };
-    auto read_b = [&](int st, bf16x8_t* b) __attribute__((always_inline)) {
+    auto a_frag = [&](int st, int g) __attribute__((always_inline)) {
+        if constexpr (FP8) return frag_at(smem + st * STAGE + (wm0 + 32 * g + l32) * 64);
+        else return frag_at(smem + st * STAGE + (wm0 + 16 * ((g + rot_a) & 7) + l16) * 64);
+    };
+    auto read_b = [&](int st, Frag* b) __attribute__((always_inline)) {
         const unsigned char* tb = smem + st * STAGE + Cf::A_BYTES;
 #pragma unroll
-        for (int h = 0; h < 4; ++h) b[h] = *(const bf16x8_t*)(tb + (wn0 + 16 * ((h + rot_b) & 3) + l16) * 64 + fo);
+        for (int h = 0; h < FN; ++h) {
+            if constexpr (FP8) b[h] = frag_at(tb + (wn0 + 32 * h + l32) * 64);
+            else b[h] = frag_at(tb + (wn0 + 16 * ((h + rot_b) & 3) + l16) * 64);
+        }
     };
     auto read_x = [&](int st) __attribute__((always_inline)) {
         if constexpr (MODE == 1) {
@@ -289,13 +322,17 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
     // A fragments 0 and 1 against x[1] (row blocks 2 wc and 2 wc + 1 after the
     // rotation), column checksums of x[0] against B fragments 0 and 1 (column
     // blocks 2 wr and 2 wr + 1).
-    auto mfmas = [&](const bf16x8_t* b, int st, auto refill) __attribute__((always_inline)) {
+    auto mfmas = [&](const Frag* b, int st, auto refill) __attribute__((always_inline)) {
 #pragma unroll
-        for (int g = 0; g < 8; ++g) {
+        for (int g = 0; g < FM; ++g) {
 #pragma unroll
-            for (int h = 0; h < 4; ++h)
-                acc[g][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[g], b[h], acc[g][h], 0, 0, 0);
-            if constexpr (MODE == 1) {
+            for (int h = 0; h < FN; ++h) {
+                if constexpr (FP8)
+                    acc[g][h] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa[g], b[h], acc[g][h], 0, 0, 0, 127, 0, 127);
+                else
+                    acc[g][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[g], b[h], acc[g][h], 0, 0, 0);
+            }
+            if constexpr (MODE == 1 && !FP8) {
                 if (g < 2) accr[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[g], fx[1], accr[g], 0, 0, 0);
                 if (g == 7) {
                     accc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fx[0], b[0], accc[0], 0, 0, 0);
@@ -323,9 +360,9 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
         // them through an empty asm so that no wait for them is placed after
         // the next block's reads
 #pragma unroll
-        for (int g = 0; g < 8; ++g) asm volatile("" : "+v"(fa[g]));
+        for (int g = 0; g < FM; ++g) asm volatile("" : "+v"(fa[g]));
 #pragma unroll
-        for (int h = 0; h < 4; ++h) asm volatile("" : "+v"(fb[0][h]));
+        for (int h = 0; h < FN; ++h) asm volatile("" : "+v"(fb[0][h]));
         if constexpr (MODE == 1) {
             asm volatile("" : "+v"(fx[0]));
             asm volatile("" : "+v"(fx[1]));
@@ -335,7 +372,7 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
         __builtin_amdgcn_sched_barrier(0);
         mfmas(fb[0], (kb + 1) & (NS - 1), std::true_type{});
 #pragma unroll
-        for (int h = 0; h < 4; ++h) fb[0][h] = fb[1][h];
+        for (int h = 0; h < FN; ++h) fb[0][h] = fb[1][h];
         read_x((kb + 1) & (NS - 1));
     };
 #pragma unroll 1
@@ -343,7 +380,7 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
     // block 0: this wave's loads of blocks 1 .. NS - 1 may stay in flight
     wait_blocks(min(nkb - 1, NS - 1));
 #pragma unroll
-    for (int g = 0; g < 8; ++g) fa[g] = a_frag(0, g);
+    for (int g = 0; g < FM; ++g) fa[g] = a_frag(0, g);
     read_b(0, fb[0]);
     read_x(0);
     for (int kb = 0; kb < nkb; ++kb) {
@@ -394,14 +431,30 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
     auto pass = [&](bool store, bool sums) __attribute__((always_inline)) {
         double rsl[4] = {0.0, 0.0, 0.0, 0.0}, cirl[4] = {0.0, 0.0, 0.0, 0.0}, cial[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int h = 0; h < 4; ++h) {
+        for (int hs = 0; hs < 4; ++hs) {
+            // stage column block hs (16 columns) of the wave
+            if constexpr (FP8) {
+                // fragment hs / 2, its columns 16 (hs % 2) .. + 15
+                const int h = hs >> 1;
+                if ((l32 >> 4) == (hs & 1)) {
 #pragma unroll
-            for (int g = 0; g < 8; ++g) *(f32x4_t*)(stg + l16 * kWideCP + 16 * ((g + rot_a) & 7) + 4 * lq) = acc[g][h];
+                    for (int g = 0; g < FM; ++g)
+#pragma unroll
+                        for (int rq = 0; rq < 4; ++rq)
+                            *(f32x4_t*)(stg + (l32 & 15) * kWideCP + 32 * g + 8 * rq + 4 * lh) =
+                                (f32x4_t){acc[g][h][4 * rq], acc[g][h][4 * rq + 1], acc[g][h][4 * rq + 2],
+                                          acc[g][h][4 * rq + 3]};
+                }
+            } else {
+#pragma unroll
+                for (int g = 0; g < FM; ++g)
+                    *(f32x4_t*)(stg + l16 * kWideCP + 16 * ((g + rot_a) & 7) + 4 * lq) = acc[g][hs];
+            }
             __builtin_amdgcn_wave_barrier();
 #pragma unroll 1
             for (int p = 0; p < 8; ++p) {
                 const int c = 2 * p + cl;
-                const int col = wn0 + 16 * ((h + rot_b) & 3) + c;
+                const int col = wn0 + 16 * (FP8 ? hs : ((hs + rot_b) & 3)) + c;
                 const f32x4_t v = *(const f32x4_t*)(stg + c * kWideCP + rl);
                 const bool colok = col < Q;
                 const bool full = colok && row + 4 <= R;
@@ -476,7 +529,7 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
     if constexpr (MODE == 0) {
         pass(true, false);
     } else {
-        if (!cin) {
+        if (!FP8 && !cin) {
             // column sums of the final values alpha s acc over the wave's 128
             // rows, straight from the accumulators: the products are the ones
             // the pass below stores (the same binary32 multiply)

@@ -1,5 +1,6 @@
 """GPU parity of the wide low-precision tile (configuration 2: 256 x 256 outputs per
-workgroup, eight waves of 128 x 64) against the CPU oracle, through the C ABI.
+workgroup, eight waves of 128 x 64; bf16 plain and protected, fp8 plain on the
+full-rate f8f6f4 MFMA) against the CPU oracle, through the C ABI.
 
 Same bars as the 128 x 128 kernel: integer-exact inputs give the oracle's result
 bitwise (FP32 accumulation is exact there), random inputs stay within the
@@ -33,6 +34,30 @@ def test_wide_integer_exact_bitwise(env, ta, tb, m, n, k):
 def test_wide_random_within_fp32_bound(env, ta, tb):
     ftgemm = env[0]
     r = Run(env, "bf16", 600, 650, 1024, ta, tb, seed=32)
+    for alpha, beta in [(1.0, 0.0), (1.5, 0.5)]:
+        out, _ = r.gpu(alpha, beta, ftgemm.make_config(abft=False, tile=WIDE))
+        assert_close32(out, r.oracle(alpha, beta), r.magnitude(alpha, beta), r.k)
+
+
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("m,n,k", [(520, 300, 192), (257, 513, 64), (300, 290, 320)])
+def test_wide_fp8_integer_exact_bitwise(env, ta, tb, m, n, k):
+    """fp8 on the full-rate 32x32x64 f8f6f4 MFMA (k a multiple of its 64-step
+    k-block): integer-valued e4m3 inputs give the oracle's result bitwise, equal
+    to the 128 x 128 kernel's."""
+    ftgemm = env[0]
+    r = Run(env, "fp8", m, n, k, ta, tb, seed=38, integer=True)
+    for alpha, beta in [(1.0, 0.0), (-2.0, 0.5)]:
+        out, _ = r.gpu(alpha, beta, ftgemm.make_config(abft=False, tile=WIDE), nan_c=(beta == 0.0))
+        np.testing.assert_array_equal(out, r.oracle(alpha, beta))
+        ref, _ = r.gpu(alpha, beta, ftgemm.make_config(abft=False, tile=1), nan_c=(beta == 0.0))
+        np.testing.assert_array_equal(out, ref)
+
+
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0)])
+def test_wide_fp8_random_within_fp32_bound(env, ta, tb):
+    ftgemm = env[0]
+    r = Run(env, "fp8", 600, 650, 1024, ta, tb, seed=39)
     for alpha, beta in [(1.0, 0.0), (1.5, 0.5)]:
         out, _ = r.gpu(alpha, beta, ftgemm.make_config(abft=False, tile=WIDE))
         assert_close32(out, r.oracle(alpha, beta), r.magnitude(alpha, beta), r.k)
