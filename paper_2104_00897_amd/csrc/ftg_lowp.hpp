@@ -51,11 +51,12 @@ struct LowpArgs {
     // `slices` / `slices_c` such partial products, er_stride / ec_stride apart
     int ksplit, slices, slices_c;
     int vec_c;  // C base 16-byte aligned and ldc a multiple of 4
-    // wide tile, protected: the encode pass's bf16 checksum pieces of A and B
-    // (k-major rows of K elements; XSB after XSA, less than 2^31 bytes apart),
-    // multiplied inside the product instead of by separate GEMMs
-    const uint16_t* XSA;
-    const uint16_t* XSB;
+    // wide tile, protected: the encode pass's checksum pieces of A and B
+    // (k-major rows of K elements: bf16 XS, or e4m3 XS8 for fp8 operands; XSB
+    // after XSA, less than 2^31 bytes apart), multiplied inside the product
+    // instead of by separate GEMMs
+    const void* XSA;
+    const void* XSB;
     int64_t cslice, er_stride, ec_stride;
 };
 
@@ -67,7 +68,9 @@ struct EncOperand {
     int rows, K, kcontig;
     int vec;             // 16-byte loads allowed (base and ld aligned)
     int panels, chunks;  // panel = output-tile extent; chunk = kLowpChunk steps
-    uint16_t* XS;        // bf16 pieces: XS[(3 panel + s) K + p]
+    uint16_t* XS;        // bf16 pieces: XS[(3 panel + s) K + p] (NULL: not written)
+    uint8_t* XS8;        // e4m3 pieces with scales 2^(7 - 4 t):
+                         // XS8[(8 panel + t) K + p] (NULL: not written)
     float* XRp;          // partial |x| row sums: XRp[chunk rows + r]
     float* XMp;          // partial panel maxima: XMp[panel chunks + chunk]
     float* XR;           // finalised: XR[r] = sum_p |x(r, p)| (rounded up)
@@ -78,6 +81,7 @@ struct EncArgs {
 };
 
 constexpr int kLowpTile = 128;   // output tile extent (rows and columns)
+constexpr int kFp8Pieces = 8;    // e4m3 pieces of a panel sum (wide fp8 protected)
 constexpr int kLowpBK = 64;      // k-block
 constexpr int kLowpChunk = 64;   // k steps per encode block
 
@@ -99,7 +103,6 @@ hipError_t launch_lowp_t(const LowpArgs& a, int ta, int tb, hipStream_t s);
 void lowp_tile_shape(ftg_dtype t, int id, int* bm, int* bn, int* bk);
 // tile configuration 2: workgroups of 2 x 2 checksum tiles (256 x 256 outputs),
 // k-contiguous operands with 16-byte rows and K a multiple of the k-block
-// (bf16 plain and protected, fp8 plain)
 constexpr int kLowpWideTile = 2;
 bool lowp_wide_ok(const LowpArgs& a, ftg_dtype t, int mode);
 hipError_t launch_lowp_wide(const LowpArgs& a, ftg_dtype t, int mode, hipStream_t s);

@@ -1089,7 +1089,7 @@ ftg_status ftg_workspace_reserve(ftg_handle h, size_t bytes)
 namespace {
 
 struct LowpLayout {
-    size_t xs_a, xs_b, xrp_a, xrp_b, xmp_a, xmp_b, ra, cb, ma, mb, er, ec, total;
+    size_t xs_a, xs_b, xs8_a, xs8_b, xrp_a, xrp_b, xmp_a, xmp_b, ra, cb, ma, mb, er, ec, total;
 };
 
 // k slices of the checksum products: enough workgroups to fill the chip twice,
@@ -1110,6 +1110,8 @@ LowpLayout lowp_layout(int64_t m, int64_t n, int64_t k, int ks_r, int ks_c)
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
     L.xs_a = take((size_t)(3 * tm * k) * 2);
     L.xs_b = take((size_t)(3 * tn * k) * 2);
+    L.xs8_a = take((size_t)(ftg::kFp8Pieces * tm * k));
+    L.xs8_b = take((size_t)(ftg::kFp8Pieces * tn * k));
     L.xrp_a = take((size_t)(ch * m) * 4);
     L.xrp_b = take((size_t)(ch * n) * 4);
     L.xmp_a = take((size_t)(tm * ch) * 4);
@@ -1229,13 +1231,19 @@ ftg_status ftg_gemm_ex(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n,
     eb_.panels = a.tiles_n; eb_.chunks = chunks;
     eb_.XS = (uint16_t*)(w + L.xs_b); eb_.XRp = (float*)(w + L.xrp_b); eb_.XMp = (float*)(w + L.xmp_b);
     eb_.XR = (float*)(w + L.cb); eb_.XM = (float*)(w + L.mb);
+    if (wide && ab_type == FTG_F8_E4M3) {
+        // the fp8 wide product multiplies e4m3 pieces on the fp8 MFMA
+        ea.XS = nullptr; ea.XS8 = w + L.xs8_a;
+        eb_.XS = nullptr; eb_.XS8 = w + L.xs8_b;
+    }
     const int gx = std::max(a.tiles_m, a.tiles_n) * chunks;
     const int fx = (int)((std::max(m, n) + 255) / 256);
     if (ftg::launch_lowp_encode(e, ab_type, gx, fx, s) != hipSuccess) return FTG_ERR_HIP;
 
     // the wide tile multiplies the checksum pieces inside the product
     if (wide) {
-        a.XSA = ea.XS; a.XSB = eb_.XS;
+        a.XSA = ab_type == FTG_F8_E4M3 ? (const void*)ea.XS8 : (const void*)ea.XS;
+        a.XSB = ab_type == FTG_F8_E4M3 ? (const void*)eb_.XS8 : (const void*)eb_.XS;
     } else {
         // checksum products: ER = op(A) [B_J e pieces], EC = [e^T A_I pieces]^T op(B)
         ftg::LowpArgs c1;

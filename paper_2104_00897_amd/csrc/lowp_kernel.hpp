@@ -68,6 +68,25 @@ __device__ inline uint16_t f32_to_bf16_rne(float x)
     return (uint16_t)(u >> 16);
 }
 
+// binary64 -> e4m3fn code, round to nearest even, for abs(x) <= 448 (the
+// largest finite e4m3fn value; bias 7, 3 mantissa bits, subnormals k 2^-9)
+__device__ inline uint32_t f64_to_e4m3_rne(double x)
+{
+    const uint32_t sgn = x < 0.0 ? 0x80u : 0u;
+    const double a = fabs(x);
+    if (a == 0.0) return sgn;
+    int e2;
+    (void)frexp(a, &e2);
+    int E = e2 - 1;  // a in [2^E, 2^(E+1))
+    if (E < -6) {
+        const double m = rint(a * 512.0);  // subnormal steps of 2^-9 (8 steps: the smallest normal)
+        return sgn | (uint32_t)m;
+    }
+    double m = rint(ldexp(a, 3 - E));  // 8 .. 16
+    if (m >= 16.0) { m = 8.0; ++E; }
+    return sgn | ((uint32_t)(E + 7) << 3) | ((uint32_t)m - 8u);
+}
+
 // binary64 -> binary32 rounded towards +infinity (for magnitude bounds, x >= 0)
 __device__ inline float f64_to_f32_up(double x)
 {

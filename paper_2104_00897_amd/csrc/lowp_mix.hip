@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256, 4) void lowp_encode_kernel(EncArgs args)
             sa += fabs(v);
         }
         pmax[p] = f64_to_f32_up(sa);
-        if (p0 + p < E.K) {
+        if (p0 + p < E.K && E.XS) {
             // three bf16 pieces: hi + mid + lo = s to within 2^-24 |s|
             const uint16_t hi = f32_to_bf16_rne((float)s);
             const double r1 = s - (double)bf16_bits_to_f32(hi);
@@ -78,6 +78,23 @@ __global__ __launch_bounds__(256, 4) void lowp_encode_kernel(EncArgs args)
             o[0] = hi;
             o[E.K] = mid;
             o[2 * E.K] = lo;
+        }
+        if (p0 + p < E.K && E.XS8) {
+            // e4m3 pieces s = sum_t 2^(7 - 4 t) q_t (+ residual).  A panel sum of
+            // 128 e4m3 values has abs(s) <= 128 * 448; with the residual r_t below
+            // 448 * 2^(7 - 4 t) each rounding leaves at most 1/16 of it (3
+            // mantissa bits; below 2^-6 the subnormal step), so the next piece
+            // stays in range and eight pieces leave abs(r_8) <= 2^-28 abs(s) +
+            // 2^-31 (2^-21 times the half subnormal step)
+            double r = s;
+            uint8_t* o = E.XS8 + (int64_t)kFp8Pieces * pi * E.K + p0 + p;
+#pragma unroll
+            for (int t = 0; t < kFp8Pieces; ++t) {
+                const double S = ldexp(1.0, 7 - 4 * t);
+                const uint32_t q = f64_to_e4m3_rne(r / S);
+                o[(int64_t)t * E.K] = (uint8_t)q;
+                r -= S * (double)bf16_bits_to_f32(e4m3_to_bf16(q));
+            }
         }
     }
     __syncthreads();
@@ -199,7 +216,7 @@ __global__ __launch_bounds__(256) void lowp_encode_k_kernel(EncArgs args)
             sa += cpart[v][p][1];
         }
         pmax[p] = f64_to_f32_up(sa);
-        if (p0 + p < E.K) {
+        if (p0 + p < E.K && E.XS) {
             // three bf16 pieces: hi + mid + lo = s to within 2^-24 |s|
             const uint16_t hi = f32_to_bf16_rne((float)s);
             const double r1 = s - (double)bf16_bits_to_f32(hi);
@@ -210,6 +227,23 @@ __global__ __launch_bounds__(256) void lowp_encode_k_kernel(EncArgs args)
             o[0] = hi;
             o[E.K] = mid;
             o[2 * E.K] = lo;
+        }
+        if (p0 + p < E.K && E.XS8) {
+            // e4m3 pieces s = sum_t 2^(7 - 4 t) q_t (+ residual).  A panel sum of
+            // 128 e4m3 values has abs(s) <= 128 * 448; with the residual r_t below
+            // 448 * 2^(7 - 4 t) each rounding leaves at most 1/16 of it (3
+            // mantissa bits; below 2^-6 the subnormal step), so the next piece
+            // stays in range and eight pieces leave abs(r_8) <= 2^-28 abs(s) +
+            // 2^-31 (2^-21 times the half subnormal step)
+            double r = s;
+            uint8_t* o = E.XS8 + (int64_t)kFp8Pieces * pi * E.K + p0 + p;
+#pragma unroll
+            for (int t = 0; t < kFp8Pieces; ++t) {
+                const double S = ldexp(1.0, 7 - 4 * t);
+                const uint32_t q = f64_to_e4m3_rne(r / S);
+                o[(int64_t)t * E.K] = (uint8_t)q;
+                r -= S * (double)bf16_bits_to_f32(e4m3_to_bf16(q));
+            }
         }
     }
     __syncthreads();

@@ -6,7 +6,8 @@ namespace ftg {
 bool lowp_wide_ok(const LowpArgs& a, ftg_dtype t, int mode)
 {
     const int bk = t == FTG_F8_E4M3 ? WCfg<true>::BK : WCfg<false>::BK;
-    const bool type_ok = t == FTG_BF16 || (t == FTG_F8_E4M3 && mode == 0);
+    (void)mode;
+    const bool type_ok = t == FTG_BF16 || t == FTG_F8_E4M3;
     return type_ok && a.vec_a && a.vec_b && a.k >= bk && a.k % bk == 0;
 }
 
@@ -17,7 +18,7 @@ hipError_t launch_lowp_wide(const LowpArgs& a, ftg_dtype t, int mode, hipStream_
     if (mode == 1 && (!a.XSA || !a.XSB || a.XSB <= a.XSA ||
                       (const char*)a.XSB - (const char*)a.XSA >= (int64_t(1) << 31)))
         return hipErrorInvalidValue;
-    if (t == FTG_F8_E4M3) return launch_lowp_wide_t<true, 0>(a, s);
+    if (t == FTG_F8_E4M3) return mode ? launch_lowp_wide_t<true, 1>(a, s) : launch_lowp_wide_t<true, 0>(a, s);
     return mode ? launch_lowp_wide_t<false, 1>(a, s) : launch_lowp_wide_t<false, 0>(a, s);
 }
 

@@ -44,13 +44,18 @@ struct WCfg {
     static constexpr int WM = 128, WN = 64;
     static constexpr int ROWB = 64;
     static constexpr int A_BYTES = BM * ROWB, B_BYTES = BN * ROWB;  // 16 KB each
-    static constexpr int X_BYTES = 1024;                             // checksum-piece rows
+    // checksum pieces per panel sum (bf16: three of 2^0; fp8: eight e4m3 with
+    // scales 2^(7 - 4 t)); their LDS rows per stage: 8 of e^T A_I then 8 of
+    // B_J e (bf16, six used) or 16 and 16 (fp8)
+    static constexpr int PIECES = FP8 ? 8 : 3;
+    static constexpr int X_BYTES = FP8 ? 2048 : 1024;
     static constexpr int NSTAGE = 4;  // a power of two
     static constexpr int LPW = (A_BYTES + B_BYTES) / 1024 / 8;       // wave loads per stage
     static constexpr int FD = FP8 ? 32 : 16;                         // fragment edge
     static constexpr int FM = WM / FD, FN = WN / FD;
     using Frag = std::conditional_t<FP8, i32x8_t, bf16x8_t>;
     using Acc = std::conditional_t<FP8, f32x16_t, f32x4_t>;
+    static constexpr int XF = FP8 ? 1 : 2;  // checksum fragments per wave and kind
 };
 
 // 16-byte chunk c of LDS row r is stored at chunk c ^ wide_swz(r): a 16-lane
@@ -100,9 +105,10 @@ constexpr int kWideCP = 132;
 constexpr int kWideStgBytes = 8 * 16 * kWideCP * 4;
 
 // Verification bookkeeping of the protected kernel (after the staging area).
+template <int P>
 struct WVerify {
-    float er[256][6];                  // row checksum pieces: [row][3 J + piece]
-    float ec[256][6];                  // column checksum pieces: [column][3 I + piece]
+    float er[256][2 * P];              // row checksum pieces: [row][P J + piece]
+    float ec[256][2 * P];              // column checksum pieces: [column][P I + piece]
     double rs[4][256];                 // row sums over each wave column's 64 columns
     double cs[2][256];                 // column sums over each wave row's 128 rows
     double cir[4][256], cira[4][256];  // the same of C_in and abs(C_in)
@@ -117,8 +123,8 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
     using Cf = WCfg<FP8>;
     constexpr int BM = Cf::BM, BN = Cf::BN, BK = Cf::BK, NS = Cf::NSTAGE;
     constexpr int STAGE = Cf::A_BYTES + Cf::B_BYTES + (MODE == 1 ? Cf::X_BYTES : 0);
-    static_assert(kWideStgBytes + (MODE == 1 ? sizeof(WVerify) : 0) <= NS * STAGE, "epilogue area");
-    static_assert(!(FP8 && MODE == 1), "protected fp8 runs the 128 x 128 kernel");
+    using Verify = WVerify<Cf::PIECES>;
+    static_assert(kWideStgBytes + (MODE == 1 ? sizeof(Verify) : 0) <= NS * STAGE, "epilogue area");
     constexpr int FM = Cf::FM, FN = Cf::FN;
     using Frag = typename Cf::Frag;
     using Acc = typename Cf::Acc;
@@ -136,7 +142,7 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
     // and the column blocks (2 wr, 2 wr + 1) are fragments 0 and 1 of every
     // wave: the checksum MFMAs then take fixed registers (a uniform choice among
     // fragments would cost branches or selects in the loop).
-    const int rot_a = MODE == 1 ? 2 * wc : 0, rot_b = MODE == 1 ? 2 * wr : 0;
+    const int rot_a = MODE == 1 ? (FP8 ? wc : 2 * wc) : 0, rot_b = MODE == 1 ? (FP8 ? wr : 2 * wr) : 0;
 
     // wide tiles: (tiles_m + 1) / 2 x (tiles_n + 1) / 2 of the 128 x 128 tiles
     const int wtm = (args.tiles_m + 1) >> 1, wtn = (args.tiles_n + 1) >> 1;
@@ -153,29 +159,35 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
 
     // ---- staging: per stage 16 wave loads of A rows then 16 of B rows, four
     // per wave; wave load I covers rows 16 I .. 16 I + 15 (slot = 64 I + lane,
-    // row = slot / 4, chunk = slot % 4, stored at chunk ^ wide_swz(row)).
-    // Rows past the matrix load its last row: they only feed accumulators
+    // row = slot / 4, chunk = slot % 4, stored at chunk ^ wide_swz(row)).  A
+    // wave's load u covers rows 64 (wave % 4) + 16 u + lane / 4: the same lane
+    // offset from a resource that starts 16 u rows further and ends after the
+    // last row of the matrix (the range check applies to the lane offset), so
+    // loads of rows past the matrix return zeros; they only feed accumulators
     // that are never stored or checked.
-    int voff[Cf::LPW];
-#pragma unroll
-    for (int u = 0; u < Cf::LPW; ++u) {
-        const int I = wave * Cf::LPW + u;
-        const int J = I & 15, sl = 64 * J + lane, x = sl >> 2;
-        const int c = (sl & 3) ^ wide_swz(x);
-        voff[u] = I < 16 ? (int)((int64_t)min(x, R - 1) * lda * Cf::EB + 16 * c)
-                         : (int)((int64_t)min(x, Q - 1) * ldb * Cf::EB + 16 * c);
-    }
     const bool a_wave = wave < 4;  // waves 0-3 load A, 4-7 load B
-    const unsigned char* src0 = a_wave ? A + m0 * lda * Cf::EB : B + n0 * ldb * Cf::EB;
-    // protected: wave 0 adds one load per stage of the checksum pieces (k-major
-    // rows of K bf16), lanes 0-23 the six rows of e^T A_I of the workgroup's two
-    // tile rows, lanes 32-55 the six of B_J e; a missing second tile reads the
-    // last row (its checks are skipped)
-    const bool xw = MODE == 1 && wave == 0;
-    const unsigned char* XS = (const unsigned char*)args.XSA;
+    const int64_t ldx = (a_wave ? lda : ldb) * Cf::EB;  // bytes between rows
+    const int rows_left = (a_wave ? R : Q) - 64 * (wave & 3);
+    int voff0;
+    {
+        const int x = lane / 4;
+        voff0 = (int)((int64_t)x * ldx + 16 * ((lane & 3) ^ wide_swz(x)));
+    }
+    const unsigned char* src0 = (a_wave ? A + m0 * lda * Cf::EB : B + n0 * ldb * Cf::EB) + 64 * (wave & 3) * ldx;
+    // protected, bf16: wave 0 adds one load per stage of the checksum pieces
+    // (k-major rows of K bf16), lanes 0-23 the six rows of e^T A_I of the
+    // workgroup's two tile rows, lanes 32-55 the six of B_J e.  fp8: waves 0
+    // and 1 add one each, the sixteen rows (K bytes) of e^T A_I and of B_J e.
+    // A missing second tile reads the last rows (its checks are skipped).
+    const bool xw = MODE == 1 && (FP8 ? wave < 2 : wave == 0);
+    const unsigned char* XS = (const unsigned char*)(FP8 && wave == 1 ? args.XSB : args.XSA);
     int xoff = 0;
     bool xlane = false;
-    if constexpr (MODE == 1) {
+    // fp8: the first piece row and the last row of the wave's pieces (the lane
+    // offset is formed at each load, keeping no register through the loop)
+    const int x8_r0 = (FP8 && MODE == 1) ? 2 * Cf::PIECES * (wave == 1 ? tn : tm) : 0;
+    const int x8_rmax = (FP8 && MODE == 1) ? Cf::PIECES * (wave == 1 ? args.tiles_n : args.tiles_m) - 1 : 0;
+    if constexpr (MODE == 1 && !FP8) {
         const int64_t xsb = (const unsigned char*)args.XSB - XS;
         if (lane < 24) {
             const int r = min(6 * tm + lane / 4, 3 * args.tiles_m - 1);
@@ -188,13 +200,25 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
         }
     }
     auto issue = [&](int kb, int st) __attribute__((always_inline)) {
-        unsigned char* base = smem + st * STAGE + (a_wave ? 0 : Cf::A_BYTES);
+        unsigned char* base = smem + st * STAGE + (a_wave ? 0 : Cf::A_BYTES) + 4096 * (wave & 3);
         if (MODE == 1 && xw) {
-            if (xlane) lds_dma16(make_rsrc(XS + (int64_t)kb * 64), smem + st * STAGE + Cf::A_BYTES + Cf::B_BYTES, xoff);
+            unsigned char* xd = smem + st * STAGE + Cf::A_BYTES + Cf::B_BYTES + (FP8 ? 1024 * wave : 0);
+            if constexpr (FP8) {
+                const int xo = min(x8_r0 + lane / 4, x8_rmax) * K + 16 * (lane % 4);
+                lds_dma16(make_rsrc(XS + (int64_t)kb * 64), xd, xo);
+            } else if (xlane) {
+                lds_dma16(make_rsrc(XS + (int64_t)kb * 64), xd, xoff);
+            }
         }
-        const __amdgpu_buffer_rsrc_t rs = make_rsrc(src0 + (int64_t)kb * 64);
 #pragma unroll
-        for (int u = 0; u < Cf::LPW; ++u) lds_dma16(rs, base + 1024 * ((wave * Cf::LPW + u) & 15), voff[u]);
+        for (int u = 0; u < Cf::LPW; ++u) {
+            // rows 16 u .. of this wave's 64 that exist: up to the last one's 64 bytes
+            const int left = rows_left - 16 * u;
+            const int nrec = left > 0 ? (int)((int64_t)(min(left, 16) - 1) * ldx + 64) : 0;
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<unsigned char*>(src0 + 16 * u * ldx + (int64_t)kb * 64), (short)0, nrec, 0x00020000);
+            lds_dma16(rs, base + 1024 * u, voff0);
+        }
     };
     // wait for a block whose successors (this wave's loads of them) may stay
     // in flight, then publish it to every wave
@@ -211,9 +235,9 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
     // protected: row checksums of rows 16 (2 wc + i) + .. against the pieces of
     // B_J e (columns 3 J + piece), column checksums of columns 16 (2 wr + i) + ..
     // against the pieces of e^T A_I (rows 3 I + piece)
-    f32x4_t accr[2], accc[2];
+    Acc accr[Cf::XF], accc[Cf::XF];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) accr[i] = accc[i] = (f32x4_t){0.0f, 0.0f, 0.0f, 0.0f};
+    for (int i = 0; i < Cf::XF; ++i) accr[i] = accc[i] = Acc{};
 
     // ---- injection plan of this wave's checksum tile (I, J) = (wr, wc / 2):
     // up to two faults, applied to the accumulator after their k-block by the
@@ -248,10 +272,36 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
         const int rr = __builtin_amdgcn_readfirstlane(f2[q].row), col = __builtin_amdgcn_readfirstlane(f2[q].col);
         const int cc = col % 64, bit = __builtin_amdgcn_readfirstlane(f2[q].bit);
         const bool own = lane == ((rr % 16) / 4) * 16 + cc % 16;
+        float oldv = 0.0f, newv = 0.0f;
+        if constexpr (FP8) {
+            // 32 x 32 fragments: block (rr / 32, cc / 32), lane (lh, cc % 32) with
+            // lh = (rr % 32) / 4 % 2, element 4 ((rr % 32) / 8) + rr % 4
+            const int i = rr % 32;
+            const bool own8 = lane == 32 * ((i / 4) % 2) + cc % 32;
+            const int gh = ((rr / 32 - rot_a) & 3) * 2 + ((cc / 32 - rot_b) & 1), qe = 4 * (i / 8) + i % 4;
+#pragma unroll
+            for (int g = 0; g < FM; ++g)
+#pragma unroll
+                for (int h = 0; h < FN; ++h)
+                    if (g * FN + h == gh) {
+                        Acc v = acc[g][h];
+#pragma unroll
+                        for (int e = 0; e < 16; ++e)
+                            if (e == qe) oldv = v[e];
+                        newv = flip_f32(oldv, bit);
+#pragma unroll
+                        for (int e = 0; e < 16; ++e)
+                            if (e == qe && own8) v[e] = newv;
+                        acc[g][h] = v;
+                    }
+            if (own8)
+                push_inject(ar->rep, ar->problem, tmw, tnw, 0, m0 + 128 * wr + rr, n0 + 128 * (wc >> 1) + col,
+                            f2[q].pflip, bit, FTG_TARGET_ACC, (double)oldv, (double)newv);
+            return;
+        }
         // fragment (g, h) = (rr / 16, cc / 16) by a uniform branch, then the
         // element rr % 4 of the lane's four
         const int gh = ((rr / 16 - rot_a) & 7) * 4 + ((cc / 16 - rot_b) & 3), re = rr % 4;
-        float oldv = 0.0f, newv = 0.0f;
 #pragma unroll
         for (int g = 0; g < FM; ++g)
 #pragma unroll
@@ -285,8 +335,7 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
     // fragments (x[0]: e^T A_I rows, x[1]: B_J e rows; rows 6 and 7 of each
     // only feed accumulator lanes that are never read): one set, refilled
     // after the block's last MFMA
-    Frag fa[FM], fb[2][FN];
-    bf16x8_t fx[2];
+    Frag fa[FM], fb[2][FN], fx[2];
     // fp8: the lane's 32 steps are chunks 2 (lane / 32) and + 1 of its row
     const int l32 = lane & 31, lh = lane >> 5;
     const int fo8a = 16 * ((2 * lh) ^ wide_swz(l32)), fo8b = 16 * ((2 * lh + 1) ^ wide_swz(l32));
@@ -299,22 +348,30 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
         }
     };
     auto a_frag = [&](int st, int g) __attribute__((always_inline)) {
-        if constexpr (FP8) return frag_at(smem + st * STAGE + (wm0 + 32 * g + l32) * 64);
+        if constexpr (FP8) return frag_at(smem + st * STAGE + (wm0 + 32 * ((g + rot_a) & 3) + l32) * 64);
         else return frag_at(smem + st * STAGE + (wm0 + 16 * ((g + rot_a) & 7) + l16) * 64);
     };
     auto read_b = [&](int st, Frag* b) __attribute__((always_inline)) {
         const unsigned char* tb = smem + st * STAGE + Cf::A_BYTES;
 #pragma unroll
         for (int h = 0; h < FN; ++h) {
-            if constexpr (FP8) b[h] = frag_at(tb + (wn0 + 32 * h + l32) * 64);
+            if constexpr (FP8) b[h] = frag_at(tb + (wn0 + 32 * ((h + rot_b) & 1) + l32) * 64);
             else b[h] = frag_at(tb + (wn0 + 16 * ((h + rot_b) & 3) + l16) * 64);
         }
     };
+    // fp8: piece fragment i (0: e^T A_I rows, 1: B_J e rows) of the block in
+    // stage st, rows l32 % 16 (rows 16-31 of the fragment repeat 0-15: they
+    // only feed accumulator lanes that are never read), steps 32 lh .. + 31
+    auto x8_frag = [&](int st, int i) __attribute__((always_inline)) {
+        const unsigned char* tx = smem + st * STAGE + Cf::A_BYTES + Cf::B_BYTES + 1024 * i + (l32 & 15) * 64 + 32 * lh;
+        const u32x4_t lo = *(const u32x4_t*)tx, hi = *(const u32x4_t*)(tx + 16);
+        return (i32x8_t){(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+    };
     auto read_x = [&](int st) __attribute__((always_inline)) {
-        if constexpr (MODE == 1) {
+        if constexpr (MODE == 1 && !FP8) {
             const unsigned char* tx = smem + st * STAGE + Cf::A_BYTES + Cf::B_BYTES + (l16 & 7) * 64 + 16 * lq;
-            fx[0] = *(const bf16x8_t*)tx;
-            fx[1] = *(const bf16x8_t*)(tx + 512);
+            fx[0] = *(const Frag*)tx;
+            fx[1] = *(const Frag*)(tx + 512);
         }
     };
     // MFMAs of the current block; with `refill` each A fragment is then
@@ -322,7 +379,7 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
     // A fragments 0 and 1 against x[1] (row blocks 2 wc and 2 wc + 1 after the
     // rotation), column checksums of x[0] against B fragments 0 and 1 (column
     // blocks 2 wr and 2 wr + 1).
-    auto mfmas = [&](const Frag* b, int st, auto refill) __attribute__((always_inline)) {
+    auto mfmas = [&](const Frag* b, int st, auto refill, int st_cur) __attribute__((always_inline)) {
 #pragma unroll
         for (int g = 0; g < FM; ++g) {
 #pragma unroll
@@ -332,7 +389,15 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
                 else
                     acc[g][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[g], b[h], acc[g][h], 0, 0, 0);
             }
-            if constexpr (MODE == 1 && !FP8) {
+            if constexpr (MODE == 1 && FP8) {
+                // one piece-fragment register set: B_J e rows (read with the
+                // block's first fragments), then e^T A_I rows (read here)
+                if (g == 0) {
+                    accr[0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa[0], fx[0], accr[0], 0, 0, 0, 127, 0, 127);
+                    fx[0] = x8_frag(st_cur, 0);
+                }
+                if (g == FM - 1) accc[0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fx[0], b[0], accc[0], 0, 0, 0, 127, 0, 127);
+            } else if constexpr (MODE == 1) {
                 if (g < 2) accr[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[g], fx[1], accr[g], 0, 0, 0);
                 if (g == 7) {
                     accc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fx[0], b[0], accc[0], 0, 0, 0);
@@ -346,6 +411,11 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
         }
     };
 
+    // Blocks loaded ahead: NS (each step refills the stage of the block whose
+    // MFMAs it runs: its fragments were read in the step before), except for
+    // protected fp8, which reads that block's checksum-piece fragments during
+    // its step and refills the previous block's stage instead (NS - 1 ahead).
+    constexpr int LA = (FP8 && MODE == 1) ? NS - 1 : NS;
     // ---- k loop over the ring, software-pipelined: block kb + 1's fragments
     // are read while block kb's MFMAs run.  The wait for block kb + 1 (its
     // loads by every wave, then a barrier) also retires every wave's reads of
@@ -355,7 +425,7 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
     // joins and would then wait for the fragments just requested; injected
     // faults are applied between segments of that loop.)
     auto step = [&](int kb) __attribute__((always_inline)) {
-        wait_blocks(min(nkb - 1, kb + NS - 1) - (kb + 1));
+        wait_blocks(min(nkb - 1, kb + LA - 1) - (kb + 1));
         // the wait above retired the reads of this block's fragments; pass
         // them through an empty asm so that no wait for them is placed after
         // the next block's reads
@@ -363,39 +433,52 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
         for (int g = 0; g < FM; ++g) asm volatile("" : "+v"(fa[g]));
 #pragma unroll
         for (int h = 0; h < FN; ++h) asm volatile("" : "+v"(fb[0][h]));
-        if constexpr (MODE == 1) {
+        if constexpr (MODE == 1 && !FP8) {
             asm volatile("" : "+v"(fx[0]));
             asm volatile("" : "+v"(fx[1]));
         }
-        if (kb + NS < nkb) issue(kb + NS, kb & (NS - 1));
-        read_b((kb + 1) & (NS - 1), fb[1]);
+        if (kb + LA < nkb) issue(kb + LA, (kb + LA) & (NS - 1));
+        // (protected fp8 has no registers for a second B set: its next B
+        // fragments are read after the block's last MFMA, during the wait
+        // that follows)
+        constexpr bool single_b = FP8 && MODE == 1;
+        if constexpr (!single_b) read_b((kb + 1) & (NS - 1), fb[1]);
         __builtin_amdgcn_sched_barrier(0);
-        mfmas(fb[0], (kb + 1) & (NS - 1), std::true_type{});
+        if constexpr (FP8 && MODE == 1) fx[0] = x8_frag(kb & (NS - 1), 1);
+        mfmas(fb[0], (kb + 1) & (NS - 1), std::true_type{}, kb & (NS - 1));
+        if constexpr (single_b) {
+            read_b((kb + 1) & (NS - 1), fb[0]);
+        } else {
 #pragma unroll
-        for (int h = 0; h < FN; ++h) fb[0][h] = fb[1][h];
+            for (int h = 0; h < FN; ++h) fb[0][h] = fb[1][h];
+        }
         read_x((kb + 1) & (NS - 1));
     };
 #pragma unroll 1
-    for (int b = 0; b < NS && b < nkb; ++b) issue(b, b);
+    for (int b = 0; b < LA && b < nkb; ++b) issue(b, b);
     // block 0: this wave's loads of blocks 1 .. NS - 1 may stay in flight
-    wait_blocks(min(nkb - 1, NS - 1));
+    wait_blocks(min(nkb - 1, LA - 1));
 #pragma unroll
     for (int g = 0; g < FM; ++g) fa[g] = a_frag(0, g);
     read_b(0, fb[0]);
     read_x(0);
-    for (int kb = 0; kb < nkb; ++kb) {
-        // the next block after which a fault is applied, else the last block
-        int stop = nkb - 1;
+    // blocks 0 .. nkb - 2 (each with a successor) in segments that end at a
+    // block after which a fault is applied (one copy of the block step: a
+    // second one would not fit the registers), then the last block
+    int kb = 0;
+    while (kb <= nkb - 2) {
+        int stop = nkb - 2;
         if (MODE == 1) {
             if (fkb[0] >= kb) stop = min(stop, fkb[0]);
             if (fkb[1] >= kb) stop = min(stop, fkb[1]);
         }
 #pragma unroll 1
-        for (; kb < stop; ++kb) step(kb);
-        if (kb + 1 < nkb) step(kb);
-        else mfmas(fb[0], 0, std::false_type{});
-        faults_after(kb);
+        for (; kb <= stop; ++kb) step(kb);
+        faults_after(stop);
     }
+    if constexpr (FP8 && MODE == 1) fx[0] = x8_frag((nkb - 1) & (NS - 1), 1);
+    mfmas(fb[0], 0, std::false_type{}, (nkb - 1) & (NS - 1));
+    faults_after(nkb - 1);
 
     // ---- epilogue.  Lane (lq, l16) of fragment (g, h) holds rows
     // wm0 + 16 g + 4 lq + (0 .. 3) of column wn0 + 16 h + l16.  Column-major C
@@ -412,17 +495,30 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
     // the lane's rows and column pair in the staged layout
     const int rl = 4 * (lane & 31), cl = lane >> 5;
     const int row = wm0 + rl;
-    WVerify& V = *(WVerify*)(smem + kWideStgBytes);
+    Verify& V = *(Verify*)(smem + kWideStgBytes);
+    // scale of checksum piece t (the encode pass's split)
+    auto piece_weight = [](int t) __attribute__((always_inline)) { return FP8 ? ldexp(1.0, 7 - 4 * t) : 1.0; };
     __syncthreads();  // every wave is done with the ring
     if constexpr (MODE == 1) {
         // expected pieces from the checksum accumulators
+        if constexpr (FP8) {
+            // accr: rows of row block wc x pieces (columns) l32; accc: pieces (rows)
+            // x columns of column block wr
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                if (l16 < 6) V.er[wm0 + 16 * (2 * wc + i) + 4 * lq + r][l16] = accr[i][r];
-                if (4 * lq + r < 6) V.ec[wn0 + 16 * (2 * wr + i) + l16][4 * lq + r] = accc[i][r];
+            for (int q = 0; q < 16; ++q) {
+                const int rq = 8 * (q / 4) + 4 * lh + q % 4;
+                if (l32 < 16) V.er[wm0 + 32 * wc + rq][l32] = accr[0][q];
+                if (rq < 16) V.ec[wn0 + 32 * wr + l32][rq] = accc[0][q];
             }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (l16 < 6) V.er[wm0 + 16 * (2 * wc + i) + 4 * lq + r][l16] = accr[i][r];
+                    if (4 * lq + r < 6) V.ec[wn0 + 16 * (2 * wr + i) + l16][4 * lq + r] = accc[i][r];
+                }
+        }
         if (tid < 4) { V.nfr[tid] = 0; V.nfc[tid] = 0; }
     }
     // One pass over the tile: the final values alpha s acc + beta C_in; with
@@ -434,14 +530,15 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
         for (int hs = 0; hs < 4; ++hs) {
             // stage column block hs (16 columns) of the wave
             if constexpr (FP8) {
-                // fragment hs / 2, its columns 16 (hs % 2) .. + 15
+                // register fragment hs / 2 (column block (hs / 2 + rot_b) % 2), its
+                // columns 16 (hs % 2) .. + 15
                 const int h = hs >> 1;
                 if ((l32 >> 4) == (hs & 1)) {
 #pragma unroll
                     for (int g = 0; g < FM; ++g)
 #pragma unroll
                         for (int rq = 0; rq < 4; ++rq)
-                            *(f32x4_t*)(stg + (l32 & 15) * kWideCP + 32 * g + 8 * rq + 4 * lh) =
+                            *(f32x4_t*)(stg + (l32 & 15) * kWideCP + 32 * ((g + rot_a) & 3) + 8 * rq + 4 * lh) =
                                 (f32x4_t){acc[g][h][4 * rq], acc[g][h][4 * rq + 1], acc[g][h][4 * rq + 2],
                                           acc[g][h][4 * rq + 3]};
                 }
@@ -454,7 +551,7 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
 #pragma unroll 1
             for (int p = 0; p < 8; ++p) {
                 const int c = 2 * p + cl;
-                const int col = wn0 + 16 * (FP8 ? hs : ((hs + rot_b) & 3)) + c;
+                const int col = wn0 + (FP8 ? 32 * (((hs >> 1) + rot_b) & 1) + 16 * (hs & 1) : 16 * ((hs + rot_b) & 3)) + c;
                 const f32x4_t v = *(const f32x4_t*)(stg + c * kWideCP + rl);
                 const bool colok = col < Q;
                 const bool full = colok && row + 4 <= R;
@@ -529,10 +626,26 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
     if constexpr (MODE == 0) {
         pass(true, false);
     } else {
-        if (!FP8 && !cin) {
+        if (FP8 && !cin) {
             // column sums of the final values alpha s acc over the wave's 128
             // rows, straight from the accumulators: the products are the ones
             // the pass below stores (the same binary32 multiply)
+#pragma unroll
+            for (int h = 0; h < FN; ++h) {
+                const int col = wn0 + 32 * ((h + rot_b) & 1) + l32;
+                double sh = 0.0;
+#pragma unroll
+                for (int g = 0; g < FM; ++g)
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        const int rw = wm0 + 32 * ((g + rot_a) & 3) + 8 * (q / 4) + 4 * lh + q % 4;
+                        sh += (rw < R && col < Q) ? (double)(as * acc[g][h][q]) : 0.0;
+                    }
+                sh += __shfl_xor(sh, 32);
+                if (lh == 0) V.cs[wr][col] = sh;
+            }
+        } else if (!cin) {
+            // the same for the 16 x 16 fragments
 #pragma unroll
             for (int h = 0; h < 4; ++h) {
                 const int col = wn0 + 16 * ((h + rot_b) & 3) + l16;
@@ -570,16 +683,18 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
             if (isrow) {
                 const int rw = 128 * I + xi;
                 ref = V.rs[2 * J][rw] + V.rs[2 * J + 1][rw];
-                double e = (double)V.er[rw][3 * J] + (double)V.er[rw][3 * J + 1] + (double)V.er[rw][3 * J + 2];
+                double e = 0.0;
+#pragma unroll
+                for (int t = 0; t < Cf::PIECES; ++t) e += piece_weight(t) * (double)V.er[rw][Cf::PIECES * J + t];
                 if (inj && ea->inj.target == FTG_TARGET_CHECKSUM) {
                     const InjectParams ipe = inject_of(ea);
                     Fault f2[2];
                     const int nf = slot_faults(ipe, (uint64_t)tnc * ea->tiles_m + tmc, Rt, Qt, 0, K, f2);
                     for (int q = 0; q < nf; ++q)
                         if (f2[q].row == xi) {
-                            const float o = V.er[rw][3 * J];
+                            const float o = V.er[rw][Cf::PIECES * J];
                             const float nv = flip_f32(o, f2[q].bit);
-                            e += (double)nv - (double)o;
+                            e += piece_weight(0) * ((double)nv - (double)o);
                             push_inject(ea->rep, ea->problem, tmc, tnc, 0, m0 + rw, -1, f2[q].pflip, f2[q].bit,
                                         FTG_TARGET_CHECKSUM, (double)o, (double)nv);
                         }
@@ -593,7 +708,9 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
             } else {
                 const int cw = 128 * J + xi;
                 ref = V.cs[I][cw];
-                const double e = (double)V.ec[cw][3 * I] + (double)V.ec[cw][3 * I + 1] + (double)V.ec[cw][3 * I + 2];
+                double e = 0.0;
+#pragma unroll
+                for (int t = 0; t < Cf::PIECES; ++t) e += piece_weight(t) * (double)V.ec[cw][Cf::PIECES * I + t];
                 ex = asd * e;
                 mag = fabs(asd) * (double)ea->CB[n0 + cw] * (double)ea->MA[tmc];
                 if (cin) { ex += bd * V.cic[I][cw]; mag += fabs(bd) * V.cica[I][cw]; }

@@ -1,6 +1,6 @@
 """GPU parity of the wide low-precision tile (configuration 2: 256 x 256 outputs per
-workgroup, eight waves of 128 x 64; bf16 plain and protected, fp8 plain on the
-full-rate f8f6f4 MFMA) against the CPU oracle, through the C ABI.
+workgroup, eight waves of 128 x 64; bf16, and fp8 on the full-rate f8f6f4 MFMA,
+plain and protected) against the CPU oracle, through the C ABI.
 
 Same bars as the 128 x 128 kernel: integer-exact inputs give the oracle's result
 bitwise (FP32 accumulation is exact there), random inputs stay within the
@@ -115,6 +115,55 @@ def test_wide_checksum_target_and_two_in_slot(env):
     out, rep = r.gpu(1.0, 1.0, cfg)
     assert rep.injected == 4 and rep.checksum_only == 4
     assert all(g["kind"] == ftgemm.KIND_CHECKSUM_ONLY and g["col"] == -1 for g in rep.records)
+    assert_close32(out, r.oracle(1.0, 1.0), r.magnitude(1.0, 1.0), r.k)
+    cfg = ftgemm.make_config(seed=5, n_faults=2, bit_lo=26, bit_hi=30, target=ftgemm.TARGET_TWO_IN_SLOT,
+                             tile=WIDE)
+    out, rep = r.gpu(1.0, 0.0, cfg)
+    assert rep.injected == 4 and rep.uncorrectable == 2 and rep.status == ftgemm.ERR_UNCORRECTED
+
+
+# ---- protected fp8: e4m3 checksum pieces (eight per panel sum, scales
+# 2^(7 - 4 t)) multiplied on the fp8 MFMA
+
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_wide_fp8_protected_integer_exact(env, ta, tb):
+    ftgemm = env[0]
+    r = Run(env, "fp8", 520, 300, 192, ta, tb, seed=40, integer=True)
+    for alpha, beta in [(1.0, 0.0), (1.0, 1.0), (-2.0, 0.5)]:
+        out, rep = r.gpu(alpha, beta, ftgemm.make_config(tile=WIDE), nan_c=(beta == 0.0))
+        np.testing.assert_array_equal(out, r.oracle(alpha, beta))
+        assert rep.detected == 0, rep.records[:3]
+
+
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0)])
+def test_wide_fp8_protected_random_no_false_flags(env, ta, tb):
+    ftgemm = env[0]
+    r = Run(env, "fp8", 600, 650, 1024, ta, tb, seed=41)
+    for alpha, beta in [(1.0, 0.0), (1.5, 0.5)]:
+        out, rep = r.gpu(alpha, beta, ftgemm.make_config(tile=WIDE))
+        assert_close32(out, r.oracle(alpha, beta), r.magnitude(alpha, beta), r.k)
+        assert rep.detected == 0, rep.records[:3]
+
+
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0)])
+def test_wide_fp8_flips_located_and_corrected(env, ta, tb):
+    ftgemm = env[0]
+    r = Run(env, "fp8", 530, 400, 704, ta, tb, seed=42)
+    F = 12
+    for alpha, beta in [(1.0, 0.0), (1.5, 0.5)]:
+        cfg = ftgemm.make_config(seed=31, n_faults=F, bit_lo=24, bit_hi=30, tile=WIDE)
+        out, rep = r.gpu(alpha, beta, cfg)
+        plan = plan_for(r, 31, F, 24, 30)
+        assert rep.injected == F and rep.uncorrectable == 0
+        assert check_flips(r, alpha, beta, out, rep, plan) >= F // 2
+
+
+def test_wide_fp8_checksum_target_and_two_in_slot(env):
+    ftgemm = env[0]
+    r = Run(env, "fp8", 256, 384, 320, 0, 0, seed=43)
+    cfg = ftgemm.make_config(seed=3, n_faults=4, bit_lo=25, bit_hi=30, target=ftgemm.TARGET_CHECKSUM, tile=WIDE)
+    out, rep = r.gpu(1.0, 1.0, cfg)
+    assert rep.injected == 4 and rep.checksum_only == 4
     assert_close32(out, r.oracle(1.0, 1.0), r.magnitude(1.0, 1.0), r.k)
     cfg = ftgemm.make_config(seed=5, n_faults=2, bit_lo=26, bit_hi=30, target=ftgemm.TARGET_TWO_IN_SLOT,
                              tile=WIDE)
