@@ -58,10 +58,13 @@ struct WCfg {
     static constexpr int XF = FP8 ? 1 : 2;  // checksum fragments per wave and kind
 };
 
-// 16-byte chunk c of LDS row r is stored at chunk c ^ wide_swz(r): a 16-lane
-// fragment read (rows r0 .. r0 + 15, one chunk) then touches every bank once
-// per pair of rows.
-__device__ __attribute__((always_inline)) inline int wide_swz(int r) { return (r >> 1) & 3; }
+// 16-byte chunk c of LDS row r is stored at chunk c ^ wide_swz(r).  A
+// fragment read has 16 (bf16) or 32 (fp8) lanes on consecutive rows and one
+// chunk; rows r and r + 4 share banks (64-byte rows), and the swizzle moves
+// them to different chunks, so any 16 or 32 consecutive rows spread evenly
+// over the banks (a period of 8 rows, (r >> 1) & 3, measured 4 conflict
+// cycles per fp8 read).
+__device__ __attribute__((always_inline)) inline int wide_swz(int r) { return (r >> 2) & 3; }
 
 // Waits until at most `later` blocks of this wave's loads (PER each) are in
 // flight, and for its LDS reads; then a barrier publishes the block.
