@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void lowp_encode_k_kernel(EncArgs args)
     constexpr int RG = 256 / SG;                   // row groups
     constexpr int RPT = kLowpTile / RG;            // rows per thread
     static_assert(kLowpTile % RG == 0 && 64 % SG == 0, "encode map");
-    __shared__ double cpart[4][kLowpChunk][2];
+    __shared__ double cpart[4][4][kLowpChunk][2];  // [wave][16-lane row][step]
     __shared__ float pmax[kLowpChunk];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int sg = tid % SG, rg = tid / SG;
@@ -175,18 +175,22 @@ __global__ __launch_bounds__(256) void lowp_encode_k_kernel(EncArgs args)
     auto val = [&](int u, int e) __attribute__((always_inline)) -> double {
         return (double)bf16_bits_to_f32((hv[u][e / 2] >> (16 * (e % 2))) & 0xFFFFu);
     };
-    // row sums of |x| over this block's steps
+    // row sums of |x| over this block's steps: the 8 step groups of a row are
+    // 8 neighbouring lanes, summed by data-parallel moves (no LDS traffic)
+    static_assert(SG == 8, "lane map of the reductions");
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
         double ra = 0.0;
 #pragma unroll
         for (int e = 0; e < V; ++e) ra += fabs(val(u, e));
-#pragma unroll
-        for (int off = 1; off < SG; off <<= 1) ra += __shfl_xor(ra, off);
+        ra += dpp_f64<0xB1>(ra);   // quad_perm [1,0,3,2]
+        ra += dpp_f64<0x4E>(ra);   // quad_perm [2,3,0,1]
+        ra += dpp_f64<0x141>(ra);  // row_half_mirror: the other quad of the 8
         const int64_t r = r0 + rg * RPT + u;
         if (sg == 0 && r < E.rows) E.XRp[(int64_t)c * E.rows + r] = f64_to_f32_up(ra);
     }
-    // column sums over this block's rows
+    // column sums over this block's rows: the two row groups of a 16-lane row
+    // by a rotation of 8 lanes, the 4 x 4 rows of the workgroup through LDS
 #pragma unroll
     for (int e = 0; e < V; ++e) {
         double cs = 0.0, ca = 0.0;
@@ -196,14 +200,11 @@ __global__ __launch_bounds__(256) void lowp_encode_k_kernel(EncArgs args)
             cs += v;
             ca += fabs(v);
         }
-#pragma unroll
-        for (int off = SG; off < 64; off <<= 1) {
-            cs += __shfl_xor(cs, off);
-            ca += __shfl_xor(ca, off);
-        }
-        if (lane < SG) {
-            cpart[w][sg * V + e][0] = cs;
-            cpart[w][sg * V + e][1] = ca;
+        cs += dpp_f64<0x128>(cs);  // row_ror:8
+        ca += dpp_f64<0x128>(ca);
+        if ((lane & 8) == 0) {
+            cpart[w][lane >> 4][sg * V + e][0] = cs;
+            cpart[w][lane >> 4][sg * V + e][1] = ca;
         }
     }
     __syncthreads();
@@ -211,10 +212,12 @@ __global__ __launch_bounds__(256) void lowp_encode_k_kernel(EncArgs args)
         const int p = tid;
         double s = 0.0, sa = 0.0;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            s += cpart[v][p][0];
-            sa += cpart[v][p][1];
-        }
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                s += cpart[v][q][p][0];
+                sa += cpart[v][q][p][1];
+            }
         pmax[p] = f64_to_f32_up(sa);
         if (p0 + p < E.K && E.XS) {
             // three bf16 pieces: hi + mid + lo = s to within 2^-24 |s|
@@ -256,27 +259,37 @@ __global__ __launch_bounds__(256) void lowp_encode_k_kernel(EncArgs args)
 }
 
 // XR[r] = sum over chunks (binary64, rounded up); XM[panel] = max over chunks.
+// A workgroup takes 64 rows; its four waves sum every fourth chunk, then the
+// partial sums are added through LDS (the chunks of a row are far apart in
+// memory, the rows of a chunk contiguous).
+constexpr int kFinishRows = 64;
 __global__ __launch_bounds__(256) void lowp_encode_finish_kernel(EncArgs args)
 {
     const EncOperand& E = args.op[blockIdx.y];
-    const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    __shared__ double part[4][kFinishRows];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t x = (int64_t)blockIdx.x * kFinishRows + lane;
+    double s = 0.0;
     if (x < E.rows) {
-        double s = 0.0;
-        int c = 0;
-        for (; c + 16 <= E.chunks; c += 16) {
-            float v[16];
+        int c = w;
+        for (; c + 12 < E.chunks; c += 16) {
+            float v[4];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) v[u] = E.XRp[(int64_t)(c + u) * E.rows + x];
+            for (int u = 0; u < 4; ++u) v[u] = E.XRp[(int64_t)(c + 4 * u) * E.rows + x];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) s += (double)v[u];
+            for (int u = 0; u < 4; ++u) s += (double)v[u];
         }
-        for (; c < E.chunks; ++c) s += (double)E.XRp[(int64_t)c * E.rows + x];
-        E.XR[x] = f64_to_f32_up(s);
+        for (; c < E.chunks; c += 4) s += (double)E.XRp[(int64_t)c * E.rows + x];
     }
-    if (x < E.panels) {
+    part[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && x < E.rows)
+        E.XR[x] = f64_to_f32_up(part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]);
+    const int64_t pnl = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (pnl < E.panels) {
         float mx = 0.0f;
-        for (int c = 0; c < E.chunks; ++c) mx = fmaxf(mx, E.XMp[x * E.chunks + c]);
-        E.XM[x] = mx;
+        for (int c = 0; c < E.chunks; ++c) mx = fmaxf(mx, E.XMp[pnl * E.chunks + c]);
+        E.XM[pnl] = mx;
     }
 }
 
@@ -312,7 +325,11 @@ hipError_t launch_lowp_encode(const EncArgs& e, ftg_dtype st, int grid_x, int fi
     }
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(lowp_encode_finish_kernel, dim3(finish_x, 2), dim3(256), 0, s, e);
+    (void)finish_x;
+    const int64_t rows = std::max<int64_t>(std::max(e.op[0].rows, e.op[1].rows),
+                                           (int64_t)std::max(e.op[0].panels, e.op[1].panels));
+    hipLaunchKernelGGL(lowp_encode_finish_kernel, dim3((unsigned)((rows + kFinishRows - 1) / kFinishRows), 2),
+                       dim3(256), 0, s, e);
     return hipGetLastError();
 }
 
