@@ -58,13 +58,16 @@ struct WCfg {
     static constexpr int XF = FP8 ? 1 : 2;  // checksum fragments per wave and kind
 };
 
-// 16-byte chunk c of LDS row r is stored at chunk c ^ wide_swz(r).  A
-// fragment read has 16 (bf16) or 32 (fp8) lanes on consecutive rows and one
-// chunk; rows r and r + 4 share banks (64-byte rows), and the swizzle moves
-// them to different chunks, so any 16 or 32 consecutive rows spread evenly
-// over the banks (a period of 8 rows, (r >> 1) & 3, measured 4 conflict
-// cycles per fp8 read).
-__device__ __attribute__((always_inline)) inline int wide_swz(int r) { return (r >> 2) & 3; }
+// 16-byte chunk c of LDS row r is stored at chunk c ^ wide_swz<FP8>(r).
+// Measured with SQ_LDS_BANK_CONFLICT: the bf16 fragment reads (16 lanes on
+// consecutive rows per chunk) are conflict-free with (r >> 1) & 3 and take
+// about 4 conflict cycles per read with (r >> 2) & 3; the fp8 reads (32 lanes
+// on consecutive rows, two chunks each) the other way round.
+template <bool FP8>
+__device__ __attribute__((always_inline)) inline int wide_swz(int r)
+{
+    return FP8 ? (r >> 2) & 3 : (r >> 1) & 3;
+}
 
 // Waits until at most `later` blocks of this wave's loads (PER each) are in
 // flight, and for its LDS reads; then a barrier publishes the block.
@@ -162,7 +165,7 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
 
     // ---- staging: per stage 16 wave loads of A rows then 16 of B rows, four
     // per wave; wave load I covers rows 16 I .. 16 I + 15 (slot = 64 I + lane,
-    // row = slot / 4, chunk = slot % 4, stored at chunk ^ wide_swz(row)).  A
+    // row = slot / 4, chunk = slot % 4, stored at chunk ^ wide_swz<FP8>(row)).  A
     // wave's load u covers rows 64 (wave % 4) + 16 u + lane / 4: the same lane
     // offset from a resource that starts 16 u rows further and ends after the
     // last row of the matrix (the range check applies to the lane offset), so
@@ -174,7 +177,7 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
     int voff0;
     {
         const int x = lane / 4;
-        voff0 = (int)((int64_t)x * ldx + 16 * ((lane & 3) ^ wide_swz(x)));
+        voff0 = (int)((int64_t)x * ldx + 16 * ((lane & 3) ^ wide_swz<FP8>(x)));
     }
     const unsigned char* src0 = (a_wave ? A + m0 * lda * Cf::EB : B + n0 * ldb * Cf::EB) + 64 * (wave & 3) * ldx;
     // protected, bf16: wave 0 adds one load per stage of the checksum pieces
@@ -332,7 +335,7 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
     };
 
     // fragment read offset inside a row: chunk lq, swizzled by the row (l16)
-    const int fo = 16 * (lq ^ wide_swz(l16));
+    const int fo = 16 * (lq ^ wide_swz<FP8>(l16));
     // A fragments: one set, each refilled with the next block's as soon as
     // its four MFMAs are issued; B fragments: two sets; checksum-piece
     // fragments (x[0]: e^T A_I rows, x[1]: B_J e rows; rows 6 and 7 of each
@@ -341,7 +344,7 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
     Frag fa[FM], fb[2][FN], fx[2];
     // fp8: the lane's 32 steps are chunks 2 (lane / 32) and + 1 of its row
     const int l32 = lane & 31, lh = lane >> 5;
-    const int fo8a = 16 * ((2 * lh) ^ wide_swz(l32)), fo8b = 16 * ((2 * lh + 1) ^ wide_swz(l32));
+    const int fo8a = 16 * ((2 * lh) ^ wide_swz<FP8>(l32)), fo8b = 16 * ((2 * lh + 1) ^ wide_swz<FP8>(l32));
     auto frag_at = [&](const unsigned char* rowp) __attribute__((always_inline)) {
         if constexpr (FP8) {
             const u32x4_t lo = *(const u32x4_t*)(rowp + fo8a), hi = *(const u32x4_t*)(rowp + fo8b);
