@@ -136,11 +136,14 @@ def measure(torch, ftgemm, h, m, n, k, alpha, beta, ta, tb, steps, warmup, tile,
 
 
 def timed_ab(torch, fns, steps, warmup, rounds=2):
-    """Median ms per call of each function, alternating them round by round."""
+    """Median ms per call of each function, alternating them round by round.  The
+    order rotates from round to round (at least one round per function), so that
+    no function always runs first, right after whatever preceded the leg."""
     out = {name: [] for name in fns}
-    for _ in range(rounds):
-        for name, fn in fns.items():
-            out[name].append(time_calls(torch, fn, steps, warmup))
+    names = list(fns)
+    for r in range(max(rounds, len(names))):
+        for name in names[r % len(names):] + names[:r % len(names)]:
+            out[name].append(time_calls(torch, fns[name], steps, warmup))
     return {name: float(np.median(v)) for name, v in out.items()}
 
 
