@@ -169,3 +169,21 @@ def test_wide_fp8_checksum_target_and_two_in_slot(env):
                              tile=WIDE)
     out, rep = r.gpu(1.0, 0.0, cfg)
     assert rep.injected == 4 and rep.uncorrectable == 2 and rep.status == ftgemm.ERR_UNCORRECTED
+
+
+@pytest.mark.parametrize("kind", ["bf16", "fp8"])
+def test_wide_protected_edges(env, kind):
+    """Protected wide calls on a C whose leading dimension rules out 16-byte
+    stores (m = 301), with beta != 0 (the tile is stored by a second pass after
+    the checks) and with a NaN-filled C at beta = 0 (C is not read); a k that is
+    no multiple of the k-block falls back to the 128 x 128 kernel."""
+    ftgemm = env[0]
+    r = Run(env, kind, 301, 530, 192, 0, 0, seed=44, integer=True)
+    for alpha, beta in [(1.0, 0.0), (-2.0, 0.5)]:
+        out, rep = r.gpu(alpha, beta, ftgemm.make_config(tile=WIDE), nan_c=(beta == 0.0))
+        np.testing.assert_array_equal(out, r.oracle(alpha, beta))
+        assert rep.detected == 0, rep.records[:3]
+    r = Run(env, kind, 300, 280, 200, 1, 0, seed=45, integer=True)
+    out, rep = r.gpu(1.0, 1.0, ftgemm.make_config(tile=WIDE))
+    np.testing.assert_array_equal(out, r.oracle(1.0, 1.0))
+    assert rep.detected == 0
