@@ -69,7 +69,8 @@ class _Params(ct.Structure):
                 ("lda", ct.c_int64), ("ldb", ct.c_int64), ("ldc", ct.c_int64),
                 ("bm", ct.c_int64), ("bn", ct.c_int64), ("kc", ct.c_int64),
                 ("acc32", ct.c_int32), ("lam", ct.c_double),
-                ("correct_policy", ct.c_int32), ("uncorrectable_policy", ct.c_int32)]
+                ("correct_policy", ct.c_int32), ("uncorrectable_policy", ct.c_int32),
+                ("split", ct.c_int32)]
 
 
 class _Record(ct.Structure):
@@ -253,15 +254,21 @@ class Record:
 
 
 def abft(A, B, C=None, alpha=1.0, beta=0.0, ta=0, tb=0, bm=128, bn=128, kc=0, plan=(),
-         acc32=False, lam=1.0, correct_policy=0, uncorrectable_policy=0, cap=4096):
-    """Simulates the protected product; returns (C_out, records, counts dict)."""
+         acc32=False, lam=1.0, correct_policy=0, uncorrectable_policy=0, cap=4096, split=False):
+    """Simulates the protected product; returns (C_out, records, counts dict).
+
+    split: with intervals (kc), C is the accumulator from one interval to the
+    next (the K_c loop of the blocked GEMM, §5.1): interval t is checked as the
+    product C := alpha A_t B_t + beta_t C with its own accumulator, checksums and
+    magnitudes, beta_t = beta for the first interval and 1 after; without it the
+    accumulator runs on through the intervals (the online scheme of §2.1)."""
     A = _f64(A); B = _f64(B)
     m = A.shape[1] if ta else A.shape[0]
     k = A.shape[0] if ta else A.shape[1]
     n = B.shape[0] if tb else B.shape[1]
     C = np.zeros((m, n), order="F") if C is None else _f64(C).copy(order="F")
     P = _Params(ta, tb, m, n, k, alpha, beta, _ld(A), _ld(B), _ld(C), bm, bn, kc, int(acc32),
-                lam, correct_policy, uncorrectable_policy)
+                lam, correct_policy, uncorrectable_policy, int(split))
     plan = list(plan)
     pa = (_Fault * max(1, len(plan)))()
     for q, f in enumerate(plan):

@@ -25,6 +25,10 @@
  *                   magnitude at that position (§6.3), one error corrected per
  *                   interval without checkpoint/rollback (§2.1), and the C
  *                   checksums of beta*C_in fused with the scaling (§5.2).
+ *                   With `split` set, C itself is the accumulator across the
+ *                   intervals, as in the K_c loop of the blocked GEMM (§5.1:
+ *                   each rank-K_c update C := alpha A_t B_t + beta_t C is
+ *                   checked on its own, beta_t = beta for the first and 1 after).
  *  - fault plan     the seeded injection plan: which (tile, interval) slots
  *                   receive a fault and the element, step and bit of each
  *                   (§6.3 injects one error per injection interval into a
@@ -284,6 +288,7 @@ typedef struct {
     double lambda;    /* threshold scale for acc32 */
     int32_t correct_policy;       /* 0: subtract, re-verify, recompute; 1: recompute */
     int32_t uncorrectable_policy; /* 0: report only; 1: recompute the tile */
+    int32_t split;    /* 1: every interval is a product of its own (see ftgo_abft) */
 } ftgo_params;
 
 typedef struct {
@@ -339,6 +344,10 @@ typedef struct {
     double *rs, *cs, *out;
     const ftgo_params* P;
     const double *A, *B, *Cin;
+    /* first step of the product being checked (0, or the interval's with
+     * `split`) and the beta that scales C_in at its final check */
+    int64_t plo;
+    double beta_t;
 } tile_state;
 
 static double tA(const tile_state* T, int64_t i, int64_t p)
@@ -397,11 +406,11 @@ static void advance(tile_state* T, int64_t plo, int64_t phi, const ftgo_fault* p
     }
 }
 
-/* Fresh dot product of row i and column j over steps [0, pend), ascending. */
+/* Fresh dot product of row i and column j over steps [plo, pend), ascending. */
 static double dot_fresh(const tile_state* T, int64_t i, int64_t j, int64_t pend)
 {
     double s = 0.0;
-    for (int64_t p = 0; p < pend; ++p) s = s + tA(T, i, p) * tB(T, p, j);
+    for (int64_t p = T->plo; p < pend; ++p) s = s + tA(T, i, p) * tB(T, p, j);
     return s;
 }
 
@@ -412,7 +421,7 @@ static double out_value(const tile_state* T, int final, double accv, int64_t i, 
 {
     if (!final) return accv;
     const ftgo_params* P = T->P;
-    return (P->beta == 0.0) ? P->alpha * accv : P->alpha * accv + P->beta * tC(T, i, j);
+    return (T->beta_t == 0.0) ? P->alpha * accv : P->alpha * accv + T->beta_t * tC(T, i, j);
 }
 
 typedef struct { double d, tau; } check;
@@ -427,7 +436,7 @@ static check check_line(const tile_state* T, int final, int64_t pend, int dir, i
     for (int64_t y = 0; y < len; ++y) {
         int64_t i = dir == 0 ? x : y, j = dir == 0 ? y : x;
         ref = ref + T->out[i + j * R];
-        if (final && P->beta != 0.0) { double c = tC(T, i, j); cin = cin + c; cinabs = cinabs + fabs(c); }
+        if (final && T->beta_t != 0.0) { double c = tC(T, i, j); cin = cin + c; cinabs = cinabs + fabs(c); }
     }
     double maint = dir == 0 ? T->er[x] : T->ec[x];
     double mag = dir == 0 ? T->mr[x] : T->mc[x];
@@ -438,11 +447,11 @@ static check check_line(const tile_state* T, int final, int64_t pend, int dir, i
     if (final) {
         expect = P->alpha * maint;
         mag = fabs(P->alpha) * mag;
-        if (P->beta != 0.0) { expect = expect + P->beta * cin; mag = mag + fabs(P->beta) * cinabs; }
+        if (T->beta_t != 0.0) { expect = expect + T->beta_t * cin; mag = mag + fabs(T->beta_t) * cinabs; }
     }
     check c;
     c.d = ref - expect;
-    c.tau = ftgo_tau(P->acc32, P->lambda, pend + len + 8, mag);
+    c.tau = ftgo_tau(P->acc32, P->lambda, pend - T->plo + len + 8, mag);
     return c;
 }
 
@@ -535,7 +544,7 @@ static void verify_slot(tile_state* T, int final, int64_t pend, int64_t tm, int6
         memset(T->ra, 0, sizeof(double) * R);
         memset(T->cb, 0, sizeof(double) * Q);
         T->mxb = T->mxa = 0.0;
-        advance(T, 0, pend, plan, nplan, 0, cnt);
+        advance(T, T->plo, pend, plan, nplan, 0, cnt);
         for (int64_t j = 0; j < Q; ++j)
             for (int64_t i = 0; i < R; ++i)
                 T->out[i + j * R] = out_value(T, final, T->acc[i + j * R], i, j);
@@ -591,21 +600,30 @@ int ftgo_abft(const ftgo_params* P, const double* A, const double* B, double* C,
         for (int64_t tm = 0; tm < tiles_m; ++tm) {
             T.i0 = tm * P->bm; T.j0 = tn * P->bn;
             T.R = min64(P->bm, P->m - T.i0); T.Q = min64(P->bn, P->n - T.j0);
-            memset(T.acc, 0, sizeof(double) * T.R * T.Q);
-            memset(T.er, 0, sizeof(double) * T.R);
-            memset(T.mr, 0, sizeof(double) * T.R);
-            memset(T.ec, 0, sizeof(double) * T.Q);
-            memset(T.mc, 0, sizeof(double) * T.Q);
-            memset(T.ra, 0, sizeof(double) * T.R);
-            memset(T.cb, 0, sizeof(double) * T.Q);
-            T.mxb = T.mxa = 0.0;
             int64_t ns = 0; /* this tile's faults */
             for (int64_t f = 0; f < nplan; ++f)
                 if (plan[f].tile_m == tm && plan[f].tile_n == tn) sub[ns++] = plan[f];
+            T.plo = 0;
+            T.beta_t = P->beta;
             for (int64_t t = 0; t < n_int; ++t) {
                 int64_t plo = t * kc, phi = min64(P->k, plo + kc);
+                if (t == 0 || P->split) {
+                    /* a fresh accumulator, checksums and magnitude sums: the
+                     * product's start (with `split`, every interval's, whose
+                     * check then also covers C_in as left by the interval
+                     * before, with beta_t = 1) */
+                    memset(T.acc, 0, sizeof(double) * T.R * T.Q);
+                    memset(T.er, 0, sizeof(double) * T.R);
+                    memset(T.mr, 0, sizeof(double) * T.R);
+                    memset(T.ec, 0, sizeof(double) * T.Q);
+                    memset(T.mc, 0, sizeof(double) * T.Q);
+                    memset(T.ra, 0, sizeof(double) * T.R);
+                    memset(T.cb, 0, sizeof(double) * T.Q);
+                    T.mxb = T.mxa = 0.0;
+                }
+                if (P->split) { T.plo = plo; T.beta_t = t == 0 ? P->beta : 1.0; }
                 advance(&T, plo, phi, sub, ns, 1, counts);
-                verify_slot(&T, t == n_int - 1, phi, tm, tn, t, sub, ns, recs, cap, counts);
+                verify_slot(&T, P->split || t == n_int - 1, phi, tm, tn, t, sub, ns, recs, cap, counts);
             }
         }
     }

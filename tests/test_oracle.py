@@ -424,6 +424,79 @@ def test_acc32_absorbing_flip_recomputed_small_flip_subtracted():
         np.testing.assert_allclose(C, ref, rtol=0, atol=1e-9 * np.abs(A).sum(axis=1).max() * np.abs(B).max())
 
 
+# ----------------------------------------------------------------------------- split intervals
+def _np_flip32(x, bit):
+    """IEEE binary32 bit flip by the bit layout (numpy view), independent of the oracle."""
+    u = np.array([x], dtype=np.float32).view(np.uint32)
+    u ^= np.uint32(1 << bit)
+    return float(u.view(np.float32)[0])
+
+
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 1)])
+@pytest.mark.parametrize("alpha,beta", [(1.0, 0.0), (1.5, 0.5), (-2.0, 1.0)])
+def test_split_intervals_integer_exact(ta, tb, alpha, beta):
+    """C as the accumulator across K_c intervals (each interval its own product,
+    beta only on the first): with no fault the result is the exact product,
+    nothing is flagged, and one interval reproduces the unsplit call bitwise."""
+    m, n, k = 37, 29, 50
+    A, B, C = inputs.integer_operands(m, n, k, seed=21, ta=ta, tb=tb)
+    exact = exact_product(A, B, C, alpha, beta, ta, tb)
+    for kc in (16, 32, 48):
+        out, recs, cnt = oracle.abft(A, B, C, alpha, beta, ta, tb, bm=16, bn=16, kc=kc, acc32=True,
+                                     lam=4.0, split=True)
+        np.testing.assert_array_equal(out, exact)
+        assert cnt["detected"] == 0 and not recs
+    one, _, _ = oracle.abft(A, B, C, alpha, beta, ta, tb, bm=16, bn=16, kc=0, acc32=True, lam=4.0,
+                            split=True)
+    ref, _, _ = oracle.abft(A, B, C, alpha, beta, ta, tb, bm=16, bn=16, kc=0, acc32=True, lam=4.0)
+    np.testing.assert_array_equal(one, ref)
+
+
+def test_split_delta_is_the_flip_of_the_interval_partial_sum():
+    """A flip of the accumulator after step p of interval t changes the element by
+    flip(s) - s with s the interval's own partial sum a_i[plo..p] . b_j[plo..p]
+    (split), but the running sum over [0, p] in the online scheme, unscaled
+    before the final check.  Partial sums are small integers here, so both are
+    exact; each fault is located in its interval and corrected bitwise."""
+    m, n, k, kc = 16, 16, 96, 32
+    A, B, C = inputs.integer_operands(m, n, k, seed=8)
+    alpha, beta = 1.5, 0.5
+    plan = [oracle.Fault(0, 0, t, 2 + t, 5 + 2 * t, kc * t + 9 + 5 * t, 23, oracle.TARGET_ACC)
+            for t in range(3)]
+    for split in (True, False):
+        out, recs, cnt = oracle.abft(A, B, C, alpha, beta, bm=16, bn=16, kc=kc, plan=plan, acc32=True,
+                                     lam=4.0, split=split)
+        np.testing.assert_array_equal(out, exact_product(A, B, C, alpha, beta, 0, 0))
+        assert [(r.interval, r.row, r.col) for r in recs] == [(f.interval, f.row, f.col) for f in plan]
+        for f, r in zip(plan, recs):
+            lo = kc * f.interval if split else 0
+            s = float(A[f.row, lo:f.pflip + 1] @ B[lo:f.pflip + 1, f.col])
+            assert s != 0.0
+            scale = alpha if (split or f.interval == 2) else 1.0
+            assert r.delta == scale * (_np_flip32(s, 23) - s), (split, f, r)
+            assert r.kind == oracle.KIND_SUBTRACT
+
+
+def test_split_threshold_closed_form():
+    """All-ones operands and C: interval 1 of a split call checks
+    alpha A_1 B_1 + 1 C_1 with C_1 = alpha kc + beta left by interval 0, so the
+    row bound is |alpha| kc Q + Q (alpha kc + beta) over kc + Q + 8 terms."""
+    m, n, k, kc, lam = 32, 16, 48, 16, 2.0
+    A = np.ones((m, k), order="F")
+    B = np.ones((k, n), order="F")
+    C = np.ones((m, n), order="F")
+    alpha, beta = 2.0, 0.5
+    plan = [oracle.Fault(0, 0, 1, 4, 7, 2 * kc - 1, 30, oracle.TARGET_ACC)]
+    out, recs, cnt = oracle.abft(A, B, C, alpha, beta, bm=32, bn=16, kc=kc, plan=plan, acc32=True,
+                                 lam=lam, split=True)
+    assert cnt["detected"] == 1 and recs[0].interval == 1 and (recs[0].row, recs[0].col) == (4, 7)
+    Q = 16
+    M = alpha * kc * Q + Q * (alpha * kc + beta)
+    want = 2.0 * lam * math.sqrt(kc + Q + 8) * 2.0 ** -24 * M * (1 + 2.0 ** -20)
+    assert recs[0].tau == pytest.approx(want, rel=1e-12)
+    np.testing.assert_array_equal(out, alpha * k * np.ones((m, n)) + beta)
+
+
 # ----------------------------------------------------------------------------- FP64 threshold, closed form
 U64 = 2.0 ** -53
 
