@@ -58,6 +58,13 @@ struct LowpArgs {
     const void* XSA;
     const void* XSB;
     int64_t cslice, er_stride, ec_stride;
+    // verification intervals: this launch is the rank-k update of interval
+    // `interval` of n_int (steps plo .. plo + k - 1 of the whole product; A, B
+    // and XSA / XSB already point at step plo), whose injection slot is
+    // tile * n_int + interval; ldxs = elements between rows of XSA / XSB
+    int n_int, interval;
+    int64_t plo;
+    int ldxs;
 };
 
 // Encode pass over one operand.  // One operand X with rows r (i of op(A), or j of op(B)) and steps p:
@@ -68,13 +75,15 @@ struct EncOperand {
     int rows, K, kcontig;
     int vec;             // 16-byte loads allowed (base and ld aligned)
     int panels, chunks;  // panel = output-tile extent; chunk = kLowpChunk steps
+    int ichunks;         // chunks per verification interval (XR, XM: one set per interval)
     uint16_t* XS;        // bf16 pieces: XS[(3 panel + s) K + p] (NULL: not written)
     uint8_t* XS8;        // e4m3 pieces with scales 2^(7 - 4 t):
                          // XS8[(8 panel + t) K + p] (NULL: not written)
     float* XRp;          // partial |x| row sums: XRp[chunk rows + r]
     float* XMp;          // partial panel maxima: XMp[panel chunks + chunk]
-    float* XR;           // finalised: XR[r] = sum_p |x(r, p)| (rounded up)
-    float* XM;           // finalised: XM[panel] = max_p sum_{r in panel} |x(r, p)|
+    float* XR;           // finalised per interval t (steps of chunks t ichunks ..):
+                         // XR[t rows + r] = sum_p |x(r, p)| (rounded up)
+    float* XM;           // XM[t panels + panel] = max_p sum_{r in panel} |x(r, p)|
 };
 struct EncArgs {
     EncOperand op[2];

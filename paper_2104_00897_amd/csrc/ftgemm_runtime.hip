@@ -1101,7 +1101,7 @@ int lowp_ksplit(int64_t tiles, int64_t k)
     return s;
 }
 
-LowpLayout lowp_layout(int64_t m, int64_t n, int64_t k, int ks_r, int ks_c)
+LowpLayout lowp_layout(int64_t m, int64_t n, int64_t k, int ks_r, int ks_c, int64_t n_int)
 {
     const int64_t tm = (m + ftg::kLowpTile - 1) / ftg::kLowpTile, tn = (n + ftg::kLowpTile - 1) / ftg::kLowpTile;
     const int64_t ch = (k + ftg::kLowpChunk - 1) / ftg::kLowpChunk;
@@ -1116,10 +1116,10 @@ LowpLayout lowp_layout(int64_t m, int64_t n, int64_t k, int ks_r, int ks_c)
     L.xrp_b = take((size_t)(ch * n) * 4);
     L.xmp_a = take((size_t)(tm * ch) * 4);
     L.xmp_b = take((size_t)(tn * ch) * 4);
-    L.ra = take((size_t)m * 4);
-    L.cb = take((size_t)n * 4);
-    L.ma = take((size_t)tm * 4);
-    L.mb = take((size_t)tn * 4);
+    L.ra = take((size_t)(n_int * m) * 4);  // one set of magnitude sums per interval
+    L.cb = take((size_t)(n_int * n) * 4);
+    L.ma = take((size_t)(n_int * tm) * 4);
+    L.mb = take((size_t)(n_int * tn) * 4);
     L.er = take((size_t)ks_r * (size_t)(m * 3 * tn) * 4);
     L.ec = take((size_t)ks_c * (size_t)(3 * tm * n) * 4);
     L.total = o;
@@ -1155,7 +1155,11 @@ ftg_status ftg_gemm_ex(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n,
         lda >= (1 << 20) || ldb >= (1 << 20) || ldc >= (1 << 20))
         return FTG_ERR_UNSUPPORTED;
     const bool abft = !cfg || cfg->abft;
-    if (abft && cfg && cfg->interval_k > 0 && cfg->interval_k < k) return FTG_ERR_UNSUPPORTED;
+    // verification intervals (K_c, a multiple of 128): the product runs as
+    // rank-K_c updates of C, each protected and verified on its own
+    const int64_t kc = (abft && cfg && cfg->interval_k > 0 && cfg->interval_k < k) ? cfg->interval_k : k;
+    const int64_t n_int = (k + kc - 1) / kc;
+    if (n_int > ftg::kMaxIntervals) return FTG_ERR_UNSUPPORTED;
     int tile = cfg && cfg->tile ? cfg->tile : h->tune[ab_type][bucket(m)][bucket(n)][bucket(k)];
     if (!tile) tile = ftg::lowp_heuristic_tile(ab_type, m, n, k);
     int bm, bn, bk;
@@ -1177,6 +1181,7 @@ ftg_status ftg_gemm_ex(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n,
     a.scale_a = ab_type == FTG_F8_E4M3 ? scale_a : nullptr;
     a.scale_b = ab_type == FTG_F8_E4M3 ? scale_b : nullptr;
     a.rep = h->rep;
+    a.n_int = 1; a.ldxs = (int)k;
     // Operands whose rows are contiguous (op(A) = A, op(B) = B^T) are first
     // packed into k-major copies in the workspace: the product kernels stage
     // k-contiguous operands without register transposes (about twice as fast).
@@ -1192,7 +1197,7 @@ ftg_status ftg_gemm_ex(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n,
     const int64_t chk_tiles_r = (int64_t)a.tiles_m * ((3 * a.tiles_n + bn - 1) / bn);
     const int64_t chk_tiles_c = (int64_t)((3 * a.tiles_m + bm - 1) / bm) * a.tiles_n;
     const int ks_r = lowp_ksplit(chk_tiles_r, k), ks_c = lowp_ksplit(chk_tiles_c, k);
-    const LowpLayout L = lowp_layout(m, n, k, ks_r, ks_c);
+    const LowpLayout L = lowp_layout(m, n, k, ks_r, ks_c, n_int);
     if (abft) work_base = align256(L.total);
     // workspace (grows; allocation is not allowed under stream capture)
     if ((st = ensure_work(h, work_base + pa_bytes + pb_bytes, s)) != FTG_OK) return st;
@@ -1218,6 +1223,30 @@ ftg_status ftg_gemm_ex(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n,
     }
     const int chunks = (int)((k + ftg::kLowpChunk - 1) / ftg::kLowpChunk);
 
+    // Interval t is the update C := alpha op(A)[:, S_t] op(B)[S_t, :] + beta_t C
+    // over the steps S_t = plo .. plo + kt - 1 (beta_t = beta for the first, 1
+    // after): the operands and checksum pieces are read from step plo on, the
+    // thresholds use the interval's own magnitude sums, and the repair of its
+    // flagged slots runs before the next interval reads C.
+    auto interval_args = [&](int64_t t) {
+        ftg::LowpArgs at = a;
+        const int64_t plo = t * kc, kt = std::min(kc, k - plo);
+        at.A = (const unsigned char*)a.A + plo * eb;
+        at.B = (const unsigned char*)a.B + plo * eb;
+        at.k = (int)kt;
+        at.vec_a = vec_ok(at.A, at.lda, eb);
+        at.vec_b = vec_ok(at.B, at.ldb, eb);
+        at.beta = t == 0 ? beta : 1.0f;
+        at.n_int = (int)n_int; at.interval = (int)t; at.plo = plo;
+        at.ldxs = (int)k;
+        return at;
+    };
+    auto interval_wide = [&](const ftg::LowpArgs& at) {
+        return tile == ftg::kLowpWideTile && ftg::lowp_wide_ok(at, ab_type, 1);
+    };
+    bool any_wide = false, any_narrow = false;
+    for (int64_t t = 0; t < n_int; ++t) (interval_wide(interval_args(t)) ? any_wide : any_narrow) = true;
+
     // encode: checksum pieces and magnitude sums of both operands
     ftg::EncArgs e;
     std::memset(&e, 0, sizeof(e));
@@ -1231,73 +1260,88 @@ ftg_status ftg_gemm_ex(ftg_handle h, ftg_op ta, ftg_op tb, int64_t m, int64_t n,
     eb_.panels = a.tiles_n; eb_.chunks = chunks;
     eb_.XS = (uint16_t*)(w + L.xs_b); eb_.XRp = (float*)(w + L.xrp_b); eb_.XMp = (float*)(w + L.xmp_b);
     eb_.XR = (float*)(w + L.cb); eb_.XM = (float*)(w + L.mb);
-    if (wide && ab_type == FTG_F8_E4M3) {
-        // the fp8 wide product multiplies e4m3 pieces on the fp8 MFMA
-        ea.XS = nullptr; ea.XS8 = w + L.xs8_a;
-        eb_.XS = nullptr; eb_.XS8 = w + L.xs8_b;
+    // magnitude sums per interval (kc is a multiple of the chunk when n_int > 1)
+    ea.ichunks = eb_.ichunks = (int)((kc + ftg::kLowpChunk - 1) / ftg::kLowpChunk);
+    if (ab_type == FTG_F8_E4M3) {
+        // the fp8 wide product multiplies e4m3 pieces on the fp8 MFMA; the
+        // 128 x 128 tile's checksum products take bf16 pieces
+        if (any_wide) { ea.XS8 = w + L.xs8_a; eb_.XS8 = w + L.xs8_b; }
+        if (!any_narrow) { ea.XS = nullptr; eb_.XS = nullptr; }
     }
     const int gx = std::max(a.tiles_m, a.tiles_n) * chunks;
     const int fx = (int)((std::max(m, n) + 255) / 256);
     if (ftg::launch_lowp_encode(e, ab_type, gx, fx, s) != hipSuccess) return FTG_ERR_HIP;
 
-    // the wide tile multiplies the checksum pieces inside the product
-    if (wide) {
-        a.XSA = ab_type == FTG_F8_E4M3 ? (const void*)ea.XS8 : (const void*)ea.XS;
-        a.XSB = ab_type == FTG_F8_E4M3 ? (const void*)eb_.XS8 : (const void*)eb_.XS;
-    } else {
-        // checksum products: ER = op(A) [B_J e pieces], EC = [e^T A_I pieces]^T op(B)
-        ftg::LowpArgs c1;
-        std::memset(&c1, 0, sizeof(c1));
-        c1.A = a.A; c1.lda = a.lda; c1.B = eb_.XS; c1.ldb = (int)k;
-        c1.C = (float*)(w + L.er); c1.ldc = (int)m;
-        c1.m = (int)m; c1.n = 3 * a.tiles_n; c1.k = (int)k;
-        c1.tiles_m = a.tiles_m; c1.tiles_n = (c1.n + bn - 1) / bn;
-        c1.vec_a = a.vec_a; c1.vec_b = vec_ok(c1.B, k, 2);
-        c1.alpha = 1.0f; c1.beta = 0.0f;
-        c1.ksplit = ks_r; c1.cslice = (int64_t)m * 3 * a.tiles_n;
-        if (ftg::launch_lowp_gemm(c1, ab_type, FTG_BF16, ita, 0, 0, s) != hipSuccess) return FTG_ERR_HIP;
-        ftg::LowpArgs c2;
-        std::memset(&c2, 0, sizeof(c2));
-        c2.A = ea.XS; c2.lda = (int)k; c2.B = a.B; c2.ldb = a.ldb;
-        c2.C = (float*)(w + L.ec); c2.ldc = 3 * a.tiles_m;
-        c2.m = 3 * a.tiles_m; c2.n = (int)n; c2.k = (int)k;
-        c2.tiles_m = (c2.m + bm - 1) / bm; c2.tiles_n = a.tiles_n;
-        c2.vec_a = vec_ok(c2.A, k, 2); c2.vec_b = a.vec_b;
-        c2.alpha = 1.0f; c2.beta = 0.0f;
-        c2.ksplit = ks_c; c2.cslice = (int64_t)3 * a.tiles_m * n;
-        if (ftg::launch_lowp_gemm(c2, FTG_BF16, ab_type, 1, itb, 0, s) != hipSuccess) return FTG_ERR_HIP;
-        a.ER = c1.C; a.lder = (int)m;
-        a.EC = c2.C; a.ldec = 3 * a.tiles_m;
-        a.slices = ks_r;
-        a.slices_c = ks_c;
-        a.er_stride = c1.cslice;
-        a.ec_stride = c2.cslice;
-    }
-
-    // protected product
-    a.RA = ea.XR; a.MA = ea.XM; a.CB = eb_.XR; a.MB = eb_.XM;
-    a.lambda = (cfg && cfg->lambda > 0.0) ? cfg->lambda : kDefaultLambda;
-    a.problem = 0;
+    ftg::InjectParams inj;
+    std::memset(&inj, 0, sizeof(inj));
     if (cfg && cfg->inject) {
-        const int64_t slots = (int64_t)a.tiles_m * a.tiles_n;
-        if (!ftg::make_inject(cfg->inject, m, n, k, slots, 13, 31, &a.inj, 0, false)) return FTG_ERR_UNSUPPORTED;
+        // one slot per (128 x 128 tile, interval)
+        const int64_t slots = (int64_t)a.tiles_m * a.tiles_n * n_int;
+        if (!ftg::make_inject(cfg->inject, m, n, k, slots, 13, 31, &inj, 0, false)) return FTG_ERR_UNSUPPORTED;
     }
-    {
-        LaunchTimer timer(h, s);
-        const hipError_t e = wide ? ftg::launch_lowp_wide(a, ab_type, 1, s)
-                                  : ftg::launch_lowp_gemm(a, ab_type, ab_type, ita, itb, 1, s);
-        timer.end();
-        if (e != hipSuccess) return FTG_ERR_HIP;
+    for (int64_t t = 0; t < n_int; ++t) {
+        ftg::LowpArgs at = interval_args(t);
+        const int64_t plo = at.plo, kt = at.k;
+        const bool wide = interval_wide(at);
+        if (wide) {
+            // the wide tile multiplies the checksum pieces inside the product
+            at.XSA = ab_type == FTG_F8_E4M3 ? (const void*)(ea.XS8 + plo) : (const void*)(ea.XS + plo);
+            at.XSB = ab_type == FTG_F8_E4M3 ? (const void*)(eb_.XS8 + plo) : (const void*)(eb_.XS + plo);
+        } else {
+            // checksum products: ER = op(A) [B_J e pieces], EC = [e^T A_I pieces]^T op(B)
+            const int ksr = lowp_ksplit(chk_tiles_r, kt), ksc = lowp_ksplit(chk_tiles_c, kt);
+            ftg::LowpArgs c1;
+            std::memset(&c1, 0, sizeof(c1));
+            c1.A = at.A; c1.lda = at.lda; c1.B = eb_.XS + plo; c1.ldb = (int)k;
+            c1.C = (float*)(w + L.er); c1.ldc = (int)m;
+            c1.m = (int)m; c1.n = 3 * a.tiles_n; c1.k = (int)kt;
+            c1.tiles_m = a.tiles_m; c1.tiles_n = (c1.n + bn - 1) / bn;
+            c1.vec_a = at.vec_a; c1.vec_b = vec_ok(c1.B, k, 2);
+            c1.alpha = 1.0f; c1.beta = 0.0f;
+            c1.ksplit = ksr; c1.cslice = (int64_t)m * 3 * a.tiles_n;
+            if (ftg::launch_lowp_gemm(c1, ab_type, FTG_BF16, ita, 0, 0, s) != hipSuccess) return FTG_ERR_HIP;
+            ftg::LowpArgs c2;
+            std::memset(&c2, 0, sizeof(c2));
+            c2.A = ea.XS + plo; c2.lda = (int)k; c2.B = at.B; c2.ldb = at.ldb;
+            c2.C = (float*)(w + L.ec); c2.ldc = 3 * a.tiles_m;
+            c2.m = 3 * a.tiles_m; c2.n = (int)n; c2.k = (int)kt;
+            c2.tiles_m = (c2.m + bm - 1) / bm; c2.tiles_n = a.tiles_n;
+            c2.vec_a = vec_ok(c2.A, k, 2); c2.vec_b = at.vec_b;
+            c2.alpha = 1.0f; c2.beta = 0.0f;
+            c2.ksplit = ksc; c2.cslice = (int64_t)3 * a.tiles_m * n;
+            if (ftg::launch_lowp_gemm(c2, FTG_BF16, ab_type, 1, itb, 0, s) != hipSuccess) return FTG_ERR_HIP;
+            at.ER = c1.C; at.lder = (int)m;
+            at.EC = c2.C; at.ldec = 3 * a.tiles_m;
+            at.slices = ksr;
+            at.slices_c = ksc;
+            at.er_stride = c1.cslice;
+            at.ec_stride = c2.cslice;
+        }
+
+        // protected product of this interval
+        at.RA = ea.XR + t * m; at.MA = ea.XM + t * a.tiles_m;
+        at.CB = eb_.XR + t * n; at.MB = eb_.XM + t * a.tiles_n;
+        at.lambda = (cfg && cfg->lambda > 0.0) ? cfg->lambda : kDefaultLambda;
+        at.problem = 0;
+        at.inj = inj;
+        {
+            LaunchTimer timer(h, s);
+            const hipError_t e2 = wide ? ftg::launch_lowp_wide(at, ab_type, 1, s)
+                                       : ftg::launch_lowp_gemm(at, ab_type, ab_type, ita, itb, 1, s);
+            timer.end();
+            if (e2 != hipSuccess) return FTG_ERR_HIP;
+        }
+        ftg::RepairProblem rp;
+        std::memset(&rp, 0, sizeof(rp));
+        rp.A = at.A; rp.B = at.B; rp.C = C;  // the packed copies are still in the workspace
+        rp.lda = at.lda; rp.ldb = at.ldb; rp.ldc = ldc; rp.k = kt;
+        rp.ta = ita; rp.tb = itb; rp.correct_policy = cfg ? cfg->correct_policy : 0;
+        rp.ab_type = ab_type; rp.c_type = FTG_F32;
+        rp.alpha = alpha; rp.beta = at.beta;
+        rp.scale_a = a.scale_a; rp.scale_b = a.scale_b;
+        if (ftg::launch_repair(h->rep, rp, nullptr, s) != hipSuccess) return FTG_ERR_HIP;
     }
-    ftg::RepairProblem rp;
-    std::memset(&rp, 0, sizeof(rp));
-    rp.A = a.A; rp.B = a.B; rp.C = C;  // the packed copies are still in the workspace
-    rp.lda = a.lda; rp.ldb = a.ldb; rp.ldc = ldc; rp.k = k;
-    rp.ta = ita; rp.tb = itb; rp.correct_policy = cfg ? cfg->correct_policy : 0;
-    rp.ab_type = ab_type; rp.c_type = FTG_F32;
-    rp.alpha = alpha; rp.beta = beta;
-    rp.scale_a = a.scale_a; rp.scale_b = a.scale_b;
-    return ftg::launch_repair(h->rep, rp, nullptr, s) == hipSuccess ? FTG_OK : FTG_ERR_HIP;
+    return FTG_OK;
 }
 
 // ---------------------------------------------------------------- batched

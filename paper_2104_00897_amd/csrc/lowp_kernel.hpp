@@ -471,7 +471,9 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
     if (inj) {
         Fault f2[2];
         const uint64_t tile_id = (uint64_t)tn * args.tiles_m + tm;
-        nflt = __builtin_amdgcn_readfirstlane(slot_faults(args.inj, tile_id, R, Q, 0, K, f2));
+        // the slot of this launch's verification interval: steps plo .. plo + K - 1
+        nflt = __builtin_amdgcn_readfirstlane(
+            slot_faults(args.inj, tile_id * args.n_int + args.interval, R, Q, args.plo, args.plo + K, f2));
 #pragma unroll
         for (int q = 0; q < 2; ++q)
             if (q < nflt) {
@@ -481,8 +483,8 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
                 flt[q][3] = __builtin_amdgcn_readfirstlane(f2[q].bit);
             }
     }
-    const int fkb0 = nflt > 0 ? flt[0][2] / BK : -1;
-    const int fkb1 = nflt > 1 ? flt[1][2] / BK : -1;
+    const int fkb0 = nflt > 0 ? (int)((flt[0][2] - args.plo) / BK) : -1;
+    const int fkb1 = nflt > 1 ? (int)((flt[1][2] - args.plo) / BK) : -1;
     auto apply_fault = [&](int q) __attribute__((always_inline)) {
         const int row = q ? flt[1][0] : flt[0][0];
         const int col = q ? flt[1][1] : flt[0][1];
@@ -506,7 +508,7 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
                         acc[g][h][r] = own ? newv : oldv;
                     }
         if (own)
-            push_inject(args.rep, args.problem, tm, tn, 0, m0 + row, n0 + col, pfl, bit, FTG_TARGET_ACC,
+            push_inject(args.rep, args.problem, tm, tn, args.interval, m0 + row, n0 + col, pfl, bit, FTG_TARGET_ACC,
                         (double)oldv, (double)newv);
     };
 
@@ -701,7 +703,7 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
                             const float o = er[0];
                             const float nv = flip_f32(o, fb);
                             e += (double)nv - (double)o;
-                            push_inject(args.rep, args.problem, tm, tn, 0, m0 + x, -1, fp, fb, FTG_TARGET_CHECKSUM,
+                            push_inject(args.rep, args.problem, tm, tn, args.interval, m0 + x, -1, fp, fb, FTG_TARGET_CHECKSUM,
                                         (double)o, (double)nv);
                         }
                     }
@@ -740,7 +742,7 @@ __global__ __launch_bounds__(256, 2) void lowp_gemm_kernel(LowpArgs args)
         if (nr != 0 || nc != 0) {
             if (tid == 0) {
                 RepairReq q;
-                q.problem = args.problem; q.tm = tm; q.tn = tn; q.interval = 0;
+                q.problem = args.problem; q.tm = tm; q.tn = tn; q.interval = args.interval;
                 q.nr = nr; q.nc = nc; q.fi = V.fi; q.fj = V.fj; q.R = R; q.Q = Q;
                 q.whole = q.pad1 = 0; q.m0 = m0; q.n0 = n0;
                 q.dfi = V.dfi; q.tfi = V.tfi; q.dfj = V.dfj; q.tfj = V.tfj;

@@ -258,7 +258,8 @@ __global__ __launch_bounds__(256) void lowp_encode_k_kernel(EncArgs args)
     }
 }
 
-// XR[r] = sum over chunks (binary64, rounded up); XM[panel] = max over chunks.
+// XR[r] = sum over chunks (binary64, rounded up); XM[panel] = max over chunks,
+// per verification interval (blockIdx.z: chunks z ichunks .. + ichunks - 1).
 // A workgroup takes 64 rows; its four waves sum every fourth chunk, then the
 // partial sums are added through LDS (the chunks of a row are far apart in
 // memory, the rows of a chunk contiguous).
@@ -269,27 +270,29 @@ __global__ __launch_bounds__(256) void lowp_encode_finish_kernel(EncArgs args)
     __shared__ double part[4][kFinishRows];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t x = (int64_t)blockIdx.x * kFinishRows + lane;
+    const int c0 = blockIdx.z * E.ichunks, c1 = min(E.chunks, c0 + E.ichunks);
     double s = 0.0;
     if (x < E.rows) {
-        int c = w;
-        for (; c + 12 < E.chunks; c += 16) {
+        int c = c0 + w;
+        for (; c + 12 < c1; c += 16) {
             float v[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) v[u] = E.XRp[(int64_t)(c + 4 * u) * E.rows + x];
 #pragma unroll
             for (int u = 0; u < 4; ++u) s += (double)v[u];
         }
-        for (; c < E.chunks; c += 4) s += (double)E.XRp[(int64_t)c * E.rows + x];
+        for (; c < c1; c += 4) s += (double)E.XRp[(int64_t)c * E.rows + x];
     }
     part[w][lane] = s;
     __syncthreads();
     if (w == 0 && x < E.rows)
-        E.XR[x] = f64_to_f32_up(part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]);
+        E.XR[(int64_t)blockIdx.z * E.rows + x] =
+            f64_to_f32_up(part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]);
     const int64_t pnl = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (pnl < E.panels) {
         float mx = 0.0f;
-        for (int c = 0; c < E.chunks; ++c) mx = fmaxf(mx, E.XMp[pnl * E.chunks + c]);
-        E.XM[pnl] = mx;
+        for (int c = c0; c < c1; ++c) mx = fmaxf(mx, E.XMp[pnl * E.chunks + c]);
+        E.XM[(int64_t)blockIdx.z * E.panels + pnl] = mx;
     }
 }
 
@@ -314,6 +317,8 @@ hipError_t launch_lowp_gemm(const LowpArgs& a, ftg_dtype sta, ftg_dtype stb, int
 
 hipError_t launch_lowp_encode(const EncArgs& e, ftg_dtype st, int grid_x, int finish_x, hipStream_t s)
 {
+    if (e.op[0].ichunks <= 0 || e.op[0].ichunks != e.op[1].ichunks || e.op[0].chunks != e.op[1].chunks)
+        return hipErrorInvalidValue;
     // operands with contiguous steps (both, once packed) take the k-major encode
     const bool kc = e.op[0].kcontig && e.op[1].kcontig;
     if (st == FTG_F8_E4M3) {
@@ -328,7 +333,10 @@ hipError_t launch_lowp_encode(const EncArgs& e, ftg_dtype st, int grid_x, int fi
     (void)finish_x;
     const int64_t rows = std::max<int64_t>(std::max(e.op[0].rows, e.op[1].rows),
                                            (int64_t)std::max(e.op[0].panels, e.op[1].panels));
-    hipLaunchKernelGGL(lowp_encode_finish_kernel, dim3((unsigned)((rows + kFinishRows - 1) / kFinishRows), 2),
+    // one z layer per verification interval (both operands share the split)
+    const int n_int = (e.op[0].chunks + e.op[0].ichunks - 1) / e.op[0].ichunks;
+    hipLaunchKernelGGL(lowp_encode_finish_kernel,
+                       dim3((unsigned)((rows + kFinishRows - 1) / kFinishRows), 2, (unsigned)std::max(1, n_int)),
                        dim3(256), 0, s, e);
     return hipGetLastError();
 }

@@ -158,6 +158,7 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
     const int R = (int)min((int64_t)BM, (int64_t)args.m - m0);
     const int Q = (int)min((int64_t)BN, (int64_t)args.n - n0);
     const int K = args.k;
+    const int ldxs = args.ldxs;  // elements between rows of the checksum pieces
     const int nkb = K / BK;
     const int64_t lda = args.lda, ldb = args.ldb;
     const unsigned char* A = (const unsigned char*)args.A;
@@ -197,11 +198,11 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
         const int64_t xsb = (const unsigned char*)args.XSB - XS;
         if (lane < 24) {
             const int r = min(6 * tm + lane / 4, 3 * args.tiles_m - 1);
-            xoff = (int)((int64_t)r * K * 2 + 16 * (lane % 4));
+            xoff = (int)((int64_t)r * args.ldxs * 2 + 16 * (lane % 4));
             xlane = true;
         } else if (lane >= 32 && lane < 56) {
             const int j = lane - 32, r = min(6 * tn + j / 4, 3 * args.tiles_n - 1);
-            xoff = (int)(xsb + (int64_t)r * K * 2 + 16 * (j % 4));
+            xoff = (int)(xsb + (int64_t)r * args.ldxs * 2 + 16 * (j % 4));
             xlane = true;
         }
     }
@@ -210,7 +211,7 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
         if (MODE == 1 && xw) {
             unsigned char* xd = smem + st * STAGE + Cf::A_BYTES + Cf::B_BYTES + (FP8 ? 1024 * wave : 0);
             if constexpr (FP8) {
-                const int xo = min(x8_r0 + lane / 4, x8_rmax) * K + 16 * (lane % 4);
+                const int xo = min(x8_r0 + lane / 4, x8_rmax) * ldxs + 16 * (lane % 4);
                 lds_dma16(make_rsrc(XS + (int64_t)kb * 64), xd, xo);
             } else if (xlane) {
                 lds_dma16(make_rsrc(XS + (int64_t)kb * 64), xd, xoff);
@@ -252,12 +253,13 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
     // loop; the rest of the plan is drawn again when a fault is applied.
     const bool inj = MODE == 1 && args.inj.on;
     const int tmw = 2 * tm + wr, tnw = 2 * tn + (wc >> 1);  // this wave's checksum tile
-    auto wave_faults = [&](const InjectParams& ip, int tiles_m, int tiles_n, int m, int n, int k, Fault* f2)
-        __attribute__((always_inline)) {
+    // (the slot of interval `it` of n_int: steps plo .. plo + k - 1)
+    auto wave_faults = [&](const InjectParams& ip, int tiles_m, int tiles_n, int m, int n, int k, int n_int, int it,
+                           int64_t plo, Fault* f2) __attribute__((always_inline)) {
         int nf = 0;
         if (ip.on && ip.target != FTG_TARGET_CHECKSUM && tmw < tiles_m && tnw < tiles_n)
-            nf = slot_faults(ip, (uint64_t)tnw * tiles_m + tmw, min(128, m - 128 * tmw), min(128, n - 128 * tnw), 0,
-                             k, f2);
+            nf = slot_faults(ip, ((uint64_t)tnw * tiles_m + tmw) * n_int + it, min(128, m - 128 * tmw),
+                             min(128, n - 128 * tnw), plo, plo + k, f2);
         return nf;
     };
     // (the same plan in every lane; read from the first so that the k loop's
@@ -265,16 +267,18 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
     int fkb[2] = {-1, -1};
     if (inj) {
         Fault f2[2];
-        const int nf = wave_faults(args.inj, args.tiles_m, args.tiles_n, args.m, args.n, K, f2);
+        const int nf = wave_faults(args.inj, args.tiles_m, args.tiles_n, args.m, args.n, K, args.n_int,
+                                   args.interval, args.plo, f2);
 #pragma unroll
         for (int q = 0; q < 2; ++q)
-            fkb[q] = __builtin_amdgcn_readfirstlane(q < nf && f2[q].col / 64 == (wc & 1) ? (int)(f2[q].pflip / BK) : -1);
+            fkb[q] = __builtin_amdgcn_readfirstlane(
+                q < nf && f2[q].col / 64 == (wc & 1) ? (int)((f2[q].pflip - args.plo) / BK) : -1);
     }
     auto apply_fault = [&](int q) __attribute__((always_inline)) {
         const KArgsPtr ar = launder_args();
         const InjectParams ip = inject_of(ar);
         Fault f2[2];
-        wave_faults(ip, ar->tiles_m, ar->tiles_n, ar->m, ar->n, ar->k, f2);
+        wave_faults(ip, ar->tiles_m, ar->tiles_n, ar->m, ar->n, ar->k, ar->n_int, ar->interval, ar->plo, f2);
         const int rr = __builtin_amdgcn_readfirstlane(f2[q].row), col = __builtin_amdgcn_readfirstlane(f2[q].col);
         const int cc = col % 64, bit = __builtin_amdgcn_readfirstlane(f2[q].bit);
         const bool own = lane == ((rr % 16) / 4) * 16 + cc % 16;
@@ -301,7 +305,7 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
                         acc[g][h] = v;
                     }
             if (own8)
-                push_inject(ar->rep, ar->problem, tmw, tnw, 0, m0 + 128 * wr + rr, n0 + 128 * (wc >> 1) + col,
+                push_inject(ar->rep, ar->problem, tmw, tnw, ar->interval, m0 + 128 * wr + rr, n0 + 128 * (wc >> 1) + col,
                             f2[q].pflip, bit, FTG_TARGET_ACC, (double)oldv, (double)newv);
             return;
         }
@@ -324,7 +328,7 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
                     acc[g][h] = v;
                 }
         if (own)
-            push_inject(ar->rep, ar->problem, tmw, tnw, 0, m0 + 128 * wr + rr, n0 + 128 * (wc >> 1) + col,
+            push_inject(ar->rep, ar->problem, tmw, tnw, ar->interval, m0 + 128 * wr + rr, n0 + 128 * (wc >> 1) + col,
                         f2[q].pflip, bit, FTG_TARGET_ACC, (double)oldv, (double)newv);
     };
     auto faults_after = [&](int kb) __attribute__((always_inline)) {
@@ -695,13 +699,14 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
                 if (inj && ea->inj.target == FTG_TARGET_CHECKSUM) {
                     const InjectParams ipe = inject_of(ea);
                     Fault f2[2];
-                    const int nf = slot_faults(ipe, (uint64_t)tnc * ea->tiles_m + tmc, Rt, Qt, 0, K, f2);
+                    const int nf = slot_faults(ipe, ((uint64_t)tnc * ea->tiles_m + tmc) * ea->n_int + ea->interval,
+                                               Rt, Qt, ea->plo, ea->plo + K, f2);
                     for (int q = 0; q < nf; ++q)
                         if (f2[q].row == xi) {
                             const float o = V.er[rw][Cf::PIECES * J];
                             const float nv = flip_f32(o, f2[q].bit);
                             e += piece_weight(0) * ((double)nv - (double)o);
-                            push_inject(ea->rep, ea->problem, tmc, tnc, 0, m0 + rw, -1, f2[q].pflip, f2[q].bit,
+                            push_inject(ea->rep, ea->problem, tmc, tnc, ea->interval, m0 + rw, -1, f2[q].pflip, f2[q].bit,
                                         FTG_TARGET_CHECKSUM, (double)o, (double)nv);
                         }
                 }
@@ -741,7 +746,7 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
             const int nr = V.nfr[t], nc = V.nfc[t];
             if (tmc < ea->tiles_m && tnc < ea->tiles_n && (nr != 0 || nc != 0)) {
                 RepairReq q;
-                q.problem = ea->problem; q.tm = tmc; q.tn = tnc; q.interval = 0;
+                q.problem = ea->problem; q.tm = tmc; q.tn = tnc; q.interval = ea->interval;
                 q.nr = nr; q.nc = nc; q.fi = V.fi[t]; q.fj = V.fj[t];
                 q.R = min(128, ea->m - 128 * tmc); q.Q = min(128, ea->n - 128 * tnc);
                 q.whole = q.pad1 = 0; q.m0 = 128 * (int64_t)tmc; q.n0 = 128 * (int64_t)tnc;
