@@ -279,6 +279,13 @@ def cfg3_lowp(torch, ftgemm, h, kind, steps, n=8192, fp_calls=1000):
         f0()
     torch.cuda.synchronize()
     fp = h.read()
+    # verification intervals: the product as rank-K_c updates of C, fault-free
+    ivl = {kc: (lambda c=ftgemm.make_config(interval_k=kc): ftgemm.gemm_lowp(h, dA, dB, dC, 1.0, 0.0, 0, 0, ab,
+                                                                           sa, sb, c))
+           for kc in (4096, 2048, 1024)}
+    h.reset()
+    ti = timed_ab(torch, ivl, max(2, steps // 2), 1)
+    ivl_flags = h.read().detected
     return {"workload": f"{kind} {n}^3 NN -> FP32, 16 flips/call", "ms_protected": t["p"],
             "ms_unprotected": t["u"], "ms_protected_no_faults": t["p0"],
             "tflops_protected": fl / t["p"] / 1e9, "tflops_unprotected": fl / t["u"] / 1e9,
@@ -289,7 +296,9 @@ def cfg3_lowp(torch, ftgemm, h, kind, steps, n=8192, fp_calls=1000):
             "lambda": lam, "error_vs_fp64": err,
             "false_positives": {"calls": fp_calls, "flagged_slots": fp.detected,
                                 "checks_per_call": 2 * n * (n // 128),
-                                "max_pass_ratio": fp.max_pass_ratio}}
+                                "max_pass_ratio": fp.max_pass_ratio},
+            "intervals": {"ms_protected_no_faults": {str(kc): ms for kc, ms in ti.items()},
+                          "flagged_slots": ivl_flags}}
 
 
 def calibrate_lambda(torch, ftgemm, h, calls):

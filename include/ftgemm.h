@@ -122,7 +122,9 @@ typedef struct ftg_config {
                             code compiled out (for overhead measurement)        */
     int32_t interval_k;  /* verification interval in steps of k; 0 = the whole
                             k loop (one verification per tile); otherwise a
-                            multiple of 128                                     */
+                            multiple of 128 (FP64: checks of the accumulators
+                            in the k loop; BF16/FP8: rank-K_c updates of C,
+                            see ftg_gemm_ex)                                    */
     double lambda;       /* threshold scale of the FP32-accumulating paths
                             (0 = ftg_default_lambda()); unused for FP64        */
     int32_t correct_policy;       /* 0: subtract, re-verify, else recompute;
@@ -366,7 +368,15 @@ ftg_status ftg_dtrsv(ftg_handle h, ftg_uplo uplo, ftg_op trans, ftg_diag diag, i
  * the product is alpha * s_A * s_B * (A_q B_q) + beta * C; they are ignored
  * (may be NULL) for FTG_BF16.  The verification threshold uses the
  * probabilistic rounding bound lambda * sqrt(n) * 2^-24 in place of
- * gamma(n).  cfg->inject->bit_lo/hi refer to the FP32 accumulator. */
+ * gamma(n).  cfg->inject->bit_lo/hi refer to the FP32 accumulator.
+ * cfg->interval_k = K_c < k runs the product as rank-K_c updates of C
+ * (the K_c loop of the blocked GEMM, §5.1, checked after every update as in
+ * §2.1): update t computes C := alpha op(A)[:, S_t] op(B)[S_t, :] + beta_t C
+ * over the steps S_t = t K_c .. min(k, (t + 1) K_c) - 1, beta_t = beta for
+ * the first update and 1 after, each verified with its own thresholds and
+ * repaired before the next reads C.  So one error per 128 x 128 tile and
+ * interval is corrected; injection slots, records and the log carry the
+ * interval.  At most 128 intervals (else FTG_ERR_UNSUPPORTED). */
 ftg_status ftg_gemm_ex(ftg_handle h, ftg_op transa, ftg_op transb, int64_t m, int64_t n,
                        int64_t k, ftg_dtype ab_type, ftg_dtype c_type, const float* scale_a,
                        const float* scale_b, float alpha, const void* A, int64_t lda,
