@@ -87,6 +87,27 @@ __device__ inline uint32_t f64_to_e4m3_rne(double x)
     return sgn | ((uint32_t)(E + 7) << 3) | ((uint32_t)m - 8u);
 }
 
+// The same rounding, also giving the code's value (exact in binary64): for
+// abs(x) <= 448, *val = the e4m3fn value nearest x (ties to even)
+__device__ inline uint32_t f64_to_e4m3_rne(double x, double* val)
+{
+    const uint32_t sgn = x < 0.0 ? 0x80u : 0u;
+    const double a = fabs(x);
+    if (a == 0.0) { *val = 0.0; return sgn; }
+    int e2;
+    (void)frexp(a, &e2);
+    int E = e2 - 1;
+    if (E < -6) {
+        const double m = rint(a * 512.0);
+        *val = copysign(m * 0x1p-9, x);
+        return sgn | (uint32_t)m;
+    }
+    double m = rint(ldexp(a, 3 - E));
+    if (m >= 16.0) { m = 8.0; ++E; }
+    *val = copysign(ldexp(m, E - 3), x);
+    return sgn | ((uint32_t)(E + 7) << 3) | ((uint32_t)m - 8u);
+}
+
 // binary64 -> binary32 rounded towards +infinity (for magnitude bounds, x >= 0)
 __device__ inline float f64_to_f32_up(double x)
 {

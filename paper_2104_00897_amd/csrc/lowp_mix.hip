@@ -9,6 +9,31 @@ template hipError_t launch_lowp_t<StFP8, StBF16, false, 0>(const LowpArgs&, int,
 template hipError_t launch_lowp_t<StBF16, StFP8, false, 0>(const LowpArgs&, int, int, hipStream_t);
 
 // ---------------------------------------------------------------- encode
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+// A binary32 value moved between lanes of a 16-lane row by a DPP control.
+template <int CTRL>
+__device__ inline float dpp_f32(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+// e4m3 pieces of a panel sum s = sum_t 2^(7 - 4 t) q_t (+ residual), written
+// to o[t stride].  Each step scales the residual by a power of two (exact),
+// rounds it to e4m3 and subtracts the rounded value, taken straight from the
+// rounding (exact in binary64).
+__device__ inline void e4m3_pieces(double s, uint8_t* o, int64_t stride)
+{
+    double r = s;
+#pragma unroll
+    for (int t = 0; t < kFp8Pieces; ++t) {
+        double v;
+        const uint32_t q = f64_to_e4m3_rne(r * ldexp(1.0, 4 * t - 7), &v);
+        o[(int64_t)t * stride] = (uint8_t)q;
+        r -= ldexp(v, 7 - 4 * t);
+    }
+}
+
 template <typename ST>
 __global__ __launch_bounds__(256, 4) void lowp_encode_kernel(EncArgs args)
 {
@@ -86,15 +111,7 @@ __global__ __launch_bounds__(256, 4) void lowp_encode_kernel(EncArgs args)
             // mantissa bits; below 2^-6 the subnormal step), so the next piece
             // stays in range and eight pieces leave abs(r_8) <= 2^-28 abs(s) +
             // 2^-31 (2^-21 times the half subnormal step)
-            double r = s;
-            uint8_t* o = E.XS8 + (int64_t)kFp8Pieces * pi * E.K + p0 + p;
-#pragma unroll
-            for (int t = 0; t < kFp8Pieces; ++t) {
-                const double S = ldexp(1.0, 7 - 4 * t);
-                const uint32_t q = f64_to_e4m3_rne(r / S);
-                o[(int64_t)t * E.K] = (uint8_t)q;
-                r -= S * (double)bf16_bits_to_f32(e4m3_to_bf16(q));
-            }
+            e4m3_pieces(s, E.XS8 + (int64_t)kFp8Pieces * pi * E.K + p0 + p, E.K);
         }
     }
     __syncthreads();
@@ -112,7 +129,8 @@ __global__ __launch_bounds__(256, 4) void lowp_encode_kernel(EncArgs args)
 // Column sums: per thread over its rows, then a fixed xor butterfly over the
 // lanes of a wave that share its steps, then the four waves in order through
 // LDS.  Row sums of |x|: per thread over its steps, then a fixed butterfly
-// over the SG lanes that share its rows.
+// over the SG lanes that share its rows.  bf16 sums are binary64; fp8 sums
+// are binary32 up to the LDS stage, where they are still exact.
 template <typename ST>
 __global__ __launch_bounds__(256) void lowp_encode_k_kernel(EncArgs args)
 {
@@ -156,55 +174,89 @@ __global__ __launch_bounds__(256) void lowp_encode_k_kernel(EncArgs args)
             x[u] = (u32x4_t){wv[0], wv[1], wv[2], wv[3]};
         }
     }
-    // fp8 codes widened to bf16 pairs by the hardware conversion (exact:
-    // every e4m3fn value is a bf16 value), so both types read bf16 halves
-    uint32_t hv[RPT][V / 2];
+    static_assert(SG == 8, "lane map of the reductions");
+    if constexpr (ST::bytes == 1) {
+        // e4m3fn values are multiples of 2^-9 of magnitude at most 448, so every
+        // sum formed here (64 steps of a row, 8 rows of a step: below 2^24
+        // units of 2^-9) is exact in binary32 and equals the binary64 sum
+        float xf[RPT][V];
 #pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-        if constexpr (ST::bytes == 1) {
+        for (int u = 0; u < RPT; ++u)
 #pragma unroll
             for (int q = 0; q < V / 4; ++q) {
-                hv[u][2 * q] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(x[u][q], 1.0f, false));
-                hv[u][2 * q + 1] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(x[u][q], 1.0f, true));
+                const f32x2_t lo = __builtin_amdgcn_cvt_scalef32_pk_f32_fp8(x[u][q], 1.0f, false);
+                const f32x2_t hi = __builtin_amdgcn_cvt_scalef32_pk_f32_fp8(x[u][q], 1.0f, true);
+                xf[u][4 * q] = lo[0];
+                xf[u][4 * q + 1] = lo[1];
+                xf[u][4 * q + 2] = hi[0];
+                xf[u][4 * q + 3] = hi[1];
             }
-        } else {
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) {
+            float ra = 0.0f;
+#pragma unroll
+            for (int e = 0; e < V; ++e) ra += fabsf(xf[u][e]);
+            ra += dpp_f32<0xB1>(ra);
+            ra += dpp_f32<0x4E>(ra);
+            ra += dpp_f32<0x141>(ra);
+            const int64_t r = r0 + rg * RPT + u;
+            if (sg == 0 && r < E.rows) E.XRp[(int64_t)c * E.rows + r] = ra;
+        }
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            float cs = 0.0f, ca = 0.0f;
+#pragma unroll
+            for (int u = 0; u < RPT; ++u) {
+                cs += xf[u][e];
+                ca += fabsf(xf[u][e]);
+            }
+            cs += dpp_f32<0x128>(cs);
+            ca += dpp_f32<0x128>(ca);
+            if ((lane & 8) == 0) {
+                cpart[w][lane >> 4][sg * V + e][0] = (double)cs;
+                cpart[w][lane >> 4][sg * V + e][1] = (double)ca;
+            }
+        }
+    } else {
+        uint32_t hv[RPT][V / 2];
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) {
 #pragma unroll
             for (int j = 0; j < V / 2; ++j) hv[u][j] = x[u][j];
         }
-    }
-    auto val = [&](int u, int e) __attribute__((always_inline)) -> double {
-        return (double)bf16_bits_to_f32((hv[u][e / 2] >> (16 * (e % 2))) & 0xFFFFu);
-    };
-    // row sums of |x| over this block's steps: the 8 step groups of a row are
-    // 8 neighbouring lanes, summed by data-parallel moves (no LDS traffic)
-    static_assert(SG == 8, "lane map of the reductions");
-#pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-        double ra = 0.0;
-#pragma unroll
-        for (int e = 0; e < V; ++e) ra += fabs(val(u, e));
-        ra += dpp_f64<0xB1>(ra);   // quad_perm [1,0,3,2]
-        ra += dpp_f64<0x4E>(ra);   // quad_perm [2,3,0,1]
-        ra += dpp_f64<0x141>(ra);  // row_half_mirror: the other quad of the 8
-        const int64_t r = r0 + rg * RPT + u;
-        if (sg == 0 && r < E.rows) E.XRp[(int64_t)c * E.rows + r] = f64_to_f32_up(ra);
-    }
-    // column sums over this block's rows: the two row groups of a 16-lane row
-    // by a rotation of 8 lanes, the 4 x 4 rows of the workgroup through LDS
-#pragma unroll
-    for (int e = 0; e < V; ++e) {
-        double cs = 0.0, ca = 0.0;
+        auto val = [&](int u, int e) __attribute__((always_inline)) -> double {
+            return (double)bf16_bits_to_f32((hv[u][e / 2] >> (16 * (e % 2))) & 0xFFFFu);
+        };
+        // row sums of |x| over this block's steps: the 8 step groups of a row are
+        // 8 neighbouring lanes, summed by data-parallel moves (no LDS traffic)
 #pragma unroll
         for (int u = 0; u < RPT; ++u) {
-            const double v = val(u, e);
-            cs += v;
-            ca += fabs(v);
+            double ra = 0.0;
+#pragma unroll
+            for (int e = 0; e < V; ++e) ra += fabs(val(u, e));
+            ra += dpp_f64<0xB1>(ra);   // quad_perm [1,0,3,2]
+            ra += dpp_f64<0x4E>(ra);   // quad_perm [2,3,0,1]
+            ra += dpp_f64<0x141>(ra);  // row_half_mirror: the other quad of the 8
+            const int64_t r = r0 + rg * RPT + u;
+            if (sg == 0 && r < E.rows) E.XRp[(int64_t)c * E.rows + r] = f64_to_f32_up(ra);
         }
-        cs += dpp_f64<0x128>(cs);  // row_ror:8
-        ca += dpp_f64<0x128>(ca);
-        if ((lane & 8) == 0) {
-            cpart[w][lane >> 4][sg * V + e][0] = cs;
-            cpart[w][lane >> 4][sg * V + e][1] = ca;
+        // column sums over this block's rows: the two row groups of a 16-lane row
+        // by a rotation of 8 lanes, the 4 x 4 rows of the workgroup through LDS
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            double cs = 0.0, ca = 0.0;
+#pragma unroll
+            for (int u = 0; u < RPT; ++u) {
+                const double v = val(u, e);
+                cs += v;
+                ca += fabs(v);
+            }
+            cs += dpp_f64<0x128>(cs);  // row_ror:8
+            ca += dpp_f64<0x128>(ca);
+            if ((lane & 8) == 0) {
+                cpart[w][lane >> 4][sg * V + e][0] = cs;
+                cpart[w][lane >> 4][sg * V + e][1] = ca;
+            }
         }
     }
     __syncthreads();
@@ -238,15 +290,7 @@ __global__ __launch_bounds__(256) void lowp_encode_k_kernel(EncArgs args)
             // mantissa bits; below 2^-6 the subnormal step), so the next piece
             // stays in range and eight pieces leave abs(r_8) <= 2^-28 abs(s) +
             // 2^-31 (2^-21 times the half subnormal step)
-            double r = s;
-            uint8_t* o = E.XS8 + (int64_t)kFp8Pieces * pi * E.K + p0 + p;
-#pragma unroll
-            for (int t = 0; t < kFp8Pieces; ++t) {
-                const double S = ldexp(1.0, 7 - 4 * t);
-                const uint32_t q = f64_to_e4m3_rne(r / S);
-                o[(int64_t)t * E.K] = (uint8_t)q;
-                r -= S * (double)bf16_bits_to_f32(e4m3_to_bf16(q));
-            }
+            e4m3_pieces(s, E.XS8 + (int64_t)kFp8Pieces * pi * E.K + p0 + p, E.K);
         }
     }
     __syncthreads();

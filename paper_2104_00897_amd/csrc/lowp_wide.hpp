@@ -538,6 +538,30 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
         double rsl[4] = {0.0, 0.0, 0.0, 0.0}, cirl[4] = {0.0, 0.0, 0.0, 0.0}, cial[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int hs = 0; hs < 4; ++hs) {
+            auto col_of = [&](int p) __attribute__((always_inline)) {
+                const int c = 2 * p + cl;
+                return wn0 + (FP8 ? 32 * (((hs >> 1) + rot_b) & 1) + 16 * (hs & 1) : 16 * ((hs + rot_b) & 3)) + c;
+            };
+            // C_in of a group of kCinAhead column pairs, all requested before
+            // any is used (one memory round trip per group instead of one per pair)
+            constexpr int kCinAhead = 4;
+            f32x4_t civ[kCinAhead];
+            auto load_cin = [&](int p0) __attribute__((always_inline)) {
+#pragma unroll
+                for (int j = 0; j < kCinAhead; ++j) {
+                    const int col = col_of(p0 + j);
+                    const bool colok = col < Q;
+                    const int vo = (int)(((int64_t)col * ldc + row) * 4);
+                    if (vec_c && colok && row + 4 <= R) {
+                        civ[j] = __builtin_bit_cast(f32x4_t, __builtin_amdgcn_raw_buffer_load_b128(rc, vo, 0, 0));
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            civ[j][r] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+                                rc, colok && row + r < R ? vo + 4 * r : kOOB, 0, 0));
+                    }
+                }
+            };
             // stage column block hs (16 columns) of the wave
             if constexpr (FP8) {
                 // register fragment hs / 2 (column block (hs / 2 + rot_b) % 2), its
@@ -559,24 +583,18 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
             }
             __builtin_amdgcn_wave_barrier();
 #pragma unroll 1
-            for (int p = 0; p < 8; ++p) {
+            for (int pg = 0; pg < 8; pg += kCinAhead) {
+            if (cin) load_cin(pg);
+#pragma unroll
+            for (int j = 0; j < kCinAhead; ++j) {
+                const int p = pg + j;
                 const int c = 2 * p + cl;
-                const int col = wn0 + (FP8 ? 32 * (((hs >> 1) + rot_b) & 1) + 16 * (hs & 1) : 16 * ((hs + rot_b) & 3)) + c;
+                const int col = col_of(p);
                 const f32x4_t v = *(const f32x4_t*)(stg + c * kWideCP + rl);
                 const bool colok = col < Q;
                 const bool full = colok && row + 4 <= R;
                 const int vo = (int)(((int64_t)col * ldc + row) * 4);
-                f32x4_t ci = (f32x4_t){0.0f, 0.0f, 0.0f, 0.0f};
-                if (cin) {
-                    if (vec_c && full) {
-                        ci = __builtin_bit_cast(f32x4_t, __builtin_amdgcn_raw_buffer_load_b128(rc, vo, 0, 0));
-                    } else {
-#pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            ci[r] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
-                                rc, colok && row + r < R ? vo + 4 * r : kOOB, 0, 0));
-                    }
-                }
+                const f32x4_t ci = cin ? civ[j] : (f32x4_t){0.0f, 0.0f, 0.0f, 0.0f};
                 f32x4_t x;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) x[r] = cin ? fmaf(as, v[r], ea->beta * ci[r]) : as * v[r];
@@ -615,6 +633,9 @@ __global__ __launch_bounds__(512, 1) void lowp_wide_kernel(LowpArgs args)
                                                                   colok && row + r < R ? vo + 4 * r : kOOB, 0, 0);
                     }
                 }
+                // one column pair at a time (interleaving them needs more registers)
+                __builtin_amdgcn_sched_barrier(0);
+            }
             }
             __builtin_amdgcn_wave_barrier();
         }
