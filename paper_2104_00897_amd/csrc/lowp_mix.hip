@@ -306,7 +306,8 @@ __global__ __launch_bounds__(256) void lowp_encode_k_kernel(EncArgs args)
 // per verification interval (blockIdx.z: chunks z ichunks .. + ichunks - 1).
 // A workgroup takes 64 rows; its four waves sum every fourth chunk, then the
 // partial sums are added through LDS (the chunks of a row are far apart in
-// memory, the rows of a chunk contiguous).
+// memory, the rows of a chunk contiguous).  It also takes 64 panels, four
+// lanes each.
 constexpr int kFinishRows = 64;
 __global__ __launch_bounds__(256) void lowp_encode_finish_kernel(EncArgs args)
 {
@@ -317,13 +318,14 @@ __global__ __launch_bounds__(256) void lowp_encode_finish_kernel(EncArgs args)
     const int c0 = blockIdx.z * E.ichunks, c1 = min(E.chunks, c0 + E.ichunks);
     double s = 0.0;
     if (x < E.rows) {
+        // eight loads in flight per lane
         int c = c0 + w;
-        for (; c + 12 < c1; c += 16) {
-            float v[4];
+        for (; c + 28 < c1; c += 32) {
+            float v[8];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = E.XRp[(int64_t)(c + 4 * u) * E.rows + x];
+            for (int u = 0; u < 8; ++u) v[u] = E.XRp[(int64_t)(c + 4 * u) * E.rows + x];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) s += (double)v[u];
+            for (int u = 0; u < 8; ++u) s += (double)v[u];
         }
         for (; c < c1; c += 4) s += (double)E.XRp[(int64_t)c * E.rows + x];
     }
@@ -332,12 +334,26 @@ __global__ __launch_bounds__(256) void lowp_encode_finish_kernel(EncArgs args)
     if (w == 0 && x < E.rows)
         E.XR[(int64_t)blockIdx.z * E.rows + x] =
             f64_to_f32_up(part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]);
-    const int64_t pnl = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    // panel maxima: four lanes per panel, each over every fourth chunk, eight
+    // loads in flight, then the four combined by lane exchanges
+    const int64_t pnl = (int64_t)blockIdx.x * (kFinishRows) + (threadIdx.x >> 2);
+    const int q = threadIdx.x & 3;
+    float mx = 0.0f;
     if (pnl < E.panels) {
-        float mx = 0.0f;
-        for (int c = c0; c < c1; ++c) mx = fmaxf(mx, E.XMp[pnl * E.chunks + c]);
-        E.XM[(int64_t)blockIdx.z * E.panels + pnl] = mx;
+        const float* xm = E.XMp + pnl * E.chunks;
+        int c = c0 + q;
+        for (; c + 28 < c1; c += 32) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = xm[c + 4 * u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) mx = fmaxf(mx, v[u]);
+        }
+        for (; c < c1; c += 4) mx = fmaxf(mx, xm[c]);
     }
+    mx = fmaxf(mx, __shfl_xor(mx, 1));
+    mx = fmaxf(mx, __shfl_xor(mx, 2));
+    if (pnl < E.panels && q == 0) E.XM[(int64_t)blockIdx.z * E.panels + pnl] = mx;
 }
 
 
