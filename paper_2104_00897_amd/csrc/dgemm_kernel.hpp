@@ -89,7 +89,8 @@ struct VerifyLds {
 // DIR: full k-blocks of interior tiles are loaded straight into LDS (operands
 // 16-byte aligned with even leading dimensions); otherwise every block is
 // prefetched into registers one block ahead and stored after the MFMAs.
-template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool ABFT, bool IVL, bool PRE, bool DIR>
+template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool ABFT, bool IVL, bool PRE, bool DIR,
+          bool WIDE_REGS = false>
 __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs& args, const int tm,
                                                                  const int tn)
 {
@@ -781,6 +782,15 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
                     c[rr][h] = buf_load_f64(rc, c_ok(g, h, r0 + rr) ? cvo + (16 * g + 4 * (r0 + rr)) * 8 : kOOB,
                                             h * c_hstep);
         };
+        // with the register file to itself, the workgroup requests the whole
+        // of its C_in at once and keeps it for both passes
+        double call[WIDE_REGS ? 2 * FM : 1][2][FN];
+        if constexpr (WIDE_REGS) {
+            if (cin) {
+#pragma unroll
+                for (int gr = 0; gr < 2 * FM; ++gr) load_c(call[gr], gr / 2, 2 * (gr % 2));
+            }
+        }
         if (ABFT && cin) {
             double cs[FN], csa[FN];
 #pragma unroll
@@ -789,7 +799,14 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
             for (int gr = 0; gr < 2 * FM; ++gr) {
                 const int g = gr / 2, r0 = 2 * (gr % 2);
                 double c[2][FN];
-                load_c(c, g, r0);
+                if constexpr (WIDE_REGS) {
+#pragma unroll
+                    for (int rr = 0; rr < 2; ++rr)
+#pragma unroll
+                        for (int h = 0; h < FN; ++h) c[rr][h] = call[gr][rr][h];
+                } else {
+                    load_c(c, g, r0);
+                }
 #pragma unroll
                 for (int rr = 0; rr < 2; ++rr) {
                     double s = 0.0, sa = 0.0;
@@ -808,7 +825,9 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
                         Vp->cira[wc][row] = sa;
                     }
                 }
-                __builtin_amdgcn_sched_barrier(0);
+                // (one batch of C_in values at a time, unless the register
+                // file is the workgroup's alone: then the loads run ahead)
+                if constexpr (!WIDE_REGS) __builtin_amdgcn_sched_barrier(0);
             }
 #pragma unroll
             for (int h = 0; h < FN; ++h) {
@@ -823,7 +842,14 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
         for (int gr = 0; gr < 2 * FM; ++gr) {
             const int g = gr / 2, r0 = 2 * (gr % 2);
             double c[2][FN];
-            if (cin) load_c(c, g, r0);
+            if constexpr (WIDE_REGS) {
+#pragma unroll
+                for (int rr = 0; rr < 2; ++rr)
+#pragma unroll
+                    for (int h = 0; h < FN; ++h) c[rr][h] = call[gr][rr][h];
+            } else {
+                if (cin) load_c(c, g, r0);
+            }
 #pragma unroll
             for (int rr = 0; rr < 2; ++rr) {
                 const int r = r0 + rr;
@@ -840,7 +866,7 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
                     if (l16 == 0) Vp->rsum[wc][wm0 + 16 * g + 4 * r + lq] = o;
                 }
             }
-            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (!WIDE_REGS) __builtin_amdgcn_sched_barrier(0);
         }
         if (ABFT) {
 #pragma unroll
@@ -1079,10 +1105,13 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
 // (direct staging, or protected small tiles) whose accumulators take at most 64
 // registers per lane aim at two workgroups per CU, at most 32 at three (their
 // LDS fits that many times in 160 KB); the others use the configuration's MINB.
+// MINB = 0 asks for one workgroup per CU: the whole register file per lane,
+// for calls whose epilogue outweighs the k loop.
 template <int BM, int BN, int WGM, int WGN, int MINB, bool DIR, bool ABFT>
 constexpr int waves_per_simd()
 {
     constexpr int NW = WGM * WGN;
+    if constexpr (MINB == 0) return NW / 4;
     constexpr int accv = 2 * BM * BN / (NW * 64);  // accumulator VGPRs per lane
     constexpr bool one = DIR || (ABFT && DCfg<BM, BN, WGM, WGN, false, false>::ONE_COPY);
     constexpr int blocks = !one ? 0 : (accv <= 32 ? 3 : (accv <= 64 ? 2 : 0));
@@ -1096,7 +1125,7 @@ __global__ __launch_bounds__(WGM* WGN * 64, (waves_per_simd<BM, BN, WGM, WGN, MI
 {
     int tm, tn;
     tile_of_block(blockIdx.x, gridDim.x, args.tiles_m, args.tiles_n, 4, &tm, &tn);
-    dgemm_tile<BM, BN, WGM, WGN, TA, TB, ABFT, IVL, PRE, DIR>(args, tm, tn);
+    dgemm_tile<BM, BN, WGM, WGN, TA, TB, ABFT, IVL, PRE, DIR, MINB == 0>(args, tm, tn);
 }
 
 // Many problems in one persistent launch.  Work item w is tile

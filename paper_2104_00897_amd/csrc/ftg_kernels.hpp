@@ -82,6 +82,7 @@ extern template hipError_t launch_tile<128, 128, 2, 2, true, 2>(const DGemmArgs&
 extern template hipError_t launch_tile<64, 64, 2, 2, true, 2>(const DGemmArgs&, bool, hipStream_t);
 extern template hipError_t launch_tile<256, 128, 4, 2, false, 1>(const DGemmArgs&, bool, hipStream_t);
 extern template hipError_t launch_tile<128, 128, 4, 2, true, 1>(const DGemmArgs&, bool, hipStream_t);
+extern template hipError_t launch_tile<128, 128, 4, 2, true, 0>(const DGemmArgs&, bool, hipStream_t);
 
 inline hipError_t launch_dgemm(const DGemmArgs& a, int tile_id, bool abft, hipStream_t s)
 {
@@ -90,7 +91,16 @@ inline hipError_t launch_dgemm(const DGemmArgs& a, int tile_id, bool abft, hipSt
     case 2: return launch_tile<128, 128, 2, 2, true, 2>(a, abft, s);
     case 3: return launch_tile<64, 64, 2, 2, true, 2>(a, abft, s);
     case 4: return launch_tile<256, 128, 4, 2, false, 1>(a, abft, s);
-    case 5: return launch_tile<128, 128, 4, 2, true, 1>(a, abft, s);
+    case 5: {
+        // Protected calls with beta != 0 whose epilogue outweighs the k loop
+        // (short k, or at most one round of workgroups) run at one workgroup
+        // per CU: the epilogue then holds the tile's C_in in registers for
+        // both of its passes instead of reloading it in small batches.
+        const bool one_per_cu = abft && a.beta != 0.0 && a.kc >= a.k && a.asp != nullptr && a.lds_direct &&
+                                (a.k <= 256 || (int64_t)a.tiles_m * a.tiles_n <= 256);
+        return one_per_cu ? launch_tile<128, 128, 4, 2, true, 0>(a, abft, s)
+                          : launch_tile<128, 128, 4, 2, true, 1>(a, abft, s);
+    }
     default: return hipErrorInvalidValue;
     }
 }
