@@ -217,7 +217,9 @@ def test_default_bit_range_detectable_faults_corrected(env, tile):
 def test_direct_staging_all_transposes_ragged(env, tile, ta, tb):
     """Even leading dimensions and 16-byte aligned operands select the kernels that
     load full k-blocks straight into LDS; ragged edges in every dimension (the
-    edge tiles and the k tail take the register path inside the same kernel)."""
+    edge tiles and the k tail take the register path inside the same kernel).
+    With beta != 0 and at most 256 tiles, tile 5's protected calls run its
+    one-workgroup-per-CU kernel (C_in held in registers through the epilogue)."""
     ftgemm = env[0]
     m, n, k = 302, 286, 198
     A, B, C = inputs.gemm_operands_f64(m, n, k, seed=14, ta=ta, tb=tb)
