@@ -450,7 +450,11 @@ int ftg_last_error_arg(ftg_handle h);
  * and fault-injection slots), 128 x 128 for both configurations: id 1 runs
  * one such tile per workgroup, id 2 a 2 x 2 block of them (256 x 256
  * outputs, eight waves) when K is a multiple of its k-block (32 steps for
- * bf16) and the operands allow 16-byte loads, otherwise id 1's kernel. */
+ * bf16) and the operands allow 16-byte loads, otherwise id 1's kernel.
+ * For FTG_F64, id 5 (128 x 128 on eight waves) runs two workgroups per CU,
+ * except protected calls with beta != 0 and k <= 256 or at most 256 tiles,
+ * which run its kernel at one workgroup per CU (the epilogue's C_in kept in
+ * registers). */
 ftg_status ftg_tile_info(ftg_dtype ab_type, int32_t id, int32_t* bm, int32_t* bn, int32_t* bk);
 
 /* Tuning table: the tile configuration used when cfg->tile == 0.  Entries
