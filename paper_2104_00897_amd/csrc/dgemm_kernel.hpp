@@ -1180,7 +1180,9 @@ hipError_t launch_tile(const DGemmArgs& a, bool abft, hipStream_t s)
     if (ivl && !IVL_OK) return hipErrorInvalidValue;
     const bool pre = abft && a.asp != nullptr;
     constexpr bool DOK = DCfg<BM, BN, WGM, WGN, false, false>::DIRECT;
-    const bool dir = DOK && a.lds_direct && (!abft || (pre && !ivl));
+    // direct staging with interval checks only at one workgroup per CU (the
+    // interval kernels' restart path needs the whole register file)
+    const bool dir = DOK && a.lds_direct && (!abft || (pre && (!ivl || MINB == 0)));
 #define FTG_L(TA_, TB_, AB_, IV_, PR_, DR_)                                                                 \
     hipLaunchKernelGGL((dgemm_abft_kernel<BM, BN, WGM, WGN, TA_, TB_, AB_, IV_, MINB, PR_, DR_>), grid, block, 0, \
                        s, a)
@@ -1204,8 +1206,12 @@ hipError_t launch_tile(const DGemmArgs& a, bool abft, hipStream_t s)
             } else FTG_T(true, false, true, false);
         } else FTG_T(true, false, false, false);
     } else if constexpr (IVL_OK) {
-        if (pre) FTG_T(true, true, true, false);
-        else FTG_T(true, true, false, false);
+        if (pre) {
+            if constexpr (DOK && MINB == 0) {
+                if (dir) FTG_T(true, true, true, true);
+                else FTG_T(true, true, true, false);
+            } else FTG_T(true, true, true, false);
+        } else FTG_T(true, true, false, false);
     }
 #undef FTG_T
 #undef FTG_L

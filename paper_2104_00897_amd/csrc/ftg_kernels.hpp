@@ -95,9 +95,13 @@ inline hipError_t launch_dgemm(const DGemmArgs& a, int tile_id, bool abft, hipSt
         // Protected calls with beta != 0 whose epilogue outweighs the k loop
         // (short k, or at most one round of workgroups) run at one workgroup
         // per CU: the epilogue then holds the tile's C_in in registers for
-        // both of its passes instead of reloading it in small batches.
-        const bool one_per_cu = abft && a.beta != 0.0 && a.kc >= a.k && a.asp != nullptr && a.lds_direct &&
-                                (a.k <= 256 || (int64_t)a.tiles_m * a.tiles_n <= 256);
+        // both of its passes instead of reloading it in small batches.  So do
+        // protected calls with verification intervals and direct staging: the
+        // direct-staged interval kernel needs the whole register file.
+        const bool direct = abft && a.asp != nullptr && a.lds_direct;
+        const bool one_per_cu =
+            direct && ((a.kc < a.k) ||
+                       (a.beta != 0.0 && (a.k <= 256 || (int64_t)a.tiles_m * a.tiles_n <= 256)));
         return one_per_cu ? launch_tile<128, 128, 4, 2, true, 0>(a, abft, s)
                           : launch_tile<128, 128, 4, 2, true, 1>(a, abft, s);
     }

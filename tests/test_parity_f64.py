@@ -292,6 +292,49 @@ def test_interval_mode_many_faults_per_tile(env, tile):
     assert_close_f64(out, ref, magnitude(A, B, C, 1.5, 0.5, 0, 0), k)
 
 
+@pytest.mark.parametrize("tile", [2, 5])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 1)])
+def test_interval_two_faults_in_slot_recomputed(env, tile, ta, tb):
+    """Interval kernels: two faults in one (tile, interval) slot are uncorrectable;
+    under uncorrectable_policy 1 the tile restarts from its first interval, the
+    intervals up to the failed one replayed without injection.  Tile 5 with even
+    leading dimensions runs the direct-staged interval kernel."""
+    ftgemm = env[0]
+    m, n, k = 256, 256, 512
+    A, B, C = inputs.gemm_operands_f64(m, n, k, seed=8, ta=ta, tb=tb)
+    assert A.shape[0] % 2 == 0 and B.shape[0] % 2 == 0
+    kw = dict(tile=tile, interval_k=128, seed=5, n_faults=2, bit_lo=56, bit_hi=62,
+              target=ftgemm.TARGET_TWO_IN_SLOT)
+    out, rep = run(env, A, B, C, 1.0, 0.5, ta, tb, ftgemm.make_config(uncorrectable_policy=1, **kw))
+    assert rep.injected == 4 and rep.uncorrectable == 2 and rep.tiles_recomputed == 2
+    assert rep.status == ftgemm.OK
+    ref = oracle.gemm(A, B, C, 1.0, 0.5, ta, tb)
+    assert_close_f64(out, ref, magnitude(A, B, C, 1.0, 0.5, ta, tb), k)
+
+
+@pytest.mark.parametrize("ta,tb", [(1, 0), (0, 1)])
+def test_interval_mode_direct_staging_transposed(env, ta, tb):
+    """Tile 5's direct-staged interval kernel on transposed operands: one fault per
+    (tile, interval) slot in half the slots, each located where the oracle's
+    simulation locates it and corrected."""
+    ftgemm = env[0]
+    m, n, k = 300, 260, 512
+    A, B, C = inputs.gemm_operands_f64(m, n, k, seed=10, ta=ta, tb=tb)
+    assert A.shape[0] % 2 == 0 and B.shape[0] % 2 == 0
+    slots = -(-m // 128) * -(-n // 128) * (k // 128)
+    F = slots // 2
+    cfg = ftgemm.make_config(tile=5, interval_k=128, seed=23, n_faults=F, bit_lo=52, bit_hi=62)
+    out, rep = run(env, A, B, C, 1.5, 0.5, ta, tb, cfg)
+    plan = plan_for(23, F, m, n, k, 5, kc=128, bit_lo=52, bit_hi=62)
+    check_log_matches_plan(rep, plan, 5)
+    assert rep.injected == F and rep.corrected_subtract + rep.corrected_recompute == F
+    got = sorted((r["interval"], r["row"], r["col"]) for r in rep.records)
+    _, orecs, _ = oracle.abft(A, B, C, 1.5, 0.5, ta, tb, bm=128, bn=128, kc=128, plan=plan)
+    assert got == sorted((r.interval, r.row, r.col) for r in orecs)
+    ref = oracle.gemm(A, B, C, 1.5, 0.5, ta, tb)
+    assert_close_f64(out, ref, magnitude(A, B, C, 1.5, 0.5, ta, tb), k)
+
+
 def test_deterministic_rerun(env):
     ftgemm = env[0]
     m, n, k = 300, 300, 300
