@@ -362,8 +362,10 @@ def unfused_comparison(torch, ftgemm, h, steps, sizes=(4096, 8192, 16384), kc_on
     """The fused protected product against the unfused comparator (the online ABFT
     of section 5.1 built around the unprotected product, whole-matrix checksums):
     FP64 NN n^3, alpha = 1.5, beta = 0.5, U[-1,1], one flip per rank-K_c slab in
-    both (exponent bits, so each is corrected).  The unfused scheme runs offline
-    (one slab) and online (K_c = 512); its cost is compared with the paper's
+    both (exponent bits, so each is corrected).  The fused product runs with one
+    check per tile and online (per-tile checks every K_c = 512 steps); the
+    unfused scheme runs offline (one slab) and online (K_c = 512); its cost is
+    compared with the paper's
     model (6 + 2K/K_c) P_mm / (n P_mv), P_mm the unprotected product's rate and
     P_mv = 2 flop per 8 bytes at the 8 TB/s HBM peak."""
     rows = []
@@ -376,6 +378,10 @@ def unfused_comparison(torch, ftgemm, h, steps, sizes=(4096, 8192, 16384), kc_on
             "unprotected": lambda: ftgemm.gemm_f64(h, dA, dB, dC, 1.5, 0.5, cfg=ftgemm.make_config(abft=False)),
             "fused": lambda: ftgemm.gemm_f64(h, dA, dB, dC, 1.5, 0.5,
                                              cfg=ftgemm.make_config(n_faults=nint, **inj)),
+            # the fused product with the same verification interval (online, per tile)
+            "fused_online": lambda: ftgemm.gemm_f64(h, dA, dB, dC, 1.5, 0.5,
+                                                    cfg=ftgemm.make_config(interval_k=kc_online, n_faults=nint,
+                                                                           **inj)),
             "unfused_offline": lambda: ftgemm.gemm_f64_unfused(h, dA, dB, dC, 1.5, 0.5,
                                                                cfg=ftgemm.make_config(n_faults=1, **inj)),
             "unfused_online": lambda: ftgemm.gemm_f64_unfused(
