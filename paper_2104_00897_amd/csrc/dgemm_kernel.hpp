@@ -686,19 +686,18 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
                     const int fr = __builtin_amdgcn_readfirstlane(Vp->fi);
                     const int fc = __builtin_amdgcn_readfirstlane(Vp->fj);
                     if (!final) {
-                        if (nr) {
-                            const int g = (fr % WM) / 16;
+                        // (both arrays updated by value selects: conditional
+                        // updates of either array were merged by the compiler
+                        // into one through a selected pointer, which moved er
+                        // and ec to scratch for the whole k loop)
+                        const int g = (fr % WM) / 16, h = (fc % WN) / 16;
+                        const double dr = nr ? Vp->dfi : 0.0, dc = nr ? 0.0 : Vp->dfj;
+                        const bool rown = nr && fr / WM == wr && g % WGN == wc && lane == fr % 16;
+                        const bool cown = !nr && fc / WN == wc && h % WGM == wr && lane == fc % 16;
 #pragma unroll
-                            for (int q = 0; q < Cf::GSH; ++q)
-                                if (q == g / WGN && fr / WM == wr && g % WGN == wc && lane == fr % 16)
-                                    er[q] += Vp->dfi;
-                        } else {
-                            const int h = (fc % WN) / 16;
+                        for (int q = 0; q < Cf::GSH; ++q) er[q] += (rown && q == g / WGN) ? dr : 0.0;
 #pragma unroll
-                            for (int q = 0; q < Cf::HSH; ++q)
-                                if (q == h / WGM && fc / WN == wc && h % WGM == wr && lane == fc % 16)
-                                    ec[q] += Vp->dfj;
-                        }
+                        for (int q = 0; q < Cf::HSH; ++q) ec[q] += (cown && q == h / WGM) ? dc : 0.0;
                     }
                     if (tid == 0) {
                         atomicAdd(&args.rep->cnt[kChecksumOnly], 1ull);

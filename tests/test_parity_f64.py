@@ -292,6 +292,35 @@ def test_interval_mode_many_faults_per_tile(env, tile):
     assert_close_f64(out, ref, magnitude(A, B, C, 1.5, 0.5, 0, 0), k)
 
 
+@pytest.mark.parametrize("tile", [2, 3, 5])
+def test_interval_checksum_faults_rebased(env, tile):
+    """Interval kernels: a flipped maintained row checksum is a one-direction
+    mismatch at its interval end (checksum only, data untouched), after which the
+    checksum is re-based by adding the mismatch.  After a flip to a huge value that
+    addition loses the checksum's own value, so later intervals of the tile flag
+    the row again (the oracle does the same).  Records and counts equal the
+    oracle's simulation of the plan; the data is the product throughout."""
+    ftgemm = env[0]
+    m, n, k = 256, 256, 512
+    A, B, C = inputs.gemm_operands_f64(m, n, k, seed=11)
+    bm, bn = TILES[tile]
+    slots = -(-m // bm) * -(-n // bn) * (k // 128)
+    F = min(12, slots // 2)
+    cfg = ftgemm.make_config(tile=tile, interval_k=128, seed=31, n_faults=F, bit_lo=52, bit_hi=62,
+                             target=ftgemm.TARGET_CHECKSUM)
+    out, rep = run(env, A, B, C, 1.0, 1.0, 0, 0, cfg)
+    plan = plan_for(31, F, m, n, k, tile, kc=128, bit_lo=52, bit_hi=62, target=oracle.TARGET_CHECKSUM)
+    _, orecs, ocnt = oracle.abft(A, B, C, 1.0, 1.0, bm=bm, bn=bn, kc=128, plan=plan)
+    assert rep.injected == F == ocnt["injected"]
+    assert (rep.detected, rep.checksum_only, rep.uncorrectable) == \
+        (ocnt["detected"], ocnt["checksum_only"], ocnt["uncorrectable"])
+    assert rep.corrected_subtract + rep.corrected_recompute == 0
+    got = sorted((r["interval"], r["tile_m"], r["tile_n"], r["row"], r["col"], r["kind"]) for r in rep.records)
+    assert got == sorted((o.interval, o.tile_m, o.tile_n, o.row, o.col, o.kind) for o in orecs)
+    ref = oracle.gemm(A, B, C, 1.0, 1.0)
+    assert_close_f64(out, ref, magnitude(A, B, C, 1.0, 1.0, 0, 0), k)
+
+
 @pytest.mark.parametrize("tile", [2, 5])
 @pytest.mark.parametrize("ta,tb", [(0, 0), (1, 1)])
 def test_interval_two_faults_in_slot_recomputed(env, tile, ta, tb):
