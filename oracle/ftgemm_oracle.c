@@ -469,6 +469,20 @@ static void push_record(ftgo_record* recs, int64_t cap, ftgo_counts* cnt, const 
     cnt->n_records++;
 }
 
+/* Sum of row x (dir 0) or column x (dir 1) of the held values, in the order
+ * check_line forms its reference sum. */
+static double held_line_sum(const tile_state* T, int dir, int64_t x)
+{
+    int64_t R = T->R, Q = T->Q;
+    int64_t len = dir == 0 ? Q : R;
+    double ref = 0.0;
+    for (int64_t y = 0; y < len; ++y) {
+        int64_t i = dir == 0 ? x : y, j = dir == 0 ? y : x;
+        ref = ref + T->out[i + j * R];
+    }
+    return ref;
+}
+
 /* Verification of one (tile, interval) slot: flags, classification, correction. */
 static void verify_slot(tile_state* T, int final, int64_t pend, int64_t tm, int64_t tn, int64_t t,
                         const ftgo_fault* plan, int64_t nplan, ftgo_record* recs, int64_t cap,
@@ -523,9 +537,12 @@ static void verify_slot(tile_state* T, int final, int64_t pend, int64_t tm, int6
     } else if (nr + nc == 1) {
         /* one direction only: the maintained checksum is the faulty value;
          * the data passed the other direction's check and is kept.  The
-         * checksum is re-based on the data so later intervals start clean. */
-        if (nr) { if (!final) T->er[fi] = T->er[fi] + dri; }
-        else    { if (!final) T->ec[fj] = T->ec[fj] + dcj; }
+         * checksum is re-based on the data so later intervals start clean:
+         * set to the line's sum of the held values (adding the mismatch
+         * instead would lose the checksum's own value after a flip to a huge
+         * value, and the later intervals would flag the line again). */
+        if (nr) { if (!final) T->er[fi] = held_line_sum(T, 0, fi); }
+        else    { if (!final) T->ec[fj] = held_line_sum(T, 1, fj); }
         cnt->checksum_only++;
         push_record(recs, cap, cnt, T, tm, tn, t, nr ? fi : -1, nr ? -1 : fj,
                     FTGO_KIND_CHECKSUM_ONLY, nr ? dri : dcj, nr ? tri : tcj);

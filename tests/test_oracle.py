@@ -264,6 +264,21 @@ def test_checksum_only_fault_leaves_data():
     assert cnt["detected"] == 3
 
 
+def test_checksum_rebased_after_huge_flip():
+    """A flip of the top exponent bit makes the maintained checksum huge; the
+    re-based checksum is the data's line sum, so the later intervals of the tile
+    pass (adding the mismatch to the huge value would have lost the checksum's
+    own value).  Data exact, one record."""
+    m, n, k = 16, 16, 64
+    A, B, C = inputs.integer_operands(m, n, k, seed=5)
+    for bit in (62, 61, 58):
+        plan = [oracle.Fault(0, 0, 0, 3, 0, 7, bit, oracle.TARGET_CHECKSUM)]
+        out, recs, cnt = oracle.abft(A, B, C, 1.0, 1.0, bm=16, bn=16, kc=16, plan=plan)
+        np.testing.assert_array_equal(out, exact_product(A, B, C, 1.0, 1.0, 0, 0))
+        assert cnt["detected"] == 1 and cnt["checksum_only"] == 1 and cnt["uncorrectable"] == 0
+        assert [(r.interval, r.row, r.col, r.kind) for r in recs] == [(0, 3, -1, oracle.KIND_CHECKSUM_ONLY)]
+
+
 def test_two_faults_in_one_slot_uncorrectable():
     m, n, k = 32, 32, 32
     A, B, C = inputs.integer_operands(m, n, k, seed=6)
