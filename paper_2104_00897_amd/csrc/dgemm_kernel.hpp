@@ -686,18 +686,36 @@ __device__ __attribute__((always_inline)) inline void dgemm_tile(const DGemmArgs
                     const int fr = __builtin_amdgcn_readfirstlane(Vp->fi);
                     const int fc = __builtin_amdgcn_readfirstlane(Vp->fj);
                     if (!final) {
-                        // (both arrays updated by value selects: conditional
-                        // updates of either array were merged by the compiler
-                        // into one through a selected pointer, which moved er
-                        // and ec to scratch for the whole k loop)
+                        // The line's checksum is the sum of its four lanes'
+                        // partials; the first of them is set so that the sum
+                        // is the line's reference sum (adding the mismatch
+                        // instead would lose the checksum's own value after a
+                        // flip to a huge value).  Both arrays are updated by
+                        // value selects: conditional updates of either array
+                        // were merged by the compiler into one through a
+                        // selected pointer, which moved er and ec to scratch
+                        // for the whole k loop.
                         const int g = (fr % WM) / 16, h = (fc % WN) / 16;
-                        const double dr = nr ? Vp->dfi : 0.0, dc = nr ? 0.0 : Vp->dfj;
+                        double rref = 0.0, cref = 0.0;
+                        if (nr) {
+#pragma unroll
+                            for (int w = 0; w < WGN; ++w) rref += Vp->rsum[w][fr];
+                        } else {
+#pragma unroll
+                            for (int w = 0; w < WGM; ++w) cref += Vp->csum[w][fc];
+                        }
                         const bool rown = nr && fr / WM == wr && g % WGN == wc && lane == fr % 16;
                         const bool cown = !nr && fc / WN == wc && h % WGM == wr && lane == fc % 16;
 #pragma unroll
-                        for (int q = 0; q < Cf::GSH; ++q) er[q] += (rown && q == g / WGN) ? dr : 0.0;
+                        for (int q = 0; q < Cf::GSH; ++q) {
+                            const double others = quarter_sum(lq == 0 ? 0.0 : er[q]);
+                            er[q] = (rown && q == g / WGN) ? rref - others : er[q];
+                        }
 #pragma unroll
-                        for (int q = 0; q < Cf::HSH; ++q) ec[q] += (cown && q == h / WGM) ? dc : 0.0;
+                        for (int q = 0; q < Cf::HSH; ++q) {
+                            const double others = quarter_sum(lq == 0 ? 0.0 : ec[q]);
+                            ec[q] = (cown && q == h / WGM) ? cref - others : ec[q];
+                        }
                     }
                     if (tid == 0) {
                         atomicAdd(&args.rep->cnt[kChecksumOnly], 1ull);

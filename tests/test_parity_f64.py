@@ -296,10 +296,9 @@ def test_interval_mode_many_faults_per_tile(env, tile):
 def test_interval_checksum_faults_rebased(env, tile):
     """Interval kernels: a flipped maintained row checksum is a one-direction
     mismatch at its interval end (checksum only, data untouched), after which the
-    checksum is re-based by adding the mismatch.  After a flip to a huge value that
-    addition loses the checksum's own value, so later intervals of the tile flag
-    the row again (the oracle does the same).  Records and counts equal the
-    oracle's simulation of the plan; the data is the product throughout."""
+    checksum is re-based on the row's sum of the held values, so the later
+    intervals of the tile pass even after flips to huge values: one record per
+    fault, equal to the oracle's simulation of the plan; the data is the product."""
     ftgemm = env[0]
     m, n, k = 256, 256, 512
     A, B, C = inputs.gemm_operands_f64(m, n, k, seed=11)
@@ -315,6 +314,7 @@ def test_interval_checksum_faults_rebased(env, tile):
     assert (rep.detected, rep.checksum_only, rep.uncorrectable) == \
         (ocnt["detected"], ocnt["checksum_only"], ocnt["uncorrectable"])
     assert rep.corrected_subtract + rep.corrected_recompute == 0
+    assert rep.detected == rep.checksum_only == F and rep.uncorrectable == 0
     got = sorted((r["interval"], r["tile_m"], r["tile_n"], r["row"], r["col"], r["kind"]) for r in rep.records)
     assert got == sorted((o.interval, o.tile_m, o.tile_n, o.row, o.col, o.kind) for o in orecs)
     ref = oracle.gemm(A, B, C, 1.0, 1.0)
